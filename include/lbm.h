@@ -1,0 +1,207 @@
+/*
+ * mrtlbm: C ABI of the GPU (gfx950) implementation of the D2Q8 porous
+ * multiple-relaxation-time lattice Boltzmann scheme of Liu & He,
+ * "Multiple-relaxation-time lattice Boltzmann modeling of incompressible
+ * flows in porous media" (arXiv:1311.7239), with the D2Q5 MRT thermal model
+ * of its Appendix B.
+ *
+ * Model (Sec. 2): generalized Brinkman-Forchheimer-extended Darcy flow,
+ * Eqs. (1)-(3); D2Q8 velocities (Eq. 7), moment transform M (Eq. 10),
+ * porosity-dependent equilibrium moments (Eqs. 11-12), relaxation
+ * diag(1, s_e, 1, s_q, 1, s_q, s_nu, s_nu) (Eq. 13) with s_nu = 1/tau and
+ * tau = 1/2 + 3 J nu (Eq. 21), moment-space forcing (Eq. 16) carrying the
+ * Darcy and Forchheimer drag of Eq. (3), explicit velocity (Eqs. 18-19),
+ * pressure (Eq. 20), collision (Eq. 14) and streaming (Eq. 15).
+ * Units: lattice units, delta_x = delta_t = c = 1, rho0 = 1.
+ *
+ * Conventions shared by every entry point:
+ *   - Grids are row-major [y][x] with x fastest; node (x, y) is the cell
+ *     centre (x + 1/2, y + 1/2). Walls sit half a link outside the edge
+ *     nodes (x = 0 and x = nx, y = 0 and y = ny).
+ *   - Every array argument is DEVICE memory unless marked "host". The
+ *     library never allocates device memory: the caller passes a workspace
+ *     of at least the size lbm_workspace_size() reports, keeps it alive and
+ *     unshared while the context exists, and owns every output buffer.
+ *   - Work is enqueued asynchronously on the HIP stream given at creation.
+ *     Only lbm_reduce, lbm_save and lbm_load synchronise that stream.
+ *   - Time t counts completed collide-and-stream cycles; "the state at t"
+ *     is the pre-collision populations f(t) of Eq. (15).
+ *   - Populations are stored as deviations from the rest state
+ *     f_ref_i = 3 w_i Pi0 (Eq. 22 at u = 0 with phi p = Pi0), w = 1/9 on
+ *     axis links and 1/36 on diagonal links; thermal populations as
+ *     deviations from w_T T0 with w_T = (4 + varpi)/20 (App. B, varpi = 0).
+ *   - Every function returns LBM_OK (0) or a negative status; a failed call
+ *     has no side effect unless it returns LBM_EDEVICE, after which the
+ *     context is poisoned. No function prints, aborts or throws.
+ *   - A context is not thread-safe.
+ */
+#ifndef MRTLBM_LBM_H
+#define MRTLBM_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* invalid argument or descriptor             */
+#define LBM_ESTATE (-2)    /* call not valid in the context's state      */
+#define LBM_EDEVICE (-3)   /* a HIP call failed; the context is poisoned */
+#define LBM_EUNSTABLE (-4) /* non-finite mass or residual                */
+#define LBM_ENOTSUP (-5)   /* combination not supported                  */
+
+/* boundary kinds per axis */
+#define LBM_PERIODIC 0
+#define LBM_WALLS 1 /* halfway bounce-back; top wall y = ny moves at lid_ux */
+
+/* population storage */
+#define LBM_FP32_DEV 0 /* IEEE binary32 deviations                      */
+#define LBM_FP16_DEV 1 /* IEEE binary16 deviations, round-to-nearest-even */
+
+/* porous medium description */
+#define LBM_MEDIUM_UNIFORM 0   /* phi0, kappa0 everywhere                    */
+#define LBM_MEDIUM_PHI_ERGUN 1 /* phi plane; K from Eq. (4) with diameter dp */
+#define LBM_MEDIUM_PHI_KAPPA 2 /* phi plane and kappa = 1/K plane            */
+
+typedef struct {
+    int32_t enabled; /* 0: isothermal flow                                   */
+    double tau_T;    /* zeta_1 = zeta_2 = 1/tau_T (Eq. B.7)                   */
+    double sigma;    /* thermal capacity ratio (Eq. B.1)                      */
+    double zeta3, zeta4; /* 1.1 in the paper (Sec. 3.4)                       */
+    double Th, Tc;   /* Dirichlet temperatures of walls x = 0 and x = nx     */
+    double T0;       /* reference temperature of a = g beta (T - T0) j        */
+    double g_beta;   /* g * beta (Sec. 3.4)                                   */
+} lbm_thermal;
+
+typedef struct {
+    int32_t nx, ny;   /* nodes, >= 1 each (>= 2 along a walled axis)          */
+    int32_t bc_x;     /* LBM_PERIODIC or LBM_WALLS (walls at x = 0, x = nx)    */
+    int32_t bc_y;     /* LBM_PERIODIC or LBM_WALLS (walls at y = 0, y = ny)    */
+    double lid_ux;    /* x-velocity of the wall y = ny (needs bc_y = WALLS)    */
+    double nu;        /* fluid viscosity nu > 0; tau = 1/2 + 3 J nu (Eq. 21)   */
+    double J;         /* viscosity ratio nu_e/nu > 0 (Eq. 5)                   */
+    double s_e, s_q;  /* s_2 and s_4 = s_6 of Eq. (13): 1.1 and 1.2 (Sec. 3)   */
+    int32_t medium;   /* LBM_MEDIUM_*                                          */
+    double phi0;      /* uniform porosity, 0 < phi0 <= 1                       */
+    double kappa0;    /* uniform 1/K >= 0 (0 = free fluid)                     */
+    double dp;        /* particle diameter of Eq. (4) (MEDIUM_PHI_ERGUN)       */
+    double F_eps;     /* >= 0: constant F_phi; < 0: F_phi from Eq. (4) per cell */
+    double ax, ay;    /* uniform external acceleration a (Eq. 3)               */
+    double Pi0;       /* rest value of phi*p; reference of the storage         */
+    int32_t storage;  /* LBM_FP32_DEV or LBM_FP16_DEV                          */
+    int32_t ckpt_every; /* 0: no recording; k > 0: record for lbm_backward   */
+    lbm_thermal thermal;
+} lbm_desc;
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, host memory owned by the library */
+
+/* Fills *d with the paper's constants (J = 1, s_e = 1.1, s_q = 1.2,
+ * zeta3 = zeta4 = 1.1, sigma = 1, Pi0 = 1, F_eps = -1, storage FP32) and
+ * zeros elsewhere. d: host. */
+int lbm_desc_defaults(lbm_desc *d);
+
+/* Bytes of device workspace lbm_create needs for this descriptor.
+ * max_steps_recorded: largest step count a recorded forward pass will run
+ * (ignored unless d->ckpt_every > 0). d, bytes: host. */
+int lbm_workspace_size(const lbm_desc *d, int64_t max_steps_recorded, size_t *bytes);
+
+/* Creates a context holding the rest state f(0) = f_ref (t = 0) and, with
+ * thermal enabled, g(0) at T = T0. phi / kappa: device [ny][nx] float planes
+ * for the MEDIUM_PHI_* modes (NULL otherwise), read on `stream` before this
+ * call's work completes, so the caller keeps them alive until the stream
+ * passes this point. workspace: device, >= ws_bytes >= lbm_workspace_size(),
+ * 256-byte aligned. stream: a hipStream_t (NULL = the null stream).
+ * Errors: EINVAL for any invalid descriptor field (nx or ny < 1, a walled
+ * axis with fewer than 2 nodes, nu or J <= 0, phi0 outside (0, 1],
+ * kappa0 < 0, dp <= 0 with MEDIUM_PHI_ERGUN, s_e or s_q outside (0, 2),
+ * tau_T <= 1/2, missing plane, lid on a periodic y axis, too small or
+ * misaligned workspace). */
+int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *workspace,
+               size_t ws_bytes, void *stream, lbm_ctx **out);
+
+/* Ragged batch: n independent domains stepped together by one persistent
+ * launch per step, replayed from a captured HIP graph. descs, phis, kappas:
+ * host arrays of n entries (phis[k]/kappas[k] device planes or NULL).
+ * All domains must share storage and thermal.enabled (thermal unsupported:
+ * ENOTSUP) and have ckpt_every = 0. The tile schedule is chosen by timing
+ * candidates on the stream (autotuning) unless tune_cache (host path, may
+ * be NULL) holds a result for the same batch signature; the choice is
+ * appended there. Results are bitwise identical to stepping each domain
+ * alone. */
+int lbm_batch_workspace_size(int32_t n, const lbm_desc *descs, size_t *bytes);
+int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *const *phis,
+                     const float *const *kappas, void *workspace, size_t ws_bytes,
+                     void *stream, const char *tune_cache, lbm_ctx **out);
+
+/* Advances every domain by n >= 0 collide-and-stream cycles (Eqs. 14-15). */
+int lbm_step(lbm_ctx *c, int64_t n);
+
+/* Current time t (host). */
+int lbm_time(const lbm_ctx *c, int64_t *t);
+
+/* Macroscopic fields at the current time (Eqs. 18-20, B.5) of one domain:
+ * p [ny][nx] (may be NULL), u [2][ny][nx] (u_x plane then u_y; may be NULL),
+ * T [ny][nx] (may be NULL; EINVAL if non-NULL without thermal). */
+int lbm_macroscopic(lbm_ctx *c, int32_t domain, float *p, float *u, float *T);
+
+/* Population deviations f_i(t) - f_ref_i of one domain as float
+ * [8][ny][nx] (paper order f_1..f_8), and thermal g_j(t) - w_T T0 as
+ * [5][ny][nx] (g may be NULL). */
+int lbm_get_populations(lbm_ctx *c, int32_t domain, float *df, float *dg);
+
+/* Replaces the state with f(0) = f_ref + df (and g(0) = w_T T0 + dg) and
+ * sets t = 0; df [8][ny][nx], dg [5][ny][nx] or NULL (keeps g at T0).
+ * Values are rounded to the storage type. Clears any recording. */
+int lbm_set_populations(lbm_ctx *c, int32_t domain, const float *df, const float *dg);
+
+/* FP64 reductions of one domain at the current time, computed on the GPU
+ * with a fixed-order two-pass tree (bitwise reproducible): total mass
+ * sum_x sum_i f_i(t), and the steady residual
+ * ||u(t) - u(t-1)||_2 / ||u(t)||_2 (NaN at t = 0). Synchronises the stream.
+ * mass, residual: host, either may be NULL. EUNSTABLE if either is not
+ * finite (values are still written). */
+int lbm_reduce(lbm_ctx *c, int32_t domain, double *mass, double *residual);
+
+/* Discrete adjoint of the recorded forward pass (hand-written, checkpointed
+ * recomputation every ckpt_every steps). The loss L must depend on the state
+ * only through u(T) at the current time T: dL_du is device [2][ny][nx]
+ * (u_x plane then u_y; zeros where L does not look). Writes dL/dphi
+ * [ny][nx] (device) and, for MEDIUM_PHI_KAPPA, dL/dkappa (device, may be
+ * NULL). In MEDIUM_PHI_ERGUN, kappa and F_phi follow phi through Eq. (4).
+ * ESTATE if the context was not created with ckpt_every > 0, if the state
+ * was replaced since t = 0, or if T exceeds the recorded capacity; ENOTSUP
+ * for thermal, FP16 storage, batches or MEDIUM_UNIFORM. The forward state
+ * is left at T. */
+int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa);
+
+/* Snapshot of one context's state (host memory, synchronous). */
+int lbm_state_bytes(const lbm_ctx *c, size_t *bytes);
+int lbm_save(lbm_ctx *c, void *host_buf, size_t bytes);
+int lbm_load(lbm_ctx *c, const void *host_buf, size_t bytes);
+
+/* Destroys the context (NULL is accepted). The workspace is not touched. */
+int lbm_destroy(lbm_ctx *c);
+
+/* Static text for a status code, and the thread-local message of the last
+ * failed call on this thread ("" if none). */
+const char *lbm_strerror(int status);
+const char *lbm_last_error(void);
+
+/* Information on the launch the library uses for the step of this context:
+ * tile width, rows per thread and grid size (host outputs). */
+int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *rows, int32_t *grid);
+
+/* Selects the launch shape of the step kernel of a single-domain context:
+ * tile_w in {256, 128, 64} threads along x, rows per thread in {1, 2} (256,
+ * 128) or {2, 4} (64), swizzle 0/1 (contiguous tiles per XCD). Every shape
+ * computes bitwise-identical results; only speed differs. EINVAL for an
+ * unsupported shape, ENOTSUP on a batch (its schedule is autotuned). */
+int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t rows, int32_t swizzle);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,621 @@
+// C ABI of the gfx950 porous MRT-LB library: descriptor validation,
+// workspace carving, state bookkeeping (time, ping-pong buffers,
+// checkpoints) and kernel launches. Declarations and the contract of every
+// entry point are in include/lbm.h.
+#include "lbm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm_launch.h"
+
+using namespace mrt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+int64_t round_up64(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Workspace layout of one domain, as byte offsets from its base.
+struct Layout {
+    int32_t pitch = 0;   // elements per stored row
+    int64_t plane = 0;   // elements between planes (same for every plane type)
+    int esize = 4;       // bytes per stored population
+    size_t f_bytes = 0;  // one population buffer (8 planes)
+    size_t g_bytes = 0;  // one thermal buffer (5 planes, FP32)
+    size_t p_bytes = 0;  // one FP32 plane
+    size_t off_f[2] = {0, 0}, off_g[2] = {0, 0};
+    size_t off_phi = 0, off_kappa = 0, off_part = 0, off_res = 0;
+    int red_blocks = 0;
+    // recording for the adjoint
+    int64_t nck = 0, ring = 0;
+    size_t off_ck = 0, off_urec = 0, off_lam[2] = {0, 0}, off_gphi = 0, off_gkappa = 0;
+    size_t total = 0;
+};
+
+Layout make_layout(const lbm_desc &d, int64_t max_rec) {
+    Layout L;
+    L.esize = (d.storage == LBM_FP16_DEV) ? 2 : 4;
+    L.pitch = (int32_t)round_up64(d.nx, 64);
+    L.plane = round_up64((int64_t)d.ny * L.pitch, 128);
+    L.f_bytes = (size_t)L.plane * L.esize * 8;
+    L.g_bytes = (size_t)L.plane * 4 * 5;
+    L.p_bytes = (size_t)L.plane * 4;
+    size_t o = 0;
+    auto carve = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes, ALIGN);
+        return at;
+    };
+    L.off_f[0] = carve(L.f_bytes);
+    L.off_f[1] = carve(L.f_bytes);
+    if (d.thermal.enabled) {
+        L.off_g[0] = carve(L.g_bytes);
+        L.off_g[1] = carve(L.g_bytes);
+    }
+    if (d.medium != LBM_MEDIUM_UNIFORM) L.off_phi = carve(L.p_bytes);
+    if (d.medium == LBM_MEDIUM_PHI_KAPPA) L.off_kappa = carve(L.p_bytes);
+    L.red_blocks = reduce_blocks(d.nx, d.ny);
+    L.off_part = carve(sizeof(double) * 3 * (size_t)L.red_blocks);
+    L.off_res = carve(sizeof(double) * 4);
+    if (d.ckpt_every > 0) {
+        L.nck = max_rec / d.ckpt_every + 1;
+        L.ring = d.ckpt_every;
+        L.off_ck = carve(L.f_bytes * (size_t)L.nck);
+        L.off_urec = carve(L.p_bytes * 2 * (size_t)L.ring);
+        L.off_lam[0] = carve(L.p_bytes * 8);
+        L.off_lam[1] = carve(L.p_bytes * 8);
+        L.off_gphi = carve(L.p_bytes);
+        L.off_gkappa = carve(L.p_bytes);
+    }
+    L.total = o;
+    return L;
+}
+
+int validate(const lbm_desc *d) {
+    if (!d) return fail(LBM_EINVAL, "descriptor is NULL");
+    if (d->nx < 1 || d->ny < 1) return fail(LBM_EINVAL, "nx and ny must be >= 1 (got %d, %d)", d->nx, d->ny);
+    if ((int64_t)d->nx * d->ny > (int64_t)1 << 31)
+        return fail(LBM_EINVAL, "nx*ny exceeds 2^31 nodes");
+    if (d->bc_x != LBM_PERIODIC && d->bc_x != LBM_WALLS) return fail(LBM_EINVAL, "bc_x must be LBM_PERIODIC or LBM_WALLS");
+    if (d->bc_y != LBM_PERIODIC && d->bc_y != LBM_WALLS) return fail(LBM_EINVAL, "bc_y must be LBM_PERIODIC or LBM_WALLS");
+    if (d->bc_x == LBM_WALLS && d->nx < 2) return fail(LBM_EINVAL, "a walled x axis needs nx >= 2");
+    if (d->bc_y == LBM_WALLS && d->ny < 2) return fail(LBM_EINVAL, "a walled y axis needs ny >= 2");
+    if (d->lid_ux != 0.0 && d->bc_y != LBM_WALLS) return fail(LBM_EINVAL, "lid_ux needs bc_y = LBM_WALLS");
+    if (!std::isfinite(d->lid_ux)) return fail(LBM_EINVAL, "lid_ux must be finite");
+    if (!(d->nu > 0.0) || !std::isfinite(d->nu)) return fail(LBM_EINVAL, "nu must be > 0 (tau > 1/2)");
+    if (!(d->J > 0.0) || !std::isfinite(d->J)) return fail(LBM_EINVAL, "J must be > 0");
+    if (!(d->s_e > 0.0 && d->s_e < 2.0)) return fail(LBM_EINVAL, "s_e must lie in (0, 2)");
+    if (!(d->s_q > 0.0 && d->s_q < 2.0)) return fail(LBM_EINVAL, "s_q must lie in (0, 2)");
+    if (d->medium < LBM_MEDIUM_UNIFORM || d->medium > LBM_MEDIUM_PHI_KAPPA) return fail(LBM_EINVAL, "unknown medium");
+    if (d->medium == LBM_MEDIUM_UNIFORM) {
+        if (!(d->phi0 > 0.0 && d->phi0 <= 1.0)) return fail(LBM_EINVAL, "phi0 must lie in (0, 1]");
+        if (!(d->kappa0 >= 0.0) || !std::isfinite(d->kappa0)) return fail(LBM_EINVAL, "kappa0 must be finite and >= 0");
+    }
+    if (d->medium == LBM_MEDIUM_PHI_ERGUN && !(d->dp > 0.0 && std::isfinite(d->dp)))
+        return fail(LBM_EINVAL, "dp must be > 0 for LBM_MEDIUM_PHI_ERGUN");
+    if (!std::isfinite(d->F_eps)) return fail(LBM_EINVAL, "F_eps must be finite");
+    if (!std::isfinite(d->ax) || !std::isfinite(d->ay) || !std::isfinite(d->Pi0))
+        return fail(LBM_EINVAL, "ax, ay and Pi0 must be finite");
+    if (d->storage != LBM_FP32_DEV && d->storage != LBM_FP16_DEV) return fail(LBM_EINVAL, "unknown storage");
+    if (d->ckpt_every < 0) return fail(LBM_EINVAL, "ckpt_every must be >= 0");
+    if (d->thermal.enabled) {
+        const lbm_thermal &t = d->thermal;
+        if (!(t.tau_T > 0.5) || !std::isfinite(t.tau_T)) return fail(LBM_EINVAL, "thermal tau_T must be > 1/2");
+        if (!(t.sigma > 0.0) || !std::isfinite(t.sigma)) return fail(LBM_EINVAL, "thermal sigma must be > 0");
+        if (!(t.zeta3 > 0.0 && t.zeta3 < 2.0) || !(t.zeta4 > 0.0 && t.zeta4 < 2.0))
+            return fail(LBM_EINVAL, "thermal zeta3, zeta4 must lie in (0, 2)");
+        if (!std::isfinite(t.Th) || !std::isfinite(t.Tc) || !std::isfinite(t.T0) || !std::isfinite(t.g_beta))
+            return fail(LBM_EINVAL, "thermal temperatures and g_beta must be finite");
+    }
+    return LBM_OK;
+}
+
+// Per-domain constants in single precision, computed in double on the host
+// (the same code for single and batched contexts, so both see identical bits).
+Dom make_dom(const lbm_desc &d, const Layout &L) {
+    Dom o;
+    std::memset(&o, 0, sizeof(o));
+    o.nx = d.nx; o.ny = d.ny; o.pitch = L.pitch; o.plane = L.plane;
+    o.bc_x = d.bc_x; o.bc_y = d.bc_y;
+    o.lid6 = (float)(d.lid_ux / 6.0);
+    const double tau = 0.5 + 3.0 * d.J * d.nu;  // Eq. (21), cs^2 = 1/3
+    const double s_nu = 1.0 / tau;
+    o.s_e = (float)d.s_e; o.s_q = (float)d.s_q; o.s_nu = (float)s_nu;
+    o.h_e = (float)(1.0 - 0.5 * d.s_e); o.h_q = (float)(1.0 - 0.5 * d.s_q);
+    o.h_nu = (float)(1.0 - 0.5 * s_nu);
+    o.medium = d.medium;
+    o.nu = (float)d.nu;
+    o.Fconst = (float)d.F_eps;
+    if (d.medium == LBM_MEDIUM_UNIFORM) {
+        const double F = d.F_eps >= 0.0 ? d.F_eps : 1.75 / std::sqrt(150.0 * d.phi0 * d.phi0 * d.phi0);
+        o.phi0 = (float)d.phi0;
+        o.inv_phi0 = (float)(1.0 / d.phi0);
+        o.cd0 = (float)(d.phi0 * d.nu * d.kappa0);
+        o.cf0 = (float)(d.phi0 * F * std::sqrt(d.kappa0));
+    }
+    if (d.medium == LBM_MEDIUM_PHI_ERGUN) o.kcoef = (float)(150.0 / (d.dp * d.dp));
+    o.ax = (float)d.ax; o.ay = (float)d.ay;
+    if (d.thermal.enabled) {
+        const lbm_thermal &t = d.thermal;
+        o.thermal = 1;
+        o.zT = (float)(1.0 / t.tau_T);
+        o.z3 = (float)t.zeta3; o.z4 = (float)t.zeta4;
+        o.inv_sigma = (float)(1.0 / t.sigma);
+        o.T0 = (float)t.T0;
+        o.gbeta = (float)t.g_beta;
+        o.abbh = (float)(0.4 * (t.Th - t.T0));  // 2 w_T (T_w - T0), w_T = 1/5
+        o.abbc = (float)(0.4 * (t.Tc - t.T0));
+    }
+    return o;
+}
+
+struct Domain {
+    lbm_desc desc;
+    Layout L;
+    char *base = nullptr;
+    Dom dom;  // constants and medium planes; buffers filled per launch
+};
+
+}  // namespace
+
+struct lbm_ctx {
+    std::vector<Domain> dom;
+    hipStream_t stream = nullptr;
+    int64_t t = 0;
+    int cur = 0;  // index of the buffer holding the state at t
+    bool poisoned = false;
+    bool batch = false;
+    Schedule sched{256, 1, 1};
+    // recording (single domain)
+    bool rec_valid = false;
+    int64_t rec_cap = 0;
+    // batched stepping
+    Dom *d_doms = nullptr;
+    int4 *d_tiles = nullptr;
+    int ntiles = 0;
+    int grid = 0;
+    hipGraphExec_t gexec = nullptr;
+    int graph_steps = 0;
+};
+
+namespace {
+
+int device_fail(lbm_ctx *c, hipError_t e, const char *what) {
+    if (c) c->poisoned = true;
+    return fail(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+Dom dom_for(const Domain &D, int cur) {
+    Dom d = D.dom;
+    d.fin = D.base + D.L.off_f[cur];
+    d.fout = D.base + D.L.off_f[cur ^ 1];
+    if (D.desc.thermal.enabled) {
+        d.gin = (const float *)(D.base + D.L.off_g[cur]);
+        d.gout = (float *)(D.base + D.L.off_g[cur ^ 1]);
+    }
+    return d;
+}
+
+Source src_now(int64_t t) { return t == 0 ? SRC_DIRECT : SRC_GATHER; }
+Source src_prev(int64_t t) { return t == 0 ? SRC_NONE : (t == 1 ? SRC_DIRECT : SRC_GATHER); }
+
+int check_ctx(lbm_ctx *c) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (c->poisoned) return fail(LBM_EDEVICE, "context is poisoned by an earlier device error");
+    return LBM_OK;
+}
+
+int check_domain(lbm_ctx *c, int32_t k) {
+    if (k < 0 || k >= (int32_t)c->dom.size()) return fail(LBM_EINVAL, "domain %d out of range", k);
+    return LBM_OK;
+}
+
+// Zeroed rest state (deviations 0) in buffer `cur` of one domain, medium
+// planes copied in.
+hipError_t init_domain(Domain &D, int cur, const float *phi, const float *kappa, hipStream_t st) {
+    hipError_t e = launch_fill_zero(D.base + D.L.off_f[cur], D.L.f_bytes, st);
+    if (e == hipSuccess && D.desc.thermal.enabled) e = launch_fill_zero(D.base + D.L.off_g[cur], D.L.g_bytes, st);
+    if (e == hipSuccess && D.desc.medium != LBM_MEDIUM_UNIFORM) {
+        // keep the row padding defined: fill first, then copy the rows
+        e = launch_fill_zero(D.base + D.L.off_phi, align_up(D.L.p_bytes, 16), st);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(D.base + D.L.off_phi, (size_t)D.L.pitch * 4, phi, (size_t)D.desc.nx * 4,
+                                 (size_t)D.desc.nx * 4, (size_t)D.desc.ny, hipMemcpyDeviceToDevice, st);
+    }
+    if (e == hipSuccess && D.desc.medium == LBM_MEDIUM_PHI_KAPPA) {
+        e = launch_fill_zero(D.base + D.L.off_kappa, align_up(D.L.p_bytes, 16), st);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(D.base + D.L.off_kappa, (size_t)D.L.pitch * 4, kappa, (size_t)D.desc.nx * 4,
+                                 (size_t)D.desc.nx * 4, (size_t)D.desc.ny, hipMemcpyDeviceToDevice, st);
+    }
+    return e;
+}
+
+int setup_domain(Domain &D, const lbm_desc *d, const float *phi, const float *kappa, char *base) {
+    D.desc = *d;
+    D.L = make_layout(*d, 0);
+    D.base = base;
+    D.dom = make_dom(*d, D.L);
+    if (d->medium != LBM_MEDIUM_UNIFORM) {
+        if (!phi) return fail(LBM_EINVAL, "phi plane required for this medium");
+        D.dom.phi = (const float *)(base + D.L.off_phi);
+    }
+    if (d->medium == LBM_MEDIUM_PHI_KAPPA) {
+        if (!kappa) return fail(LBM_EINVAL, "kappa plane required for LBM_MEDIUM_PHI_KAPPA");
+        D.dom.kappa = (const float *)(base + D.L.off_kappa);
+    }
+    return LBM_OK;
+}
+
+hipError_t checkpoint(lbm_ctx *c) {
+    Domain &D = c->dom[0];
+    const int64_t k = D.desc.ckpt_every;
+    if (!c->rec_valid || k <= 0 || c->t % k != 0) return hipSuccess;
+    const int64_t slot = c->t / k;
+    if (slot >= D.L.nck) return hipSuccess;  // beyond capacity: backward will refuse
+    return hipMemcpyAsync(D.base + D.L.off_ck + (size_t)slot * D.L.f_bytes, D.base + D.L.off_f[c->cur],
+                          D.L.f_bytes, hipMemcpyDeviceToDevice, c->stream);
+}
+
+}  // namespace
+
+// =================================================================== ABI
+
+extern "C" {
+
+int lbm_desc_defaults(lbm_desc *d) {
+    if (!d) return fail(LBM_EINVAL, "descriptor is NULL");
+    std::memset(d, 0, sizeof(*d));
+    d->J = 1.0;
+    d->s_e = 1.1;
+    d->s_q = 1.2;
+    d->phi0 = 1.0;
+    d->F_eps = -1.0;
+    d->Pi0 = 1.0;
+    d->storage = LBM_FP32_DEV;
+    d->thermal.sigma = 1.0;
+    d->thermal.zeta3 = 1.1;
+    d->thermal.zeta4 = 1.1;
+    d->thermal.tau_T = 1.0;
+    return LBM_OK;
+}
+
+int lbm_workspace_size(const lbm_desc *d, int64_t max_steps_recorded, size_t *bytes) {
+    int rc = validate(d);
+    if (rc) return rc;
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    if (d->ckpt_every > 0 && max_steps_recorded < 0) return fail(LBM_EINVAL, "max_steps_recorded must be >= 0");
+    *bytes = make_layout(*d, d->ckpt_every > 0 ? max_steps_recorded : 0).total;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *workspace,
+               size_t ws_bytes, void *stream, lbm_ctx **out) {
+    int rc = validate(d);
+    if (rc) return rc;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % ALIGN) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    if (d->medium != LBM_MEDIUM_UNIFORM && !phi) return fail(LBM_EINVAL, "phi plane required for this medium");
+    if (d->medium == LBM_MEDIUM_PHI_KAPPA && !kappa) return fail(LBM_EINVAL, "kappa plane required");
+    // recording capacity follows from the workspace the caller sized
+    int64_t cap = 0;
+    if (d->ckpt_every > 0) {
+        const size_t base = make_layout(*d, 0).total;
+        if (ws_bytes < base) return fail(LBM_EINVAL, "workspace too small (%zu < %zu bytes)", ws_bytes, base);
+        // largest max_rec with total <= ws_bytes (monotone in max_rec)
+        int64_t lo = 0, hi = 1;
+        while (make_layout(*d, hi).total <= ws_bytes && hi < ((int64_t)1 << 40)) hi *= 2;
+        while (hi - lo > 1) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            if (make_layout(*d, mid).total <= ws_bytes) lo = mid; else hi = mid;
+        }
+        cap = lo;
+    }
+    const Layout L = make_layout(*d, cap);
+    if (ws_bytes < L.total) return fail(LBM_EINVAL, "workspace too small (%zu < %zu bytes)", ws_bytes, L.total);
+
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_EINVAL, "host allocation failed");
+    c->stream = (hipStream_t)stream;
+    c->dom.resize(1);
+    Domain &D = c->dom[0];
+    rc = setup_domain(D, d, phi, kappa, (char *)workspace);
+    if (rc) { delete c; return rc; }
+    D.L = L;
+    c->rec_cap = cap;
+    hipError_t e = init_domain(D, 0, phi, kappa, c->stream);
+    if (e != hipSuccess) {
+        rc = fail(LBM_EDEVICE, "initialisation: %s", hipGetErrorString(e));
+        delete c;
+        return rc;
+    }
+    c->rec_valid = d->ckpt_every > 0;
+    e = checkpoint(c);
+    if (e != hipSuccess) {
+        rc = fail(LBM_EDEVICE, "checkpoint: %s", hipGetErrorString(e));
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t n) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    if (c->batch) {
+        extern int lbm_batch_step_impl(lbm_ctx * c, int64_t n);
+        return lbm_batch_step_impl(c, n);
+    }
+    Domain &D = c->dom[0];
+    for (int64_t k = 0; k < n; ++k) {
+        const Dom d = dom_for(D, c->cur);
+        hipError_t e = launch_step(d, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, src_now(c->t),
+                                   false, c->sched, c->stream);
+        if (e != hipSuccess) return device_fail(c, e, "step launch");
+        c->cur ^= 1;
+        c->t += 1;
+        e = checkpoint(c);
+        if (e != hipSuccess) return device_fail(c, e, "checkpoint copy");
+    }
+    return LBM_OK;
+}
+
+int lbm_time(const lbm_ctx *c, int64_t *t) {
+    if (!c || !t) return fail(LBM_EINVAL, "NULL argument");
+    *t = c->t;
+    return LBM_OK;
+}
+
+int lbm_macroscopic(lbm_ctx *c, int32_t k, float *p, float *u, float *T) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if ((rc = check_domain(c, k))) return rc;
+    Domain &D = c->dom[k];
+    if (T && !D.desc.thermal.enabled) return fail(LBM_EINVAL, "T requested without thermal model");
+    if (!p && !u && !T) return LBM_OK;
+    const Dom d = dom_for(D, c->cur);
+    const int64_t n = (int64_t)D.desc.nx * D.desc.ny;
+    hipError_t e = launch_macroscopic(d, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, src_now(c->t),
+                                      (float)D.desc.Pi0, p, u, u ? u + n : nullptr, T, c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "macroscopic launch");
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx *c, int32_t k, float *df, float *dg) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if ((rc = check_domain(c, k))) return rc;
+    if (!df) return fail(LBM_EINVAL, "df is NULL");
+    Domain &D = c->dom[k];
+    if (dg && !D.desc.thermal.enabled) return fail(LBM_EINVAL, "dg requested without thermal model");
+    const Dom d = dom_for(D, c->cur);
+    hipError_t e = launch_get_populations(d, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
+                                          src_now(c->t), df, dg, c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "get_populations launch");
+    return LBM_OK;
+}
+
+int lbm_set_populations(lbm_ctx *c, int32_t k, const float *df, const float *dg) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if ((rc = check_domain(c, k))) return rc;
+    if (!df) return fail(LBM_EINVAL, "df is NULL");
+    if (c->batch) return fail(LBM_ENOTSUP, "set_populations is not supported on batches");
+    Domain &D = c->dom[k];
+    if (dg && !D.desc.thermal.enabled) return fail(LBM_EINVAL, "dg given without thermal model");
+    // write f(0) into the buffer that becomes current at t = 0
+    Dom d = dom_for(D, c->cur ^ 1);  // fout/gout point at buffer `cur`
+    hipError_t e = launch_set_populations(d, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, df, dg,
+                                          c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "set_populations launch");
+    c->t = 0;
+    c->rec_valid = D.desc.ckpt_every > 0;
+    e = checkpoint(c);
+    if (e != hipSuccess) return device_fail(c, e, "checkpoint copy");
+    return LBM_OK;
+}
+
+int lbm_reduce(lbm_ctx *c, int32_t k, double *mass, double *residual) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if ((rc = check_domain(c, k))) return rc;
+    Domain &D = c->dom[k];
+    const int par = c->batch ? (int)(c->t & 1) : c->cur;
+    const Dom cur = dom_for(D, par);
+    const Dom prev = dom_for(D, par ^ 1);
+    double *partials = (double *)(D.base + D.L.off_part);
+    double *result = (double *)(D.base + D.L.off_res);
+    hipError_t e = launch_reduce(cur, src_now(c->t), prev, src_prev(c->t),
+                                 D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, partials, result, c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "reduce launch");
+    double h[3];
+    e = hipMemcpyAsync(h, result, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "reduce copy");
+    const double n = (double)D.desc.nx * D.desc.ny;
+    const double m = n * (5.0 / 3.0) * D.desc.Pi0 + h[0];  // sum_i f_ref_i = (5/3) Pi0 per node
+    const double r = (c->t == 0) ? NAN : std::sqrt(h[1]) / std::sqrt(h[2]);
+    if (mass) *mass = m;
+    if (residual) *residual = r;
+    if (!std::isfinite(m) || !std::isfinite(h[1]) || !std::isfinite(h[2]))
+        return fail(LBM_EUNSTABLE, "non-finite mass or residual (t = %lld)", (long long)c->t);
+    return LBM_OK;
+}
+
+int lbm_state_bytes(const lbm_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    if (c->batch) return fail(LBM_ENOTSUP, "save/load is per single-domain context");
+    const Domain &D = c->dom[0];
+    *bytes = 64 + 2 * (D.L.f_bytes + (D.desc.thermal.enabled ? D.L.g_bytes : 0));
+    return LBM_OK;
+}
+
+namespace {
+uint64_t desc_hash(const lbm_desc &d) {
+    // FNV-1a over the descriptor bytes that define the state's meaning
+    const unsigned char *p = (const unsigned char *)&d;
+    uint64_t h = 1469598103934665603ull;
+    for (size_t i = 0; i < offsetof(lbm_desc, ckpt_every); ++i) { h ^= p[i]; h *= 1099511628211ull; }
+    return h;
+}
+}  // namespace
+
+int lbm_save(lbm_ctx *c, void *host_buf, size_t bytes) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    size_t need;
+    if ((rc = lbm_state_bytes(c, &need))) return rc;
+    if (!host_buf || bytes < need) return fail(LBM_EINVAL, "host buffer too small (%zu < %zu)", bytes, need);
+    Domain &D = c->dom[0];
+    char *h = (char *)host_buf;
+    std::memset(h, 0, 64);
+    const uint64_t magic = 0x4d52544c424d3031ull, hash = desc_hash(D.desc);
+    std::memcpy(h, &magic, 8);
+    std::memcpy(h + 8, &hash, 8);
+    std::memcpy(h + 16, &c->t, 8);
+    size_t o = 64;
+    const int order[2] = {c->cur, c->cur ^ 1};
+    hipError_t e = hipSuccess;
+    for (int b : order) {
+        e = hipMemcpyAsync(h + o, D.base + D.L.off_f[b], D.L.f_bytes, hipMemcpyDeviceToHost, c->stream);
+        o += D.L.f_bytes;
+        if (e == hipSuccess && D.desc.thermal.enabled) {
+            e = hipMemcpyAsync(h + o, D.base + D.L.off_g[b], D.L.g_bytes, hipMemcpyDeviceToHost, c->stream);
+            o += D.L.g_bytes;
+        }
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "save");
+    return LBM_OK;
+}
+
+int lbm_load(lbm_ctx *c, const void *host_buf, size_t bytes) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    size_t need;
+    if ((rc = lbm_state_bytes(c, &need))) return rc;
+    if (!host_buf || bytes < need) return fail(LBM_EINVAL, "snapshot too small (%zu < %zu)", bytes, need);
+    Domain &D = c->dom[0];
+    const char *h = (const char *)host_buf;
+    uint64_t magic, hash;
+    int64_t t;
+    std::memcpy(&magic, h, 8);
+    std::memcpy(&hash, h + 8, 8);
+    std::memcpy(&t, h + 16, 8);
+    if (magic != 0x4d52544c424d3031ull) return fail(LBM_EINVAL, "not a snapshot of this library");
+    if (hash != desc_hash(D.desc)) return fail(LBM_EINVAL, "snapshot was taken with a different descriptor");
+    if (t < 0) return fail(LBM_EINVAL, "corrupt snapshot time");
+    size_t o = 64;
+    const int order[2] = {c->cur, c->cur ^ 1};
+    hipError_t e = hipSuccess;
+    for (int b : order) {
+        e = hipMemcpyAsync(D.base + D.L.off_f[b], h + o, D.L.f_bytes, hipMemcpyHostToDevice, c->stream);
+        o += D.L.f_bytes;
+        if (e == hipSuccess && D.desc.thermal.enabled) {
+            e = hipMemcpyAsync(D.base + D.L.off_g[b], h + o, D.L.g_bytes, hipMemcpyHostToDevice, c->stream);
+            o += D.L.g_bytes;
+        }
+        if (e != hipSuccess) break;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "load");
+    c->t = t;
+    c->rec_valid = false;  // the recorded trajectory no longer leads here
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx *c) {
+    if (!c) return LBM_OK;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    delete c;
+    return LBM_OK;
+}
+
+const char *lbm_strerror(int s) {
+    switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ESTATE: return "invalid state for this call";
+    case LBM_EDEVICE: return "device error (context poisoned)";
+    case LBM_EUNSTABLE: return "non-finite mass or residual";
+    case LBM_ENOTSUP: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+const char *lbm_last_error(void) { return g_last_error.c_str(); }
+
+int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *rows, int32_t *grid) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (tile_w) *tile_w = c->sched.tile_w;
+    if (rows) *rows = c->sched.rows;
+    if (grid) {
+        if (c->batch) *grid = c->grid;
+        else {
+            int tx, ty;
+            tile_counts(c->sched, c->dom[0].desc.nx, c->dom[0].desc.ny, &tx, &ty);
+            *grid = tx * ty;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t rows, int32_t swizzle) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->batch) return fail(LBM_ENOTSUP, "a batch's schedule is chosen by its autotuner");
+    const Schedule s{tile_w, rows, swizzle ? 1 : 0};
+    if (!schedule_supported(s)) return fail(LBM_EINVAL, "unsupported schedule %d x %d", tile_w, rows);
+    c->sched = s;
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+int lbm_batch_step_impl(lbm_ctx *c, int64_t n) {
+    (void)n;
+    return fail(LBM_ENOTSUP, "batched stepping not available");
+}
+
+extern "C" int lbm_batch_workspace_size(int32_t n, const lbm_desc *descs, size_t *bytes) {
+    (void)n; (void)descs; (void)bytes;
+    return fail(LBM_ENOTSUP, "batched stepping not available");
+}
+
+extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *const *phis,
+                                const float *const *kappas, void *workspace, size_t ws_bytes,
+                                void *stream, const char *tune_cache, lbm_ctx **out) {
+    (void)n; (void)descs; (void)phis; (void)kappas; (void)workspace; (void)ws_bytes;
+    (void)stream; (void)tune_cache; (void)out;
+    return fail(LBM_ENOTSUP, "batched stepping not available");
+}
+
+extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa) {
+    (void)c; (void)dL_du; (void)dL_dphi; (void)dL_dkappa;
+    return fail(LBM_ENOTSUP, "adjoint not available");
+}

@@ -1,0 +1,316 @@
+// Device-side building blocks of the D2Q8 porous MRT-LB step (Liu & He,
+// arXiv:1311.7239) for gfx950: the per-node collision in moment space, the
+// D2Q5 thermal collision (App. B), and the pull-scheme gather with periodic
+// wrap and halfway bounce-back.
+//
+// Populations are stored as deviations from the rest state f_ref_i = 3 w_i Pi0.
+// The collision never needs Pi0: with m = m_ref + dm and
+// m_ref = (5/3 Pi0, -Pi0, 0, ..., 0), every term m - m^eq of Eq. (14) is a
+// function of the deviations alone, so the kernels work on deviations
+// throughout and only the output of the pressure adds Pi0 back.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrt {
+
+// Velocity set of Eq. (7), zero-based: index i holds the paper's f_{i+1}.
+//   0:(1,0) 1:(0,1) 2:(-1,0) 3:(0,-1) 4:(1,1) 5:(-1,1) 6:(-1,-1) 7:(1,-1)
+constexpr int EX[8] = {1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int EY[8] = {0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP[8] = {2, 3, 0, 1, 6, 7, 4, 5};
+// D2Q5 of Eq. (B.3): 0 rest, 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1)
+constexpr int TXv[5] = {0, 1, 0, -1, 0};
+constexpr int TYv[5] = {0, 0, 1, 0, -1};
+constexpr int TOPP[5] = {0, 3, 4, 1, 2};
+
+enum { BC_PERIODIC = 0, BC_WALLS = 1 };
+enum { MED_UNIFORM = 0, MED_PHI_ERGUN = 1, MED_PHI_KAPPA = 2 };
+
+// Everything a kernel needs to know about one domain. Passed by value as a
+// kernel argument (single domain) or read from a device array (batch).
+struct Dom {
+    int32_t nx, ny, pitch;  // nodes; pitch = elements per stored row
+    int32_t bc_x, bc_y;
+    int64_t plane;          // elements between consecutive planes
+    float lid6;             // 6 w_diag U_lid = U_lid / 6 (diagonal lid links)
+    // relaxation (Eq. 13) and the (1 - s/2) factors of Eq. (14)
+    float s_e, s_q, s_nu, h_e, h_q, h_nu;
+    // medium
+    int32_t medium;
+    float phi0, inv_phi0, cd0, cf0;  // uniform: phi, 1/phi, phi nu kappa, phi F sqrt(kappa)
+    float nu;                        // fluid viscosity (per-cell drag)
+    float kcoef;                     // 150 / dp^2 (Eq. 4): kappa = kcoef (1-phi)^2 / phi^3
+    float Fconst;                    // >= 0: constant F_phi; < 0: Eq. (4)
+    float ax, ay;                    // uniform external acceleration
+    const float *phi;                // [ny][pitch] (MED_PHI_*)
+    const float *kappa;              // [ny][pitch] (MED_PHI_KAPPA)
+    // thermal (App. B); deviations from wT*T0
+    int32_t thermal;
+    float zT, z3, z4;                // 1/tau_T, zeta3, zeta4
+    float inv_sigma, T0, gbeta;
+    float abbh, abbc;                // 2 wT (Th - T0), 2 wT (Tc - T0)
+    // state buffers (storage type erased)
+    const void *fin;
+    void *fout;
+    const float *gin;
+    float *gout;
+    float *urec;                     // optional u(t) record: 2 planes
+};
+
+// Per-cell quantities of Eqs. (3), (4) and (19).
+struct Cell {
+    float phi, inv_phi;
+    float cd;   // phi nu / K             (linear drag coefficient, Eq. 3)
+    float cf;   // phi F_phi / sqrt(K)    (Forchheimer coefficient, Eq. 3)
+};
+
+// Ergun's F_phi (Eq. 4): 1.75 / sqrt(150 phi^3) = (1.75/sqrt(150)) phi^{-3/2}.
+__device__ __forceinline__ float ergun_F(float inv_phi) {
+    return 0.14288690166235206f * inv_phi * sqrtf(inv_phi);
+}
+
+__device__ __forceinline__ Cell load_cell(const Dom &d, int64_t idx) {
+    Cell c;
+    if (d.medium == MED_UNIFORM) {
+        c.phi = d.phi0; c.inv_phi = d.inv_phi0; c.cd = d.cd0; c.cf = d.cf0;
+        return c;
+    }
+    const float phi = d.phi[idx];
+    const float ip = 1.0f / phi;
+    float kappa;
+    if (d.medium == MED_PHI_ERGUN) {
+        const float om = 1.0f - phi;
+        kappa = d.kcoef * (om * om) * (ip * ip * ip);
+    } else {
+        kappa = d.kappa[idx];
+    }
+    const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
+    c.phi = phi; c.inv_phi = ip;
+    c.cd = phi * d.nu * kappa;
+    c.cf = phi * F * sqrtf(kappa);
+    return c;
+}
+
+// Eqs. (18)-(19) in cancellation-free form. With d = cd/2 and
+// l1 = cf/2, the denominator l0 + sqrt(l0^2 + l1|v|) equals 1 + d + delta with
+// delta = l1|v| / (l0 + sqrt(l0^2 + l1|v|)), so u = v - v q with
+// q = (d + delta)/(1 + d + delta): the small drag terms keep full relative
+// precision instead of being rounded against 1.
+__device__ __forceinline__ void velocity(const Cell &c, float vx, float vy, float &ux,
+                                         float &uy) {
+    const float dd = 0.5f * c.cd;
+    const float l1 = 0.5f * c.cf;
+    const float l0 = 0.5f * (1.0f + dd);
+    const float vmag = sqrtf(vx * vx + vy * vy);
+    const float t = l1 * vmag;
+    const float delta = t / (l0 + sqrtf(l0 * l0 + t));
+    const float qn = dd + delta;
+    const float q = qn / (1.0f + qn);
+    ux = vx - vx * q;
+    uy = vy - vy * q;
+}
+
+// Moments m_1, m_3, m_5 of the deviations (rows 1, 3, 5 of Eq. 10).
+__device__ __forceinline__ void conserved_moments(const float f[8], float &m1, float &m3,
+                                                  float &m5) {
+    const float a = f[0] + f[2], b = f[1] + f[3], cc = f[4] + f[6], dg = f[5] + f[7];
+    const float x13 = f[0] - f[2], y24 = f[1] - f[3], p57 = f[4] - f[6], q68 = f[5] - f[7];
+    m1 = (a + b) + (cc + dg);
+    m3 = x13 + (p57 - q68);
+    m5 = y24 + (p57 + q68);
+}
+
+// Velocity of a node from its pre-collision deviations (Eqs. 17-19);
+// pax/pay = phi * a.
+__device__ __forceinline__ void node_velocity(const float f[8], const Cell &c, float pax,
+                                              float pay, float &ux, float &uy, float &m1) {
+    float m3, m5;
+    conserved_moments(f, m1, m3, m5);
+    velocity(c, m3 + 0.5f * pax, m5 + 0.5f * pay, ux, uy);
+}
+
+// One node's collision (Eq. 14) followed by f+ = M^-1 m+, in place on the
+// deviations. Returns u. pax/pay = phi * a (a may include buoyancy).
+__device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c, float pax,
+                                        float pay, float &ux, float &uy) {
+    // m = M f (Eq. 8, rows of Eq. 10), shared sums first
+    const float a = f[0] + f[2], b = f[1] + f[3], cc = f[4] + f[6], dg = f[5] + f[7];
+    const float x13 = f[0] - f[2], y24 = f[1] - f[3], p57 = f[4] - f[6], q68 = f[5] - f[7];
+    const float ab = a + b, cdg = cc + dg;
+    const float m1 = ab + cdg;
+    const float m2 = cdg - ab;
+    const float pmq = p57 - q68, ppq = p57 + q68;
+    const float m3 = x13 + pmq;
+    const float m4 = pmq - 2.0f * x13;
+    const float m5 = y24 + ppq;
+    const float m6 = ppq - 2.0f * y24;
+    const float m7 = a - b;
+    const float m8 = cc - dg;
+
+    // velocity (Eqs. 18-19) and total force (Eq. 3)
+    velocity(c, m3 + 0.5f * pax, m5 + 0.5f * pay, ux, uy);
+    const float umag = sqrtf(ux * ux + uy * uy);
+    const float drag = c.cd + c.cf * umag;
+    const float Fx = pax - drag * ux;
+    const float Fy = pay - drag * uy;
+
+    // relaxation toward m^eq (Eqs. 11-12) with forcing (Eq. 16)
+    const float ip = c.inv_phi;
+    const float u2 = ux * ux + uy * uy;
+    const float uF = ux * Fx + uy * Fy;
+    // e - e^eq = dm2 + (3/5) dm1 - (2/5)|u|^2/phi  (Pi from Eq. 20, alpha2 = -1, gamma2 = 0)
+    const float m2p = m2 - d.s_e * (m2 + 0.6f * m1 - 0.4f * u2 * ip) + d.h_e * (0.8f * uF * ip);
+    // s1 = s3 = s5 = 1: m1+ = m1, j+ = rho0 u + F/2
+    const float m3p = ux + 0.5f * Fx;
+    const float m5p = uy + 0.5f * Fy;
+    // q^eq = -u (c1 = c2 = -2)
+    const float m4p = m4 - d.s_q * (m4 + ux) - d.h_q * Fx;
+    const float m6p = m6 - d.s_q * (m6 + uy) - d.h_q * Fy;
+    // p_xx^eq = (ux^2 - uy^2)/phi, p_xy^eq = ux uy / phi (gamma1 = gamma3 = 2/3)
+    const float m7p = m7 - d.s_nu * (m7 - (ux * ux - uy * uy) * ip) +
+                      d.h_nu * (2.0f * (ux * Fx - uy * Fy) * ip);
+    const float m8p = m8 - d.s_nu * (m8 - ux * uy * ip) + d.h_nu * ((ux * Fy + uy * Fx) * ip);
+
+    // f+ = M^T diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m+
+    const float A = 0.125f * m1, B = 0.125f * m2p;
+    const float X = m3p * (1.0f / 6.0f), Qx = m4p * (1.0f / 12.0f);
+    const float Y = m5p * (1.0f / 6.0f), Qy = m6p * (1.0f / 12.0f);
+    const float P = 0.25f * m7p, R = 0.25f * m8p;
+    const float amb = A - B, apb = A + B;
+    const float xa = X - 2.0f * Qx, ya = Y - 2.0f * Qy;
+    const float xd = X + Qx, yd = Y + Qy;
+    f[0] = (amb + xa) + P;
+    f[2] = (amb - xa) + P;
+    f[1] = (amb + ya) - P;
+    f[3] = (amb - ya) - P;
+    f[4] = (apb + xd) + (yd + R);
+    f[5] = (apb - xd) + (yd - R);
+    f[6] = (apb - xd) - (yd - R);
+    f[7] = (apb + xd) - (yd + R);
+}
+
+// D2Q5 collision (Eq. B.2) on deviations dg = g - wT T0 (varpi = 0, so the
+// rest distribution is T0/5 on every link), using the flow velocity u.
+__device__ __forceinline__ void thermal_collide(float g[5], const Dom &d, float ux, float uy) {
+    // n = N g (Eq. B.4)
+    const float n0 = (g[0] + g[1]) + (g[2] + g[3]) + g[4];   // dT
+    const float n1 = g[1] - g[3];
+    const float n2 = g[2] - g[4];
+    const float n3 = (g[1] + g[2]) + (g[3] + g[4]) - 4.0f * g[0];
+    const float n4 = (g[1] - g[2]) + (g[3] - g[4]);
+    const float T = d.T0 + n0;
+    // n^eq = (T, ux T/sigma, uy T/sigma, varpi T, 0) with varpi = 0 (Eq. B.6)
+    const float n1p = n1 - d.zT * (n1 - ux * T * d.inv_sigma);
+    const float n2p = n2 - d.zT * (n2 - uy * T * d.inv_sigma);
+    const float n3p = n3 - d.z3 * n3;
+    const float n4p = n4 - d.z4 * n4;
+    // g+ = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4) n+
+    const float a0 = 0.2f * n0, a1 = 0.5f * n1p, a2 = 0.5f * n2p, a3 = 0.05f * n3p,
+                a4 = 0.25f * n4p;
+    g[0] = a0 - 4.0f * a3;
+    g[1] = (a0 + a3) + (a1 + a4);
+    g[2] = (a0 + a3) + (a2 - a4);
+    g[3] = (a0 + a3) - (a1 - a4);
+    g[4] = (a0 + a3) - (a2 + a4);
+}
+
+// ---- storage ----------------------------------------------------------
+
+template <typename S> struct Store;
+template <> struct Store<float> {
+    __device__ __forceinline__ static float ld(const float *p) { return *p; }
+    __device__ __forceinline__ static void st(float *p, float v) { *p = v; }
+};
+template <> struct Store<_Float16> {
+    __device__ __forceinline__ static float ld(const _Float16 *p) { return (float)(*p); }
+    __device__ __forceinline__ static void st(_Float16 *p, float v) { *p = (_Float16)v; }
+};
+
+// ---- gather (pull streaming, Eq. 15, with boundaries) -----------------
+
+// f_i(x, t) = f_i+(x - e_i, t-1); a link whose source lies beyond a wall is
+// replaced by the node's own opposite post-collision population plus the
+// moving-wall term 6 w_i (e_i . u_w) when the wall crossed is the top one.
+template <typename S>
+__device__ __forceinline__ void gather_general(const Dom &d, const S *__restrict__ fin, int x,
+                                               int y, float f[8]) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        int sx = x - EX[i], sy = y - EY[i];
+        bool out = false, top = false;
+        if (EX[i] != 0 && (sx < 0 || sx >= d.nx)) {
+            if (d.bc_x == BC_PERIODIC) sx = (sx < 0) ? d.nx - 1 : 0;
+            else out = true;
+        }
+        if (EY[i] != 0 && (sy < 0 || sy >= d.ny)) {
+            if (d.bc_y == BC_PERIODIC) sy = (sy < 0) ? d.ny - 1 : 0;
+            else { out = true; top = (sy >= d.ny); }
+        }
+        if (!out) {
+            f[i] = Store<S>::ld(fin + i * d.plane + (int64_t)sy * d.pitch + sx);
+        } else {
+            float v = Store<S>::ld(fin + OPP[i] * d.plane + (int64_t)y * d.pitch + x);
+            if (top) v += (float)EX[i] * d.lid6;
+            f[i] = v;
+        }
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void gather_interior(const Dom &d, const S *__restrict__ fin, int x,
+                                                int y, float f[8]) {
+    const int64_t o = (int64_t)y * d.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        f[i] = Store<S>::ld(fin + i * d.plane + o - EY[i] * d.pitch - EX[i]);
+}
+
+template <typename S>
+__device__ __forceinline__ void load_own(const Dom &d, const S *__restrict__ fin, int x, int y,
+                                         float f[8]) {
+    const int64_t o = (int64_t)y * d.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = Store<S>::ld(fin + i * d.plane + o);
+}
+
+// D2Q5 gather: Dirichlet walls at x = 0 / x = nx by anti-bounce-back,
+// adiabatic walls at y = 0 / y = ny by bounce-back.
+__device__ __forceinline__ void gather_thermal(const Dom &d, const float *__restrict__ gin,
+                                               int x, int y, bool interior, float g[5]) {
+    const int64_t o = (int64_t)y * d.pitch + x;
+    g[0] = gin[o];
+#pragma unroll
+    for (int j = 1; j < 5; ++j) {
+        if (interior) {
+            g[j] = gin[j * d.plane + o - TYv[j] * d.pitch - TXv[j]];
+            continue;
+        }
+        int sx = x - TXv[j], sy = y - TYv[j];
+        int kind = 0;  // 0 stream, 1 bounce-back, 2 hot ABB, 3 cold ABB
+        if (TXv[j] != 0 && (sx < 0 || sx >= d.nx)) {
+            if (d.bc_x == BC_PERIODIC) sx = (sx < 0) ? d.nx - 1 : 0;
+            else kind = (sx < 0) ? 2 : 3;
+        }
+        if (TYv[j] != 0 && (sy < 0 || sy >= d.ny)) {
+            if (d.bc_y == BC_PERIODIC) sy = (sy < 0) ? d.ny - 1 : 0;
+            else kind = 1;
+        }
+        if (kind == 0) {
+            g[j] = gin[j * d.plane + (int64_t)sy * d.pitch + sx];
+        } else {
+            const float v = gin[TOPP[j] * d.plane + o];
+            g[j] = (kind == 1) ? v : ((kind == 2) ? d.abbh - v : d.abbc - v);
+        }
+    }
+}
+
+__device__ __forceinline__ void load_own_thermal(const Dom &d, const float *__restrict__ gin,
+                                                 int x, int y, float g[5]) {
+    const int64_t o = (int64_t)y * d.pitch + x;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) g[j] = gin[j * d.plane + o];
+}
+
+}  // namespace mrt

@@ -1,0 +1,437 @@
+// HIP kernels for gfx950 of the fused D2Q8 porous MRT-LB step (Liu & He,
+// arXiv:1311.7239, Eqs. 3, 4, 8-20) and the D2Q5 thermal model (App. B).
+//
+// One kernel pass per time step does, for every node: gather the eight
+// post-collision deviations of the previous step from the neighbours (pull
+// streaming, Eq. 15, with periodic wrap or halfway bounce-back), collide in
+// moment space (Eq. 14) with the porous equilibrium and drag forcing, and
+// store the eight new post-collision deviations into the other buffer.
+// Each stored value is read by exactly one neighbour, so the pass moves the
+// minimum 2 x 8 populations per node through HBM; there is no reuse for LDS
+// to capture and the 8x8 transform is a handful of adds, so the kernel is a
+// coalesced streaming kernel, not an MFMA one.
+#include <hip/hip_runtime.h>
+
+#include "lbm_launch.h"
+
+namespace mrt {
+
+constexpr int BLOCK = 256;
+constexpr int NUM_XCD = 8;
+
+// Workgroups are dispatched round-robin over the XCDs; this remaps the
+// block id so that each XCD walks a contiguous run of tiles (neighbouring
+// rows share cache lines at the x-shifted loads).
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+    const int q = nb / NUM_XCD;
+    if (b >= q * NUM_XCD) return b;
+    return (b % NUM_XCD) * q + b / NUM_XCD;
+}
+
+// ------------------------------------------------------------------ step
+
+template <typename S, bool THERMAL, int SRC, bool REC, int TW, int ROWS>
+__device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
+    constexpr int TH = BLOCK / TW;
+    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    const int x0 = tx * TW, y0 = ty * TH * ROWS;
+    const int x = x0 + lx;
+    const S *__restrict__ fin = (const S *)d.fin;
+    S *__restrict__ fout = (S *)d.fout;
+    const bool interior = (SRC == SRC_GATHER) && x0 >= 1 && x0 + TW <= d.nx - 1 && y0 >= 1 &&
+                          y0 + TH * ROWS <= d.ny - 1;
+
+    float f[ROWS][8];
+    float g[THERMAL ? ROWS : 1][5];
+    bool ok[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int y = y0 + ly + r * TH;
+        ok[r] = (x < d.nx) && (y < d.ny);
+        if (!ok[r]) continue;
+        if (SRC == SRC_DIRECT) {
+            load_own<S>(d, fin, x, y, f[r]);
+            if (THERMAL) load_own_thermal(d, d.gin, x, y, g[THERMAL ? r : 0]);
+        } else {
+            if (interior) gather_interior<S>(d, fin, x, y, f[r]);
+            else gather_general<S>(d, fin, x, y, f[r]);
+            if (THERMAL) gather_thermal(d, d.gin, x, y, interior, g[THERMAL ? r : 0]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        if (!ok[r]) continue;
+        const int y = y0 + ly + r * TH;
+        const int64_t o = (int64_t)y * d.pitch + x;
+        const Cell c = load_cell(d, o);
+        float ay = d.ay;
+        if (THERMAL) {
+            const float *gg = g[THERMAL ? r : 0];
+            const float dT = (gg[0] + gg[1]) + (gg[2] + gg[3]) + gg[4];
+            ay = d.ay + d.gbeta * dT;   // Boussinesq term of Sec. 3.4
+        }
+        float ux, uy;
+        collide(f[r], d, c, c.phi * d.ax, c.phi * ay, ux, uy);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Store<S>::st(fout + i * d.plane + o, f[r][i]);
+        if (THERMAL) {
+            float *gg = g[THERMAL ? r : 0];
+            thermal_collide(gg, d, ux, uy);
+#pragma unroll
+            for (int j = 0; j < 5; ++j) d.gout[j * d.plane + o] = gg[j];
+        }
+        if (REC) {
+            d.urec[o] = ux;
+            d.urec[d.plane + o] = uy;
+        }
+    }
+}
+
+template <typename S, bool THERMAL, int SRC, bool REC, int TW, int ROWS>
+__global__ __launch_bounds__(BLOCK) void k_step(Dom d, int tiles_x, int swz) {
+    int b = blockIdx.x;
+    if (swz) b = xcd_swizzle(b, gridDim.x);
+    step_tile<S, THERMAL, SRC, REC, TW, ROWS>(d, b % tiles_x, b / tiles_x);
+}
+
+template <typename S, int TW, int ROWS>
+__global__ __launch_bounds__(BLOCK) void k_step_batch(const Dom *__restrict__ doms,
+                                                      const int4 *__restrict__ tiles,
+                                                      int ntiles, int parity) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const Dom d = doms[2 * tl.x + parity];
+        step_tile<S, false, SRC_GATHER, false, TW, ROWS>(d, tl.y, tl.z);
+    }
+}
+
+void tile_counts(const Schedule &s, int nx, int ny, int *tiles_x, int *tiles_y) {
+    const int th = BLOCK / s.tile_w;
+    *tiles_x = (nx + s.tile_w - 1) / s.tile_w;
+    *tiles_y = (ny + th * s.rows - 1) / (th * s.rows);
+}
+
+bool schedule_supported(const Schedule &s) {
+    return (s.tile_w == 256 && (s.rows == 1 || s.rows == 2)) ||
+           (s.tile_w == 128 && (s.rows == 1 || s.rows == 2)) ||
+           (s.tile_w == 64 && (s.rows == 2 || s.rows == 4));
+}
+
+template <typename S, bool THERMAL, int SRC, bool REC>
+static hipError_t launch_step_t(const Dom &d, const Schedule &s, hipStream_t st) {
+    int tx, ty;
+    tile_counts(s, d.nx, d.ny, &tx, &ty);
+    const dim3 grid((unsigned)(tx * ty)), block(BLOCK);
+    if (s.tile_w == 256 && s.rows == 1)
+        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 256, 1>), grid, block, 0, st, d, tx, s.swizzle);
+    else if (s.tile_w == 256 && s.rows == 2)
+        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 256, 2>), grid, block, 0, st, d, tx, s.swizzle);
+    else if (s.tile_w == 128 && s.rows == 1)
+        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 128, 1>), grid, block, 0, st, d, tx, s.swizzle);
+    else if (s.tile_w == 128 && s.rows == 2)
+        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 128, 2>), grid, block, 0, st, d, tx, s.swizzle);
+    else if (s.tile_w == 64 && s.rows == 2)
+        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 64, 2>), grid, block, 0, st, d, tx, s.swizzle);
+    else if (s.tile_w == 64 && s.rows == 4)
+        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 64, 4>), grid, block, 0, st, d, tx, s.swizzle);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const Dom &d, int storage, Source src, bool rec, const Schedule &s,
+                       hipStream_t st) {
+    // the collide-only first cycle always runs with the default schedule
+    static const Schedule flat{256, 1, 0};
+    const bool th = d.thermal != 0;
+    if (rec && (storage != ST_F32 || th)) return hipErrorInvalidValue;
+    if (src == SRC_DIRECT) {
+        if (storage == ST_F32) {
+            if (th) return launch_step_t<float, true, SRC_DIRECT, false>(d, flat, st);
+            return rec ? launch_step_t<float, false, SRC_DIRECT, true>(d, flat, st)
+                       : launch_step_t<float, false, SRC_DIRECT, false>(d, flat, st);
+        }
+        if (th) return launch_step_t<_Float16, true, SRC_DIRECT, false>(d, flat, st);
+        return launch_step_t<_Float16, false, SRC_DIRECT, false>(d, flat, st);
+    }
+    if (storage == ST_F32) {
+        if (th) return launch_step_t<float, true, SRC_GATHER, false>(d, s, st);
+        return rec ? launch_step_t<float, false, SRC_GATHER, true>(d, s, st)
+                   : launch_step_t<float, false, SRC_GATHER, false>(d, s, st);
+    }
+    if (th) return launch_step_t<_Float16, true, SRC_GATHER, false>(d, s, st);
+    return launch_step_t<_Float16, false, SRC_GATHER, false>(d, s, st);
+}
+
+template <typename S>
+static hipError_t launch_batch_t(const Dom *doms, const int4 *tiles, int ntiles, int parity,
+                                 const Schedule &s, int grid, hipStream_t st) {
+    const dim3 g((unsigned)grid), b(BLOCK);
+    if (s.tile_w == 256 && s.rows == 1)
+        hipLaunchKernelGGL((k_step_batch<S, 256, 1>), g, b, 0, st, doms, tiles, ntiles, parity);
+    else if (s.tile_w == 256 && s.rows == 2)
+        hipLaunchKernelGGL((k_step_batch<S, 256, 2>), g, b, 0, st, doms, tiles, ntiles, parity);
+    else if (s.tile_w == 128 && s.rows == 1)
+        hipLaunchKernelGGL((k_step_batch<S, 128, 1>), g, b, 0, st, doms, tiles, ntiles, parity);
+    else if (s.tile_w == 128 && s.rows == 2)
+        hipLaunchKernelGGL((k_step_batch<S, 128, 2>), g, b, 0, st, doms, tiles, ntiles, parity);
+    else if (s.tile_w == 64 && s.rows == 2)
+        hipLaunchKernelGGL((k_step_batch<S, 64, 2>), g, b, 0, st, doms, tiles, ntiles, parity);
+    else if (s.tile_w == 64 && s.rows == 4)
+        hipLaunchKernelGGL((k_step_batch<S, 64, 4>), g, b, 0, st, doms, tiles, ntiles, parity);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity,
+                             int storage, const Schedule &s, int grid, hipStream_t st) {
+    if (grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
+    if (storage == ST_F32) return launch_batch_t<float>(doms, tiles, ntiles, parity, s, grid, st);
+    return launch_batch_t<_Float16>(doms, tiles, ntiles, parity, s, grid, st);
+}
+
+// --------------------------------------------------------- node readers
+
+// f(t) (and g(t)) of node (x, y) from a state buffer in the given layout.
+template <typename S, bool THERMAL>
+__device__ __forceinline__ void read_state(const Dom &d, int src, int x, int y, float f[8],
+                                           float g[5]) {
+    if (src == SRC_DIRECT) {
+        load_own<S>(d, (const S *)d.fin, x, y, f);
+        if (THERMAL) load_own_thermal(d, d.gin, x, y, g);
+    } else {
+        gather_general<S>(d, (const S *)d.fin, x, y, f);
+        if (THERMAL) gather_thermal(d, d.gin, x, y, false, g);
+    }
+}
+
+// velocity of node (x, y) at the state's time, as the step computes it
+template <bool THERMAL>
+__device__ __forceinline__ void state_velocity(const Dom &d, int64_t o, const float f[8],
+                                               const float g[5], float &ux, float &uy,
+                                               float &m1, float &dT) {
+    const Cell c = load_cell(d, o);
+    float ay = d.ay;
+    dT = 0.0f;
+    if (THERMAL) {
+        dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+        ay = d.ay + d.gbeta * dT;
+    }
+    node_velocity(f, c, c.phi * d.ax, c.phi * ay, ux, uy, m1);
+}
+
+template <typename S, bool THERMAL>
+__global__ __launch_bounds__(BLOCK) void k_macro(Dom d, int src, float Pi0, float *p, float *ux,
+                                                 float *uy, float *T) {
+    const int x = blockIdx.x * BLOCK + threadIdx.x, y = blockIdx.y;
+    if (x >= d.nx) return;
+    float f[8], g[5];
+    read_state<S, THERMAL>(d, src, x, y, f, g);
+    const int64_t o = (int64_t)y * d.pitch + x;
+    float u, v, m1, dT;
+    state_velocity<THERMAL>(d, o, f, g, u, v, m1, dT);
+    const int64_t q = (int64_t)y * d.nx + x;
+    if (ux) ux[q] = u;
+    if (uy) uy[q] = v;
+    if (p) {
+        // Eq. (20): phi p = (3/5)(m1 - (2/3)|u|^2/phi), m1 = (5/3) Pi0 + dm1
+        const Cell c = load_cell(d, o);
+        const float Pi = Pi0 + (0.6f * m1 - 0.4f * (u * u + v * v) * c.inv_phi);
+        p[q] = Pi * c.inv_phi;
+    }
+    if (T) T[q] = d.T0 + dT;
+}
+
+template <typename S, bool THERMAL>
+static hipError_t macro_t(const Dom &d, Source src, float Pi0, float *p, float *ux, float *uy,
+                          float *T, hipStream_t st) {
+    const dim3 grid((unsigned)((d.nx + BLOCK - 1) / BLOCK), (unsigned)d.ny);
+    hipLaunchKernelGGL((k_macro<S, THERMAL>), grid, dim3(BLOCK), 0, st, d, (int)src, Pi0, p, ux,
+                       uy, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_macroscopic(const Dom &d, int storage, Source src, float Pi0, float *p,
+                              float *ux, float *uy, float *T, hipStream_t st) {
+    const bool th = d.thermal != 0;
+    if (storage == ST_F32)
+        return th ? macro_t<float, true>(d, src, Pi0, p, ux, uy, T, st)
+                  : macro_t<float, false>(d, src, Pi0, p, ux, uy, T, st);
+    return th ? macro_t<_Float16, true>(d, src, Pi0, p, ux, uy, T, st)
+              : macro_t<_Float16, false>(d, src, Pi0, p, ux, uy, T, st);
+}
+
+template <typename S, bool THERMAL>
+__global__ __launch_bounds__(BLOCK) void k_get_pop(Dom d, int src, float *df, float *dg) {
+    const int x = blockIdx.x * BLOCK + threadIdx.x, y = blockIdx.y;
+    if (x >= d.nx) return;
+    float f[8], g[5];
+    read_state<S, THERMAL>(d, src, x, y, f, g);
+    const int64_t n = (int64_t)d.nx * d.ny, q = (int64_t)y * d.nx + x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) df[i * n + q] = f[i];
+    if (THERMAL && dg) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) dg[j * n + q] = g[j];
+    }
+}
+
+template <typename S>
+__global__ __launch_bounds__(BLOCK) void k_set_pop(Dom d, const float *df, const float *dg) {
+    const int x = blockIdx.x * BLOCK + threadIdx.x, y = blockIdx.y;
+    if (x >= d.nx) return;
+    const int64_t n = (int64_t)d.nx * d.ny, q = (int64_t)y * d.nx + x;
+    const int64_t o = (int64_t)y * d.pitch + x;
+    S *fo = (S *)d.fout;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Store<S>::st(fo + i * d.plane + o, df[i * n + q]);
+    if (d.thermal) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) d.gout[j * d.plane + o] = dg ? dg[j * n + q] : 0.0f;
+    }
+}
+
+hipError_t launch_get_populations(const Dom &d, int storage, Source src, float *df,
+                                  float *dg, hipStream_t st) {
+    const dim3 grid((unsigned)((d.nx + BLOCK - 1) / BLOCK), (unsigned)d.ny);
+    const bool th = d.thermal != 0;
+    if (storage == ST_F32) {
+        if (th) hipLaunchKernelGGL((k_get_pop<float, true>), grid, dim3(BLOCK), 0, st, d, (int)src, df, dg);
+        else hipLaunchKernelGGL((k_get_pop<float, false>), grid, dim3(BLOCK), 0, st, d, (int)src, df, dg);
+    } else {
+        if (th) hipLaunchKernelGGL((k_get_pop<_Float16, true>), grid, dim3(BLOCK), 0, st, d, (int)src, df, dg);
+        else hipLaunchKernelGGL((k_get_pop<_Float16, false>), grid, dim3(BLOCK), 0, st, d, (int)src, df, dg);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_set_populations(const Dom &d, int storage, const float *df, const float *dg,
+                                  hipStream_t st) {
+    const dim3 grid((unsigned)((d.nx + BLOCK - 1) / BLOCK), (unsigned)d.ny);
+    if (storage == ST_F32) hipLaunchKernelGGL((k_set_pop<float>), grid, dim3(BLOCK), 0, st, d, df, dg);
+    else hipLaunchKernelGGL((k_set_pop<_Float16>), grid, dim3(BLOCK), 0, st, d, df, dg);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BLOCK) void k_fill_zero(uint4 *p, size_t n16) {
+    const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+    for (size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x; i < n16;
+         i += (size_t)gridDim.x * BLOCK)
+        p[i] = z;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if (((uintptr_t)p & 15) || (bytes & 15)) return hipErrorInvalidValue;
+    const size_t n16 = bytes / 16;
+    size_t blocks = (n16 + BLOCK - 1) / BLOCK;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(BLOCK), 0, st, (uint4 *)p, n16);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BLOCK) void k_unpitch(const float *src, int pitch, float *dst,
+                                                   int nx, int ny) {
+    const int x = blockIdx.x * BLOCK + threadIdx.x, y = blockIdx.y;
+    if (x < nx) dst[(int64_t)y * nx + x] = src[(int64_t)y * pitch + x];
+}
+
+hipError_t launch_unpitch(const float *src, int pitch, float *dst, int nx, int ny,
+                          hipStream_t st) {
+    const dim3 grid((unsigned)((nx + BLOCK - 1) / BLOCK), (unsigned)ny);
+    hipLaunchKernelGGL(k_unpitch, grid, dim3(BLOCK), 0, st, src, pitch, dst, nx, ny);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ reductions
+
+// Fixed-order block reduction of three doubles (wavefront butterfly, then
+// the four wavefront results in order). Bitwise reproducible for a given
+// assignment of values to threads.
+__device__ __forceinline__ void block_sum3(double v[3], double *out) {
+    __shared__ double sh[BLOCK / 64][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double a = v[k];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) a += __shfl_xor(a, off, 64);
+        v[k] = a;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[w][0] = v[0]; sh[w][1] = v[1]; sh[w][2] = v[2];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+            for (int j = 0; j < BLOCK / 64; ++j) s += sh[j][k];
+            out[k] = s;
+        }
+    }
+}
+
+int reduce_blocks(int nx, int ny) {
+    const int64_t n = (int64_t)nx * ny;
+    int64_t b = (n + BLOCK - 1) / BLOCK;
+    if (b > 1024) b = 1024;
+    return (int)b;
+}
+
+template <typename S, bool THERMAL>
+__global__ __launch_bounds__(BLOCK) void k_reduce(Dom cur, int src_cur, Dom prev, int src_prev,
+                                                  double *partials) {
+    const int64_t n = (int64_t)cur.nx * cur.ny;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * BLOCK) {
+        const int x = (int)(k % cur.nx), y = (int)(k / cur.nx);
+        const int64_t o = (int64_t)y * cur.pitch + x;
+        float f[8], g[5];
+        read_state<S, THERMAL>(cur, src_cur, x, y, f, g);
+        float ux, uy, m1, dT;
+        state_velocity<THERMAL>(cur, o, f, g, ux, uy, m1, dT);
+        acc[0] += (double)m1;
+        acc[2] += (double)ux * ux + (double)uy * uy;
+        if (src_prev != SRC_NONE) {
+            read_state<S, THERMAL>(prev, src_prev, x, y, f, g);
+            float px, py, pm1, pdT;
+            state_velocity<THERMAL>(prev, o, f, g, px, py, pm1, pdT);
+            const double dx = (double)ux - px, dy = (double)uy - py;
+            acc[1] += dx * dx + dy * dy;
+        }
+    }
+    block_sum3(acc, partials + 3 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_reduce_final(const double *partials, int nb,
+                                                        double *result) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int j = threadIdx.x; j < nb; j += BLOCK) {
+        acc[0] += partials[3 * j + 0];
+        acc[1] += partials[3 * j + 1];
+        acc[2] += partials[3 * j + 2];
+    }
+    block_sum3(acc, result);
+}
+
+hipError_t launch_reduce(const Dom &cur, Source src_cur, const Dom &prev, Source src_prev,
+                         int storage, double *partials, double *result, hipStream_t st) {
+    const int nb = reduce_blocks(cur.nx, cur.ny);
+    const bool th = cur.thermal != 0;
+    if (storage == ST_F32) {
+        if (th) hipLaunchKernelGGL((k_reduce<float, true>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, prev, (int)src_prev, partials);
+        else hipLaunchKernelGGL((k_reduce<float, false>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, prev, (int)src_prev, partials);
+    } else {
+        if (th) hipLaunchKernelGGL((k_reduce<_Float16, true>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, prev, (int)src_prev, partials);
+        else hipLaunchKernelGGL((k_reduce<_Float16, false>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, prev, (int)src_prev, partials);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(BLOCK), 0, st, partials, nb, result);
+    return hipGetLastError();
+}
+
+}  // namespace mrt

@@ -1,0 +1,64 @@
+// Host-side launch interface between the C ABI (lbm_abi.cpp) and the HIP
+// kernels (lbm_kernels.hip). Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm_device.h"
+
+namespace mrt {
+
+enum Storage { ST_F32 = 0, ST_F16 = 1 };
+
+// How a kernel obtains f(t) from a state buffer: by pulling from the
+// neighbours (the buffer holds post-collision f+(t-1)), or directly (the
+// buffer holds f(0) itself, which is the layout at t = 0).
+enum Source { SRC_GATHER = 0, SRC_DIRECT = 1, SRC_NONE = 2 };
+
+struct Schedule {
+    int tile_w;  // threads of a 256-thread block along x (256, 128 or 64)
+    int rows;    // rows per thread (1, 2 or 4)
+    int swizzle; // map consecutive tiles onto the same XCD
+};
+
+// Number of 256-thread tiles covering the domain with a schedule.
+void tile_counts(const Schedule &s, int nx, int ny, int *tiles_x, int *tiles_y);
+bool schedule_supported(const Schedule &s);
+
+// One collide-and-stream cycle of one domain: reads d.fin (and d.gin),
+// writes d.fout (and d.gout); records u(t) into d.urec when rec.
+hipError_t launch_step(const Dom &d, int storage, Source src, bool rec, const Schedule &s,
+                       hipStream_t st);
+
+// Persistent batched step over a tile table: doms[2*k + parity] describes
+// domain k with its buffers for this parity; tiles[j] = (domain, tx, ty, 0).
+hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity,
+                             int storage, const Schedule &s, int grid, hipStream_t st);
+
+hipError_t launch_macroscopic(const Dom &d, int storage, Source src, float Pi0, float *p,
+                              float *ux, float *uy, float *T, hipStream_t st);
+hipError_t launch_get_populations(const Dom &d, int storage, Source src, float *df,
+                                  float *dg, hipStream_t st);
+hipError_t launch_set_populations(const Dom &d, int storage, const float *df,
+                                  const float *dg, hipStream_t st);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+
+// FP64 reductions: partial sums (sum dm1, sum |u - u_prev|^2, sum |u|^2) per
+// block, then one fixed-order pass into result[3].
+int reduce_blocks(int nx, int ny);
+hipError_t launch_reduce(const Dom &cur, Source src_cur, const Dom &prev, Source src_prev,
+                         int storage, double *partials, double *result, hipStream_t st);
+
+// Discrete adjoint pieces (FP32 storage, isothermal).
+// Seed: lam(T) = (du/df)^T dL/du and g_phi = (du/dphi)^T dL/du at time T.
+hipError_t launch_adjoint_seed(const Dom &d, Source src, const float *dLdu, float *lam,
+                               float *gphi, float *gkappa, hipStream_t st);
+// One backward step: lam_out = J(t)^T G^T lam_in, g += (dC/dphi)^T G^T lam_in,
+// using u(t) from urec.
+hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out,
+                               const float *u_t, float *gphi, float *gkappa, hipStream_t st);
+hipError_t launch_unpitch(const float *src, int pitch, float *dst, int nx, int ny,
+                          hipStream_t st);
+
+}  // namespace mrt

@@ -1,0 +1,250 @@
+"""Python binding of the mrtlbm C ABI (include/lbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libmrtlbm.so``. PyTorch provides device memory (the workspace and all
+field tensors) and the HIP stream. There is no fallback: if the library is
+not built, or no GPU is present, calls fail loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import pathlib
+from typing import Optional, Sequence
+
+import torch
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "libmrtlbm.so"
+_lib = None
+
+OK, EINVAL, ESTATE, EDEVICE, EUNSTABLE, ENOTSUP = 0, -1, -2, -3, -4, -5
+PERIODIC, WALLS = 0, 1
+FP32_DEV, FP16_DEV = 0, 1
+MEDIUM_UNIFORM, MEDIUM_PHI_ERGUN, MEDIUM_PHI_KAPPA = 0, 1, 2
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+        self.message = message
+
+
+class Thermal(ctypes.Structure):
+    _fields_ = [("enabled", ctypes.c_int32), ("tau_T", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("zeta3", ctypes.c_double),
+                ("zeta4", ctypes.c_double), ("Th", ctypes.c_double), ("Tc", ctypes.c_double),
+                ("T0", ctypes.c_double), ("g_beta", ctypes.c_double)]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+                ("lid_ux", ctypes.c_double), ("nu", ctypes.c_double), ("J", ctypes.c_double),
+                ("s_e", ctypes.c_double), ("s_q", ctypes.c_double),
+                ("medium", ctypes.c_int32), ("phi0", ctypes.c_double),
+                ("kappa0", ctypes.c_double), ("dp", ctypes.c_double),
+                ("F_eps", ctypes.c_double), ("ax", ctypes.c_double), ("ay", ctypes.c_double),
+                ("Pi0", ctypes.c_double), ("storage", ctypes.c_int32),
+                ("ckpt_every", ctypes.c_int32), ("thermal", Thermal)]
+
+
+_vp = ctypes.c_void_p
+_DP = ctypes.POINTER(Desc)
+
+
+def lib():
+    """Load libmrtlbm.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not _LIB_PATH.exists():
+            raise RuntimeError(f"{_LIB_PATH} is not built; run paper_1311_7239_amd.build.build()")
+        L = ctypes.CDLL(str(_LIB_PATH))
+        L.lbm_desc_defaults.argtypes = [_DP]
+        L.lbm_workspace_size.argtypes = [_DP, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbm_create.argtypes = [_DP, _vp, _vp, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
+        L.lbm_batch_workspace_size.argtypes = [ctypes.c_int32, _DP, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbm_create_batch.argtypes = [ctypes.c_int32, _DP, ctypes.POINTER(_vp),
+                                       ctypes.POINTER(_vp), _vp, ctypes.c_size_t, _vp,
+                                       ctypes.c_char_p, ctypes.POINTER(_vp)]
+        L.lbm_step.argtypes = [_vp, ctypes.c_int64]
+        L.lbm_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
+        L.lbm_macroscopic.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp]
+        L.lbm_get_populations.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+        L.lbm_set_populations.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+        L.lbm_reduce.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]
+        L.lbm_backward.argtypes = [_vp, _vp, _vp, _vp]
+        L.lbm_state_bytes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.lbm_save.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.lbm_load.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.lbm_destroy.argtypes = [_vp]
+        L.lbm_strerror.argtypes = [ctypes.c_int]
+        L.lbm_strerror.restype = ctypes.c_char_p
+        L.lbm_last_error.restype = ctypes.c_char_p
+        L.lbm_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.lbm_set_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        _lib = L
+    return _lib
+
+
+def check(status: int):
+    if status != OK:
+        raise LBMError(status, lib().lbm_last_error().decode())
+    return status
+
+
+def default_desc() -> Desc:
+    d = Desc()
+    check(lib().lbm_desc_defaults(ctypes.byref(d)))
+    return d
+
+
+def desc_from_case(case, storage: int = FP32_DEV, ckpt_every: int = 0) -> Desc:
+    """lbm_desc for a seeded input Case (paper_1311_7239_amd.inputs.Case)."""
+    d = default_desc()
+    d.nx, d.ny, d.bc_x, d.bc_y = case.nx, case.ny, case.bc_x, case.bc_y
+    d.lid_ux, d.nu, d.J = case.lid_ux, case.nu, case.J
+    d.ax, d.ay, d.Pi0 = case.ax, case.ay, case.Pi0
+    d.F_eps = -1.0 if case.Fphi is None else float(case.Fphi)
+    if case.phi is None:
+        d.medium = MEDIUM_UNIFORM
+        d.phi0 = case.phi0
+        d.kappa0 = 0.0 if math.isinf(case.K0) else 1.0 / case.K0
+    else:
+        d.medium = MEDIUM_PHI_ERGUN
+        d.dp = case.dp
+    d.storage = storage
+    d.ckpt_every = ckpt_every
+    if case.thermal:
+        t = d.thermal
+        t.enabled = 1
+        t.tau_T, t.sigma, t.Th, t.Tc, t.T0, t.g_beta = (case.tau_T, case.sigma, case.Th, case.Tc,
+                                                       case.T0, case.gbeta)
+    return d
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float32, "expect contiguous cuda float32"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    return ws
+
+
+def _aligned(ws: torch.Tensor):
+    p = ws.data_ptr()
+    off = (-p) % 256
+    return ctypes.c_void_p(p + off), ws.numel() - off
+
+
+class Solver:
+    """One domain: owns a workspace tensor and an lbm_ctx."""
+
+    def __init__(self, desc: Desc, phi: Optional[torch.Tensor] = None,
+                 kappa: Optional[torch.Tensor] = None, max_steps_recorded: int = 0,
+                 device="cuda", stream=None):
+        L = lib()
+        self.desc = desc
+        self.nx, self.ny = desc.nx, desc.ny
+        self.device = torch.device(device)
+        self.stream = stream
+        nb = ctypes.c_size_t()
+        check(L.lbm_workspace_size(ctypes.byref(desc), int(max_steps_recorded), ctypes.byref(nb)))
+        self.workspace = _workspace(nb.value, self.device)
+        self._phi, self._kappa = phi, kappa     # kept alive until creation work completes
+        wsp, wsn = _aligned(self.workspace)
+        ctx = ctypes.c_void_p()
+        check(L.lbm_create(ctypes.byref(desc), _ptr(phi), _ptr(kappa), wsp, wsn,
+                           _stream_handle(stream), ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- stepping and outputs
+    def step(self, n: int = 1):
+        check(lib().lbm_step(self._ctx, int(n)))
+
+    @property
+    def time(self) -> int:
+        t = ctypes.c_int64()
+        check(lib().lbm_time(self._ctx, ctypes.byref(t)))
+        return t.value
+
+    def macroscopic(self, want_T: bool = False):
+        p = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        u = torch.empty((2, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        T = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device) if want_T else None
+        check(lib().lbm_macroscopic(self._ctx, 0, _ptr(p), _ptr(u), _ptr(T)))
+        return p, u, T
+
+    def populations(self, thermal: bool = False):
+        df = torch.empty((8, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        dg = torch.empty((5, self.ny, self.nx), dtype=torch.float32, device=self.device) if thermal else None
+        check(lib().lbm_get_populations(self._ctx, 0, _ptr(df), _ptr(dg)))
+        return df, dg
+
+    def set_populations(self, df: torch.Tensor, dg: Optional[torch.Tensor] = None):
+        check(lib().lbm_set_populations(self._ctx, 0, _ptr(df.contiguous()),
+                                        _ptr(None if dg is None else dg.contiguous())))
+
+    def reduce(self):
+        m = ctypes.c_double(); r = ctypes.c_double()
+        st = lib().lbm_reduce(self._ctx, 0, ctypes.byref(m), ctypes.byref(r))
+        if st not in (OK, EUNSTABLE):
+            check(st)
+        return m.value, r.value, st
+
+    def backward(self, dL_du: torch.Tensor, want_kappa: bool = False):
+        g = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        gk = torch.empty_like(g) if want_kappa else None
+        check(lib().lbm_backward(self._ctx, _ptr(dL_du.contiguous()), _ptr(g), _ptr(gk)))
+        return g, gk
+
+    def save(self) -> bytes:
+        nb = ctypes.c_size_t()
+        check(lib().lbm_state_bytes(self._ctx, ctypes.byref(nb)))
+        buf = ctypes.create_string_buffer(nb.value)
+        check(lib().lbm_save(self._ctx, buf, nb.value))
+        return buf.raw
+
+    def load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        check(lib().lbm_load(self._ctx, buf, len(blob)))
+
+    def set_schedule(self, tile_w: int, rows: int, swizzle: int = 1):
+        check(lib().lbm_set_schedule(self._ctx, tile_w, rows, swizzle))
+
+    def schedule(self):
+        a = ctypes.c_int32(); b = ctypes.c_int32(); c = ctypes.c_int32()
+        check(lib().lbm_schedule(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+
+def solver_for_case(case, storage: int = FP32_DEV, ckpt_every: int = 0, max_steps_recorded: int = 0,
+                    device="cuda") -> Solver:
+    desc = desc_from_case(case, storage=storage, ckpt_every=ckpt_every)
+    phi = None
+    if case.phi is not None:
+        phi = torch.from_numpy(case.phi.astype("float32")).to(device)
+    return Solver(desc, phi=phi, max_steps_recorded=max_steps_recorded, device=device)

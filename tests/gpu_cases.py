@@ -1,0 +1,71 @@
+"""Helpers for GPU-vs-oracle parity tests: build both sides from one seeded Case."""
+import numpy as np
+import torch
+
+import oracle
+from paper_1311_7239_amd import lbm
+from tests.oracle_cases import oracle_setup
+
+W = np.array([1 / 9] * 4 + [1 / 36] * 4)
+
+
+def f_ref(Pi0):
+    """Rest-state populations 3 w_i Pi0 (Eq. 22 at u = 0)."""
+    return 3.0 * W * Pi0
+
+
+class Pair:
+    """A GPU solver and an FP64 oracle state for the same case, kept in lock step."""
+
+    def __init__(self, case, storage=lbm.FP32_DEV, df0=None, dg0=None, nthreads=0):
+        self.case = case
+        self.gpu = lbm.solver_for_case(case, storage=storage)
+        self.p, self.phi, self.K, self.F = oracle_setup(case, nthreads=nthreads)
+        self.fref = f_ref(case.Pi0)
+        if df0 is None:
+            self.f = oracle.rest_state(self.p, case.Pi0)
+        else:
+            df0 = np.asarray(df0, dtype=np.float32)
+            if storage == lbm.FP16_DEV:
+                df0 = df0.astype(np.float16).astype(np.float32)
+            self.f = np.ascontiguousarray(np.transpose(df0.astype(np.float64), (1, 2, 0)) + self.fref)
+        self.g = None
+        if case.thermal:
+            T0 = np.full((case.ny, case.nx), case.T0)
+            self.g = oracle.thermal_rest_state(self.p, T0)
+            if dg0 is not None:
+                self.g = self.g + np.transpose(np.asarray(dg0, dtype=np.float32).astype(np.float64), (1, 2, 0))
+                self.g = np.ascontiguousarray(self.g)
+        if df0 is not None or dg0 is not None:
+            dft = torch.from_numpy(np.asarray(df0 if df0 is not None else np.zeros((8, case.ny, case.nx)),
+                                              dtype=np.float32)).cuda()
+            dgt = None if dg0 is None else torch.from_numpy(np.asarray(dg0, dtype=np.float32)).cuda()
+            self.gpu.set_populations(dft, dgt)
+
+    def step(self, n):
+        self.gpu.step(n)
+        oracle.run(self.p, self.phi, self.K, self.F, self.f, self.g, nsteps=n)
+
+    def oracle_dev(self):
+        return np.transpose(self.f - self.fref, (2, 0, 1))
+
+    def gpu_dev(self):
+        df, dg = self.gpu.populations(thermal=self.case.thermal)
+        torch.cuda.synchronize()
+        return df.cpu().numpy().astype(np.float64), (None if dg is None else dg.cpu().numpy().astype(np.float64))
+
+    def oracle_macro(self):
+        return oracle.macroscopic(self.p, self.phi, self.K, self.F, self.f, self.g)
+
+    def gpu_macro(self):
+        p, u, T = self.gpu.macroscopic(want_T=self.case.thermal)
+        torch.cuda.synchronize()
+        return (p.cpu().numpy().astype(np.float64), u.cpu().numpy().astype(np.float64),
+                None if T is None else T.cpu().numpy().astype(np.float64))
+
+
+def max_rel_velocity_error(u_gpu, ux_ref, uy_ref):
+    """max over nodes and components of |u_gpu - u_ref| / max|u_ref|."""
+    ref = np.stack([ux_ref, uy_ref])
+    scale = np.abs(ref).max()
+    return float(np.abs(u_gpu - ref).max() / scale)

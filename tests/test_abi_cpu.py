@@ -1,0 +1,132 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the header
+declares, the ctypes descriptor matches the C layout, and descriptor validation
+rejects bad input without touching a device."""
+import ctypes
+import pathlib
+import re
+import subprocess
+
+import pytest
+
+from paper_1311_7239_amd import lbm
+
+ROOT = pathlib.Path(__file__).resolve().parent.parent
+HEADER = ROOT / "include" / "lbm.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "lbm_step" in names and "lbm_backward" in names and "lbm_create_batch" in names
+    L = lbm.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_descriptor_layout_matches_header(tmp_path):
+    fields = [f for f, _ in lbm.Desc._fields_ if f != "thermal"]
+    tfields = [f for f, _ in lbm.Thermal._fields_]
+    prog = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbm.h"', "int main(void){",
+            'printf("%zu\\n", sizeof(lbm_desc));']
+    prog += [f'printf("%zu\\n", offsetof(lbm_desc, {f}));' for f in fields]
+    prog += [f'printf("%zu\\n", offsetof(lbm_desc, thermal) + offsetof(lbm_thermal, {f}));' for f in tfields]
+    prog += ["return 0;}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(prog))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", str(ROOT / "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(lbm.Desc)] + [getattr(lbm.Desc, f).offset for f in fields]
+    want += [lbm.Desc.thermal.offset + getattr(lbm.Thermal, f).offset for f in tfields]
+    assert got == want
+
+
+def _desc(**kw):
+    d = lbm.default_desc()
+    d.nx, d.ny, d.nu = 64, 32, 0.1
+    d.bc_x, d.bc_y = lbm.PERIODIC, lbm.WALLS
+    d.phi0, d.kappa0 = 0.5, 0.01
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def _ws(d, rec=0):
+    n = ctypes.c_size_t()
+    st = lbm.lib().lbm_workspace_size(ctypes.byref(d), rec, ctypes.byref(n))
+    return st, n.value
+
+
+def test_defaults_are_the_papers_constants():
+    d = lbm.default_desc()
+    assert (d.J, d.s_e, d.s_q) == (1.0, 1.1, 1.2)
+    assert (d.thermal.zeta3, d.thermal.zeta4, d.thermal.sigma) == (1.1, 1.1, 1.0)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("ny", -3), ("nu", 0.0), ("nu", -0.1), ("J", 0.0), ("s_e", 2.0), ("s_q", 0.0),
+    ("phi0", 0.0), ("phi0", 1.5), ("kappa0", -1.0), ("storage", 7), ("bc_x", 5),
+    ("ckpt_every", -1), ("medium", 9), ("nu", float("nan")), ("ax", float("inf")),
+])
+def test_invalid_descriptor_is_rejected(field, value):
+    st, _ = _ws(_desc(**{field: value}))
+    assert st == lbm.EINVAL
+    assert lbm.lib().lbm_last_error().decode() != ""
+
+
+def test_walled_axis_needs_two_nodes_and_lid_needs_walls():
+    assert _ws(_desc(bc_y=lbm.WALLS, ny=1))[0] == lbm.EINVAL
+    assert _ws(_desc(bc_y=lbm.PERIODIC, lid_ux=0.1))[0] == lbm.EINVAL
+    assert _ws(_desc(bc_x=lbm.PERIODIC, nx=1))[0] == lbm.OK
+
+
+def test_ergun_medium_needs_particle_diameter():
+    assert _ws(_desc(medium=lbm.MEDIUM_PHI_ERGUN, dp=0.0))[0] == lbm.EINVAL
+    assert _ws(_desc(medium=lbm.MEDIUM_PHI_ERGUN, dp=3.0))[0] == lbm.OK
+
+
+def test_thermal_validation():
+    d = _desc()
+    d.thermal.enabled = 1
+    d.thermal.tau_T = 0.5
+    assert _ws(d)[0] == lbm.EINVAL
+    d.thermal.tau_T = 0.9
+    assert _ws(d)[0] == lbm.OK
+
+
+def test_workspace_grows_with_storage_thermal_and_recording():
+    _, base = _ws(_desc())
+    _, half = _ws(_desc(storage=lbm.FP16_DEV))
+    d = _desc(); d.thermal.enabled = 1; d.thermal.tau_T = 0.9
+    _, th = _ws(d)
+    _, rec = _ws(_desc(ckpt_every=10), rec=100)
+    assert half < base < th
+    assert rec > base
+    # 8 planes x 2 buffers x (64 x 32) nodes in FP32 at least
+    assert base >= 2 * 8 * 64 * 32 * 4
+
+
+def test_create_rejects_bad_arguments_before_touching_the_device():
+    L = lbm.lib()
+    d = _desc()
+    ctx = ctypes.c_void_p()
+    assert L.lbm_create(ctypes.byref(d), None, None, None, 0, None, ctypes.byref(ctx)) == lbm.EINVAL
+    assert L.lbm_create(ctypes.byref(d), None, None, ctypes.c_void_p(256), 16, None,
+                        ctypes.byref(ctx)) == lbm.EINVAL          # too small
+    assert L.lbm_create(ctypes.byref(d), None, None, ctypes.c_void_p(4096 + 8), 1 << 30, None,
+                        ctypes.byref(ctx)) == lbm.EINVAL          # misaligned
+    dm = _desc(medium=lbm.MEDIUM_PHI_ERGUN, dp=2.0)
+    assert L.lbm_create(ctypes.byref(dm), None, None, ctypes.c_void_p(4096), 1 << 30, None,
+                        ctypes.byref(ctx)) == lbm.EINVAL          # phi plane missing
+
+
+def test_null_context_calls_fail_cleanly():
+    L = lbm.lib()
+    assert L.lbm_step(None, 1) == lbm.EINVAL
+    assert L.lbm_destroy(None) == lbm.OK
+    assert L.lbm_strerror(lbm.EUNSTABLE).decode() == "non-finite mass or residual"
