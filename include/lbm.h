@@ -191,15 +191,19 @@ const char *lbm_strerror(int status);
 const char *lbm_last_error(void);
 
 /* Information on the launch the library uses for the step of this context:
- * tile width, rows per thread and grid size (host outputs). */
-int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *rows, int32_t *grid);
+ * threads along x per 256-thread block, nodes per thread along x, rows per
+ * thread and grid size (host outputs, each may be NULL). */
+int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows, int32_t *grid);
 
 /* Selects the launch shape of the step kernel of a single-domain context:
- * tile_w in {256, 128, 64} threads along x, rows per thread in {1, 2} (256,
- * 128) or {2, 4} (64), swizzle 0/1 (contiguous tiles per XCD). Every shape
- * computes bitwise-identical results; only speed differs. EINVAL for an
- * unsupported shape, ENOTSUP on a batch (its schedule is autotuned). */
-int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t rows, int32_t swizzle);
+ * tile_w threads along x per 256-thread block, vec consecutive nodes per
+ * thread along x, rows per thread, swizzle 0/1 (contiguous tiles per XCD).
+ * Compiled shapes (tile_w, vec, rows): (256,1,1) (256,1,2) (128,1,1)
+ * (128,1,2) (64,1,2) (64,1,4) (128,2,1) (64,2,2) (64,4,1) (32,4,2) (64,4,2)
+ * (16,4,4). Every shape computes bitwise-identical results; only speed
+ * differs. EINVAL for another shape, ENOTSUP on a batch (its schedule is
+ * autotuned). */
+int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int32_t swizzle);
 
 #ifdef __cplusplus
 }

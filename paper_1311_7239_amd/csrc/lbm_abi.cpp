@@ -50,6 +50,7 @@ struct Layout {
     // recording for the adjoint
     int64_t nck = 0, ring = 0;
     size_t off_ck = 0, off_urec = 0, off_lam[2] = {0, 0}, off_gphi = 0, off_gkappa = 0;
+    size_t off_rf[2] = {0, 0};  // recomputation buffers (the forward state stays put)
     size_t total = 0;
 };
 
@@ -87,6 +88,8 @@ Layout make_layout(const lbm_desc &d, int64_t max_rec) {
         L.off_lam[1] = carve(L.p_bytes * 8);
         L.off_gphi = carve(L.p_bytes);
         L.off_gkappa = carve(L.p_bytes);
+        L.off_rf[0] = carve(L.f_bytes);
+        L.off_rf[1] = carve(L.f_bytes);
     }
     L.total = o;
     return L;
@@ -186,7 +189,7 @@ struct lbm_ctx {
     int cur = 0;  // index of the buffer holding the state at t
     bool poisoned = false;
     bool batch = false;
-    Schedule sched{256, 1, 1};
+    Schedule sched{128, 1, 2, 1};
     // recording (single domain)
     bool rec_valid = false;
     int64_t rec_cap = 0;
@@ -570,9 +573,10 @@ const char *lbm_strerror(int s) {
 
 const char *lbm_last_error(void) { return g_last_error.c_str(); }
 
-int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *rows, int32_t *grid) {
+int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows, int32_t *grid) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
     if (tile_w) *tile_w = c->sched.tile_w;
+    if (vec) *vec = c->sched.vec;
     if (rows) *rows = c->sched.rows;
     if (grid) {
         if (c->batch) *grid = c->grid;
@@ -585,12 +589,13 @@ int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *rows, int32_t *grid
     return LBM_OK;
 }
 
-int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t rows, int32_t swizzle) {
+int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int32_t swizzle) {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (c->batch) return fail(LBM_ENOTSUP, "a batch's schedule is chosen by its autotuner");
-    const Schedule s{tile_w, rows, swizzle ? 1 : 0};
-    if (!schedule_supported(s)) return fail(LBM_EINVAL, "unsupported schedule %d x %d", tile_w, rows);
+    const Schedule s{tile_w, vec, rows, swizzle ? 1 : 0};
+    if (!schedule_supported(s))
+        return fail(LBM_EINVAL, "unsupported schedule %d x %d x %d", tile_w, vec, rows);
     c->sched = s;
     return LBM_OK;
 }
@@ -616,6 +621,60 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
 }
 
 extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa) {
-    (void)c; (void)dL_du; (void)dL_dphi; (void)dL_dkappa;
-    return fail(LBM_ENOTSUP, "adjoint not available");
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->batch) return fail(LBM_ENOTSUP, "the adjoint runs on single-domain contexts");
+    Domain &D = c->dom[0];
+    const lbm_desc &d = D.desc;
+    if (!dL_du || !dL_dphi) return fail(LBM_EINVAL, "dL_du and dL_dphi are required");
+    if (d.ckpt_every <= 0) return fail(LBM_ESTATE, "context was created without recording (ckpt_every = 0)");
+    if (d.thermal.enabled) return fail(LBM_ENOTSUP, "adjoint of the thermal coupling is not implemented");
+    if (d.storage != LBM_FP32_DEV) return fail(LBM_ENOTSUP, "adjoint needs FP32 storage");
+    if (d.medium == LBM_MEDIUM_UNIFORM) return fail(LBM_ENOTSUP, "adjoint needs a porosity plane");
+    if (dL_dkappa && d.medium != LBM_MEDIUM_PHI_KAPPA) return fail(LBM_EINVAL, "dL_dkappa needs LBM_MEDIUM_PHI_KAPPA");
+    if (!c->rec_valid) return fail(LBM_ESTATE, "no recorded trajectory leads to the current state");
+    const int64_t T = c->t, k = d.ckpt_every;
+    if (T > 0 && (T - 1) / k >= D.L.nck)
+        return fail(LBM_ESTATE, "t = %lld exceeds the recorded capacity", (long long)T);
+
+    const Layout &L = D.L;
+    float *lam[2] = {(float *)(D.base + L.off_lam[0]), (float *)(D.base + L.off_lam[1])};
+    float *gphi = (float *)(D.base + L.off_gphi);
+    float *gk = d.medium == LBM_MEDIUM_PHI_KAPPA ? (float *)(D.base + L.off_gkappa) : nullptr;
+    float *urec = (float *)(D.base + L.off_urec);
+    hipStream_t st = c->stream;
+
+    hipError_t e = launch_adjoint_seed(dom_for(D, c->cur), src_now(T), dL_du, lam[0], gphi, gk, st);
+    if (e != hipSuccess) return device_fail(c, e, "adjoint seed");
+    int la = 0;  // lam[la] holds a(t + 1)
+    if (T > 0) {
+        for (int64_t s0 = ((T - 1) / k) * k; s0 >= 0; s0 -= k) {
+            const int64_t s1 = (s0 + k < T) ? s0 + k : T;
+            // recompute the segment from its checkpoint, recording u(t)
+            e = hipMemcpyAsync(D.base + L.off_rf[0], D.base + L.off_ck + (size_t)(s0 / k) * L.f_bytes,
+                               L.f_bytes, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return device_fail(c, e, "checkpoint restore");
+            int p = 0;
+            for (int64_t t = s0; t < s1; ++t) {
+                Dom dr = D.dom;
+                dr.fin = D.base + L.off_rf[p];
+                dr.fout = D.base + L.off_rf[p ^ 1];
+                dr.urec = urec + (size_t)(t - s0) * 2 * (size_t)L.plane;
+                e = launch_step(dr, ST_F32, t == 0 ? SRC_DIRECT : SRC_GATHER, true, c->sched, st);
+                if (e != hipSuccess) return device_fail(c, e, "recompute step");
+                p ^= 1;
+            }
+            // backward through the segment
+            for (int64_t t = s1 - 1; t >= s0; --t) {
+                e = launch_adjoint_step(D.dom, lam[la], lam[la ^ 1],
+                                        urec + (size_t)(t - s0) * 2 * (size_t)L.plane, gphi, gk, st);
+                if (e != hipSuccess) return device_fail(c, e, "adjoint step");
+                la ^= 1;
+            }
+        }
+    }
+    e = launch_unpitch(gphi, L.pitch, dL_dphi, d.nx, d.ny, st);
+    if (e == hipSuccess && dL_dkappa) e = launch_unpitch(gk, L.pitch, dL_dkappa, d.nx, d.ny, st);
+    if (e != hipSuccess) return device_fail(c, e, "gradient copy");
+    return LBM_OK;
 }

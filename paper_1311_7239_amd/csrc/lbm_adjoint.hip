@@ -1,0 +1,253 @@
+// Hand-written discrete adjoint of the fused D2Q8 porous MRT-LB step
+// (Liu & He, arXiv:1311.7239, Eqs. 3, 4, 14-19) for gfx950.
+//
+// Forward: f(t+1) = G(C(f(t); phi)), with C the per-node collision
+// (moments, velocity recovery, drag forcing, relaxation, back-transform) and
+// G the pull streaming with halfway bounce-back. For a loss L(u(T)):
+//   a(T)   = (du/df)^T dL/du,            g = (du/dphi)^T dL/du
+//   b(t)   = G^T a(t+1)                  (adjoint of the post-collision state)
+//   a(t)   = (dC/df)^T b(t),             g += (dC/dphi)^T b(t)
+// G^T is a pull in the opposite direction: b_i(x) = a_i(x + e_i), or a_ibar(x)
+// when the link x -> x + e_i crosses a wall (the lid's constant drops out).
+// The Jacobian of C depends on f only through u (m^eq and S depend on m_1
+// linearly and on u), so each backward step needs u(x, t) and the medium,
+// which the checkpointed recomputation records; never f itself.
+#include <hip/hip_runtime.h>
+
+#include "lbm_launch.h"
+
+namespace mrt {
+
+constexpr int ABLOCK = 256;
+
+// Adjoints of the intermediate medium quantities: phi*a (per component),
+// cd = phi nu kappa, cf = phi F sqrt(kappa), and 1/phi.
+struct ParamBar {
+    float pax, pay, cd, cf, ip;
+};
+
+// y -> M^T y with the paper's M (Eq. 10); y in moment order.
+__device__ __forceinline__ void apply_MT(const float y[8], float f[8]) {
+    const float amb = y[0] - y[1], apb = y[0] + y[1];
+    const float xa = y[2] - 2.0f * y[3], ya = y[4] - 2.0f * y[5];
+    const float xd = y[2] + y[3], yd = y[4] + y[5];
+    f[0] = (amb + xa) + y[6];
+    f[2] = (amb - xa) + y[6];
+    f[1] = (amb + ya) - y[6];
+    f[3] = (amb - ya) - y[6];
+    f[4] = (apb + xd) + (yd + y[7]);
+    f[5] = (apb - xd) + (yd - y[7]);
+    f[6] = (apb - xd) - (yd - y[7]);
+    f[7] = (apb + xd) - (yd + y[7]);
+}
+
+// Reverse mode of the velocity recovery u = v / D(|v|), D = l0 + sqrt(l0^2 + l1|v|)
+// (Eqs. 18-19), given the total adjoint ub of u. Writes vb and adds the
+// adjoints of cd and cf (through l0 = (1 + cd/2)/2, l1 = cf/2).
+__device__ __forceinline__ void velocity_adjoint(const Cell &c, float ux, float uy, float ubx,
+                                                 float uby, float &vbx, float &vby,
+                                                 ParamBar &pb) {
+    const float umag = sqrtf(ux * ux + uy * uy);
+    const float l0 = 0.5f * (1.0f + 0.5f * c.cd);
+    const float l1 = 0.5f * c.cf;
+    const float R = l0 + l1 * umag;   // sqrt(l0^2 + l1|v|) on the solution
+    const float D = l0 + R;           // = 2 l0 + l1 |u|
+    const float uub = ux * ubx + uy * uby;
+    const float corr = (umag > 0.0f) ? (l1 / (2.0f * R)) * uub / umag : 0.0f;
+    vbx = (ubx - corr * ux) / D;
+    vby = (uby - corr * uy) / D;
+    pb.cd += 0.25f * (-uub / R);
+    pb.cf += 0.5f * (-uub * umag / (2.0f * R));
+    pb.pax += 0.5f * vbx;
+    pb.pay += 0.5f * vby;
+}
+
+// Reverse mode of one node's collision (Eq. 14 and f+ = M^-1 m+): given the
+// adjoint b of f+, returns the adjoint a of the pre-collision f and the
+// medium adjoints. u is the node's velocity at this time step.
+__device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, const Cell &c,
+                                                float pax, float pay, float ux, float uy,
+                                                float a[8], ParamBar &pb) {
+    // mbar+ = diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) M b
+    const float A1 = b[0] + b[2], B1 = b[1] + b[3], C1 = b[4] + b[6], D1 = b[5] + b[7];
+    const float x13 = b[0] - b[2], y24 = b[1] - b[3], p57 = b[4] - b[6], q68 = b[5] - b[7];
+    const float pmq = p57 - q68, ppq = p57 + q68;
+    const float P1 = 0.125f * ((A1 + B1) + (C1 + D1));
+    const float P2 = 0.125f * ((C1 + D1) - (A1 + B1));
+    const float P3 = (x13 + pmq) * (1.0f / 6.0f);
+    const float P4 = (pmq - 2.0f * x13) * (1.0f / 12.0f);
+    const float P5 = (y24 + ppq) * (1.0f / 6.0f);
+    const float P6 = (ppq - 2.0f * y24) * (1.0f / 12.0f);
+    const float P7 = 0.25f * (A1 - B1);
+    const float P8 = 0.25f * (C1 - D1);
+
+    // forward quantities on this node
+    const float ip = c.inv_phi;
+    const float umag = sqrtf(ux * ux + uy * uy);
+    const float drag = c.cd + c.cf * umag;
+    const float Fx = pax - drag * ux, Fy = pay - drag * uy;
+    const float u2 = ux * ux + uy * uy, uF = ux * Fx + uy * Fy;
+
+    float mb[8];
+    mb[0] = P1 - 0.6f * d.s_e * P2;
+    mb[1] = (1.0f - d.s_e) * P2;
+    mb[3] = (1.0f - d.s_q) * P4;
+    mb[5] = (1.0f - d.s_q) * P6;
+    mb[6] = (1.0f - d.s_nu) * P7;
+    mb[7] = (1.0f - d.s_nu) * P8;
+
+    // u and F enter m2+, m3+..m8+ directly
+    float ubx = (0.8f * d.s_e * ux + 0.8f * d.h_e * Fx) * ip * P2 + P3 - d.s_q * P4 +
+                (2.0f * d.s_nu * ux + 2.0f * d.h_nu * Fx) * ip * P7 +
+                (d.s_nu * uy + d.h_nu * Fy) * ip * P8;
+    float uby = (0.8f * d.s_e * uy + 0.8f * d.h_e * Fy) * ip * P2 + P5 - d.s_q * P6 -
+                (2.0f * d.s_nu * uy + 2.0f * d.h_nu * Fy) * ip * P7 +
+                (d.s_nu * ux + d.h_nu * Fx) * ip * P8;
+    const float Fbx = 0.8f * d.h_e * ux * ip * P2 + 0.5f * P3 - d.h_q * P4 +
+                      2.0f * d.h_nu * ux * ip * P7 + d.h_nu * uy * ip * P8;
+    const float Fby = 0.8f * d.h_e * uy * ip * P2 + 0.5f * P5 - d.h_q * P6 -
+                      2.0f * d.h_nu * uy * ip * P7 + d.h_nu * ux * ip * P8;
+    pb.ip = (0.4f * d.s_e * u2 + 0.8f * d.h_e * uF) * P2 +
+            (d.s_nu * (ux * ux - uy * uy) + 2.0f * d.h_nu * (ux * Fx - uy * Fy)) * P7 +
+            (d.s_nu * ux * uy + d.h_nu * (ux * Fy + uy * Fx)) * P8;
+
+    // F = phi a - (cd + cf |u|) u  (Eq. 3)
+    const float uFb = ux * Fbx + uy * Fby;
+    const float nl = (umag > 0.0f) ? c.cf * uFb / umag : 0.0f;
+    ubx += -drag * Fbx - nl * ux;
+    uby += -drag * Fby - nl * uy;
+    pb.pax = Fbx;
+    pb.pay = Fby;
+    pb.cd = -uFb;
+    pb.cf = -umag * uFb;
+
+    float vbx, vby;
+    velocity_adjoint(c, ux, uy, ubx, uby, vbx, vby, pb);
+    mb[2] = vbx;
+    mb[4] = vby;
+    apply_MT(mb, a);
+}
+
+// Medium adjoints -> dL/dphi (and dL/dkappa with a kappa plane).
+__device__ __forceinline__ void medium_gradient(const Dom &d, const Cell &c, float kappa,
+                                                const ParamBar &pb, float ax, float ay,
+                                                float &gphi, float &gkappa) {
+    const float phi = c.phi, ip = c.inv_phi;
+    float dcd, dcf;
+    gkappa = 0.0f;
+    if (d.medium == MED_PHI_ERGUN) {
+        // kappa = kcoef (1-phi)^2 / phi^3; sqrt(kappa) = sk (1 - phi)
+        const float om = 1.0f - phi;
+        const float sk = sqrtf(d.kcoef) * ip * sqrtf(ip);
+        const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
+        dcd = -2.0f * d.nu * d.kcoef * om * (ip * ip * ip);
+        dcf = ((d.Fconst >= 0.0f) ? -0.5f : -2.0f) * c.cf * ip - phi * F * sk;
+    } else {
+        const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
+        const float sq = sqrtf(kappa);
+        dcd = d.nu * kappa;
+        dcf = ((d.Fconst >= 0.0f) ? 1.0f : -0.5f) * F * sq;
+        const float dcf_dk = (kappa > 0.0f) ? phi * F / (2.0f * sq) : 0.0f;
+        gkappa = pb.cd * phi * d.nu + pb.cf * dcf_dk;
+    }
+    gphi = ax * pb.pax + ay * pb.pay + pb.cd * dcd + pb.cf * dcf - pb.ip * ip * ip;
+}
+
+__device__ __forceinline__ float kappa_at(const Dom &d, int64_t o) {
+    return d.medium == MED_PHI_KAPPA ? d.kappa[o] : 0.0f;
+}
+
+// a(T) and the direct medium gradient of u(T), from f(T) and dL/du(T).
+template <int SRC_T>
+__global__ __launch_bounds__(ABLOCK) void k_adjoint_seed(Dom d, const float *__restrict__ dLdu,
+                                                         float *__restrict__ lam,
+                                                         float *__restrict__ gphi,
+                                                         float *__restrict__ gkappa) {
+    const int x = blockIdx.x * ABLOCK + threadIdx.x, y = blockIdx.y;
+    if (x >= d.nx) return;
+    float f[8];
+    if (SRC_T == SRC_DIRECT) load_own<float>(d, (const float *)d.fin, x, y, f);
+    else gather_general<float>(d, (const float *)d.fin, x, y, f);
+    const int64_t o = (int64_t)y * d.pitch + x;
+    const Cell c = load_cell(d, o);
+    const float pax = c.phi * d.ax, pay = c.phi * d.ay;
+    float ux, uy, m1;
+    node_velocity(f, c, pax, pay, ux, uy, m1);
+    const int64_t q = (int64_t)y * d.nx + x, n = (int64_t)d.nx * d.ny;
+    ParamBar pb{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    float vbx, vby;
+    velocity_adjoint(c, ux, uy, dLdu[q], dLdu[n + q], vbx, vby, pb);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lam[i * d.plane + o] = (float)EX[i] * vbx + (float)EY[i] * vby;
+    float gp, gk;
+    medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
+    gphi[o] = gp;
+    if (gkappa) gkappa[o] = gk;
+}
+
+// One backward step at time t: lam_out = a(t), lam_in = a(t+1), u_t = u(t).
+__global__ __launch_bounds__(ABLOCK) void k_adjoint_step(Dom d, const float *__restrict__ lam_in,
+                                                         float *__restrict__ lam_out,
+                                                         const float *__restrict__ u_t,
+                                                         float *__restrict__ gphi,
+                                                         float *__restrict__ gkappa,
+                                                         int tiles_x) {
+    const int tx = blockIdx.x % tiles_x, y = blockIdx.x / tiles_x;
+    const int x = tx * ABLOCK + threadIdx.x;
+    if (x >= d.nx) return;
+    const int64_t o = (int64_t)y * d.pitch + x;
+    const bool interior = tx * ABLOCK >= 1 && tx * ABLOCK + ABLOCK <= d.nx - 1 && y >= 1 &&
+                          y <= d.ny - 2;
+    // b_i(x) = a_i(x + e_i), or a_ibar(x) across a wall (G^T)
+    float b[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if (interior) {
+            b[i] = lam_in[i * d.plane + o + EY[i] * d.pitch + EX[i]];
+            continue;
+        }
+        int sx = x + EX[i], sy = y + EY[i];
+        bool out = false;
+        if (EX[i] != 0 && (sx < 0 || sx >= d.nx)) {
+            if (d.bc_x == BC_PERIODIC) sx = (sx < 0) ? d.nx - 1 : 0;
+            else out = true;
+        }
+        if (EY[i] != 0 && (sy < 0 || sy >= d.ny)) {
+            if (d.bc_y == BC_PERIODIC) sy = (sy < 0) ? d.ny - 1 : 0;
+            else out = true;
+        }
+        b[i] = out ? lam_in[OPP[i] * d.plane + o] : lam_in[i * d.plane + (int64_t)sy * d.pitch + sx];
+    }
+    const Cell c = load_cell(d, o);
+    const float ux = u_t[o], uy = u_t[d.plane + o];
+    float a[8];
+    ParamBar pb;
+    collide_adjoint(b, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, a, pb);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lam_out[i * d.plane + o] = a[i];
+    float gp, gk;
+    medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
+    gphi[o] += gp;
+    if (gkappa) gkappa[o] += gk;
+}
+
+hipError_t launch_adjoint_seed(const Dom &d, Source src, const float *dLdu, float *lam,
+                               float *gphi, float *gkappa, hipStream_t st) {
+    const dim3 grid((unsigned)((d.nx + ABLOCK - 1) / ABLOCK), (unsigned)d.ny);
+    if (src == SRC_DIRECT)
+        hipLaunchKernelGGL(k_adjoint_seed<SRC_DIRECT>, grid, dim3(ABLOCK), 0, st, d, dLdu, lam, gphi, gkappa);
+    else
+        hipLaunchKernelGGL(k_adjoint_seed<SRC_GATHER>, grid, dim3(ABLOCK), 0, st, d, dLdu, lam, gphi, gkappa);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out,
+                               const float *u_t, float *gphi, float *gkappa, hipStream_t st) {
+    const int tiles_x = (d.nx + ABLOCK - 1) / ABLOCK;
+    const dim3 grid((unsigned)(tiles_x * d.ny));
+    hipLaunchKernelGGL(k_adjoint_step, grid, dim3(ABLOCK), 0, st, d, lam_in, lam_out, u_t, gphi,
+                       gkappa, tiles_x);
+    return hipGetLastError();
+}
+
+}  // namespace mrt

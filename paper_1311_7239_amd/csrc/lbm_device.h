@@ -71,26 +71,32 @@ __device__ __forceinline__ float ergun_F(float inv_phi) {
     return 0.14288690166235206f * inv_phi * sqrtf(inv_phi);
 }
 
-__device__ __forceinline__ Cell load_cell(const Dom &d, int64_t idx) {
+// Per-cell drag coefficients from the porosity (and 1/K when it has its own
+// plane); kappa is ignored unless the medium is MED_PHI_KAPPA.
+__device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_plane) {
     Cell c;
     if (d.medium == MED_UNIFORM) {
         c.phi = d.phi0; c.inv_phi = d.inv_phi0; c.cd = d.cd0; c.cf = d.cf0;
         return c;
     }
-    const float phi = d.phi[idx];
     const float ip = 1.0f / phi;
     float kappa;
     if (d.medium == MED_PHI_ERGUN) {
         const float om = 1.0f - phi;
-        kappa = d.kcoef * (om * om) * (ip * ip * ip);
+        kappa = d.kcoef * (om * om) * (ip * ip * ip);   // 1/K of Eq. (4)
     } else {
-        kappa = d.kappa[idx];
+        kappa = kappa_plane;
     }
     const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
     c.phi = phi; c.inv_phi = ip;
     c.cd = phi * d.nu * kappa;
     c.cf = phi * F * sqrtf(kappa);
     return c;
+}
+
+__device__ __forceinline__ Cell load_cell(const Dom &d, int64_t idx) {
+    if (d.medium == MED_UNIFORM) return cell_from(d, 0.0f, 0.0f);
+    return cell_from(d, d.phi[idx], d.medium == MED_PHI_KAPPA ? d.kappa[idx] : 0.0f);
 }
 
 // Eqs. (18)-(19) in cancellation-free form. With d = cd/2 and
@@ -227,6 +233,26 @@ template <> struct Store<_Float16> {
     __device__ __forceinline__ static float ld(const _Float16 *p) { return (float)(*p); }
     __device__ __forceinline__ static void st(_Float16 *p, float v) { *p = (_Float16)v; }
 };
+
+// NX consecutive values of a row; p is aligned to the element size only (the
+// x-shifted planes start one element off a vector boundary).
+template <typename S, int NX>
+__device__ __forceinline__ void load_row(const S *p, float out[NX]) {
+    S tmp[NX];
+    __builtin_memcpy(tmp, p, sizeof(S) * NX);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) out[k] = (float)tmp[k];
+}
+
+// NX consecutive values of a row to an address aligned to NX elements.
+template <typename S, int NX>
+__device__ __forceinline__ void store_row(S *p, const float in[NX]) {
+    S tmp[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) tmp[k] = (S)in[k];
+    S *q = (S *)__builtin_assume_aligned(p, sizeof(S) * NX);
+    __builtin_memcpy(q, tmp, sizeof(S) * NX);
+}
 
 // ---- gather (pull streaming, Eq. 15, with boundaries) -----------------
 

@@ -30,91 +30,164 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
 
 // ------------------------------------------------------------------ step
 
-template <typename S, bool THERMAL, int SRC, bool REC, int TW, int ROWS>
+// Thermal-coupled acceleration phi*a of one node (Sec. 3.4 buoyancy on top
+// of the uniform a), and the rest of the per-node update shared by both
+// paths below: collide, then return u.
+template <bool THERMAL>
+__device__ __forceinline__ void node_update(const Dom &d, const Cell &c, float f[8], float g[5],
+                                            float &ux, float &uy) {
+    float ay = d.ay;
+    if (THERMAL) {
+        const float dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+        ay = d.ay + d.gbeta * dT;
+    }
+    collide(f, d, c, c.phi * d.ax, c.phi * ay, ux, uy);
+    if (THERMAL) thermal_collide(g, d, ux, uy);
+}
+
+// One 256-thread tile: TWT threads along x, each handling NX consecutive
+// nodes in each of ROWS rows (rows TH apart). Tiles that touch no boundary
+// take vector loads of whole rows of NX values per plane; edge tiles gather
+// node by node with wrap/bounce-back. Both paths run the same per-node
+// arithmetic, so every schedule produces the same bits.
+template <typename S, bool THERMAL, int SRC, bool REC, int TWT, int NX, int ROWS>
 __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
-    constexpr int TH = BLOCK / TW;
-    const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+    constexpr int TH = BLOCK / TWT;
+    constexpr int TW = TWT * NX;
+    const int lx = threadIdx.x % TWT, ly = threadIdx.x / TWT;
     const int x0 = tx * TW, y0 = ty * TH * ROWS;
-    const int x = x0 + lx;
+    const int xb = x0 + lx * NX;
     const S *__restrict__ fin = (const S *)d.fin;
     S *__restrict__ fout = (S *)d.fout;
     const bool interior = (SRC == SRC_GATHER) && x0 >= 1 && x0 + TW <= d.nx - 1 && y0 >= 1 &&
                           y0 + TH * ROWS <= d.ny - 1;
 
-    float f[ROWS][8];
-    float g[THERMAL ? ROWS : 1][5];
-    bool ok[ROWS];
+    if (interior) {
+        float f[ROWS][8][NX];
+        float g[THERMAL ? ROWS : 1][5][NX];
+        float ph[ROWS][NX] = {}, kp[ROWS][NX] = {};
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) {
-        const int y = y0 + ly + r * TH;
-        ok[r] = (x < d.nx) && (y < d.ny);
-        if (!ok[r]) continue;
-        if (SRC == SRC_DIRECT) {
-            load_own<S>(d, fin, x, y, f[r]);
-            if (THERMAL) load_own_thermal(d, d.gin, x, y, g[THERMAL ? r : 0]);
-        } else {
-            if (interior) gather_interior<S>(d, fin, x, y, f[r]);
-            else gather_general<S>(d, fin, x, y, f[r]);
-            if (THERMAL) gather_thermal(d, d.gin, x, y, interior, g[THERMAL ? r : 0]);
+        for (int r = 0; r < ROWS; ++r) {
+            const int64_t o = (int64_t)(y0 + ly + r * TH) * d.pitch + xb;
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                load_row<S, NX>(fin + i * d.plane + o - EY[i] * d.pitch - EX[i], f[r][i]);
+            if (THERMAL) {
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                    load_row<float, NX>(d.gin + j * d.plane + o - TYv[j] * d.pitch - TXv[j],
+                                        g[THERMAL ? r : 0][j]);
+            }
+            if (d.medium != MED_UNIFORM) load_row<float, NX>(d.phi + o, ph[r]);
+            if (d.medium == MED_PHI_KAPPA) load_row<float, NX>(d.kappa + o, kp[r]);
         }
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int64_t o = (int64_t)(y0 + ly + r * TH) * d.pitch + xb;
+            float ux[NX], uy[NX];
+#pragma unroll
+            for (int k = 0; k < NX; ++k) {
+                float fn[8], gn[5];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) fn[i] = f[r][i][k];
+                if (THERMAL) {
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) gn[j] = g[THERMAL ? r : 0][j][k];
+                }
+                const Cell c = cell_from(d, ph[r][k], kp[r][k]);
+                node_update<THERMAL>(d, c, fn, gn, ux[k], uy[k]);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) f[r][i][k] = fn[i];
+                if (THERMAL) {
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) g[THERMAL ? r : 0][j][k] = gn[j];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) store_row<S, NX>(fout + i * d.plane + o, f[r][i]);
+            if (THERMAL) {
+#pragma unroll
+                for (int j = 0; j < 5; ++j) store_row<float, NX>(d.gout + j * d.plane + o, g[THERMAL ? r : 0][j]);
+            }
+            if (REC) {
+                store_row<float, NX>(d.urec + o, ux);
+                store_row<float, NX>(d.urec + d.plane + o, uy);
+            }
+        }
+        return;
     }
+
+    // edge tiles (and the collide-only first cycle): node by node
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) {
-        if (!ok[r]) continue;
         const int y = y0 + ly + r * TH;
-        const int64_t o = (int64_t)y * d.pitch + x;
-        const Cell c = load_cell(d, o);
-        float ay = d.ay;
-        if (THERMAL) {
-            const float *gg = g[THERMAL ? r : 0];
-            const float dT = (gg[0] + gg[1]) + (gg[2] + gg[3]) + gg[4];
-            ay = d.ay + d.gbeta * dT;   // Boussinesq term of Sec. 3.4
-        }
-        float ux, uy;
-        collide(f[r], d, c, c.phi * d.ax, c.phi * ay, ux, uy);
+        if (y >= d.ny) continue;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) Store<S>::st(fout + i * d.plane + o, f[r][i]);
-        if (THERMAL) {
-            float *gg = g[THERMAL ? r : 0];
-            thermal_collide(gg, d, ux, uy);
+        for (int k = 0; k < NX; ++k) {
+            const int x = xb + k;
+            if (x >= d.nx) continue;
+            float fn[8], gn[5];
+            if (SRC == SRC_DIRECT) {
+                load_own<S>(d, fin, x, y, fn);
+                if (THERMAL) load_own_thermal(d, d.gin, x, y, gn);
+            } else {
+                gather_general<S>(d, fin, x, y, fn);
+                if (THERMAL) gather_thermal(d, d.gin, x, y, false, gn);
+            }
+            const int64_t o = (int64_t)y * d.pitch + x;
+            const Cell c = load_cell(d, o);
+            float ux, uy;
+            node_update<THERMAL>(d, c, fn, gn, ux, uy);
 #pragma unroll
-            for (int j = 0; j < 5; ++j) d.gout[j * d.plane + o] = gg[j];
-        }
-        if (REC) {
-            d.urec[o] = ux;
-            d.urec[d.plane + o] = uy;
+            for (int i = 0; i < 8; ++i) Store<S>::st(fout + i * d.plane + o, fn[i]);
+            if (THERMAL) {
+#pragma unroll
+                for (int j = 0; j < 5; ++j) d.gout[j * d.plane + o] = gn[j];
+            }
+            if (REC) {
+                d.urec[o] = ux;
+                d.urec[d.plane + o] = uy;
+            }
         }
     }
 }
 
-template <typename S, bool THERMAL, int SRC, bool REC, int TW, int ROWS>
+template <typename S, bool THERMAL, int SRC, bool REC, int TWT, int NX, int ROWS>
 __global__ __launch_bounds__(BLOCK) void k_step(Dom d, int tiles_x, int swz) {
     int b = blockIdx.x;
     if (swz) b = xcd_swizzle(b, gridDim.x);
-    step_tile<S, THERMAL, SRC, REC, TW, ROWS>(d, b % tiles_x, b / tiles_x);
+    step_tile<S, THERMAL, SRC, REC, TWT, NX, ROWS>(d, b % tiles_x, b / tiles_x);
 }
 
-template <typename S, int TW, int ROWS>
+template <typename S, int TWT, int NX, int ROWS>
 __global__ __launch_bounds__(BLOCK) void k_step_batch(const Dom *__restrict__ doms,
                                                       const int4 *__restrict__ tiles,
                                                       int ntiles, int parity) {
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int4 tl = tiles[t];
         const Dom d = doms[2 * tl.x + parity];
-        step_tile<S, false, SRC_GATHER, false, TW, ROWS>(d, tl.y, tl.z);
+        step_tile<S, false, SRC_GATHER, false, TWT, NX, ROWS>(d, tl.y, tl.z);
     }
 }
 
 void tile_counts(const Schedule &s, int nx, int ny, int *tiles_x, int *tiles_y) {
     const int th = BLOCK / s.tile_w;
-    *tiles_x = (nx + s.tile_w - 1) / s.tile_w;
+    const int tw = s.tile_w * s.vec;
+    *tiles_x = (nx + tw - 1) / tw;
     *tiles_y = (ny + th * s.rows - 1) / (th * s.rows);
 }
 
+// The schedules compiled into the library: (threads along x, nodes per
+// thread along x, rows per thread).
+#define MRT_SCHEDULES(X) \
+    X(256, 1, 1) X(256, 1, 2) X(128, 1, 1) X(128, 1, 2) X(64, 1, 2) X(64, 1, 4) \
+    X(128, 2, 1) X(64, 2, 2) X(64, 4, 1) X(32, 4, 2) X(64, 4, 2) X(16, 4, 4)
+
 bool schedule_supported(const Schedule &s) {
-    return (s.tile_w == 256 && (s.rows == 1 || s.rows == 2)) ||
-           (s.tile_w == 128 && (s.rows == 1 || s.rows == 2)) ||
-           (s.tile_w == 64 && (s.rows == 2 || s.rows == 4));
+#define MRT_SUP(T, V, R) if (s.tile_w == T && s.vec == V && s.rows == R) return true;
+    MRT_SCHEDULES(MRT_SUP)
+#undef MRT_SUP
+    return false;
 }
 
 template <typename S, bool THERMAL, int SRC, bool REC>
@@ -122,27 +195,21 @@ static hipError_t launch_step_t(const Dom &d, const Schedule &s, hipStream_t st)
     int tx, ty;
     tile_counts(s, d.nx, d.ny, &tx, &ty);
     const dim3 grid((unsigned)(tx * ty)), block(BLOCK);
-    if (s.tile_w == 256 && s.rows == 1)
-        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 256, 1>), grid, block, 0, st, d, tx, s.swizzle);
-    else if (s.tile_w == 256 && s.rows == 2)
-        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 256, 2>), grid, block, 0, st, d, tx, s.swizzle);
-    else if (s.tile_w == 128 && s.rows == 1)
-        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 128, 1>), grid, block, 0, st, d, tx, s.swizzle);
-    else if (s.tile_w == 128 && s.rows == 2)
-        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 128, 2>), grid, block, 0, st, d, tx, s.swizzle);
-    else if (s.tile_w == 64 && s.rows == 2)
-        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 64, 2>), grid, block, 0, st, d, tx, s.swizzle);
-    else if (s.tile_w == 64 && s.rows == 4)
-        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, 64, 4>), grid, block, 0, st, d, tx, s.swizzle);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+#define MRT_LAUNCH(T, V, R)                                                                  \
+    if (s.tile_w == T && s.vec == V && s.rows == R) {                                        \
+        hipLaunchKernelGGL((k_step<S, THERMAL, SRC, REC, T, V, R>), grid, block, 0, st, d, tx, \
+                           s.swizzle);                                                       \
+        return hipGetLastError();                                                            \
+    }
+    MRT_SCHEDULES(MRT_LAUNCH)
+#undef MRT_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_step(const Dom &d, int storage, Source src, bool rec, const Schedule &s,
                        hipStream_t st) {
-    // the collide-only first cycle always runs with the default schedule
-    static const Schedule flat{256, 1, 0};
+    // the collide-only first cycle always runs with the plain schedule
+    static const Schedule flat{256, 1, 1, 0};
     const bool th = d.thermal != 0;
     if (rec && (storage != ST_F32 || th)) return hipErrorInvalidValue;
     if (src == SRC_DIRECT) {
@@ -167,21 +234,14 @@ template <typename S>
 static hipError_t launch_batch_t(const Dom *doms, const int4 *tiles, int ntiles, int parity,
                                  const Schedule &s, int grid, hipStream_t st) {
     const dim3 g((unsigned)grid), b(BLOCK);
-    if (s.tile_w == 256 && s.rows == 1)
-        hipLaunchKernelGGL((k_step_batch<S, 256, 1>), g, b, 0, st, doms, tiles, ntiles, parity);
-    else if (s.tile_w == 256 && s.rows == 2)
-        hipLaunchKernelGGL((k_step_batch<S, 256, 2>), g, b, 0, st, doms, tiles, ntiles, parity);
-    else if (s.tile_w == 128 && s.rows == 1)
-        hipLaunchKernelGGL((k_step_batch<S, 128, 1>), g, b, 0, st, doms, tiles, ntiles, parity);
-    else if (s.tile_w == 128 && s.rows == 2)
-        hipLaunchKernelGGL((k_step_batch<S, 128, 2>), g, b, 0, st, doms, tiles, ntiles, parity);
-    else if (s.tile_w == 64 && s.rows == 2)
-        hipLaunchKernelGGL((k_step_batch<S, 64, 2>), g, b, 0, st, doms, tiles, ntiles, parity);
-    else if (s.tile_w == 64 && s.rows == 4)
-        hipLaunchKernelGGL((k_step_batch<S, 64, 4>), g, b, 0, st, doms, tiles, ntiles, parity);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+#define MRT_BLAUNCH(T, V, R)                                                              \
+    if (s.tile_w == T && s.vec == V && s.rows == R) {                                     \
+        hipLaunchKernelGGL((k_step_batch<S, T, V, R>), g, b, 0, st, doms, tiles, ntiles, parity); \
+        return hipGetLastError();                                                         \
+    }
+    MRT_SCHEDULES(MRT_BLAUNCH)
+#undef MRT_BLAUNCH
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity,

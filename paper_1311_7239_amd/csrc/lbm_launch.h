@@ -17,8 +17,9 @@ enum Storage { ST_F32 = 0, ST_F16 = 1 };
 enum Source { SRC_GATHER = 0, SRC_DIRECT = 1, SRC_NONE = 2 };
 
 struct Schedule {
-    int tile_w;  // threads of a 256-thread block along x (256, 128 or 64)
-    int rows;    // rows per thread (1, 2 or 4)
+    int tile_w;  // threads of a 256-thread block along x
+    int vec;     // consecutive nodes per thread along x (1, 2 or 4)
+    int rows;    // rows per thread
     int swizzle; // map consecutive tiles onto the same XCD
 };
 

@@ -82,9 +82,10 @@ def lib():
         L.lbm_strerror.argtypes = [ctypes.c_int]
         L.lbm_strerror.restype = ctypes.c_char_p
         L.lbm_last_error.restype = ctypes.c_char_p
-        L.lbm_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32),
+        L.lbm_schedule.argtypes = [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
-        L.lbm_set_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.lbm_set_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -232,13 +233,14 @@ class Solver:
         buf = ctypes.create_string_buffer(blob, len(blob))
         check(lib().lbm_load(self._ctx, buf, len(blob)))
 
-    def set_schedule(self, tile_w: int, rows: int, swizzle: int = 1):
-        check(lib().lbm_set_schedule(self._ctx, tile_w, rows, swizzle))
+    def set_schedule(self, tile_w: int, vec: int, rows: int, swizzle: int = 1):
+        check(lib().lbm_set_schedule(self._ctx, tile_w, vec, rows, swizzle))
 
     def schedule(self):
-        a = ctypes.c_int32(); b = ctypes.c_int32(); c = ctypes.c_int32()
-        check(lib().lbm_schedule(self._ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return a.value, b.value, c.value
+        a, v, b, c = (ctypes.c_int32() for _ in range(4))
+        check(lib().lbm_schedule(self._ctx, ctypes.byref(a), ctypes.byref(v), ctypes.byref(b),
+                                 ctypes.byref(c)))
+        return a.value, v.value, b.value, c.value
 
 
 def solver_for_case(case, storage: int = FP32_DEV, ckpt_every: int = 0, max_steps_recorded: int = 0,

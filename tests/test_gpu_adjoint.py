@@ -1,0 +1,146 @@
+"""The hand-written discrete adjoint (lbm_backward) against finite differences of the
+FP64 oracle, and against finite differences of the GPU forward at full size."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1311_7239_amd import inputs as I
+from paper_1311_7239_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def twin(nx=96, ny=64, seed=21, steps=300):
+    """Small log-normal porous channel: same recipe as the 2048^2 inverse problem,
+    with a drag strong enough that the medium matters within a few hundred steps."""
+    c = I.lognormal_channel(n=max(nx, ny), seed=seed, ell=8.0, K_ref=40.0, drive=0.02)
+    c.nx, c.ny = nx, ny
+    c.phi = np.ascontiguousarray(c.phi[:ny, :nx])
+    c.steps = steps
+    return c
+
+
+def oracle_outlet(case, phi, K=None, steps=None):
+    """u at the outlet column x = nx-1 after `steps` FP64 oracle steps."""
+    p = oracle.make_params(case.nx, case.ny, bc_x=case.bc_x, bc_y=case.bc_y, nu=case.nu,
+                           ax=case.ax, nthreads=8)
+    phi = np.asarray(phi, dtype=np.float64)
+    Ke, F = oracle.ergun(phi, case.dp)
+    if K is None:
+        K = Ke
+    f = oracle.rest_state(p, case.Pi0)
+    oracle.run(p, phi, K, F, f, nsteps=case.steps if steps is None else steps)
+    ux, uy, _, _ = oracle.macroscopic(p, phi, K, F, f)
+    return np.stack([ux[:, -1], uy[:, -1]])
+
+
+def loss(u_out, target):
+    return 0.5 * float(np.sum((u_out - target) ** 2))
+
+
+def gpu_gradient(case, target, kappa=None, ckpt=64):
+    desc = lbm.desc_from_case(case, ckpt_every=ckpt)
+    phi = torch.from_numpy(case.phi).cuda()
+    kap = None
+    if kappa is not None:
+        desc.medium = lbm.MEDIUM_PHI_KAPPA
+        kap = torch.from_numpy(kappa.astype(np.float32)).cuda()
+    s = lbm.Solver(desc, phi=phi, kappa=kap, max_steps_recorded=case.steps)
+    s.step(case.steps)
+    _, u, _ = s.macroscopic()
+    dLdu = torch.zeros_like(u)
+    dLdu[:, :, -1] = u[:, :, -1] - torch.from_numpy(target.astype(np.float32)).cuda()
+    g, gk = s.backward(dLdu, want_kappa=kappa is not None)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64), (None if gk is None else gk.cpu().numpy().astype(np.float64))
+
+
+def test_adjoint_matches_oracle_finite_differences():
+    case = twin()
+    target = oracle_outlet(case, twin(seed=55).phi)
+    g, _ = gpu_gradient(case, target)
+    phi0 = case.phi.astype(np.float64)
+    # 16 cells: the 8 largest |g| and 8 seeded random cells with |g| above 1% of the max
+    order = np.argsort(-np.abs(g).ravel())
+    rng = np.random.default_rng(505)
+    big = [int(i) for i in order[:8]]
+    pool = [int(i) for i in order if abs(g.ravel()[i]) > 1e-2 * abs(g).max() and int(i) not in big]
+    cells = big + [int(i) for i in rng.choice(pool, size=8, replace=False)]
+    worst = 0.0
+    for idx in cells:
+        j, i = divmod(idx, case.nx)
+        h = 1e-4 * phi0[j, i]
+        pp = phi0.copy(); pp[j, i] += h
+        pm = phi0.copy(); pm[j, i] -= h
+        fd = (loss(oracle_outlet(case, pp), target) - loss(oracle_outlet(case, pm), target)) / (2 * h)
+        worst = max(worst, abs(g[j, i] - fd) / abs(fd))
+    assert worst < 2e-3, worst
+
+
+def test_adjoint_directional_derivative():
+    """All cells perturbed along a seeded random direction: the FD of the FP64 oracle loss
+    matches <g, dphi>."""
+    case = twin(seed=22, steps=257)
+    target = oracle_outlet(case, twin(seed=56, steps=257).phi)
+    g, _ = gpu_gradient(case, target, ckpt=50)
+    rng = np.random.default_rng(77)
+    dphi = rng.uniform(-1.0, 1.0, size=g.shape) * case.phi
+    phi0 = case.phi.astype(np.float64)
+    h = 1e-5
+    fd = (loss(oracle_outlet(case, phi0 + h * dphi), target)
+          - loss(oracle_outlet(case, phi0 - h * dphi), target)) / (2 * h)
+    assert abs(np.sum(g * dphi) / fd - 1.0) < 1e-3
+
+
+def test_adjoint_with_independent_kappa_plane():
+    """MEDIUM_PHI_KAPPA: dL/dphi at fixed kappa and dL/dkappa, against oracle FD
+    (the oracle takes K = 1/kappa)."""
+    case = twin(nx=64, ny=48, seed=23, steps=200)
+    Ke, _ = oracle.ergun(case.phi.astype(np.float64), case.dp)
+    kappa = (1.0 / Ke).astype(np.float32)
+    target = np.zeros((2, case.ny))
+    g, gk = gpu_gradient(case, target, kappa=kappa.astype(np.float64), ckpt=64)
+    phi0 = case.phi.astype(np.float64)
+    k0 = kappa.astype(np.float64)
+    rng = np.random.default_rng(9)
+    dphi = rng.uniform(-1, 1, size=g.shape) * phi0
+    dk = rng.uniform(-1, 1, size=g.shape) * k0
+    h = 1e-5
+    fd_phi = (loss(oracle_outlet(case, phi0 + h * dphi, K=1.0 / k0), target)
+              - loss(oracle_outlet(case, phi0 - h * dphi, K=1.0 / k0), target)) / (2 * h)
+    fd_k = (loss(oracle_outlet(case, phi0, K=1.0 / (k0 + h * dk)), target)
+            - loss(oracle_outlet(case, phi0, K=1.0 / (k0 - h * dk)), target)) / (2 * h)
+    assert abs(np.sum(g * dphi) / fd_phi - 1.0) < 1e-3
+    assert abs(np.sum(gk * dk) / fd_k - 1.0) < 1e-3
+
+
+def test_backward_state_errors():
+    case = twin(nx=32, ny=16, steps=10)
+    s = lbm.solver_for_case(case)                       # no recording
+    s.step(3)
+    dLdu = torch.zeros((2, 16, 32), device="cuda")
+    with pytest.raises(lbm.LBMError) as e:
+        s.backward(dLdu)
+    assert e.value.status == lbm.ESTATE
+    r = lbm.solver_for_case(case, ckpt_every=4, max_steps_recorded=8)
+    r.step(13)                                          # beyond the recorded capacity
+    with pytest.raises(lbm.LBMError) as e:
+        r.backward(dLdu)
+    assert e.value.status == lbm.ESTATE
+
+
+def test_backward_leaves_forward_state_and_repeats_bitwise():
+    case = twin(nx=64, ny=32, steps=130)
+    s = lbm.solver_for_case(case, ckpt_every=32, max_steps_recorded=130)
+    s.step(130)
+    before, _ = s.populations()
+    _, u, _ = s.macroscopic()
+    dLdu = torch.zeros_like(u); dLdu[:, :, -1] = 1.0
+    g1, _ = s.backward(dLdu)
+    g2, _ = s.backward(dLdu)
+    after, _ = s.populations()
+    torch.cuda.synchronize()
+    assert torch.equal(before, after)
+    assert torch.equal(g1, g2)
+    assert s.time == 130
