@@ -123,14 +123,18 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
                size_t ws_bytes, void *stream, lbm_ctx **out);
 
 /* Ragged batch: n independent domains stepped together by one persistent
- * launch per step, replayed from a captured HIP graph. descs, phis, kappas:
- * host arrays of n entries (phis[k]/kappas[k] device planes or NULL).
- * All domains must share storage and thermal.enabled (thermal unsupported:
- * ENOTSUP) and have ckpt_every = 0. The tile schedule is chosen by timing
- * candidates on the stream (autotuning) unless tune_cache (host path, may
- * be NULL) holds a result for the same batch signature; the choice is
- * appended there. Results are bitwise identical to stepping each domain
- * alone. */
+ * launch per step (a tile table maps workgroups to (domain, tile)), replayed
+ * from a HIP graph of graph_steps launches (default 32). descs, phis,
+ * kappas: host arrays of n entries (phis[k]/kappas[k] device planes or
+ * NULL). All domains must share the storage; thermal domains and
+ * ckpt_every > 0 give ENOTSUP. The tile schedule and persistent grid size
+ * are chosen by timing every compiled candidate on the stream (autotuning,
+ * which synchronises the stream) unless tune_cache (host path, may be NULL)
+ * already holds a choice for the same batch signature (sizes, boundaries,
+ * media, storage, device); a new choice is appended there as a text line.
+ * Results are bitwise identical to stepping each domain alone. The
+ * per-domain calls (lbm_macroscopic, lbm_get_populations, lbm_reduce) take
+ * the domain index. */
 int lbm_batch_workspace_size(int32_t n, const lbm_desc *descs, size_t *bytes);
 int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *const *phis,
                      const float *const *kappas, void *workspace, size_t ws_bytes,
@@ -204,6 +208,12 @@ int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows,
  * differs. EINVAL for another shape, ENOTSUP on a batch (its schedule is
  * autotuned). */
 int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int32_t swizzle);
+
+/* Number of steps lbm_step replays from one hand-built HIP graph of kernel
+ * nodes (an even number up to 4096; 0 launches every step separately).
+ * Defaults: 0 for single domains, 32 for batches. Graphs are not used while
+ * a trajectory is recorded for lbm_backward. Results do not depend on it. */
+int lbm_set_graph_steps(lbm_ctx *c, int32_t steps);
 
 #ifdef __cplusplus
 }

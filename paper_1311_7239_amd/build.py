@@ -13,7 +13,7 @@ PKG = pathlib.Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libmrtlbm.so"
-SOURCES = ["lbm_kernels.hip", "lbm_adjoint.hip", "lbm_batch.hip", "lbm_abi.cpp"]
+SOURCES = ["lbm_kernels.hip", "lbm_adjoint.hip", "lbm_abi.cpp"]
 
 # -ffp-contract=off: every kernel variant (single domain, batch, schedules)
 # evaluates the per-node arithmetic with the same rounding, which is what

@@ -198,8 +198,13 @@ struct lbm_ctx {
     int4 *d_tiles = nullptr;
     int ntiles = 0;
     int grid = 0;
-    hipGraphExec_t gexec = nullptr;
+    int storage = ST_F32;
+    std::vector<Dom> h_doms;    // host copies (kept alive for the async upload)
+    std::vector<int4> h_tiles;
+    // steps replayed from one hand-built HIP graph (0: launch each step);
+    // one executable graph per starting buffer parity
     int graph_steps = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -279,6 +284,57 @@ hipError_t checkpoint(lbm_ctx *c) {
     if (slot >= D.L.nck) return hipSuccess;  // beyond capacity: backward will refuse
     return hipMemcpyAsync(D.base + D.L.off_ck + (size_t)slot * D.L.f_bytes, D.base + D.L.off_f[c->cur],
                           D.L.f_bytes, hipMemcpyDeviceToDevice, c->stream);
+}
+
+}  // namespace
+
+namespace {
+
+void reset_graphs(lbm_ctx *c) {
+    for (auto &g : c->gexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+// A chain of graph_steps kernel nodes, alternating the buffer parity, built
+// node by node (no stream capture, so any stream, including the null stream,
+// can launch it). Contains kernel nodes only.
+hipError_t build_graph(lbm_ctx *c, int parity) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return e;
+    hipGraphNode_t prev = nullptr;
+    for (int k = 0; k < c->graph_steps && e == hipSuccess; ++k) {
+        int p = parity ^ (k & 1);
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof(kp));
+        kp.blockDim = dim3(256);
+        Dom d;
+        int tx = 0, ty = 0, swz = c->sched.swizzle;
+        void *args_b[4] = {&c->d_doms, &c->d_tiles, &c->ntiles, &p};
+        void *args_s[3] = {&d, &tx, &swz};
+        if (c->batch) {
+            kp.func = (void *)batch_kernel_fn(c->storage, c->sched);
+            kp.gridDim = dim3((unsigned)c->grid);
+            kp.kernelParams = args_b;
+        } else {
+            Domain &D = c->dom[0];
+            d = dom_for(D, p);
+            tile_counts(c->sched, D.desc.nx, D.desc.ny, &tx, &ty);
+            kp.func = (void *)step_kernel_fn(D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
+                                             D.desc.thermal.enabled != 0, c->sched);
+            kp.gridDim = dim3((unsigned)(tx * ty));
+            kp.kernelParams = args_s;
+        }
+        if (!kp.func) { e = hipErrorInvalidValue; break; }
+        hipGraphNode_t node;
+        e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        prev = node;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec[parity], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e;
 }
 
 }  // namespace
@@ -369,20 +425,45 @@ int lbm_step(lbm_ctx *c, int64_t n) {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
-    if (c->batch) {
-        extern int lbm_batch_step_impl(lbm_ctx * c, int64_t n);
-        return lbm_batch_step_impl(c, n);
-    }
-    Domain &D = c->dom[0];
-    for (int64_t k = 0; k < n; ++k) {
-        const Dom d = dom_for(D, c->cur);
-        hipError_t e = launch_step(d, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, src_now(c->t),
-                                   false, c->sched, c->stream);
+    while (n > 0) {
+        hipError_t e;
+        if (c->t == 0) {
+            // collide-only first cycle of every domain
+            for (Domain &D : c->dom) {
+                e = launch_step(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
+                                SRC_DIRECT, false, c->sched, c->stream);
+                if (e != hipSuccess) return device_fail(c, e, "step launch");
+            }
+            c->cur ^= 1;
+            c->t = 1;
+            n -= 1;
+            if ((e = checkpoint(c)) != hipSuccess) return device_fail(c, e, "checkpoint copy");
+            continue;
+        }
+        const bool recording = c->rec_valid && c->dom[0].desc.ckpt_every > 0;
+        if (c->graph_steps > 0 && n >= c->graph_steps && !recording) {
+            if (!c->gexec[c->cur]) {
+                if ((e = build_graph(c, c->cur)) != hipSuccess) return device_fail(c, e, "graph build");
+            }
+            if ((e = hipGraphLaunch(c->gexec[c->cur], c->stream)) != hipSuccess)
+                return device_fail(c, e, "graph launch");
+            c->t += c->graph_steps;  // graph_steps is even: parity unchanged
+            n -= c->graph_steps;
+            continue;
+        }
+        if (c->batch) {
+            e = launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, c->cur, c->storage, c->sched, c->grid,
+                                  c->stream);
+        } else {
+            Domain &D = c->dom[0];
+            e = launch_step(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, SRC_GATHER,
+                            false, c->sched, c->stream);
+        }
         if (e != hipSuccess) return device_fail(c, e, "step launch");
         c->cur ^= 1;
         c->t += 1;
-        e = checkpoint(c);
-        if (e != hipSuccess) return device_fail(c, e, "checkpoint copy");
+        n -= 1;
+        if ((e = checkpoint(c)) != hipSuccess) return device_fail(c, e, "checkpoint copy");
     }
     return LBM_OK;
 }
@@ -447,9 +528,8 @@ int lbm_reduce(lbm_ctx *c, int32_t k, double *mass, double *residual) {
     if (rc) return rc;
     if ((rc = check_domain(c, k))) return rc;
     Domain &D = c->dom[k];
-    const int par = c->batch ? (int)(c->t & 1) : c->cur;
-    const Dom cur = dom_for(D, par);
-    const Dom prev = dom_for(D, par ^ 1);
+    const Dom cur = dom_for(D, c->cur);
+    const Dom prev = dom_for(D, c->cur ^ 1);
     double *partials = (double *)(D.base + D.L.off_part);
     double *result = (double *)(D.base + D.L.off_res);
     hipError_t e = launch_reduce(cur, src_now(c->t), prev, src_prev(c->t),
@@ -554,7 +634,7 @@ int lbm_load(lbm_ctx *c, const void *host_buf, size_t bytes) {
 
 int lbm_destroy(lbm_ctx *c) {
     if (!c) return LBM_OK;
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    reset_graphs(c);
     delete c;
     return LBM_OK;
 }
@@ -597,27 +677,249 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
     if (!schedule_supported(s))
         return fail(LBM_EINVAL, "unsupported schedule %d x %d x %d", tile_w, vec, rows);
     c->sched = s;
+    reset_graphs(c);
+    return LBM_OK;
+}
+
+int lbm_set_graph_steps(lbm_ctx *c, int32_t steps) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (steps < 0 || (steps & 1) || steps > 4096)
+        return fail(LBM_EINVAL, "graph steps must be an even number in [0, 4096]");
+    c->graph_steps = steps;
+    reset_graphs(c);
     return LBM_OK;
 }
 
 }  // extern "C"
 
-int lbm_batch_step_impl(lbm_ctx *c, int64_t n) {
-    (void)n;
-    return fail(LBM_ENOTSUP, "batched stepping not available");
+// ============================================================ batches
+
+namespace {
+
+const Schedule kCandidates[] = {{256, 1, 1, 0}, {256, 1, 2, 0}, {128, 1, 1, 0}, {128, 1, 2, 0},
+                                {64, 1, 2, 0},  {64, 1, 4, 0},  {128, 2, 1, 0}, {64, 2, 2, 0},
+                                {64, 4, 1, 0},  {32, 4, 2, 0},  {64, 4, 2, 0},  {16, 4, 4, 0}};
+
+int validate_batch(int32_t n, const lbm_desc *descs) {
+    if (n < 1) return fail(LBM_EINVAL, "batch needs n >= 1 domains");
+    if (!descs) return fail(LBM_EINVAL, "descs is NULL");
+    for (int32_t k = 0; k < n; ++k) {
+        int rc = validate(&descs[k]);
+        if (rc) return fail(rc, "domain %d: %s", k, g_last_error.c_str());
+        if (descs[k].thermal.enabled) return fail(LBM_ENOTSUP, "domain %d: thermal batches are not supported", k);
+        if (descs[k].ckpt_every != 0) return fail(LBM_ENOTSUP, "domain %d: batches do not record for the adjoint", k);
+        if (descs[k].storage != descs[0].storage) return fail(LBM_EINVAL, "domain %d: storage differs from domain 0", k);
+    }
+    return LBM_OK;
 }
 
+int64_t batch_tiles(int32_t n, const lbm_desc *descs, const Schedule &s) {
+    int64_t total = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        int tx, ty;
+        tile_counts(s, descs[k].nx, descs[k].ny, &tx, &ty);
+        total += (int64_t)tx * ty;
+    }
+    return total;
+}
+
+struct BatchLayout {
+    std::vector<size_t> off;  // per-domain base offsets
+    size_t off_doms = 0, off_tiles = 0, total = 0;
+    int64_t max_tiles = 0;
+};
+
+BatchLayout batch_layout(int32_t n, const lbm_desc *descs) {
+    BatchLayout B;
+    size_t o = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        B.off.push_back(o);
+        o = align_up(o + make_layout(descs[k], 0).total, ALIGN);
+    }
+    for (const Schedule &s : kCandidates) {
+        const int64_t t = batch_tiles(n, descs, s);
+        if (t > B.max_tiles) B.max_tiles = t;
+    }
+    B.off_doms = o;
+    o = align_up(o + sizeof(Dom) * 2 * (size_t)n, ALIGN);
+    B.off_tiles = o;
+    o = align_up(o + sizeof(int4) * (size_t)B.max_tiles, ALIGN);
+    B.total = o;
+    return B;
+}
+
+void fill_tiles(const lbm_ctx *c, const Schedule &s, std::vector<int4> &out) {
+    out.clear();
+    for (size_t k = 0; k < c->dom.size(); ++k) {
+        int tx, ty;
+        tile_counts(s, c->dom[k].desc.nx, c->dom[k].desc.ny, &tx, &ty);
+        for (int y = 0; y < ty; ++y)
+            for (int x = 0; x < tx; ++x) out.push_back(make_int4((int)k, x, y, 0));
+    }
+}
+
+uint64_t batch_signature(const lbm_ctx *c) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) { h ^= (uint64_t)((v >> (8 * b)) & 0xff); h *= 1099511628211ull; }
+    };
+    mix((int64_t)c->dom.size());
+    mix(c->storage);
+    for (const Domain &D : c->dom) {
+        mix(D.desc.nx); mix(D.desc.ny); mix(D.desc.bc_x); mix(D.desc.bc_y); mix(D.desc.medium);
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        for (const char *p = prop.gcnArchName; *p; ++p) mix(*p);
+        mix(prop.multiProcessorCount);
+    }
+    return h;
+}
+
+bool cache_lookup(const char *path, uint64_t sig, Schedule &s, int &grid) {
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    unsigned long long key;
+    int tw, v, r, g;
+    bool found = false;
+    while (fscanf(f, "%llx %d %d %d %d", &key, &tw, &v, &r, &g) == 5) {
+        const Schedule cand{tw, v, r, 0};
+        if (key == sig && schedule_supported(cand) && g > 0) { s = cand; grid = g; found = true; }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, uint64_t sig, const Schedule &s, int grid) {
+    if (!path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%016llx %d %d %d %d\n", (unsigned long long)sig, s.tile_w, s.vec, s.rows, grid);
+    fclose(f);
+}
+
+hipError_t upload_tiles(lbm_ctx *c, const Schedule &s) {
+    fill_tiles(c, s, c->h_tiles);
+    c->ntiles = (int)c->h_tiles.size();
+    hipError_t e = hipMemcpyAsync(c->d_tiles, c->h_tiles.data(), sizeof(int4) * c->h_tiles.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+}
+
+// Times every (schedule, grid) candidate on the batch. Each timing launch
+// reads buffer 0 (the rest state f(0)) and writes buffer 1, which the first
+// real cycle overwrites, so tuning leaves the state untouched.
+hipError_t autotune(lbm_ctx *c, Schedule &best, int &best_grid) {
+    int dev = 0, ncu = 256;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    hipEvent_t a = nullptr, b = nullptr;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&b)) != hipSuccess) { (void)hipEventDestroy(a); return e; }
+    float best_ms = 1e30f;
+    for (const Schedule &s : kCandidates) {
+        if ((e = upload_tiles(c, s)) != hipSuccess) break;
+        const int grids[5] = {2 * ncu, 4 * ncu, 8 * ncu, 16 * ncu, c->ntiles};
+        for (int g : grids) {
+            if (g > c->ntiles) g = c->ntiles;
+            for (int w = 0; w < 2 && e == hipSuccess; ++w)
+                e = launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, 0, c->storage, s, g, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(a, c->stream);
+            for (int w = 0; w < 5 && e == hipSuccess; ++w)
+                e = launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, 0, c->storage, s, g, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(b, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) break;
+            if (ms < best_ms) { best_ms = ms; best = s; best_grid = g; }
+        }
+        if (e != hipSuccess) break;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return e;
+}
+
+}  // namespace
+
 extern "C" int lbm_batch_workspace_size(int32_t n, const lbm_desc *descs, size_t *bytes) {
-    (void)n; (void)descs; (void)bytes;
-    return fail(LBM_ENOTSUP, "batched stepping not available");
+    int rc = validate_batch(n, descs);
+    if (rc) return rc;
+    if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+    *bytes = batch_layout(n, descs).total;
+    return LBM_OK;
 }
 
 extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *const *phis,
                                 const float *const *kappas, void *workspace, size_t ws_bytes,
                                 void *stream, const char *tune_cache, lbm_ctx **out) {
-    (void)n; (void)descs; (void)phis; (void)kappas; (void)workspace; (void)ws_bytes;
-    (void)stream; (void)tune_cache; (void)out;
-    return fail(LBM_ENOTSUP, "batched stepping not available");
+    int rc = validate_batch(n, descs);
+    if (rc) return rc;
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    if (!workspace) return fail(LBM_EINVAL, "workspace is NULL");
+    if ((uintptr_t)workspace % ALIGN) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    const BatchLayout B = batch_layout(n, descs);
+    if (ws_bytes < B.total) return fail(LBM_EINVAL, "workspace too small (%zu < %zu bytes)", ws_bytes, B.total);
+    for (int32_t k = 0; k < n; ++k) {
+        if (descs[k].medium != LBM_MEDIUM_UNIFORM && (!phis || !phis[k]))
+            return fail(LBM_EINVAL, "domain %d: phi plane required", k);
+        if (descs[k].medium == LBM_MEDIUM_PHI_KAPPA && (!kappas || !kappas[k]))
+            return fail(LBM_EINVAL, "domain %d: kappa plane required", k);
+    }
+    lbm_ctx *c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(LBM_EINVAL, "host allocation failed");
+    c->stream = (hipStream_t)stream;
+    c->batch = true;
+    c->storage = descs[0].storage == LBM_FP16_DEV ? ST_F16 : ST_F32;
+    c->dom.resize((size_t)n);
+    char *base = (char *)workspace;
+    hipError_t e = hipSuccess;
+    for (int32_t k = 0; k < n && e == hipSuccess; ++k) {
+        Domain &D = c->dom[(size_t)k];
+        const float *phi = phis ? phis[k] : nullptr;
+        const float *kap = kappas ? kappas[k] : nullptr;
+        rc = setup_domain(D, &descs[k], phi, kap, base + B.off[(size_t)k]);
+        if (rc) { delete c; return rc; }
+        e = init_domain(D, 0, phi, kap, c->stream);
+    }
+    c->d_doms = (Dom *)(base + B.off_doms);
+    c->d_tiles = (int4 *)(base + B.off_tiles);
+    c->h_doms.resize(2 * (size_t)n);
+    for (int32_t k = 0; k < n; ++k) {
+        c->h_doms[2 * (size_t)k] = dom_for(c->dom[(size_t)k], 0);
+        c->h_doms[2 * (size_t)k + 1] = dom_for(c->dom[(size_t)k], 1);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->d_doms, c->h_doms.data(), sizeof(Dom) * c->h_doms.size(), hipMemcpyHostToDevice,
+                           c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    Schedule best{128, 1, 2, 0};
+    int grid = 0;
+    const uint64_t sig = batch_signature(c);
+    if (e == hipSuccess && !cache_lookup(tune_cache, sig, best, grid)) {
+        e = autotune(c, best, grid);
+        if (e == hipSuccess) cache_store(tune_cache, sig, best, grid);
+    }
+    if (e == hipSuccess) {
+        c->sched = best;
+        e = upload_tiles(c, best);
+        if (grid > c->ntiles) grid = c->ntiles;
+        c->grid = grid;
+    }
+    if (e != hipSuccess) {
+        rc = fail(LBM_EDEVICE, "batch creation: %s", hipGetErrorString(e));
+        delete c;
+        return rc;
+    }
+    c->graph_steps = 32;
+    *out = c;
+    return LBM_OK;
 }
 
 extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa) {

@@ -159,11 +159,17 @@ __global__ __launch_bounds__(BLOCK) void k_step(Dom d, int tiles_x, int swz) {
     step_tile<S, THERMAL, SRC, REC, TWT, NX, ROWS>(d, b % tiles_x, b / tiles_x);
 }
 
+// Persistent batched step: block b walks a contiguous run of the tile table
+// (tiles of one domain row stay on one XCD and in order), so the grid size is
+// a free tuning parameter independent of the number of tiles.
 template <typename S, int TWT, int NX, int ROWS>
 __global__ __launch_bounds__(BLOCK) void k_step_batch(const Dom *__restrict__ doms,
                                                       const int4 *__restrict__ tiles,
                                                       int ntiles, int parity) {
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t nb = gridDim.x;
+    const int t0 = (int)((int64_t)blockIdx.x * ntiles / nb);
+    const int t1 = (int)(((int64_t)blockIdx.x + 1) * ntiles / nb);
+    for (int t = t0; t < t1; ++t) {
         const int4 tl = tiles[t];
         const Dom d = doms[2 * tl.x + parity];
         step_tile<S, false, SRC_GATHER, false, TWT, NX, ROWS>(d, tl.y, tl.z);
@@ -228,6 +234,34 @@ hipError_t launch_step(const Dom &d, int storage, Source src, bool rec, const Sc
     }
     if (th) return launch_step_t<_Float16, true, SRC_GATHER, false>(d, s, st);
     return launch_step_t<_Float16, false, SRC_GATHER, false>(d, s, st);
+}
+
+template <typename S, bool THERMAL, int SRC, bool REC>
+static const void *step_fn_t(const Schedule &s) {
+#define MRT_FN(T, V, R) \
+    if (s.tile_w == T && s.vec == V && s.rows == R) return (const void *)&k_step<S, THERMAL, SRC, REC, T, V, R>;
+    MRT_SCHEDULES(MRT_FN)
+#undef MRT_FN
+    return nullptr;
+}
+
+const void *step_kernel_fn(int storage, bool thermal, const Schedule &s) {
+    if (storage == ST_F32)
+        return thermal ? step_fn_t<float, true, SRC_GATHER, false>(s) : step_fn_t<float, false, SRC_GATHER, false>(s);
+    return thermal ? step_fn_t<_Float16, true, SRC_GATHER, false>(s) : step_fn_t<_Float16, false, SRC_GATHER, false>(s);
+}
+
+template <typename S>
+static const void *batch_fn_t(const Schedule &s) {
+#define MRT_BFN(T, V, R) \
+    if (s.tile_w == T && s.vec == V && s.rows == R) return (const void *)&k_step_batch<S, T, V, R>;
+    MRT_SCHEDULES(MRT_BFN)
+#undef MRT_BFN
+    return nullptr;
+}
+
+const void *batch_kernel_fn(int storage, const Schedule &s) {
+    return storage == ST_F32 ? batch_fn_t<float>(s) : batch_fn_t<_Float16>(s);
 }
 
 template <typename S>

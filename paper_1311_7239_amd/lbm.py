@@ -86,6 +86,7 @@ def lib():
                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.lbm_set_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32]
+        L.lbm_set_graph_steps.argtypes = [_vp, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -236,6 +237,9 @@ class Solver:
     def set_schedule(self, tile_w: int, vec: int, rows: int, swizzle: int = 1):
         check(lib().lbm_set_schedule(self._ctx, tile_w, vec, rows, swizzle))
 
+    def set_graph_steps(self, steps: int):
+        check(lib().lbm_set_graph_steps(self._ctx, int(steps)))
+
     def schedule(self):
         a, v, b, c = (ctypes.c_int32() for _ in range(4))
         check(lib().lbm_schedule(self._ctx, ctypes.byref(a), ctypes.byref(v), ctypes.byref(b),
@@ -250,3 +254,90 @@ def solver_for_case(case, storage: int = FP32_DEV, ckpt_every: int = 0, max_step
     if case.phi is not None:
         phi = torch.from_numpy(case.phi.astype("float32")).to(device)
     return Solver(desc, phi=phi, max_steps_recorded=max_steps_recorded, device=device)
+
+
+class Batch:
+    """Ragged batch of independent domains stepped together (lbm_create_batch)."""
+
+    def __init__(self, descs: Sequence[Desc], phis=None, kappas=None, tune_cache: Optional[str] = None,
+                 device="cuda", stream=None):
+        L = lib()
+        n = len(descs)
+        self.n = n
+        self.descs = list(descs)
+        self.device = torch.device(device)
+        arr = (Desc * n)(*descs)
+        self._arr = arr
+        nb = ctypes.c_size_t()
+        check(L.lbm_batch_workspace_size(n, arr, ctypes.byref(nb)))
+        self.workspace = _workspace(nb.value, self.device)
+        self._phis = phis
+        self._kappas = kappas
+        pp = None
+        if phis is not None:
+            pp = (ctypes.c_void_p * n)(*[None if t is None else t.data_ptr() for t in phis])
+        kp = None
+        if kappas is not None:
+            kp = (ctypes.c_void_p * n)(*[None if t is None else t.data_ptr() for t in kappas])
+        wsp, wsn = _aligned(self.workspace)
+        ctx = ctypes.c_void_p()
+        check(L.lbm_create_batch(n, arr, pp, kp, wsp, wsn, _stream_handle(stream),
+                                 None if tune_cache is None else str(tune_cache).encode(),
+                                 ctypes.byref(ctx)))
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().lbm_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nodes(self) -> int:
+        return sum(d.nx * d.ny for d in self.descs)
+
+    def step(self, n: int = 1):
+        check(lib().lbm_step(self._ctx, int(n)))
+
+    def set_graph_steps(self, steps: int):
+        check(lib().lbm_set_graph_steps(self._ctx, int(steps)))
+
+    def schedule(self):
+        a, v, b, c = (ctypes.c_int32() for _ in range(4))
+        check(lib().lbm_schedule(self._ctx, ctypes.byref(a), ctypes.byref(v), ctypes.byref(b),
+                                 ctypes.byref(c)))
+        return a.value, v.value, b.value, c.value
+
+    def macroscopic(self, k: int):
+        d = self.descs[k]
+        p = torch.empty((d.ny, d.nx), dtype=torch.float32, device=self.device)
+        u = torch.empty((2, d.ny, d.nx), dtype=torch.float32, device=self.device)
+        check(lib().lbm_macroscopic(self._ctx, k, _ptr(p), _ptr(u), None))
+        return p, u
+
+    def populations(self, k: int):
+        d = self.descs[k]
+        df = torch.empty((8, d.ny, d.nx), dtype=torch.float32, device=self.device)
+        check(lib().lbm_get_populations(self._ctx, k, _ptr(df), None))
+        return df
+
+    def reduce(self, k: int):
+        m = ctypes.c_double(); r = ctypes.c_double()
+        st = lib().lbm_reduce(self._ctx, k, ctypes.byref(m), ctypes.byref(r))
+        if st not in (OK, EUNSTABLE):
+            check(st)
+        return m.value, r.value, st
+
+
+def batch_for_cases(cases, storage: int = FP32_DEV, tune_cache=None, device="cuda") -> Batch:
+    descs = [desc_from_case(c, storage=storage) for c in cases]
+    phis = None
+    if any(c.phi is not None for c in cases):
+        phis = [None if c.phi is None else torch.from_numpy(c.phi.astype("float32")).to(device)
+                for c in cases]
+    return Batch(descs, phis=phis, tune_cache=tune_cache, device=device)
