@@ -1,11 +1,15 @@
 """Throughput benchmark of the fused D2Q8 porous MRT-LB step on one MI355X.
 
-Default workload: the 8192 x 8192 log-normal porous channel (x periodic, walls in
-y, per-cell porosity plane with Ergun permeability and F_phi), FP32 deviation
-storage, forward stepping. Prints one JSON line with MLUPS, the HBM roofline of
-the step kernel and the FP64 CPU oracle timed on a bounded sample.
+Headline workload: the 8192 x 8192 log-normal porous channel (x periodic, walls
+in y, per-cell porosity plane with Ergun permeability and F_phi, tau = 0.8),
+FP32 deviation storage, forward stepping. One JSON line reports MLUPS, the HBM
+roofline of the step kernel, the FP64 CPU oracle timed on a bounded sample, and
+(under "extras") the other workloads: FP16-deviation storage, the 512^2 porous
+lid cavity, the 1024^2 natural-convection cavity, the ragged batch of 256
+cavities (FP32 and FP16) and the adjoint/forward time ratio of the 2048^2
+inverse problem.
 
-    python bench.py [--gpus 1] [--steps 2000] [--warmup 500]
+    python bench.py [--gpus 1] [--steps 2000] [--warmup 500] [--no-extras]
 """
 from __future__ import annotations
 
@@ -18,29 +22,39 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, published
+METRIC = "MLUPS & % of HBM roofline per collide-stream step; adjoint/forward time ratio"
+COUNTERS = os.path.join(ROOT, "profiles", "counters_step_lognormal8192_f32.json")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def time_steps(solver, steps, warmup):
+def timed(stepper, steps, warmup):
+    """Average ms per step over `steps` steps on the current stream (HIP events),
+    after `warmup` untimed steps."""
     import torch
-    solver.step(warmup)
+    stepper.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    solver.step(steps)
+    stepper.step(steps)
     e1.record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / steps  # ms per step
+    return e0.elapsed_time(e1) / steps
 
 
-def cpu_baseline(n=1024, steps=120):
-    """FP64 oracle on the same workload recipe at n x n (bounded sample)."""
+def roofline(nodes, bytes_per_node, ms):
+    achieved = nodes * bytes_per_node / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4)}
+
+
+def cpu_baseline(n=1024, steps=1500):
+    """FP64 oracle on the same workload recipe at n x n (a bounded sample)."""
     import numpy as np
     import oracle
     from paper_1311_7239_amd import inputs as I
@@ -56,10 +70,81 @@ def cpu_baseline(n=1024, steps=120):
     t0 = time.perf_counter()
     oracle.run(p, phi, K, F, f, nsteps=steps)
     dt = time.perf_counter() - t0
-    return {"value": round(case.nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": threads,
+    return {"value": round(case.nodes * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": f"{n}x{n} log-normal porous channel (same recipe), {steps} FP64 steps, "
-                      f"{dt:.1f} s"}
+            "sample": f"{n}x{n} log-normal porous channel (same recipe), {steps} FP64 steps, {dt:.1f} s"}
+
+
+def extras(args):
+    import torch
+    from paper_1311_7239_amd import inputs as I
+    from paper_1311_7239_amd import lbm
+
+    out = {}
+    n = args.n
+    # FP16-deviation storage on the headline workload
+    case = I.lognormal_channel(n=n, seed=5, K_ref=1e-6 * 2048.0 ** 2)
+    s = lbm.solver_for_case(case, storage=lbm.FP16_DEV)
+    s.set_schedule(64, 2, 2, 1)
+    ms = timed(s, args.steps, args.warmup)
+    out["fp16_lognormal_channel"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+                                     "bytes_per_node": 36, "roofline": roofline(case.nodes, 36, ms)}
+    del s
+    torch.cuda.empty_cache()
+    log("bench: 512^2 porous lid cavity")
+    case = I.lid_cavity(n=512)
+    s = lbm.solver_for_case(case)
+    s.set_graph_steps(64)
+    ms = timed(s, 20000, 2000)
+    out["cavity512"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 5),
+                        "bytes_per_node": 64, "note": "working set fits the 256 MB Infinity Cache"}
+    del s
+    log("bench: 1024^2 natural convection (D2Q8 + D2Q5)")
+    case = I.natural_convection(n=1024)
+    s = lbm.solver_for_case(case)
+    s.set_graph_steps(64)
+    ms = timed(s, 4000, 500)
+    out["convection1024"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 5),
+                             "bytes_per_node": 104, "note": "working set fits the 256 MB Infinity Cache"}
+    del s
+    torch.cuda.empty_cache()
+    for storage, name, bpn in ((lbm.FP32_DEV, "batch256_f32", 64), (lbm.FP16_DEV, "batch256_f16", 32)):
+        log(f"bench: ragged batch of 256 lid cavities ({name})")
+        cases = I.cavity_batch()
+        b = lbm.batch_for_cases(cases, storage=storage,
+                                tune_cache=os.path.join(ROOT, "gpurun_out", "tune_cache.txt")
+                                if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+        ms = timed(b, args.steps, args.warmup)
+        out[name] = {"mlups": round(b.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4), "nodes": b.nodes,
+                     "bytes_per_node": bpn, "schedule": list(b.schedule()),
+                     "roofline": roofline(b.nodes, bpn, ms)}
+        del b
+        torch.cuda.empty_cache()
+    log("bench: adjoint of the 2048^2 inverse problem (4000 steps, checkpoint every 200)")
+    case = I.lognormal_channel(n=2048, seed=5)
+    s = lbm.solver_for_case(case, ckpt_every=200, max_steps_recorded=4000)
+    f = lbm.solver_for_case(case)
+    f.step(10)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    f.step(4000)
+    e[1].record()
+    s.step(4000)
+    _, u, _ = s.macroscopic()
+    dLdu = torch.zeros_like(u)
+    dLdu[:, :, -1] = u[:, :, -1]
+    torch.cuda.synchronize()
+    e[2].record()
+    s.backward(dLdu)
+    e[3].record()
+    torch.cuda.synchronize()
+    fwd = e[0].elapsed_time(e[1])
+    bwd = e[2].elapsed_time(e[3])
+    out["adjoint2048"] = {"forward_ms": round(fwd, 2), "backward_ms": round(bwd, 2),
+                          "adjoint_forward_ratio": round(bwd / fwd, 3),
+                          "note": "backward = recomputation from checkpoints + adjoint steps"}
+    return out
 
 
 def main():
@@ -69,19 +154,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="also time the other workloads")
+    ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design note, not part of this build)",
-              file=sys.stderr)
+              "(the multi-GPU decomposition is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_1311_7239_amd import inputs as I
     from paper_1311_7239_amd import lbm
+    from paper_1311_7239_amd import profiling
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -92,17 +177,21 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     n = args.n
-    log(f"bench: generating {n}x{n} log-normal porosity field")
+    log(f"bench: generating the {n}x{n} log-normal porosity field")
     case = I.lognormal_channel(n=n, seed=5, K_ref=1e-6 * 2048.0 ** 2)
     solver = lbm.solver_for_case(case, storage=lbm.FP32_DEV)
     log(f"bench: stepping ({args.warmup} warmup + {args.steps} timed)")
-    ms = time_steps(solver, args.steps, args.warmup)
+    ms = timed(solver, args.steps, args.warmup)
     mlups = case.nodes / (ms * 1e-3) / 1e6
-    bytes_per_node = 68  # 8 FP32 loads + 8 FP32 stores + 1 FP32 porosity load
-    achieved = case.nodes * bytes_per_node / (ms * 1e-3) / 1e9
-    mass, res, st = solver.reduce()
+    bytes_per_node = 68  # 8 FP32 loads + 8 FP32 stores + the FP32 porosity load
+    rl = roofline(case.nodes, bytes_per_node, ms)
+    traffic = profiling.traffic_bytes(COUNTERS) if n == 8192 else None
+    rl["traffic"] = None if traffic is None else round(traffic / 1e9, 4)
+    rl["traffic_unit"] = "GB per launch"
+    rl["algorithmic_bytes_per_launch"] = case.nodes * bytes_per_node
+    mass, res, _ = solver.reduce()
     out = {
-        "metric": "MLUPS & % of HBM roofline per collide-stream step; adjoint/forward time ratio",
+        "metric": METRIC,
         "value": round(mlups, 1),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -114,16 +203,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"log-normal porous channel {n}x{n}: x periodic, walls in y, "
-                               "per-cell porosity (sigma 0.5, correlation 64) with Ergun K and "
+        "config": {"workload": f"log-normal porous channel {n}x{n}: x periodic, walls in y, per-cell "
+                               "porosity (log-normal, sigma 0.5, correlation 64, seed 5) with Ergun K and "
                                "F_phi, tau 0.8, FP32 deviation storage, forward steps",
                    "nodes": case.nodes, "schedule": list(solver.schedule())},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None},
-        "mass_check": {"mass": mass, "residual": res},
+        "roofline": rl,
+        "state_check": {"mass": mass, "residual": res},
     }
     del solver
     torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["extras"] = extras(args)
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline()

@@ -1,0 +1,82 @@
+"""D2Q5 thermal coupling (Appendix B, Sec. 3.4) on the GPU against the FP64 oracle, and
+the Nusselt number of Table 1."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1311_7239_amd import inputs as I
+from paper_1311_7239_amd import lbm
+from tests.gpu_cases import Pair, max_rel_velocity_error
+from tests.test_oracle_thermal_pins import nusselt_hot_wall, table1
+
+pytestmark = pytest.mark.gpu
+
+
+def conv_case(nx, ny):
+    c = I.natural_convection(n=max(nx, ny))
+    c.nx, c.ny = nx, ny
+    return c
+
+
+@pytest.mark.parametrize("nx,ny,sched", [(300, 37, None), (1100, 45, (64, 4, 1)), (1100, 45, (128, 1, 2))])
+def test_thermal_steps_match_oracle(nx, ny, sched):
+    case = conv_case(nx, ny)
+    case.gbeta *= 1e3          # make the buoyancy visible within a few steps
+    df0 = I.random_deviation_state(ny, nx, 1e-3, seed=31)
+    dg0 = I.random_deviation_state(ny, nx, 0.5, seed=32, channels=5)
+    pair = Pair(case, df0=df0, dg0=dg0)
+    if sched is not None:
+        pair.gpu.set_schedule(*sched, 1)
+    for t in (1, 4):
+        pair.step(1 if t == 1 else 3)
+        f_ref = pair.oracle_dev()
+        g_ref = np.transpose(pair.g, (2, 0, 1)) - case.T0 / 5.0
+        got_f, got_g = pair.gpu_dev()
+        assert np.abs(got_f - f_ref).max() / np.abs(f_ref).max() < 3e-6 * t
+        assert np.abs(got_g - g_ref).max() / np.abs(g_ref).max() < 3e-6 * t
+        p, u, T = pair.gpu_macro()
+        ux, uy, pr, Tr = pair.oracle_macro()
+        assert max_rel_velocity_error(u, ux, uy) < 1e-5
+        np.testing.assert_allclose(T, Tr, rtol=0, atol=2e-5)
+
+
+def test_convection_1024_matches_oracle_samples():
+    """The 1024^2 natural-convection workload (phi = 0.6, Da = 1e-4, Ra = 1e5), 2000 steps
+    from rest, against stored FP64 oracle values at 520 sampled nodes."""
+    import pathlib
+    path = pathlib.Path(__file__).parent / "golden" / "convection1024_2k.txt"
+    case = I.natural_convection(n=1024)
+    s = lbm.solver_for_case(case)
+    s.step(2000)
+    _, u, T = s.macroscopic(want_T=True)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().astype(np.float64)
+    T = T.cpu().numpy().astype(np.float64)
+    rows = np.loadtxt(path)
+    umax = float([l for l in path.read_text().splitlines() if l.startswith("# max_abs_u")][0].split()[-1])
+    x, y = rows[:, 0].astype(int), rows[:, 1].astype(int)
+    err = max(np.abs(u[0, y, x] - rows[:, 2]).max(), np.abs(u[1, y, x] - rows[:, 3]).max()) / umax
+    assert err <= 1e-5, err
+    assert np.abs(T[y, x] - rows[:, 5]).max() < 1e-4
+
+
+def test_nusselt_on_200_grid_matches_table1():
+    """Table 1 (phi = 0.6, Da = 1e-4, Ra = 1e5): Nu = 1.068 on the paper's 200^2 grid, within
+    1%, run to a steady Nusselt number from the conduction profile."""
+    n = 200
+    case = I.natural_convection(n=n)
+    s = lbm.solver_for_case(case)
+    s.set_graph_steps(200)
+    x = np.arange(n) + 0.5
+    T0 = case.Th + (case.Tc - case.Th) * x / n
+    dg = np.broadcast_to((T0 - case.T0) / 5.0, (5, n, n)).astype(np.float32).copy()
+    s.set_populations(torch.zeros((8, n, n), device="cuda"), torch.from_numpy(dg).cuda())
+    prev = None
+    for _ in range(400):
+        s.step(4000)
+        _, _, T = s.macroscopic(want_T=True)
+        nu = nusselt_hot_wall(T.cpu().numpy().astype(np.float64), case.Th, case.Tc)
+        if prev is not None and abs(nu - prev) < 1e-6:
+            break
+        prev = nu
+    assert abs(nu / table1(1e-4, 1e5, 0.6) - 1.0) < 0.01, nu
