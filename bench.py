@@ -82,6 +82,22 @@ def extras(args):
 
     out = {}
     n = args.n
+    # reference: the runtime's own device-to-device copy of 2 GiB (read + write)
+    src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    ms = c0.elapsed_time(c1) / 10
+    out["copy_reference"] = {"gbs": round(2 * src.numel() * 4 / (ms * 1e-3) / 1e9, 1),
+                             "what": "device-to-device copy of 2 GiB (runtime copy kernel), read + write"}
+    del src, dst
+    torch.cuda.empty_cache()
     # FP16-deviation storage on the headline workload
     case = I.lognormal_channel(n=n, seed=5, K_ref=1e-6 * 2048.0 ** 2)
     s = lbm.solver_for_case(case, storage=lbm.FP16_DEV)

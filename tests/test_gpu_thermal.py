@@ -79,4 +79,5 @@ def test_nusselt_on_200_grid_matches_table1():
         if prev is not None and abs(nu - prev) < 1e-6:
             break
         prev = nu
+    print(f"Nu on 200^2 after {s.time} steps: {nu:.5f} (Table 1: 1.068)")
     assert abs(nu / table1(1e-4, 1e5, 0.6) - 1.0) < 0.01, nu
