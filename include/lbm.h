@@ -209,6 +209,16 @@ int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows,
  * autotuned). */
 int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int32_t swizzle);
 
+/* Cycles per HBM pass of a single-domain isothermal context: 1, or 2
+ * (temporal blocking: one launch gathers, collides on its tile plus a
+ * one-node ring kept in LDS, then collides again, so each population crosses
+ * HBM about once per two cycles). Results are bitwise identical either way.
+ * Two-cycle passes are skipped for t = 0, while recording for lbm_backward,
+ * and for the last cycle of each lbm_step call (so lbm_reduce's residual
+ * always compares u(t) with u(t-1)). Default: 2 for FP32 isothermal single
+ * domains, 1 otherwise. ENOTSUP on batches, EINVAL otherwise. */
+int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
+
 /* Number of steps lbm_step replays from one hand-built HIP graph of kernel
  * nodes (an even number up to 4096; 0 launches every step separately).
  * Defaults: 0 for single domains, 32 for batches. Graphs are not used while

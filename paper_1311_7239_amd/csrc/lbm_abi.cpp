@@ -205,6 +205,8 @@ struct lbm_ctx {
     // one executable graph per starting buffer parity
     int graph_steps = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    // cycles per HBM pass of a single-domain isothermal context (1 or 2)
+    int tblock = 1;
 };
 
 namespace {
@@ -290,6 +292,9 @@ hipError_t checkpoint(lbm_ctx *c) {
 
 namespace {
 
+// cycles advanced by one kernel node of the step graph
+int graph_node_steps(const lbm_ctx *c) { return (!c->batch && c->tblock == 2) ? 2 : 1; }
+
 void reset_graphs(lbm_ctx *c) {
     for (auto &g : c->gexec) {
         if (g) (void)hipGraphExecDestroy(g);
@@ -305,7 +310,8 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
     hipError_t e = hipGraphCreate(&g, 0);
     if (e != hipSuccess) return e;
     hipGraphNode_t prev = nullptr;
-    for (int k = 0; k < c->graph_steps && e == hipSuccess; ++k) {
+    const int nodes = c->graph_steps / graph_node_steps(c);
+    for (int k = 0; k < nodes && e == hipSuccess; ++k) {
         int p = parity ^ (k & 1);
         hipKernelNodeParams kp;
         std::memset(&kp, 0, sizeof(kp));
@@ -318,6 +324,13 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
             kp.func = (void *)batch_kernel_fn(c->storage, c->sched);
             kp.gridDim = dim3((unsigned)c->grid);
             kp.kernelParams = args_b;
+        } else if (c->tblock == 2) {
+            Domain &D = c->dom[0];
+            d = dom_for(D, p);
+            step2_tiles(D.desc.nx, D.desc.ny, &tx, &ty);
+            kp.func = (void *)step2_kernel_fn(D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32);
+            kp.gridDim = dim3((unsigned)(tx * ty));
+            kp.kernelParams = args_s;
         } else {
             Domain &D = c->dom[0];
             d = dom_for(D, p);
@@ -404,6 +417,8 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     if (rc) { delete c; return rc; }
     D.L = L;
     c->rec_cap = cap;
+    c->tblock = (d->storage == LBM_FP32_DEV && !d->thermal.enabled) ? 2 : 1;
+    if (d->storage == LBM_FP16_DEV) c->sched = Schedule{64, 2, 2, 1};
     hipError_t e = init_domain(D, 0, phi, kappa, c->stream);
     if (e != hipSuccess) {
         rc = fail(LBM_EDEVICE, "initialisation: %s", hipGetErrorString(e));
@@ -441,14 +456,29 @@ int lbm_step(lbm_ctx *c, int64_t n) {
             continue;
         }
         const bool recording = c->rec_valid && c->dom[0].desc.ckpt_every > 0;
-        if (c->graph_steps > 0 && n >= c->graph_steps && !recording) {
+        // two cycles per pass while at least one single cycle remains for the end of
+        // this call (so the previous buffer always holds f+(t-2) -> u(t-1) for the residual)
+        const bool fused = !c->batch && c->tblock == 2 && !recording && !c->dom[0].desc.thermal.enabled;
+        if (c->graph_steps > 0 && !recording && n - (fused ? 1 : 0) >= c->graph_steps) {
             if (!c->gexec[c->cur]) {
                 if ((e = build_graph(c, c->cur)) != hipSuccess) return device_fail(c, e, "graph build");
             }
             if ((e = hipGraphLaunch(c->gexec[c->cur], c->stream)) != hipSuccess)
                 return device_fail(c, e, "graph launch");
-            c->t += c->graph_steps;  // graph_steps is even: parity unchanged
+            const int nodes = c->graph_steps / graph_node_steps(c);
+            c->cur ^= (nodes & 1);
+            c->t += c->graph_steps;
             n -= c->graph_steps;
+            continue;
+        }
+        if (fused && n >= 3) {
+            Domain &D = c->dom[0];
+            e = launch_step2(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
+                             c->sched.swizzle, c->stream);
+            if (e != hipSuccess) return device_fail(c, e, "step launch");
+            c->cur ^= 1;
+            c->t += 2;
+            n -= 2;
             continue;
         }
         if (c->batch) {
@@ -677,6 +707,16 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
     if (!schedule_supported(s))
         return fail(LBM_EINVAL, "unsupported schedule %d x %d x %d", tile_w, vec, rows);
     c->sched = s;
+    reset_graphs(c);
+    return LBM_OK;
+}
+
+int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (cycles_per_pass != 1 && cycles_per_pass != 2) return fail(LBM_EINVAL, "cycles per pass must be 1 or 2");
+    if (c->batch && cycles_per_pass != 1) return fail(LBM_ENOTSUP, "batches advance one cycle per pass");
+    c->tblock = cycles_per_pass;
     reset_graphs(c);
     return LBM_OK;
 }

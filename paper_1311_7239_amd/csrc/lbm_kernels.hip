@@ -285,6 +285,115 @@ hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int
     return launch_batch_t<_Float16>(doms, tiles, ntiles, parity, s, grid, st);
 }
 
+// ------------------------------------------------- two steps per pass
+
+// Temporal blocking: one launch advances t -> t + 2 with a single HBM pass.
+// A workgroup owns a TW x TH output tile. Phase A gathers f(t) (from the
+// post-collision state s_t in HBM) and collides on the tile plus a one-node
+// ring, keeping s_{t+1} in LDS; phase B gathers f(t+1) from LDS (periodic
+// neighbours are in the ring, walls bounce back), collides, and stores
+// s_{t+2}. Per output node the pass reads (TW+2)(TH+2)/(TW TH) populations and
+// writes one, instead of reading and writing one per step. Every node runs
+// the same per-node code as the one-step kernel, and FP16 storage rounds the
+// intermediate state exactly as a store/reload would, so the result is
+// bitwise that of two one-step launches.
+template <typename S, int TW, int TH>
+__global__ __launch_bounds__(BLOCK) void k_step2(Dom d, int tiles_x, int swz) {
+    constexpr int EW = TW + 2, EH = TH + 2, EN = EW * EH;
+    __shared__ float lds[8][EH][EW];
+    int b = blockIdx.x;
+    if (swz) b = xcd_swizzle(b, gridDim.x);
+    const int x0 = (b % tiles_x) * TW, y0 = (b / tiles_x) * TH;
+    const S *__restrict__ fin = (const S *)d.fin;
+    S *__restrict__ fout = (S *)d.fout;
+    // every source of phase A inside the domain, no wrap needed
+    const bool interior = x0 >= 2 && x0 + TW + 2 <= d.nx && y0 >= 2 && y0 + TH + 2 <= d.ny;
+
+    // phase A: s_{t+1} on the extended tile
+    for (int e = threadIdx.x; e < EN; e += BLOCK) {
+        const int ex = e % EW, ey = e / EW;
+        int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        float f[8];
+        if (interior) {
+            gather_interior<S>(d, fin, gx, gy, f);
+        } else {
+            if (gx < 0 || gx >= d.nx) {
+                if (d.bc_x != BC_PERIODIC) continue;
+                gx = ((gx % d.nx) + d.nx) % d.nx;
+            }
+            if (gy < 0 || gy >= d.ny) {
+                if (d.bc_y != BC_PERIODIC) continue;
+                gy = ((gy % d.ny) + d.ny) % d.ny;
+            }
+            gather_general<S>(d, fin, gx, gy, f);
+        }
+        const Cell c = load_cell(d, (int64_t)gy * d.pitch + gx);
+        float ux, uy;
+        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[i][ey][ex] = (float)(S)f[i];
+    }
+    __syncthreads();
+
+    // phase B: s_{t+2} on the tile
+    for (int q = threadIdx.x; q < TW * TH; q += BLOCK) {
+        const int lx = q % TW, ly = q / TW;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= d.nx || gy >= d.ny) continue;
+        // one LDS read per link at a selected index (the neighbour's value, or the
+        // node's own opposite value across a wall); written as an index select
+        // rather than two guarded reads, a form the compiler got wrong here
+        float f[8];
+        const float *flat = &lds[0][0][0];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            bool out = false, top = false;
+            if (!interior) {
+                const int sx = gx - EX[i], sy = gy - EY[i];
+                if (EX[i] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) out = true;
+                if (EY[i] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) {
+                    out = true;
+                    top = (sy >= d.ny);
+                }
+            }
+            const int src = out ? (OPP[i] * EH + ly + 1) * EW + lx + 1
+                                : (i * EH + ly + 1 - EY[i]) * EW + lx + 1 - EX[i];
+            const float v = flat[src];
+            f[i] = top ? v + (float)EX[i] * d.lid6 : v;
+        }
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = load_cell(d, o);
+        float ux, uy;
+        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Store<S>::st(fout + i * d.plane + o, f[i]);
+    }
+}
+
+constexpr int STEP2_TW = 64, STEP2_TH = 16;
+
+void step2_tiles(int nx, int ny, int *tiles_x, int *tiles_y) {
+    *tiles_x = (nx + STEP2_TW - 1) / STEP2_TW;
+    *tiles_y = (ny + STEP2_TH - 1) / STEP2_TH;
+}
+
+hipError_t launch_step2(const Dom &d, int storage, int swizzle, hipStream_t st) {
+    if (d.thermal) return hipErrorInvalidValue;
+    int tx, ty;
+    step2_tiles(d.nx, d.ny, &tx, &ty);
+    const dim3 grid((unsigned)(tx * ty)), block(BLOCK);
+    if (storage == ST_F32)
+        hipLaunchKernelGGL((k_step2<float, STEP2_TW, STEP2_TH>), grid, block, 0, st, d, tx, swizzle);
+    else
+        hipLaunchKernelGGL((k_step2<_Float16, STEP2_TW, STEP2_TH>), grid, block, 0, st, d, tx, swizzle);
+    return hipGetLastError();
+}
+
+const void *step2_kernel_fn(int storage) {
+    return storage == ST_F32 ? (const void *)&k_step2<float, STEP2_TW, STEP2_TH>
+                             : (const void *)&k_step2<_Float16, STEP2_TW, STEP2_TH>;
+}
+
 // --------------------------------------------------------- node readers
 
 // f(t) (and g(t)) of node (x, y) from a state buffer in the given layout.

@@ -32,6 +32,13 @@ bool schedule_supported(const Schedule &s);
 hipError_t launch_step(const Dom &d, int storage, Source src, bool rec, const Schedule &s,
                        hipStream_t st);
 
+// Two cycles in one pass (temporal blocking): reads s_t from d.fin, writes
+// s_{t+2} to d.fout; isothermal, gather layout only. Arguments of the kernel
+// entry: (Dom, int tiles_x, int swizzle).
+hipError_t launch_step2(const Dom &d, int storage, int swizzle, hipStream_t st);
+void step2_tiles(int nx, int ny, int *tiles_x, int *tiles_y);
+const void *step2_kernel_fn(int storage);
+
 // Persistent batched step over a tile table: doms[2*k + parity] describes
 // domain k with its buffers for this parity; tiles[j] = (domain, tx, ty, 0).
 hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity,

@@ -87,6 +87,7 @@ def lib():
         L.lbm_set_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32]
         L.lbm_set_graph_steps.argtypes = [_vp, ctypes.c_int32]
+        L.lbm_set_time_blocking.argtypes = [_vp, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -239,6 +240,9 @@ class Solver:
 
     def set_graph_steps(self, steps: int):
         check(lib().lbm_set_graph_steps(self._ctx, int(steps)))
+
+    def set_time_blocking(self, cycles_per_pass: int):
+        check(lib().lbm_set_time_blocking(self._ctx, int(cycles_per_pass)))
 
     def schedule(self):
         a, v, b, c = (ctypes.c_int32() for _ in range(4))

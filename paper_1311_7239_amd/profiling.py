@@ -52,7 +52,7 @@ def _per_kernel(rows, counter):
     return out
 
 
-def counters_summary(fetch_csv, write_csv, out_json, command, kernel_prefix="void mrt::k_step<"):
+def counters_summary(fetch_csv, write_csv, out_json, command, kernel_prefix="void mrt::k_step"):
     fetch = _per_kernel(_rows(fetch_csv), "FETCH_SIZE")
     write = _per_kernel(_rows(write_csv), "WRITE_SIZE")
     copy_f = max(fetch.get("__amd_rocclr_copyBuffer", [0.0]))
@@ -62,7 +62,7 @@ def counters_summary(fetch_csv, write_csv, out_json, command, kernel_prefix="voi
     wscale = gib_kib / copy_w if copy_w > 0 else None
     kernels = {}
     for name, vals in fetch.items():
-        if not name.startswith(kernel_prefix) or ", 0, false" not in name:
+        if not name.startswith(kernel_prefix) or "k_step_batch" in name:
             continue
         w = write.get(name, [])
         kernels[name] = {"dispatches": len(vals), "fetch_kib": sum(vals) / len(vals),

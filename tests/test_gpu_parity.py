@@ -121,6 +121,7 @@ def test_every_schedule_gives_the_same_bits(kind, medium, storage):
     for sch in SCHEDULES:
         for swz in (0, 1):
             s = lbm.solver_for_case(case, storage=storage)
+            s.set_time_blocking(1)
             s.set_schedule(*sch, swz)
             s.set_populations(torch.from_numpy(df0).cuda())
             s.step(4)
