@@ -215,9 +215,16 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * HBM about once per two cycles). Results are bitwise identical either way.
  * Two-cycle passes are skipped for t = 0, while recording for lbm_backward,
  * and for the last cycle of each lbm_step call (so lbm_reduce's residual
- * always compares u(t) with u(t-1)). Default: 2 for FP32 isothermal single
- * domains, 1 otherwise. ENOTSUP on batches, EINVAL otherwise. */
+ * always compares u(t) with u(t-1)). The recomputation inside lbm_backward
+ * also uses two-cycle passes (recording u at both cycles). Default: 2 for
+ * isothermal single domains of at least 2^21 nodes, 1 otherwise.
+ * ENOTSUP on batches, EINVAL otherwise. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
+
+/* Workgroup shape of the two-cycle kernel: threads in {256, 512} and tile
+ * rows in {8, 16} (tiles are 64 nodes wide). Results do not depend on it.
+ * Default 512 threads, 16 rows. */
+int lbm_set_two_cycle_tile(lbm_ctx *c, int32_t threads, int32_t rows);
 
 /* Number of steps lbm_step replays from one hand-built HIP graph of kernel
  * nodes (an even number up to 4096; 0 launches every step separately).

@@ -205,8 +205,11 @@ struct lbm_ctx {
     // one executable graph per starting buffer parity
     int graph_steps = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    // cycles per HBM pass of a single-domain isothermal context (1 or 2)
+    // cycles per HBM pass of a single-domain isothermal context (1 or 2), and
+    // the two-cycle kernel's workgroup size and tile rows
     int tblock = 1;
+    int tb_threads = 512;
+    int tb_rows = 16;
 };
 
 namespace {
@@ -320,6 +323,8 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         int tx = 0, ty = 0, swz = c->sched.swizzle;
         void *args_b[4] = {&c->d_doms, &c->d_tiles, &c->ntiles, &p};
         void *args_s[3] = {&d, &tx, &swz};
+        float *no_rec = nullptr;
+        void *args_s2[4] = {&d, &tx, &swz, &no_rec};
         if (c->batch) {
             kp.func = (void *)batch_kernel_fn(c->storage, c->sched);
             kp.gridDim = dim3((unsigned)c->grid);
@@ -327,10 +332,12 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         } else if (c->tblock == 2) {
             Domain &D = c->dom[0];
             d = dom_for(D, p);
-            step2_tiles(D.desc.nx, D.desc.ny, &tx, &ty);
-            kp.func = (void *)step2_kernel_fn(D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32);
+            step2_tiles(D.desc.nx, D.desc.ny, c->tb_rows, &tx, &ty);
+            kp.func = (void *)step2_kernel_fn(D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, c->tb_threads,
+                                              c->tb_rows, false);
             kp.gridDim = dim3((unsigned)(tx * ty));
-            kp.kernelParams = args_s;
+            kp.blockDim = dim3((unsigned)c->tb_threads);
+            kp.kernelParams = args_s2;
         } else {
             Domain &D = c->dom[0];
             d = dom_for(D, p);
@@ -417,7 +424,8 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     if (rc) { delete c; return rc; }
     D.L = L;
     c->rec_cap = cap;
-    c->tblock = (d->storage == LBM_FP32_DEV && !d->thermal.enabled) ? 2 : 1;
+    // two cycles per pass pays once the domain fills the GPU several times over
+    c->tblock = (!d->thermal.enabled && (int64_t)d->nx * d->ny >= ((int64_t)1 << 21)) ? 2 : 1;
     if (d->storage == LBM_FP16_DEV) c->sched = Schedule{64, 2, 2, 1};
     hipError_t e = init_domain(D, 0, phi, kappa, c->stream);
     if (e != hipSuccess) {
@@ -474,7 +482,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         if (fused && n >= 3) {
             Domain &D = c->dom[0];
             e = launch_step2(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
-                             c->sched.swizzle, c->stream);
+                             c->sched.swizzle, c->tb_threads, c->tb_rows, nullptr, c->stream);
             if (e != hipSuccess) return device_fail(c, e, "step launch");
             c->cur ^= 1;
             c->t += 2;
@@ -717,6 +725,17 @@ int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
     if (cycles_per_pass != 1 && cycles_per_pass != 2) return fail(LBM_EINVAL, "cycles per pass must be 1 or 2");
     if (c->batch && cycles_per_pass != 1) return fail(LBM_ENOTSUP, "batches advance one cycle per pass");
     c->tblock = cycles_per_pass;
+    reset_graphs(c);
+    return LBM_OK;
+}
+
+int lbm_set_two_cycle_tile(lbm_ctx *c, int32_t threads, int32_t rows) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!step2_shape_supported(threads, rows))
+        return fail(LBM_EINVAL, "unsupported two-cycle tile: %d threads, %d rows", threads, rows);
+    c->tb_threads = threads;
+    c->tb_rows = rows;
     reset_graphs(c);
     return LBM_OK;
 }
@@ -997,12 +1016,20 @@ extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, floa
                                L.f_bytes, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return device_fail(c, e, "checkpoint restore");
             int p = 0;
-            for (int64_t t = s0; t < s1; ++t) {
+            for (int64_t t = s0; t < s1;) {
                 Dom dr = D.dom;
                 dr.fin = D.base + L.off_rf[p];
                 dr.fout = D.base + L.off_rf[p ^ 1];
                 dr.urec = urec + (size_t)(t - s0) * 2 * (size_t)L.plane;
-                e = launch_step(dr, ST_F32, t == 0 ? SRC_DIRECT : SRC_GATHER, true, c->sched, st);
+                if (c->tblock == 2 && t > 0 && t + 1 < s1) {
+                    // two cycles in one pass, recording u(t) and u(t + 1)
+                    e = launch_step2(dr, ST_F32, c->sched.swizzle, c->tb_threads, c->tb_rows,
+                                     dr.urec + 2 * (size_t)L.plane, st);
+                    t += 2;
+                } else {
+                    e = launch_step(dr, ST_F32, t == 0 ? SRC_DIRECT : SRC_GATHER, true, c->sched, st);
+                    t += 1;
+                }
                 if (e != hipSuccess) return device_fail(c, e, "recompute step");
                 p ^= 1;
             }

@@ -74,10 +74,10 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
     const float pmq = p57 - q68, ppq = p57 + q68;
     const float P1 = 0.125f * ((A1 + B1) + (C1 + D1));
     const float P2 = 0.125f * ((C1 + D1) - (A1 + B1));
-    const float P3 = (x13 + pmq) * (1.0f / 6.0f);
-    const float P4 = (pmq - 2.0f * x13) * (1.0f / 12.0f);
-    const float P5 = (y24 + ppq) * (1.0f / 6.0f);
-    const float P6 = (ppq - 2.0f * y24) * (1.0f / 12.0f);
+    const float P3 = mulc(x13 + pmq, MRT_C1_6);
+    const float P4 = mulc(pmq - 2.0f * x13, MRT_C1_12);
+    const float P5 = mulc(y24 + ppq, MRT_C1_6);
+    const float P6 = mulc(ppq - 2.0f * y24, MRT_C1_12);
     const float P7 = 0.25f * (A1 - B1);
     const float P8 = 0.25f * (C1 - D1);
 

@@ -59,6 +59,29 @@ struct Dom {
     float *urec;                     // optional u(t) record: 2 planes
 };
 
+// Square root and reciprocal by the hardware instructions (v_sqrt_f32,
+// v_rcp_f32, about 1 ulp) instead of the correctly rounded library sequences
+// (a dozen instructions each). They only enter drag coefficients, |u| and
+// the velocity-recovery ratio, where an ulp is far below the FP32 noise of
+// the populations, and they carry no systematic gain on a conserved moment.
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// x * (p/q) for the rational constants of the transforms (1/6, 1/12, 3/5, ...),
+// rounded once: the constant is split into its nearest float hi plus the float
+// lo of the remainder, and x*hi + x*lo goes through one fused multiply-add.
+// A bare x * float(1/6) is 3e-8 too large every time; through the
+// back-transform and the next moment sum the momentum would gain that factor
+// every step and settle ~1e-4 off in slowly relaxing flows.
+__device__ __forceinline__ float mulc(float x, float hi, float lo) { return fmaf(x, hi, x * lo); }
+#define MRT_C1_6 0x1.555556p-3f, -0x1.555556p-28f
+#define MRT_C1_12 0x1.555556p-4f, -0x1.555556p-29f
+#define MRT_C3_5 0x1.333334p-1f, -0x1.99999ap-26f
+#define MRT_C2_5 0x1.99999ap-2f, -0x1.99999ap-28f
+#define MRT_C4_5 0x1.99999ap-1f, -0x1.99999ap-27f
+#define MRT_C1_5 0x1.99999ap-3f, -0x1.99999ap-29f
+#define MRT_C1_20 0x1.99999ap-5f, -0x1.99999ap-31f
+
 // Per-cell quantities of Eqs. (3), (4) and (19).
 struct Cell {
     float phi, inv_phi;
@@ -68,7 +91,7 @@ struct Cell {
 
 // Ergun's F_phi (Eq. 4): 1.75 / sqrt(150 phi^3) = (1.75/sqrt(150)) phi^{-3/2}.
 __device__ __forceinline__ float ergun_F(float inv_phi) {
-    return 0.14288690166235206f * inv_phi * sqrtf(inv_phi);
+    return 0.14288690166235206f * inv_phi * hw_sqrt(inv_phi);
 }
 
 // Per-cell drag coefficients from the porosity (and 1/K when it has its own
@@ -79,7 +102,7 @@ __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_p
         c.phi = d.phi0; c.inv_phi = d.inv_phi0; c.cd = d.cd0; c.cf = d.cf0;
         return c;
     }
-    const float ip = 1.0f / phi;
+    const float ip = hw_rcp(phi);
     float kappa;
     if (d.medium == MED_PHI_ERGUN) {
         const float om = 1.0f - phi;
@@ -90,7 +113,7 @@ __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_p
     const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
     c.phi = phi; c.inv_phi = ip;
     c.cd = phi * d.nu * kappa;
-    c.cf = phi * F * sqrtf(kappa);
+    c.cf = phi * F * hw_sqrt(kappa);
     return c;
 }
 
@@ -109,11 +132,11 @@ __device__ __forceinline__ void velocity(const Cell &c, float vx, float vy, floa
     const float dd = 0.5f * c.cd;
     const float l1 = 0.5f * c.cf;
     const float l0 = 0.5f * (1.0f + dd);
-    const float vmag = sqrtf(vx * vx + vy * vy);
+    const float vmag = hw_sqrt(vx * vx + vy * vy);
     const float t = l1 * vmag;
-    const float delta = t / (l0 + sqrtf(l0 * l0 + t));
+    const float delta = t * hw_rcp(l0 + hw_sqrt(l0 * l0 + t));
     const float qn = dd + delta;
-    const float q = qn / (1.0f + qn);
+    const float q = qn * hw_rcp(1.0f + qn);
     ux = vx - vx * q;
     uy = vy - vy * q;
 }
@@ -157,7 +180,7 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
 
     // velocity (Eqs. 18-19) and total force (Eq. 3)
     velocity(c, m3 + 0.5f * pax, m5 + 0.5f * pay, ux, uy);
-    const float umag = sqrtf(ux * ux + uy * uy);
+    const float umag = hw_sqrt(ux * ux + uy * uy);
     const float drag = c.cd + c.cf * umag;
     const float Fx = pax - drag * ux;
     const float Fy = pay - drag * uy;
@@ -167,7 +190,8 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
     const float u2 = ux * ux + uy * uy;
     const float uF = ux * Fx + uy * Fy;
     // e - e^eq = dm2 + (3/5) dm1 - (2/5)|u|^2/phi  (Pi from Eq. 20, alpha2 = -1, gamma2 = 0)
-    const float m2p = m2 - d.s_e * (m2 + 0.6f * m1 - 0.4f * u2 * ip) + d.h_e * (0.8f * uF * ip);
+    const float m2p = m2 - d.s_e * (m2 + mulc(m1, MRT_C3_5) - mulc(u2 * ip, MRT_C2_5)) +
+                      d.h_e * mulc(uF * ip, MRT_C4_5);
     // s1 = s3 = s5 = 1: m1+ = m1, j+ = rho0 u + F/2
     const float m3p = ux + 0.5f * Fx;
     const float m5p = uy + 0.5f * Fy;
@@ -181,8 +205,8 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
 
     // f+ = M^T diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m+
     const float A = 0.125f * m1, B = 0.125f * m2p;
-    const float X = m3p * (1.0f / 6.0f), Qx = m4p * (1.0f / 12.0f);
-    const float Y = m5p * (1.0f / 6.0f), Qy = m6p * (1.0f / 12.0f);
+    const float X = mulc(m3p, MRT_C1_6), Qx = mulc(m4p, MRT_C1_12);
+    const float Y = mulc(m5p, MRT_C1_6), Qy = mulc(m6p, MRT_C1_12);
     const float P = 0.25f * m7p, R = 0.25f * m8p;
     const float amb = A - B, apb = A + B;
     const float xa = X - 2.0f * Qx, ya = Y - 2.0f * Qy;
@@ -213,7 +237,7 @@ __device__ __forceinline__ void thermal_collide(float g[5], const Dom &d, float 
     const float n3p = n3 - d.z3 * n3;
     const float n4p = n4 - d.z4 * n4;
     // g+ = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4) n+
-    const float a0 = 0.2f * n0, a1 = 0.5f * n1p, a2 = 0.5f * n2p, a3 = 0.05f * n3p,
+    const float a0 = mulc(n0, MRT_C1_5), a1 = 0.5f * n1p, a2 = 0.5f * n2p, a3 = mulc(n3p, MRT_C1_20),
                 a4 = 0.25f * n4p;
     g[0] = a0 - 4.0f * a3;
     g[1] = (a0 + a3) + (a1 + a4);

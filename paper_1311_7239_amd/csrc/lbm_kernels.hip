@@ -297,8 +297,8 @@ hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int
 // the same per-node code as the one-step kernel, and FP16 storage rounds the
 // intermediate state exactly as a store/reload would, so the result is
 // bitwise that of two one-step launches.
-template <typename S, int TW, int TH>
-__global__ __launch_bounds__(BLOCK) void k_step2(Dom d, int tiles_x, int swz) {
+template <typename S, int TW, int TH, int NT, bool REC>
+__global__ __launch_bounds__(NT) void k_step2(Dom d, int tiles_x, int swz, float *urec_next) {
     constexpr int EW = TW + 2, EH = TH + 2, EN = EW * EH;
     __shared__ float lds[8][EH][EW];
     int b = blockIdx.x;
@@ -309,8 +309,8 @@ __global__ __launch_bounds__(BLOCK) void k_step2(Dom d, int tiles_x, int swz) {
     // every source of phase A inside the domain, no wrap needed
     const bool interior = x0 >= 2 && x0 + TW + 2 <= d.nx && y0 >= 2 && y0 + TH + 2 <= d.ny;
 
-    // phase A: s_{t+1} on the extended tile
-    for (int e = threadIdx.x; e < EN; e += BLOCK) {
+    // phase A: s_{t+1} on the extended tile (and u(t) on the tile when recording)
+    for (int e = threadIdx.x; e < EN; e += NT) {
         const int ex = e % EW, ey = e / EW;
         int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
         float f[8];
@@ -327,16 +327,22 @@ __global__ __launch_bounds__(BLOCK) void k_step2(Dom d, int tiles_x, int swz) {
             }
             gather_general<S>(d, fin, gx, gy, f);
         }
-        const Cell c = load_cell(d, (int64_t)gy * d.pitch + gx);
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = load_cell(d, o);
         float ux, uy;
         collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy);
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[i][ey][ex] = (float)(S)f[i];
+        if (REC && ex >= 1 && ex <= TW && ey >= 1 && ey <= TH && x0 - 1 + ex < d.nx &&
+            y0 - 1 + ey < d.ny) {
+            d.urec[o] = ux;
+            d.urec[d.plane + o] = uy;
+        }
     }
     __syncthreads();
 
-    // phase B: s_{t+2} on the tile
-    for (int q = threadIdx.x; q < TW * TH; q += BLOCK) {
+    // phase B: s_{t+2} on the tile (and u(t+1) when recording)
+    for (int q = threadIdx.x; q < TW * TH; q += NT) {
         const int lx = q % TW, ly = q / TW;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= d.nx || gy >= d.ny) continue;
@@ -367,31 +373,55 @@ __global__ __launch_bounds__(BLOCK) void k_step2(Dom d, int tiles_x, int swz) {
         collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy);
 #pragma unroll
         for (int i = 0; i < 8; ++i) Store<S>::st(fout + i * d.plane + o, f[i]);
+        if (REC) {
+            urec_next[o] = ux;
+            urec_next[d.plane + o] = uy;
+        }
     }
 }
 
-constexpr int STEP2_TW = 64, STEP2_TH = 16;
+constexpr int STEP2_TW = 64;
 
-void step2_tiles(int nx, int ny, int *tiles_x, int *tiles_y) {
+// Compiled two-cycle tiles: (threads per workgroup, tile rows); tiles are 64 wide.
+#define MRT_STEP2_SHAPES(X) X(256, 16) X(512, 16) X(256, 8) X(512, 8)
+
+bool step2_shape_supported(int threads, int rows) {
+#define MRT_S2SUP(N, H) if (threads == N && rows == H) return true;
+    MRT_STEP2_SHAPES(MRT_S2SUP)
+#undef MRT_S2SUP
+    return false;
+}
+
+void step2_tiles(int nx, int ny, int rows, int *tiles_x, int *tiles_y) {
     *tiles_x = (nx + STEP2_TW - 1) / STEP2_TW;
-    *tiles_y = (ny + STEP2_TH - 1) / STEP2_TH;
+    *tiles_y = (ny + rows - 1) / rows;
 }
 
-hipError_t launch_step2(const Dom &d, int storage, int swizzle, hipStream_t st) {
+template <typename S, bool REC>
+static const void *step2_fn_t(int threads, int rows) {
+#define MRT_S2FN(N, H) if (threads == N && rows == H) return (const void *)&k_step2<S, STEP2_TW, H, N, REC>;
+    MRT_STEP2_SHAPES(MRT_S2FN)
+#undef MRT_S2FN
+    return nullptr;
+}
+
+const void *step2_kernel_fn(int storage, int threads, int rows, bool rec) {
+    if (storage == ST_F32) return rec ? step2_fn_t<float, true>(threads, rows) : step2_fn_t<float, false>(threads, rows);
+    return rec ? nullptr : step2_fn_t<_Float16, false>(threads, rows);
+}
+
+hipError_t launch_step2(const Dom &d, int storage, int swizzle, int threads, int rows,
+                        float *urec_next, hipStream_t st) {
     if (d.thermal) return hipErrorInvalidValue;
+    const bool rec = urec_next != nullptr;
+    const void *fn = step2_kernel_fn(storage, threads, rows, rec);
+    if (!fn || (rec && !d.urec)) return hipErrorInvalidValue;
     int tx, ty;
-    step2_tiles(d.nx, d.ny, &tx, &ty);
-    const dim3 grid((unsigned)(tx * ty)), block(BLOCK);
-    if (storage == ST_F32)
-        hipLaunchKernelGGL((k_step2<float, STEP2_TW, STEP2_TH>), grid, block, 0, st, d, tx, swizzle);
-    else
-        hipLaunchKernelGGL((k_step2<_Float16, STEP2_TW, STEP2_TH>), grid, block, 0, st, d, tx, swizzle);
-    return hipGetLastError();
-}
-
-const void *step2_kernel_fn(int storage) {
-    return storage == ST_F32 ? (const void *)&k_step2<float, STEP2_TW, STEP2_TH>
-                             : (const void *)&k_step2<_Float16, STEP2_TW, STEP2_TH>;
+    step2_tiles(d.nx, d.ny, rows, &tx, &ty);
+    Dom dd = d;
+    int swz = swizzle;
+    void *args[4] = {&dd, &tx, &swz, &urec_next};
+    return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3((unsigned)threads), args, 0, st);
 }
 
 // --------------------------------------------------------- node readers
@@ -440,7 +470,7 @@ __global__ __launch_bounds__(BLOCK) void k_macro(Dom d, int src, float Pi0, floa
     if (p) {
         // Eq. (20): phi p = (3/5)(m1 - (2/3)|u|^2/phi), m1 = (5/3) Pi0 + dm1
         const Cell c = load_cell(d, o);
-        const float Pi = Pi0 + (0.6f * m1 - 0.4f * (u * u + v * v) * c.inv_phi);
+        const float Pi = Pi0 + (mulc(m1, MRT_C3_5) - mulc((u * u + v * v) * c.inv_phi, MRT_C2_5));
         p[q] = Pi * c.inv_phi;
     }
     if (T) T[q] = d.T0 + dT;

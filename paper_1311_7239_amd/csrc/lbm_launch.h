@@ -33,11 +33,15 @@ hipError_t launch_step(const Dom &d, int storage, Source src, bool rec, const Sc
                        hipStream_t st);
 
 // Two cycles in one pass (temporal blocking): reads s_t from d.fin, writes
-// s_{t+2} to d.fout; isothermal, gather layout only. Arguments of the kernel
-// entry: (Dom, int tiles_x, int swizzle).
-hipError_t launch_step2(const Dom &d, int storage, int swizzle, hipStream_t st);
-void step2_tiles(int nx, int ny, int *tiles_x, int *tiles_y);
-const void *step2_kernel_fn(int storage);
+// s_{t+2} to d.fout; isothermal, gather layout only. With urec_next non-null
+// (FP32 only) it also records u(t) into d.urec and u(t+1) into urec_next.
+// Tiles are 64 wide and `rows` tall, run by `threads` threads. Kernel entry
+// arguments: (Dom, int tiles_x, int swizzle, float *urec_next).
+hipError_t launch_step2(const Dom &d, int storage, int swizzle, int threads, int rows,
+                        float *urec_next, hipStream_t st);
+bool step2_shape_supported(int threads, int rows);
+void step2_tiles(int nx, int ny, int rows, int *tiles_x, int *tiles_y);
+const void *step2_kernel_fn(int storage, int threads, int rows, bool rec);
 
 // Persistent batched step over a tile table: doms[2*k + parity] describes
 // domain k with its buffers for this parity; tiles[j] = (domain, tx, ty, 0).

@@ -88,6 +88,7 @@ def lib():
                                        ctypes.c_int32]
         L.lbm_set_graph_steps.argtypes = [_vp, ctypes.c_int32]
         L.lbm_set_time_blocking.argtypes = [_vp, ctypes.c_int32]
+        L.lbm_set_two_cycle_tile.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
         _lib = L
     return _lib
 
@@ -243,6 +244,9 @@ class Solver:
 
     def set_time_blocking(self, cycles_per_pass: int):
         check(lib().lbm_set_time_blocking(self._ctx, int(cycles_per_pass)))
+
+    def set_two_cycle_tile(self, threads: int, rows: int):
+        check(lib().lbm_set_two_cycle_tile(self._ctx, int(threads), int(rows)))
 
     def schedule(self):
         a, v, b, c = (ctypes.c_int32() for _ in range(4))
