@@ -140,9 +140,11 @@ def extras(args):
                                 tune_cache=os.path.join(ROOT, "gpurun_out", "tune_cache.txt")
                                 if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
         ms = timed(b, args.steps, args.warmup)
+        tb = b.time_blocking()
+        per_launch = ms * tb["cycles_per_pass"]
         out[name] = {"mlups": round(b.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4), "nodes": b.nodes,
-                     "bytes_per_node": bpn, "schedule": list(b.schedule()),
-                     "roofline": roofline(b.nodes, bpn, ms)}
+                     "bytes_per_node_per_launch": bpn, "schedule": list(b.schedule()), "time_blocking": tb,
+                     "roofline": roofline(b.nodes, bpn, per_launch)}
         del b
         torch.cuda.empty_cache()
     log("bench: adjoint of the 2048^2 inverse problem (4000 steps, checkpoint every 200)")
@@ -231,7 +233,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"log-normal porous channel {n}x{n}: x periodic, walls in y, per-cell "
+        "config": {"time_blocking": solver.time_blocking(),
+                   "workload": f"log-normal porous channel {n}x{n}: x periodic, walls in y, per-cell "
                                "porosity (log-normal, sigma 0.5, correlation 64, seed 5) with Ergun K and "
                                "F_phi, tau 0.8, FP32 deviation storage, forward steps, two cycles per "
                                "HBM pass",

@@ -129,9 +129,11 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
  * NULL). All domains must share the storage; thermal domains and
  * ckpt_every > 0 give ENOTSUP. The tile schedule and persistent grid size
  * are chosen by timing every compiled candidate on the stream (autotuning,
- * which synchronises the stream) unless tune_cache (host path, may be NULL)
- * already holds a choice for the same batch signature (sizes, boundaries,
- * media, storage, device); a new choice is appended there as a text line.
+ * which synchronises the stream): the one-cycle shapes and grids, and the
+ * two-cycle (temporal blocking) shapes and grids, keeping the faster mode,
+ * unless tune_cache (host path, may be NULL) already holds a choice for the
+ * same batch signature (sizes, boundaries, media, storage, device); a new
+ * choice is appended there as a text line.
  * Results are bitwise identical to stepping each domain alone. The
  * per-domain calls (lbm_macroscopic, lbm_get_populations, lbm_reduce) take
  * the domain index. */
@@ -217,13 +219,19 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * and for the last cycle of each lbm_step call (so lbm_reduce's residual
  * always compares u(t) with u(t-1)). The recomputation inside lbm_backward
  * also uses two-cycle passes (recording u at both cycles). Default: 2 for
- * isothermal single domains of at least 2^21 nodes, 1 otherwise.
- * ENOTSUP on batches, EINVAL otherwise. */
+ * isothermal single domains of at least 2^21 nodes, 1 otherwise; for
+ * batches, the autotuner's choice. ENOTSUP for thermal domains, EINVAL for
+ * another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
+
+/* Current cycles per pass and the two-cycle kernel's workgroup size, tile
+ * rows and grid size (host outputs, each may be NULL). */
+int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threads, int32_t *rows,
+                      int32_t *grid);
 
 /* Workgroup shape of the two-cycle kernel: threads in {256, 512} and tile
  * rows in {8, 16} (tiles are 64 nodes wide). Results do not depend on it.
- * Default 512 threads, 16 rows. */
+ * Default 512 threads, 16 rows. ENOTSUP on batches (autotuned). */
 int lbm_set_two_cycle_tile(lbm_ctx *c, int32_t threads, int32_t rows);
 
 /* Number of steps lbm_step replays from one hand-built HIP graph of kernel

@@ -201,6 +201,10 @@ struct lbm_ctx {
     int storage = ST_F32;
     std::vector<Dom> h_doms;    // host copies (kept alive for the async upload)
     std::vector<int4> h_tiles;
+    int4 *d_tiles2 = nullptr;   // tiles of the two-cycle kernel (64 x tb_rows)
+    int ntiles2 = 0;
+    int grid2 = 0;
+    std::vector<int4> h_tiles2;
     // steps replayed from one hand-built HIP graph (0: launch each step);
     // one executable graph per starting buffer parity
     int graph_steps = 0;
@@ -296,7 +300,7 @@ hipError_t checkpoint(lbm_ctx *c) {
 namespace {
 
 // cycles advanced by one kernel node of the step graph
-int graph_node_steps(const lbm_ctx *c) { return (!c->batch && c->tblock == 2) ? 2 : 1; }
+int graph_node_steps(const lbm_ctx *c) { return c->tblock == 2 ? 2 : 1; }
 
 void reset_graphs(lbm_ctx *c) {
     for (auto &g : c->gexec) {
@@ -325,7 +329,13 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         void *args_s[3] = {&d, &tx, &swz};
         float *no_rec = nullptr;
         void *args_s2[4] = {&d, &tx, &swz, &no_rec};
-        if (c->batch) {
+        void *args_b2[4] = {&c->d_doms, &c->d_tiles2, &c->ntiles2, &p};
+        if (c->batch && c->tblock == 2) {
+            kp.func = (void *)step2_batch_kernel_fn(c->storage, c->tb_threads, c->tb_rows);
+            kp.gridDim = dim3((unsigned)c->grid2);
+            kp.blockDim = dim3((unsigned)c->tb_threads);
+            kp.kernelParams = args_b2;
+        } else if (c->batch) {
             kp.func = (void *)batch_kernel_fn(c->storage, c->sched);
             kp.gridDim = dim3((unsigned)c->grid);
             kp.kernelParams = args_b;
@@ -466,7 +476,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         const bool recording = c->rec_valid && c->dom[0].desc.ckpt_every > 0;
         // two cycles per pass while at least one single cycle remains for the end of
         // this call (so the previous buffer always holds f+(t-2) -> u(t-1) for the residual)
-        const bool fused = !c->batch && c->tblock == 2 && !recording && !c->dom[0].desc.thermal.enabled;
+        const bool fused = c->tblock == 2 && !recording && !c->dom[0].desc.thermal.enabled;
         if (c->graph_steps > 0 && !recording && n - (fused ? 1 : 0) >= c->graph_steps) {
             if (!c->gexec[c->cur]) {
                 if ((e = build_graph(c, c->cur)) != hipSuccess) return device_fail(c, e, "graph build");
@@ -481,8 +491,12 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         }
         if (fused && n >= 3) {
             Domain &D = c->dom[0];
-            e = launch_step2(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
-                             c->sched.swizzle, c->tb_threads, c->tb_rows, nullptr, c->stream);
+            if (c->batch)
+                e = launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->tb_threads,
+                                       c->tb_rows, c->grid2, c->stream);
+            else
+                e = launch_step2(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
+                                 c->sched.swizzle, c->tb_threads, c->tb_rows, nullptr, c->stream);
             if (e != hipSuccess) return device_fail(c, e, "step launch");
             c->cur ^= 1;
             c->t += 2;
@@ -707,6 +721,23 @@ int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows,
     return LBM_OK;
 }
 
+int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threads, int32_t *rows,
+                      int32_t *grid) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (cycles_per_pass) *cycles_per_pass = c->tblock;
+    if (threads) *threads = c->tb_threads;
+    if (rows) *rows = c->tb_rows;
+    if (grid) {
+        if (c->batch) *grid = c->grid2;
+        else {
+            int tx, ty;
+            step2_tiles(c->dom[0].desc.nx, c->dom[0].desc.ny, c->tb_rows, &tx, &ty);
+            *grid = tx * ty;
+        }
+    }
+    return LBM_OK;
+}
+
 int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int32_t swizzle) {
     int rc = check_ctx(c);
     if (rc) return rc;
@@ -723,7 +754,8 @@ int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (cycles_per_pass != 1 && cycles_per_pass != 2) return fail(LBM_EINVAL, "cycles per pass must be 1 or 2");
-    if (c->batch && cycles_per_pass != 1) return fail(LBM_ENOTSUP, "batches advance one cycle per pass");
+    if (cycles_per_pass == 2 && c->dom[0].desc.thermal.enabled)
+        return fail(LBM_ENOTSUP, "thermal domains advance one cycle per pass");
     c->tblock = cycles_per_pass;
     reset_graphs(c);
     return LBM_OK;
@@ -734,6 +766,7 @@ int lbm_set_two_cycle_tile(lbm_ctx *c, int32_t threads, int32_t rows) {
     if (rc) return rc;
     if (!step2_shape_supported(threads, rows))
         return fail(LBM_EINVAL, "unsupported two-cycle tile: %d threads, %d rows", threads, rows);
+    if (c->batch) return fail(LBM_ENOTSUP, "a batch's two-cycle tile is chosen by its autotuner");
     c->tb_threads = threads;
     c->tb_rows = rows;
     reset_graphs(c);
@@ -785,9 +818,21 @@ int64_t batch_tiles(int32_t n, const lbm_desc *descs, const Schedule &s) {
 
 struct BatchLayout {
     std::vector<size_t> off;  // per-domain base offsets
-    size_t off_doms = 0, off_tiles = 0, total = 0;
-    int64_t max_tiles = 0;
+    size_t off_doms = 0, off_tiles = 0, off_tiles2 = 0, total = 0;
+    int64_t max_tiles = 0, max_tiles2 = 0;
 };
+
+const int kTwoCycleShapes[][2] = {{256, 16}, {512, 16}, {256, 8}, {512, 8}};
+
+int64_t batch_tiles2(int32_t n, const lbm_desc *descs, int rows) {
+    int64_t total = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        int tx, ty;
+        step2_tiles(descs[k].nx, descs[k].ny, rows, &tx, &ty);
+        total += (int64_t)tx * ty;
+    }
+    return total;
+}
 
 BatchLayout batch_layout(int32_t n, const lbm_desc *descs) {
     BatchLayout B;
@@ -804,6 +849,12 @@ BatchLayout batch_layout(int32_t n, const lbm_desc *descs) {
     o = align_up(o + sizeof(Dom) * 2 * (size_t)n, ALIGN);
     B.off_tiles = o;
     o = align_up(o + sizeof(int4) * (size_t)B.max_tiles, ALIGN);
+    for (const auto &sh : kTwoCycleShapes) {
+        const int64_t t = batch_tiles2(n, descs, sh[1]);
+        if (t > B.max_tiles2) B.max_tiles2 = t;
+    }
+    B.off_tiles2 = o;
+    o = align_up(o + sizeof(int4) * (size_t)B.max_tiles2, ALIGN);
     B.total = o;
     return B;
 }
@@ -816,6 +867,21 @@ void fill_tiles(const lbm_ctx *c, const Schedule &s, std::vector<int4> &out) {
         for (int y = 0; y < ty; ++y)
             for (int x = 0; x < tx; ++x) out.push_back(make_int4((int)k, x, y, 0));
     }
+}
+
+hipError_t upload_tiles2(lbm_ctx *c, int rows) {
+    c->h_tiles2.clear();
+    for (size_t k = 0; k < c->dom.size(); ++k) {
+        int tx, ty;
+        step2_tiles(c->dom[k].desc.nx, c->dom[k].desc.ny, rows, &tx, &ty);
+        for (int y = 0; y < ty; ++y)
+            for (int x = 0; x < tx; ++x) c->h_tiles2.push_back(make_int4((int)k, x, y, 0));
+    }
+    c->ntiles2 = (int)c->h_tiles2.size();
+    hipError_t e = hipMemcpyAsync(c->d_tiles2, c->h_tiles2.data(), sizeof(int4) * c->h_tiles2.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
 }
 
 uint64_t batch_signature(const lbm_ctx *c) {
@@ -837,26 +903,41 @@ uint64_t batch_signature(const lbm_ctx *c) {
     return h;
 }
 
-bool cache_lookup(const char *path, uint64_t sig, Schedule &s, int &grid) {
+// One tuning result: the one-cycle schedule and grid, and the two-cycle
+// shape and grid, plus which of the two is faster.
+struct Tuned {
+    Schedule s{128, 1, 2, 0};
+    int grid = 0;
+    int tblock = 1, tb_threads = 512, tb_rows = 16, grid2 = 0;
+};
+
+bool cache_lookup(const char *path, uint64_t sig, Tuned &out) {
     if (!path) return false;
     FILE *f = fopen(path, "r");
     if (!f) return false;
-    unsigned long long key;
-    int tw, v, r, g;
+    char line[256];
     bool found = false;
-    while (fscanf(f, "%llx %d %d %d %d", &key, &tw, &v, &r, &g) == 5) {
+    while (fgets(line, sizeof(line), f)) {
+        unsigned long long key;
+        int tw, v, r, g, tb, tt, tr, g2;
+        if (sscanf(line, "%llx %d %d %d %d %d %d %d %d", &key, &tw, &v, &r, &g, &tb, &tt, &tr, &g2) != 9) continue;
         const Schedule cand{tw, v, r, 0};
-        if (key == sig && schedule_supported(cand) && g > 0) { s = cand; grid = g; found = true; }
+        if (key == sig && schedule_supported(cand) && g > 0 && (tb == 1 || tb == 2) &&
+            step2_shape_supported(tt, tr) && g2 > 0) {
+            out.s = cand; out.grid = g; out.tblock = tb; out.tb_threads = tt; out.tb_rows = tr; out.grid2 = g2;
+            found = true;
+        }
     }
     fclose(f);
     return found;
 }
 
-void cache_store(const char *path, uint64_t sig, const Schedule &s, int grid) {
+void cache_store(const char *path, uint64_t sig, const Tuned &t) {
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%016llx %d %d %d %d\n", (unsigned long long)sig, s.tile_w, s.vec, s.rows, grid);
+    fprintf(f, "%016llx %d %d %d %d %d %d %d %d\n", (unsigned long long)sig, t.s.tile_w, t.s.vec, t.s.rows,
+            t.grid, t.tblock, t.tb_threads, t.tb_rows, t.grid2);
     fclose(f);
 }
 
@@ -872,7 +953,7 @@ hipError_t upload_tiles(lbm_ctx *c, const Schedule &s) {
 // Times every (schedule, grid) candidate on the batch. Each timing launch
 // reads buffer 0 (the rest state f(0)) and writes buffer 1, which the first
 // real cycle overwrites, so tuning leaves the state untouched.
-hipError_t autotune(lbm_ctx *c, Schedule &best, int &best_grid) {
+hipError_t autotune(lbm_ctx *c, Tuned &best) {
     int dev = 0, ncu = 256;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -880,26 +961,47 @@ hipError_t autotune(lbm_ctx *c, Schedule &best, int &best_grid) {
     hipEvent_t a = nullptr, b = nullptr;
     if ((e = hipEventCreate(&a)) != hipSuccess) return e;
     if ((e = hipEventCreate(&b)) != hipSuccess) { (void)hipEventDestroy(a); return e; }
-    float best_ms = 1e30f;
+    auto time_it = [&](auto launch, float &ms) -> hipError_t {
+        hipError_t r = hipSuccess;
+        for (int w = 0; w < 2 && r == hipSuccess; ++w) r = launch();
+        if (r == hipSuccess) r = hipEventRecord(a, c->stream);
+        for (int w = 0; w < 5 && r == hipSuccess; ++w) r = launch();
+        if (r == hipSuccess) r = hipEventRecord(b, c->stream);
+        if (r == hipSuccess) r = hipEventSynchronize(b);
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, a, b);
+        return r;
+    };
+    float best1 = 1e30f, best2 = 1e30f;  // ms per cycle
     for (const Schedule &s : kCandidates) {
         if ((e = upload_tiles(c, s)) != hipSuccess) break;
         const int grids[5] = {2 * ncu, 4 * ncu, 8 * ncu, 16 * ncu, c->ntiles};
         for (int g : grids) {
             if (g > c->ntiles) g = c->ntiles;
-            for (int w = 0; w < 2 && e == hipSuccess; ++w)
-                e = launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, 0, c->storage, s, g, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(a, c->stream);
-            for (int w = 0; w < 5 && e == hipSuccess; ++w)
-                e = launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, 0, c->storage, s, g, c->stream);
-            if (e == hipSuccess) e = hipEventRecord(b, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(b);
             float ms = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            e = time_it([&] { return launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, 0, c->storage, s, g,
+                                                       c->stream); }, ms);
             if (e != hipSuccess) break;
-            if (ms < best_ms) { best_ms = ms; best = s; best_grid = g; }
+            if (ms < best1) { best1 = ms; best.s = s; best.grid = g; }
         }
         if (e != hipSuccess) break;
     }
+    for (const auto &sh : kTwoCycleShapes) {
+        if (e != hipSuccess) break;
+        if ((e = upload_tiles2(c, sh[1])) != hipSuccess) break;
+        const int grids[4] = {2 * ncu, 4 * ncu, 8 * ncu, c->ntiles2};
+        for (int g : grids) {
+            if (g > c->ntiles2) g = c->ntiles2;
+            float ms = 0.0f;
+            e = time_it([&] { return launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, 0, c->storage, sh[0],
+                                                        sh[1], g, c->stream); }, ms);
+            if (e != hipSuccess) break;
+            if (0.5f * ms < best2) {
+                best2 = 0.5f * ms;
+                best.tb_threads = sh[0]; best.tb_rows = sh[1]; best.grid2 = g;
+            }
+        }
+    }
+    best.tblock = (best2 < best1) ? 2 : 1;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return e;
@@ -958,18 +1060,24 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
         e = hipMemcpyAsync(c->d_doms, c->h_doms.data(), sizeof(Dom) * c->h_doms.size(), hipMemcpyHostToDevice,
                            c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    Schedule best{128, 1, 2, 0};
-    int grid = 0;
+    c->d_tiles2 = (int4 *)(base + B.off_tiles2);
+    Tuned best;
     const uint64_t sig = batch_signature(c);
-    if (e == hipSuccess && !cache_lookup(tune_cache, sig, best, grid)) {
-        e = autotune(c, best, grid);
-        if (e == hipSuccess) cache_store(tune_cache, sig, best, grid);
+    if (e == hipSuccess && !cache_lookup(tune_cache, sig, best)) {
+        e = autotune(c, best);
+        if (e == hipSuccess) cache_store(tune_cache, sig, best);
     }
     if (e == hipSuccess) {
-        c->sched = best;
-        e = upload_tiles(c, best);
-        if (grid > c->ntiles) grid = c->ntiles;
-        c->grid = grid;
+        c->sched = best.s;
+        e = upload_tiles(c, best.s);
+        c->grid = best.grid > c->ntiles ? c->ntiles : best.grid;
+    }
+    if (e == hipSuccess) {
+        c->tb_threads = best.tb_threads;
+        c->tb_rows = best.tb_rows;
+        e = upload_tiles2(c, best.tb_rows);
+        c->grid2 = best.grid2 > c->ntiles2 ? c->ntiles2 : best.grid2;
+        c->tblock = best.tblock;
     }
     if (e != hipSuccess) {
         rc = fail(LBM_EDEVICE, "batch creation: %s", hipGetErrorString(e));

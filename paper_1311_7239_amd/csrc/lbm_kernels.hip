@@ -298,12 +298,9 @@ hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int
 // intermediate state exactly as a store/reload would, so the result is
 // bitwise that of two one-step launches.
 template <typename S, int TW, int TH, int NT, bool REC>
-__global__ __launch_bounds__(NT) void k_step2(Dom d, int tiles_x, int swz, float *urec_next) {
+__device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *urec_next,
+                                           float (&lds)[8][TH + 2][TW + 2]) {
     constexpr int EW = TW + 2, EH = TH + 2, EN = EW * EH;
-    __shared__ float lds[8][EH][EW];
-    int b = blockIdx.x;
-    if (swz) b = xcd_swizzle(b, gridDim.x);
-    const int x0 = (b % tiles_x) * TW, y0 = (b / tiles_x) * TH;
     const S *__restrict__ fin = (const S *)d.fin;
     S *__restrict__ fout = (S *)d.fout;
     // every source of phase A inside the domain, no wrap needed
@@ -380,6 +377,32 @@ __global__ __launch_bounds__(NT) void k_step2(Dom d, int tiles_x, int swz, float
     }
 }
 
+
+template <typename S, int TW, int TH, int NT, bool REC>
+__global__ __launch_bounds__(NT) void k_step2(Dom d, int tiles_x, int swz, float *urec_next) {
+    __shared__ float lds[8][TH + 2][TW + 2];
+    int b = blockIdx.x;
+    if (swz) b = xcd_swizzle(b, gridDim.x);
+    step2_tile<S, TW, TH, NT, REC>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec_next, lds);
+}
+
+// Persistent batched two-cycle pass over a table of 64 x TH tiles.
+template <typename S, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) void k_step2_batch(const Dom *__restrict__ doms,
+                                                    const int4 *__restrict__ tiles, int ntiles,
+                                                    int parity) {
+    __shared__ float lds[8][TH + 2][TW + 2];
+    const int64_t nb = gridDim.x;
+    const int t0 = (int)((int64_t)blockIdx.x * ntiles / nb);
+    const int t1 = (int)(((int64_t)blockIdx.x + 1) * ntiles / nb);
+    for (int t = t0; t < t1; ++t) {
+        const int4 tl = tiles[t];
+        const Dom d = doms[2 * tl.x + parity];
+        step2_tile<S, TW, TH, NT, false>(d, tl.y * TW, tl.z * TH, nullptr, lds);
+        __syncthreads();   // the next tile's phase A rewrites the LDS
+    }
+}
+
 constexpr int STEP2_TW = 64;
 
 // Compiled two-cycle tiles: (threads per workgroup, tile rows); tiles are 64 wide.
@@ -403,6 +426,26 @@ static const void *step2_fn_t(int threads, int rows) {
     MRT_STEP2_SHAPES(MRT_S2FN)
 #undef MRT_S2FN
     return nullptr;
+}
+
+template <typename S>
+static const void *step2_batch_fn_t(int threads, int rows) {
+#define MRT_S2BFN(N, H) if (threads == N && rows == H) return (const void *)&k_step2_batch<S, STEP2_TW, H, N>;
+    MRT_STEP2_SHAPES(MRT_S2BFN)
+#undef MRT_S2BFN
+    return nullptr;
+}
+
+const void *step2_batch_kernel_fn(int storage, int threads, int rows) {
+    return storage == ST_F32 ? step2_batch_fn_t<float>(threads, rows) : step2_batch_fn_t<_Float16>(threads, rows);
+}
+
+hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage,
+                              int threads, int rows, int grid, hipStream_t st) {
+    const void *fn = step2_batch_kernel_fn(storage, threads, rows);
+    if (!fn || grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
+    void *args[4] = {&doms, &tiles, &ntiles, &parity};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)threads), args, 0, st);
 }
 
 const void *step2_kernel_fn(int storage, int threads, int rows, bool rec) {

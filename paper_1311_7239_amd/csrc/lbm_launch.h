@@ -42,6 +42,11 @@ hipError_t launch_step2(const Dom &d, int storage, int swizzle, int threads, int
 bool step2_shape_supported(int threads, int rows);
 void step2_tiles(int nx, int ny, int rows, int *tiles_x, int *tiles_y);
 const void *step2_kernel_fn(int storage, int threads, int rows, bool rec);
+// Batched two-cycle pass over a table of 64 x rows tiles (domain, tx, ty, 0);
+// entry arguments (const Dom*, const int4*, int ntiles, int parity).
+hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage,
+                              int threads, int rows, int grid, hipStream_t st);
+const void *step2_batch_kernel_fn(int storage, int threads, int rows);
 
 // Persistent batched step over a tile table: doms[2*k + parity] describes
 // domain k with its buffers for this parity; tiles[j] = (domain, tx, ty, 0).

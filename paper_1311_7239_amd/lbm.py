@@ -89,6 +89,7 @@ def lib():
         L.lbm_set_graph_steps.argtypes = [_vp, ctypes.c_int32]
         L.lbm_set_time_blocking.argtypes = [_vp, ctypes.c_int32]
         L.lbm_set_two_cycle_tile.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
+        L.lbm_time_blocking.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int32)] * 4
         _lib = L
     return _lib
 
@@ -248,11 +249,20 @@ class Solver:
     def set_two_cycle_tile(self, threads: int, rows: int):
         check(lib().lbm_set_two_cycle_tile(self._ctx, int(threads), int(rows)))
 
+    def time_blocking(self):
+        return _time_blocking(self._ctx)
+
     def schedule(self):
         a, v, b, c = (ctypes.c_int32() for _ in range(4))
         check(lib().lbm_schedule(self._ctx, ctypes.byref(a), ctypes.byref(v), ctypes.byref(b),
                                  ctypes.byref(c)))
         return a.value, v.value, b.value, c.value
+
+
+def _time_blocking(ctx):
+    v = [ctypes.c_int32() for _ in range(4)]
+    check(lib().lbm_time_blocking(ctx, *[ctypes.byref(x) for x in v]))
+    return {"cycles_per_pass": v[0].value, "threads": v[1].value, "rows": v[2].value, "grid": v[3].value}
 
 
 def solver_for_case(case, storage: int = FP32_DEV, ckpt_every: int = 0, max_steps_recorded: int = 0,
@@ -314,6 +324,12 @@ class Batch:
 
     def set_graph_steps(self, steps: int):
         check(lib().lbm_set_graph_steps(self._ctx, int(steps)))
+
+    def set_time_blocking(self, cycles_per_pass: int):
+        check(lib().lbm_set_time_blocking(self._ctx, int(cycles_per_pass)))
+
+    def time_blocking(self):
+        return _time_blocking(self._ctx)
 
     def schedule(self):
         a, v, b, c = (ctypes.c_int32() for _ in range(4))

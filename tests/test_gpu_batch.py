@@ -34,9 +34,12 @@ def single_run(case, steps, storage):
 
 
 @pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
-def test_batch_is_bitwise_equal_to_single_domains(storage, tmp_path):
+@pytest.mark.parametrize("tblock", [1, 2])
+def test_batch_is_bitwise_equal_to_single_domains(storage, tblock, tmp_path):
+    """One and two cycles per pass, graph replays of 4 cycles, leftovers."""
     cases = mixed_cases()
     b = lbm.batch_for_cases(cases, storage=storage, tune_cache=tmp_path / "tune.txt")
+    b.set_time_blocking(tblock)
     b.set_graph_steps(4)
     done = 0
     for chunk in (1, 9, 3, 8):          # t = 0 cycle, graph replays, leftovers
@@ -66,7 +69,7 @@ def test_tune_cache_is_written_and_reused(tmp_path):
     path = tmp_path / "tune.txt"
     b1 = lbm.batch_for_cases(cases, tune_cache=path)
     text = path.read_text().strip().splitlines()
-    assert len(text) == 1 and len(text[0].split()) == 5
+    assert len(text) == 1 and len(text[0].split()) == 9
     b2 = lbm.batch_for_cases(cases, tune_cache=path)
     assert b1.schedule() == b2.schedule()
     assert len(path.read_text().strip().splitlines()) == 1    # found, not re-tuned
