@@ -1141,10 +1141,17 @@ extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, floa
                 if (e != hipSuccess) return device_fail(c, e, "recompute step");
                 p ^= 1;
             }
-            // backward through the segment
-            for (int64_t t = s1 - 1; t >= s0; --t) {
-                e = launch_adjoint_step(D.dom, lam[la], lam[la ^ 1],
-                                        urec + (size_t)(t - s0) * 2 * (size_t)L.plane, gphi, gk, st);
+            // backward through the segment (two steps per pass in two-cycle mode)
+            for (int64_t t = s1 - 1; t >= s0;) {
+                const float *ut = urec + (size_t)(t - s0) * 2 * (size_t)L.plane;
+                if (c->tblock == 2 && t - 1 >= s0) {
+                    e = launch_adjoint_step2(D.dom, lam[la], lam[la ^ 1], ut, ut - 2 * (size_t)L.plane, gphi, gk,
+                                             st);
+                    t -= 2;
+                } else {
+                    e = launch_adjoint_step(D.dom, lam[la], lam[la ^ 1], ut, gphi, gk, st);
+                    t -= 1;
+                }
                 if (e != hipSuccess) return device_fail(c, e, "adjoint step");
                 la ^= 1;
             }

@@ -47,17 +47,18 @@ __device__ __forceinline__ void apply_MT(const float y[8], float f[8]) {
 __device__ __forceinline__ void velocity_adjoint(const Cell &c, float ux, float uy, float ubx,
                                                  float uby, float &vbx, float &vby,
                                                  ParamBar &pb) {
-    const float umag = sqrtf(ux * ux + uy * uy);
+    const float umag = hw_sqrt(ux * ux + uy * uy);
     const float l0 = 0.5f * (1.0f + 0.5f * c.cd);
     const float l1 = 0.5f * c.cf;
     const float R = l0 + l1 * umag;   // sqrt(l0^2 + l1|v|) on the solution
     const float D = l0 + R;           // = 2 l0 + l1 |u|
     const float uub = ux * ubx + uy * uby;
-    const float corr = (umag > 0.0f) ? (l1 / (2.0f * R)) * uub / umag : 0.0f;
-    vbx = (ubx - corr * ux) / D;
-    vby = (uby - corr * uy) / D;
-    pb.cd += 0.25f * (-uub / R);
-    pb.cf += 0.5f * (-uub * umag / (2.0f * R));
+    const float rR = hw_rcp(R), rD = hw_rcp(D);
+    const float corr = (umag > 0.0f) ? (0.5f * l1 * rR) * uub * hw_rcp(umag) : 0.0f;
+    vbx = (ubx - corr * ux) * rD;
+    vby = (uby - corr * uy) * rD;
+    pb.cd += 0.25f * (-uub * rR);
+    pb.cf += 0.5f * (-0.5f * uub * umag * rR);
     pb.pax += 0.5f * vbx;
     pb.pay += 0.5f * vby;
 }
@@ -83,7 +84,7 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
 
     // forward quantities on this node
     const float ip = c.inv_phi;
-    const float umag = sqrtf(ux * ux + uy * uy);
+    const float umag = hw_sqrt(ux * ux + uy * uy);
     const float drag = c.cd + c.cf * umag;
     const float Fx = pax - drag * ux, Fy = pay - drag * uy;
     const float u2 = ux * ux + uy * uy, uF = ux * Fx + uy * Fy;
@@ -113,7 +114,7 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
 
     // F = phi a - (cd + cf |u|) u  (Eq. 3)
     const float uFb = ux * Fbx + uy * Fby;
-    const float nl = (umag > 0.0f) ? c.cf * uFb / umag : 0.0f;
+    const float nl = (umag > 0.0f) ? c.cf * uFb * hw_rcp(umag) : 0.0f;
     ubx += -drag * Fbx - nl * ux;
     uby += -drag * Fby - nl * uy;
     pb.pax = Fbx;
@@ -138,16 +139,16 @@ __device__ __forceinline__ void medium_gradient(const Dom &d, const Cell &c, flo
     if (d.medium == MED_PHI_ERGUN) {
         // kappa = kcoef (1-phi)^2 / phi^3; sqrt(kappa) = sk (1 - phi)
         const float om = 1.0f - phi;
-        const float sk = sqrtf(d.kcoef) * ip * sqrtf(ip);
+        const float sk = hw_sqrt(d.kcoef) * ip * hw_sqrt(ip);
         const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
         dcd = -2.0f * d.nu * d.kcoef * om * (ip * ip * ip);
         dcf = ((d.Fconst >= 0.0f) ? -0.5f : -2.0f) * c.cf * ip - phi * F * sk;
     } else {
         const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
-        const float sq = sqrtf(kappa);
+        const float sq = hw_sqrt(kappa);
         dcd = d.nu * kappa;
         dcf = ((d.Fconst >= 0.0f) ? 1.0f : -0.5f) * F * sq;
-        const float dcf_dk = (kappa > 0.0f) ? phi * F / (2.0f * sq) : 0.0f;
+        const float dcf_dk = (kappa > 0.0f) ? 0.5f * phi * F * hw_rcp(sq) : 0.0f;
         gkappa = pb.cd * phi * d.nu + pb.cf * dcf_dk;
     }
     gphi = ax * pb.pax + ay * pb.pay + pb.cd * dcd + pb.cf * dcf - pb.ip * ip * ip;
@@ -185,6 +186,9 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint_seed(Dom d, const float *__r
     if (gkappa) gkappa[o] = gk;
 }
 
+__device__ __forceinline__ void gather_transposed(const Dom &d, const float *__restrict__ lam, int x,
+                                                  int y, bool interior, float b[8]);
+
 // One backward step at time t: lam_out = a(t), lam_in = a(t+1), u_t = u(t).
 __global__ __launch_bounds__(ABLOCK) void k_adjoint_step(Dom d, const float *__restrict__ lam_in,
                                                          float *__restrict__ lam_out,
@@ -198,12 +202,30 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint_step(Dom d, const float *__r
     const int64_t o = (int64_t)y * d.pitch + x;
     const bool interior = tx * ABLOCK >= 1 && tx * ABLOCK + ABLOCK <= d.nx - 1 && y >= 1 &&
                           y <= d.ny - 2;
-    // b_i(x) = a_i(x + e_i), or a_ibar(x) across a wall (G^T)
     float b[8];
+    gather_transposed(d, lam_in, x, y, interior, b);
+    const Cell c = load_cell(d, o);
+    const float ux = u_t[o], uy = u_t[d.plane + o];
+    float a[8];
+    ParamBar pb;
+    collide_adjoint(b, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, a, pb);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lam_out[i * d.plane + o] = a[i];
+    float gp, gk;
+    medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
+    gphi[o] += gp;
+    if (gkappa) gkappa[o] += gk;
+}
+
+// b_i(x) = a_i(x + e_i), or a_ibar(x) across a wall: the transpose of the
+// pull gather, read from HBM for node (x, y).
+__device__ __forceinline__ void gather_transposed(const Dom &d, const float *__restrict__ lam, int x,
+                                                  int y, bool interior, float b[8]) {
+    const int64_t o = (int64_t)y * d.pitch + x;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         if (interior) {
-            b[i] = lam_in[i * d.plane + o + EY[i] * d.pitch + EX[i]];
+            b[i] = lam[i * d.plane + o + EY[i] * d.pitch + EX[i]];
             continue;
         }
         int sx = x + EX[i], sy = y + EY[i];
@@ -216,19 +238,102 @@ __global__ __launch_bounds__(ABLOCK) void k_adjoint_step(Dom d, const float *__r
             if (d.bc_y == BC_PERIODIC) sy = (sy < 0) ? d.ny - 1 : 0;
             else out = true;
         }
-        b[i] = out ? lam_in[OPP[i] * d.plane + o] : lam_in[i * d.plane + (int64_t)sy * d.pitch + sx];
+        b[i] = out ? lam[OPP[i] * d.plane + o] : lam[i * d.plane + (int64_t)sy * d.pitch + sx];
     }
-    const Cell c = load_cell(d, o);
-    const float ux = u_t[o], uy = u_t[d.plane + o];
-    float a[8];
-    ParamBar pb;
-    collide_adjoint(b, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, a, pb);
+}
+
+// Two backward steps per pass: a(t) on a 64 x 16 tile plus a one-node ring
+// from a(t+1) in HBM into LDS (phase A), then a(t-1) on the tile from LDS
+// (phase B); the medium gradient of both steps is added in one
+// read-modify-write, in the order of two single steps, so the result is
+// bitwise that of two k_adjoint_step launches.
+constexpr int ATW = 64, ATH = 16, ANT = 512;
+
+__global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__restrict__ lam_in,
+                                                       float *__restrict__ lam_out,
+                                                       const float *__restrict__ u_t,
+                                                       const float *__restrict__ u_tm1,
+                                                       float *__restrict__ gphi,
+                                                       float *__restrict__ gkappa, int tiles_x,
+                                                       int swz) {
+    constexpr int EW = ATW + 2, EH = ATH + 2, EN = EW * EH;
+    __shared__ float lds[8][EH][EW];
+    __shared__ float gA[ATH][ATW];
+    __shared__ float gkA[ATH][ATW];
+    int b = blockIdx.x;
+    if (swz) b = xcd_swizzle(b, gridDim.x);
+    const int x0 = (b % tiles_x) * ATW, y0 = (b / tiles_x) * ATH;
+    const bool interior = x0 >= 2 && x0 + ATW + 2 <= d.nx && y0 >= 2 && y0 + ATH + 2 <= d.ny;
+
+    for (int e = threadIdx.x; e < EN; e += ANT) {
+        const int ex = e % EW, ey = e / EW;
+        int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+        if (!interior) {
+            if (gx < 0 || gx >= d.nx) {
+                if (d.bc_x != BC_PERIODIC) continue;
+                gx = ((gx % d.nx) + d.nx) % d.nx;
+            }
+            if (gy < 0 || gy >= d.ny) {
+                if (d.bc_y != BC_PERIODIC) continue;
+                gy = ((gy % d.ny) + d.ny) % d.ny;
+            }
+        }
+        float bb[8];
+        gather_transposed(d, lam_in, gx, gy, interior, bb);
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = load_cell(d, o);
+        float a[8];
+        ParamBar pb;
+        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, u_t[o], u_t[d.plane + o], a, pb);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lam_out[i * d.plane + o] = a[i];
-    float gp, gk;
-    medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
-    gphi[o] += gp;
-    if (gkappa) gkappa[o] += gk;
+        for (int i = 0; i < 8; ++i) lds[i][ey][ex] = a[i];
+        if (ex >= 1 && ex <= ATW && ey >= 1 && ey <= ATH && x0 - 1 + ex < d.nx && y0 - 1 + ey < d.ny) {
+            float gp, gk;
+            medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
+            gA[ey - 1][ex - 1] = gp;
+            gkA[ey - 1][ex - 1] = gk;
+        }
+    }
+    __syncthreads();
+
+    const float *flat = &lds[0][0][0];
+    for (int q = threadIdx.x; q < ATW * ATH; q += ANT) {
+        const int lx = q % ATW, ly = q / ATW;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= d.nx || gy >= d.ny) continue;
+        float bb[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            bool out = false;
+            if (!interior) {
+                const int sx = gx + EX[i], sy = gy + EY[i];
+                if (EX[i] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) out = true;
+                if (EY[i] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) out = true;
+            }
+            const int src = out ? (OPP[i] * EH + ly + 1) * EW + lx + 1
+                                : (i * EH + ly + 1 + EY[i]) * EW + lx + 1 + EX[i];
+            bb[i] = flat[src];
+        }
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = load_cell(d, o);
+        float a[8];
+        ParamBar pb;
+        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, u_tm1[o], u_tm1[d.plane + o], a, pb);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lam_out[i * d.plane + o] = a[i];
+        float gp, gk;
+        medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
+        gphi[o] = (gphi[o] + gA[ly][lx]) + gp;
+        if (gkappa) gkappa[o] = (gkappa[o] + gkA[ly][lx]) + gk;
+    }
+}
+
+hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
+                                const float *u_tm1, float *gphi, float *gkappa, hipStream_t st) {
+    const int tiles_x = (d.nx + ATW - 1) / ATW, tiles_y = (d.ny + ATH - 1) / ATH;
+    hipLaunchKernelGGL(k_adjoint_step2, dim3((unsigned)(tiles_x * tiles_y)), dim3(ANT), 0, st, d, lam_in,
+                       lam_out, u_t, u_tm1, gphi, gkappa, tiles_x, 1);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_seed(const Dom &d, Source src, const float *dLdu, float *lam,

@@ -82,6 +82,16 @@ __device__ __forceinline__ float mulc(float x, float hi, float lo) { return fmaf
 #define MRT_C1_5 0x1.99999ap-3f, -0x1.99999ap-29f
 #define MRT_C1_20 0x1.99999ap-5f, -0x1.99999ap-31f
 
+// Workgroups are dispatched round-robin over the 8 XCDs; this remaps the
+// block id so that each XCD walks a contiguous run of tiles (neighbouring
+// tiles share cache lines at the x-shifted loads and the halo rows).
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+    constexpr int NUM_XCD = 8;
+    const int q = nb / NUM_XCD;
+    if (b >= q * NUM_XCD) return b;
+    return (b % NUM_XCD) * q + b / NUM_XCD;
+}
+
 // Per-cell quantities of Eqs. (3), (4) and (19).
 struct Cell {
     float phi, inv_phi;

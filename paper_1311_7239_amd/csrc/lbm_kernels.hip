@@ -17,16 +17,6 @@
 namespace mrt {
 
 constexpr int BLOCK = 256;
-constexpr int NUM_XCD = 8;
-
-// Workgroups are dispatched round-robin over the XCDs; this remaps the
-// block id so that each XCD walks a contiguous run of tiles (neighbouring
-// rows share cache lines at the x-shifted loads).
-__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
-    const int q = nb / NUM_XCD;
-    if (b >= q * NUM_XCD) return b;
-    return (b % NUM_XCD) * q + b / NUM_XCD;
-}
 
 // ------------------------------------------------------------------ step
 

@@ -81,6 +81,10 @@ hipError_t launch_adjoint_seed(const Dom &d, Source src, const float *dLdu, floa
 // using u(t) from urec.
 hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out,
                                const float *u_t, float *gphi, float *gkappa, hipStream_t st);
+// Two backward steps per pass: lam_out = a(t-1) from lam_in = a(t+1), using
+// u(t) and u(t-1).
+hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
+                                const float *u_tm1, float *gphi, float *gkappa, hipStream_t st);
 hipError_t launch_unpitch(const float *src, int pitch, float *dst, int nx, int ny,
                           hipStream_t st);
 

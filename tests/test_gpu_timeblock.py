@@ -63,19 +63,30 @@ def test_two_cycles_per_pass_is_bitwise_equal(name, case, storage, graph, shape)
         assert ma == mb and ra == rb
 
 
-def test_backward_recomputation_with_two_cycle_passes_is_bitwise_equal():
-    """The adjoint's recomputation may run two cycles per pass (recording u at both);
-    gradients are bitwise those of the one-cycle recomputation."""
+@pytest.mark.parametrize("kappa_plane", [False, True])
+def test_backward_with_two_cycle_passes_is_bitwise_equal(kappa_plane):
+    """In two-cycle mode the adjoint's recomputation runs two cycles per pass (recording u
+    at both) and the backward sweep runs two adjoint steps per pass; gradients are
+    bitwise those of the one-cycle path (odd step count: segments of both parities)."""
     case = I.lognormal_channel(n=160, seed=9, ell=10.0, K_ref=40.0, drive=0.02)
+    kap = None
+    if kappa_plane:
+        kap = torch.from_numpy((150.0 * (1 - case.phi) ** 2 / (case.phi ** 3 * case.dp ** 2))
+                               .astype(np.float32)).cuda()
     grads = []
     for tblock in (1, 2):
-        s = lbm.solver_for_case(case, ckpt_every=50, max_steps_recorded=230)
+        desc = lbm.desc_from_case(case, ckpt_every=50)
+        if kappa_plane:
+            desc.medium = lbm.MEDIUM_PHI_KAPPA
+        s = lbm.Solver(desc, phi=torch.from_numpy(case.phi).cuda(), kappa=kap, max_steps_recorded=231)
         s.set_time_blocking(tblock)
-        s.step(230)
+        s.step(231)
         _, u, _ = s.macroscopic()
         dLdu = torch.zeros_like(u)
         dLdu[:, :, -1] = u[:, :, -1]
-        g, _ = s.backward(dLdu)
+        g, gk = s.backward(dLdu, want_kappa=kappa_plane)
         torch.cuda.synchronize()
-        grads.append(g.cpu().numpy())
-    assert np.array_equal(grads[0], grads[1])
+        grads.append((g.cpu().numpy(), None if gk is None else gk.cpu().numpy()))
+    assert np.array_equal(grads[0][0], grads[1][0])
+    if kappa_plane:
+        assert np.array_equal(grads[0][1], grads[1][1])
