@@ -12,6 +12,7 @@ import oracle
 from paper_1311_7239_amd import inputs as I
 from paper_1311_7239_amd import lbm
 from tests.gpu_cases import Pair, max_rel_velocity_error
+from tests.oracle_cases import oracle_setup
 
 pytestmark = pytest.mark.gpu
 
@@ -135,3 +136,27 @@ def test_every_schedule_gives_the_same_bits(kind, medium, storage):
         pair.step(4)
         ref = pair.oracle_dev()
         assert np.abs(results[0] - ref).max() / np.abs(ref).max() < STEP_TOL * 4
+
+
+def test_bgk_variant_equal_rates():
+    """With every relaxation rate 1/tau (s_e = s_q = 1/tau) the scheme is the BGK model with
+    the equilibrium of Eq. (22) (Sec. 2.2); the GPU with those rates matches the oracle
+    (whose equal-rate collision is pinned to velocity-space BGK)."""
+    case = _case("cavity", 300, 45, "ergun", seed=12)
+    tau = 0.5 + 3.0 * case.J * case.nu
+    desc = lbm.desc_from_case(case)
+    desc.s_e = desc.s_q = 1.0 / tau
+    gpu = lbm.Solver(desc, phi=torch.from_numpy(case.phi).cuda())
+    df0 = I.random_deviation_state(45, 300, 1e-3, seed=13)
+    gpu.set_populations(torch.from_numpy(df0).cuda())
+    gpu.step(6)
+    got, _ = gpu.populations()
+    torch.cuda.synchronize()
+    p, phi, K, F = oracle_setup(case)
+    p.s_e = p.s_q = 1.0 / tau
+    from tests.gpu_cases import f_ref
+    f = np.ascontiguousarray(np.transpose(df0.astype(np.float64), (1, 2, 0)) + f_ref(case.Pi0))
+    oracle.run(p, phi, K, F, f, nsteps=6)
+    ref = np.transpose(f - f_ref(case.Pi0), (2, 0, 1))
+    err = np.abs(got.cpu().numpy().astype(np.float64) - ref).max() / np.abs(ref).max()
+    assert err < STEP_TOL * 6
