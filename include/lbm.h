@@ -93,6 +93,7 @@ typedef struct {
     double Pi0;       /* rest value of phi*p; reference of the storage         */
     int32_t storage;  /* LBM_FP32_DEV or LBM_FP16_DEV                          */
     int32_t ckpt_every; /* 0: no recording; k > 0: record for lbm_backward   */
+    int32_t j_plane;  /* 1: per-node viscosity ratio (lbm_set_viscosity_ratio) */
     lbm_thermal thermal;
 } lbm_desc;
 
@@ -141,6 +142,19 @@ int lbm_batch_workspace_size(int32_t n, const lbm_desc *descs, size_t *bytes);
 int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *const *phis,
                      const float *const *kappas, void *workspace, size_t ws_bytes,
                      void *stream, const char *tune_cache, lbm_ctx **out);
+
+/* Per-node viscosity ratio J = nu_e/nu of one domain (Eq. 5): each node
+ * relaxes its stress moments at s_7 = s_8 = 1/(1/2 + 3 J nu) (Eqs. 13, 21),
+ * as in the partially porous channel of Sec. 3.2, where the porous layer has
+ * its own J and the free fluid J = 1. J: device [ny][nx] float plane, read on
+ * the context's stream and copied (as rates) into the workspace before this
+ * call returns; the caller keeps ownership. The domain must have been
+ * created with j_plane = 1 (its plane then starts at the descriptor's J
+ * everywhere); works for single contexts and batch domains. Synchronises the
+ * stream. Errors: ESTATE without a plane, or once a recorded forward pass
+ * (ckpt_every > 0) has left t = 0; EINVAL for NULL or any J that is not
+ * finite and > 0 (the previous plane is kept). */
+int lbm_set_viscosity_ratio(lbm_ctx *c, int32_t domain, const float *J);
 
 /* Advances every domain by n >= 0 collide-and-stream cycles (Eqs. 14-15). */
 int lbm_step(lbm_ctx *c, int64_t n);

@@ -57,6 +57,7 @@ class Params(ctypes.Structure):
         ("Th", ctypes.c_double), ("Tc", ctypes.c_double), ("T0", ctypes.c_double),
         ("gbeta", ctypes.c_double),
         ("nthreads", ctypes.c_int),
+        ("Jcell", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -113,8 +114,9 @@ def _f64(a, shape=None):
 
 def make_params(nx, ny, *, bc_x=PERIODIC, bc_y=WALLS, lid_ux=0.0, nu, J=1.0, ax=0.0, ay=0.0,
                 thermal=False, sigma=1.0, tau_T=1.0, Th=0.0, Tc=0.0, T0=0.0, gbeta=0.0,
-                nthreads=0, **overrides) -> Params:
-    """Paper defaults (Sec. 2.2, Sec. 3) plus the run's geometry and physics."""
+                nthreads=0, Jcell=None, **overrides) -> Params:
+    """Paper defaults (Sec. 2.2, Sec. 3) plus the run's geometry and physics.
+    Jcell: optional per-node viscosity ratio [ny, nx] (kept alive on the returned object)."""
     p = Params()
     lib().orc_default_params(ctypes.byref(p))
     p.nx, p.ny, p.bc_x, p.bc_y = int(nx), int(ny), int(bc_x), int(bc_y)
@@ -122,6 +124,10 @@ def make_params(nx, ny, *, bc_x=PERIODIC, bc_y=WALLS, lid_ux=0.0, nu, J=1.0, ax=
     p.thermal = 1 if thermal else 0
     p.sigma, p.tau_T, p.Th, p.Tc, p.T0, p.gbeta = sigma, tau_T, Th, Tc, T0, gbeta
     p.nthreads = int(nthreads)
+    if Jcell is not None:
+        arr = np.ascontiguousarray(np.broadcast_to(np.asarray(Jcell, dtype=np.float64), (int(ny), int(nx))))
+        p._jcell = arr
+        p.Jcell = arr.ctypes.data_as(_D)
     for k, v in overrides.items():
         setattr(p, k, v)
     return p

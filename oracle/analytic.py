@@ -42,6 +42,26 @@ def porous_couette(y, L, u0, phi, K, nu, J=1.0):
     return u0 * np.sinh(th * y) / np.sinh(th * L)
 
 
+def partial_couette(y, L, u0, phi, Da, J=1.0):
+    """Eq. (25): Couette flow over a porous layer filling 0 <= y <= L/2 (Brinkman
+    model, F_phi = 0) under free fluid (phi = 1, nu_e = nu) up to the lid y = L.
+
+    In the layer u'' = (phi / (J Da)) u in y/L, so u = d0 sinh(th y/L)/sinh(th/2)
+    with th = sqrt(phi / (J Da)) (the paper's vartheta with K = Da L^2 and
+    nu_e = J nu); above it u is linear. Continuity of u and of the viscous flux
+    nu_e du/dy at y = L/2 and u(L) = u0 fix
+        d1 = J th coth(th/2) d0,   d0 = u0 / (1 + J th coth(th/2) / 2).
+    The printed d0 and d1 are the limit coth -> 1 of a layer many times thicker
+    than sqrt(J Da / phi) L; this finite-layer form is exact for the setup.
+    """
+    th = np.sqrt(phi / (J * Da))
+    ct = 1.0 / np.tanh(0.5 * th)
+    d0 = u0 / (1.0 + 0.5 * J * th * ct)
+    d1 = J * th * ct * d0
+    yh = np.asarray(y, dtype=np.float64) / L
+    return np.where(yh > 0.5, d0 + d1 * (yh - 0.5), d0 * np.sinh(th * yh) / np.sinh(0.5 * th))
+
+
 def _cheb(n):
     """Chebyshev differentiation matrix and points on [-1, 1] (Trefethen, 'Spectral
     Methods in MATLAB', program cheb)."""

@@ -160,9 +160,9 @@ void orc_ergun(long n, const double *phi, double dp, double *K, double *Fphi)
 
 /* Relaxation rates of Eq. (13): s1 = s3 = s5 = 1 (Sec. 3), s7 = s8 = 1/tau,
  * with nu_e = J nu = cs^2 (tau - 1/2) (Eq. 21). */
-static void relaxation_rates(const orc_params *p, double s[8])
+static void relaxation_rates(const orc_params *p, double J, double s[8])
 {
-    double nu_e = p->J * p->nu;
+    double nu_e = J * p->nu;
     double tau = 0.5 + nu_e / CS2;
     s[0] = 1.0; s[1] = p->s_e; s[2] = 1.0; s[3] = p->s_q;
     s[4] = 1.0; s[5] = p->s_q; s[6] = 1.0 / tau; s[7] = 1.0 / tau;
@@ -233,14 +233,27 @@ double orc_pressure(const orc_params *p, double phi, const double f[8], double u
     return CS2 / (phi * (1.0 - W0)) * (sum + p->rho0 * s0);
 }
 
+static void collide_node_J(const orc_params *p, double J, double phi, double K, double Fphi,
+                           double ax, double ay, const double f[8], double fplus[8],
+                           double u[2], double *pres);
+
 void orc_collide_node(const orc_params *p, double phi, double K, double Fphi,
                       double ax, double ay, const double f[8], double fplus[8],
                       double u[2], double *pres)
 {
+    collide_node_J(p, p->J, phi, K, Fphi, ax, ay, f, fplus, u, pres);
+}
+
+/* The collision of one node whose viscosity ratio is J (s_nu = 1/tau with
+ * nu_e = J nu = cs^2 (tau - 1/2), Eq. 21). */
+static void collide_node_J(const orc_params *p, double J, double phi, double K, double Fphi,
+                           double ax, double ay, const double f[8], double fplus[8],
+                           double u[2], double *pres)
+{
     ensure_matrices();
     const double dt = 1.0;
     double s[8];
-    relaxation_rates(p, s);
+    relaxation_rates(p, J, s);
 
     double m[8];
     for (int a = 0; a < 8; ++a) {
@@ -324,7 +337,8 @@ void orc_step(const orc_params *p, const double *phi, const double *K, const dou
                 ay += buoyancy_y(p, T);
             }
             double fp[8], u[2], pr;
-            orc_collide_node(p, phi[k], K[k], Fphi[k], ax, ay, &f[k * 8], fp, u, &pr);
+            collide_node_J(p, p->Jcell ? p->Jcell[k] : p->J, phi[k], K[k], Fphi[k], ax, ay,
+                           &f[k * 8], fp, u, &pr);
             for (int i = 0; i < 8; ++i) {
                 int xt = x + EX[i], yt = y + EY[i];
                 int out_x = (xt < 0 || xt >= nx), out_y = (yt < 0 || yt >= ny);

@@ -51,6 +51,9 @@ typedef struct {
     double T0;       /* reference temperature of the buoyancy term            */
     double gbeta;    /* g * beta                                              */
     int nthreads;    /* OpenMP threads for the node loops (<= 0: runtime default) */
+    const double *Jcell; /* per-node viscosity ratio (NULL: J everywhere); the
+                          * relaxation rate s_nu of a node follows its own J
+                          * (Sec. 3.2, partially porous channel) */
 } orc_params;
 
 /* Fills params with the paper's constants: rho0 = 1, J = 1, s_e = 1.1,

@@ -45,7 +45,7 @@ struct Layout {
     size_t g_bytes = 0;  // one thermal buffer (5 planes, FP32)
     size_t p_bytes = 0;  // one FP32 plane
     size_t off_f[2] = {0, 0}, off_g[2] = {0, 0};
-    size_t off_phi = 0, off_kappa = 0, off_part = 0, off_res = 0;
+    size_t off_phi = 0, off_kappa = 0, off_snu = 0, off_part = 0, off_res = 0;
     int red_blocks = 0;
     // recording for the adjoint
     int64_t nck = 0, ring = 0;
@@ -76,6 +76,7 @@ Layout make_layout(const lbm_desc &d, int64_t max_rec) {
     }
     if (d.medium != LBM_MEDIUM_UNIFORM) L.off_phi = carve(L.p_bytes);
     if (d.medium == LBM_MEDIUM_PHI_KAPPA) L.off_kappa = carve(L.p_bytes);
+    if (d.j_plane) L.off_snu = carve(L.p_bytes);
     L.red_blocks = reduce_blocks(d.nx, d.ny);
     L.off_part = carve(sizeof(double) * 3 * (size_t)L.red_blocks);
     L.off_res = carve(sizeof(double) * 4);
@@ -122,6 +123,7 @@ int validate(const lbm_desc *d) {
         return fail(LBM_EINVAL, "ax, ay and Pi0 must be finite");
     if (d->storage != LBM_FP32_DEV && d->storage != LBM_FP16_DEV) return fail(LBM_EINVAL, "unknown storage");
     if (d->ckpt_every < 0) return fail(LBM_EINVAL, "ckpt_every must be >= 0");
+    if (d->j_plane != 0 && d->j_plane != 1) return fail(LBM_EINVAL, "j_plane must be 0 or 1");
     if (d->thermal.enabled) {
         const lbm_thermal &t = d->thermal;
         if (!(t.tau_T > 0.5) || !std::isfinite(t.tau_T)) return fail(LBM_EINVAL, "thermal tau_T must be > 1/2");
@@ -146,7 +148,8 @@ Dom make_dom(const lbm_desc &d, const Layout &L) {
     const double s_nu = 1.0 / tau;
     o.s_e = (float)d.s_e; o.s_q = (float)d.s_q; o.s_nu = (float)s_nu;
     o.h_e = (float)(1.0 - 0.5 * d.s_e); o.h_q = (float)(1.0 - 0.5 * d.s_q);
-    o.h_nu = (float)(1.0 - 0.5 * s_nu);
+    // from the rounded rate, as the kernels form 1 - s/2 for a per-node rate
+    o.h_nu = (float)(1.0 - 0.5 * (double)o.s_nu);
     o.medium = d.medium;
     o.nu = (float)d.nu;
     o.Fconst = (float)d.F_eps;
@@ -266,6 +269,13 @@ hipError_t init_domain(Domain &D, int cur, const float *phi, const float *kappa,
             e = hipMemcpy2DAsync(D.base + D.L.off_kappa, (size_t)D.L.pitch * 4, kappa, (size_t)D.desc.nx * 4,
                                  (size_t)D.desc.nx * 4, (size_t)D.desc.ny, hipMemcpyDeviceToDevice, st);
     }
+    if (e == hipSuccess && D.desc.j_plane) {
+        // every node starts at the descriptor's J
+        e = launch_fill_zero(D.base + D.L.off_snu, align_up(D.L.p_bytes, 16), st);
+        if (e == hipSuccess)
+            e = launch_snu_plane(nullptr, D.desc.J, D.desc.nu, (float *)(D.base + D.L.off_snu), D.L.pitch,
+                                 D.desc.nx, D.desc.ny, nullptr, st);
+    }
     return e;
 }
 
@@ -282,6 +292,7 @@ int setup_domain(Domain &D, const lbm_desc *d, const float *phi, const float *ka
         if (!kappa) return fail(LBM_EINVAL, "kappa plane required for LBM_MEDIUM_PHI_KAPPA");
         D.dom.kappa = (const float *)(base + D.L.off_kappa);
     }
+    if (d->j_plane) D.dom.snu = (const float *)(base + D.L.off_snu);
     return LBM_OK;
 }
 
@@ -770,6 +781,32 @@ int lbm_set_two_cycle_tile(lbm_ctx *c, int32_t threads, int32_t rows) {
     c->tb_threads = threads;
     c->tb_rows = rows;
     reset_graphs(c);
+    return LBM_OK;
+}
+
+int lbm_set_viscosity_ratio(lbm_ctx *c, int32_t k, const float *J) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    rc = check_domain(c, k);
+    if (rc) return rc;
+    Domain &D = c->dom[k];
+    if (!D.desc.j_plane) return fail(LBM_ESTATE, "domain %d was created without a viscosity-ratio plane (j_plane = 0)", k);
+    if (!J) return fail(LBM_EINVAL, "J is NULL");
+    if (c->rec_valid && c->t > 0)
+        return fail(LBM_ESTATE, "the recorded forward pass has started; set J at t = 0");
+    // check on the device first, so that a rejected plane leaves the old one in place
+    int *flag = (int *)(D.base + D.L.off_part);
+    hipError_t e = launch_fill_zero(flag, 16, c->stream);
+    if (e == hipSuccess)
+        e = launch_snu_plane(J, 0.0, D.desc.nu, nullptr, D.L.pitch, D.desc.nx, D.desc.ny, flag, c->stream);
+    int bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "viscosity ratio");
+    if (bad) return fail(LBM_EINVAL, "J must be finite and > 0 at every node");
+    e = launch_snu_plane(J, 0.0, D.desc.nu, (float *)(D.base + D.L.off_snu), D.L.pitch, D.desc.nx,
+                         D.desc.ny, nullptr, c->stream);
+    if (e != hipSuccess) return device_fail(c, e, "viscosity ratio");
     return LBM_OK;
 }
 

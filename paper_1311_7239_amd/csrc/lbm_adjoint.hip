@@ -94,23 +94,23 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
     mb[1] = (1.0f - d.s_e) * P2;
     mb[3] = (1.0f - d.s_q) * P4;
     mb[5] = (1.0f - d.s_q) * P6;
-    mb[6] = (1.0f - d.s_nu) * P7;
-    mb[7] = (1.0f - d.s_nu) * P8;
+    mb[6] = (1.0f - c.s_nu) * P7;
+    mb[7] = (1.0f - c.s_nu) * P8;
 
     // u and F enter m2+, m3+..m8+ directly
     float ubx = (0.8f * d.s_e * ux + 0.8f * d.h_e * Fx) * ip * P2 + P3 - d.s_q * P4 +
-                (2.0f * d.s_nu * ux + 2.0f * d.h_nu * Fx) * ip * P7 +
-                (d.s_nu * uy + d.h_nu * Fy) * ip * P8;
+                (2.0f * c.s_nu * ux + 2.0f * c.h_nu * Fx) * ip * P7 +
+                (c.s_nu * uy + c.h_nu * Fy) * ip * P8;
     float uby = (0.8f * d.s_e * uy + 0.8f * d.h_e * Fy) * ip * P2 + P5 - d.s_q * P6 -
-                (2.0f * d.s_nu * uy + 2.0f * d.h_nu * Fy) * ip * P7 +
-                (d.s_nu * ux + d.h_nu * Fx) * ip * P8;
+                (2.0f * c.s_nu * uy + 2.0f * c.h_nu * Fy) * ip * P7 +
+                (c.s_nu * ux + c.h_nu * Fx) * ip * P8;
     const float Fbx = 0.8f * d.h_e * ux * ip * P2 + 0.5f * P3 - d.h_q * P4 +
-                      2.0f * d.h_nu * ux * ip * P7 + d.h_nu * uy * ip * P8;
+                      2.0f * c.h_nu * ux * ip * P7 + c.h_nu * uy * ip * P8;
     const float Fby = 0.8f * d.h_e * uy * ip * P2 + 0.5f * P5 - d.h_q * P6 -
-                      2.0f * d.h_nu * uy * ip * P7 + d.h_nu * ux * ip * P8;
+                      2.0f * c.h_nu * uy * ip * P7 + c.h_nu * ux * ip * P8;
     pb.ip = (0.4f * d.s_e * u2 + 0.8f * d.h_e * uF) * P2 +
-            (d.s_nu * (ux * ux - uy * uy) + 2.0f * d.h_nu * (ux * Fx - uy * Fy)) * P7 +
-            (d.s_nu * ux * uy + d.h_nu * (ux * Fy + uy * Fx)) * P8;
+            (c.s_nu * (ux * ux - uy * uy) + 2.0f * c.h_nu * (ux * Fx - uy * Fy)) * P7 +
+            (c.s_nu * ux * uy + c.h_nu * (ux * Fy + uy * Fx)) * P8;
 
     // F = phi a - (cd + cf |u|) u  (Eq. 3)
     const float uFb = ux * Fbx + uy * Fby;

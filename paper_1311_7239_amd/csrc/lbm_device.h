@@ -46,6 +46,7 @@ struct Dom {
     float ax, ay;                    // uniform external acceleration
     const float *phi;                // [ny][pitch] (MED_PHI_*)
     const float *kappa;              // [ny][pitch] (MED_PHI_KAPPA)
+    const float *snu;                // [ny][pitch] per-node s_nu (NULL: s_nu everywhere)
     // thermal (App. B); deviations from wT*T0
     int32_t thermal;
     float zT, z3, z4;                // 1/tau_T, zeta3, zeta4
@@ -97,6 +98,7 @@ struct Cell {
     float phi, inv_phi;
     float cd;   // phi nu / K             (linear drag coefficient, Eq. 3)
     float cf;   // phi F_phi / sqrt(K)    (Forchheimer coefficient, Eq. 3)
+    float s_nu, h_nu;  // s_7 = s_8 = 1/tau of the node's own J (Eq. 21) and 1 - s_nu/2
 };
 
 // Ergun's F_phi (Eq. 4): 1.75 / sqrt(150 phi^3) = (1.75/sqrt(150)) phi^{-3/2}.
@@ -108,6 +110,7 @@ __device__ __forceinline__ float ergun_F(float inv_phi) {
 // plane); kappa is ignored unless the medium is MED_PHI_KAPPA.
 __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_plane) {
     Cell c;
+    c.s_nu = d.s_nu; c.h_nu = d.h_nu;
     if (d.medium == MED_UNIFORM) {
         c.phi = d.phi0; c.inv_phi = d.inv_phi0; c.cd = d.cd0; c.cf = d.cf0;
         return c;
@@ -127,9 +130,23 @@ __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_p
     return c;
 }
 
+// A node with its own viscosity ratio J (partially porous domains, where the
+// porous part has nu_e = J nu and the free fluid nu_e = nu) relaxes its stress
+// moments at its own rate; the plane holds s_nu and 1 - s_nu/2 follows here.
+__device__ __forceinline__ void cell_viscosity(const Dom &d, Cell &c, int64_t idx) {
+    if (d.snu) {
+        const float s = d.snu[idx];
+        c.s_nu = s;
+        c.h_nu = 1.0f - 0.5f * s;
+    }
+}
+
 __device__ __forceinline__ Cell load_cell(const Dom &d, int64_t idx) {
-    if (d.medium == MED_UNIFORM) return cell_from(d, 0.0f, 0.0f);
-    return cell_from(d, d.phi[idx], d.medium == MED_PHI_KAPPA ? d.kappa[idx] : 0.0f);
+    Cell c = (d.medium == MED_UNIFORM)
+                 ? cell_from(d, 0.0f, 0.0f)
+                 : cell_from(d, d.phi[idx], d.medium == MED_PHI_KAPPA ? d.kappa[idx] : 0.0f);
+    cell_viscosity(d, c, idx);
+    return c;
 }
 
 // Eqs. (18)-(19) in cancellation-free form. With d = cd/2 and
@@ -209,9 +226,9 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
     const float m4p = m4 - d.s_q * (m4 + ux) - d.h_q * Fx;
     const float m6p = m6 - d.s_q * (m6 + uy) - d.h_q * Fy;
     // p_xx^eq = (ux^2 - uy^2)/phi, p_xy^eq = ux uy / phi (gamma1 = gamma3 = 2/3)
-    const float m7p = m7 - d.s_nu * (m7 - (ux * ux - uy * uy) * ip) +
-                      d.h_nu * (2.0f * (ux * Fx - uy * Fy) * ip);
-    const float m8p = m8 - d.s_nu * (m8 - ux * uy * ip) + d.h_nu * ((ux * Fy + uy * Fx) * ip);
+    const float m7p = m7 - c.s_nu * (m7 - (ux * ux - uy * uy) * ip) +
+                      c.h_nu * (2.0f * (ux * Fx - uy * Fy) * ip);
+    const float m8p = m8 - c.s_nu * (m8 - ux * uy * ip) + c.h_nu * ((ux * Fy + uy * Fx) * ip);
 
     // f+ = M^T diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m+
     const float A = 0.125f * m1, B = 0.125f * m2p;

@@ -84,7 +84,8 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
 #pragma unroll
                     for (int j = 0; j < 5; ++j) gn[j] = g[THERMAL ? r : 0][j][k];
                 }
-                const Cell c = cell_from(d, ph[r][k], kp[r][k]);
+                Cell c = cell_from(d, ph[r][k], kp[r][k]);
+                cell_viscosity(d, c, o + k);
                 node_update<THERMAL>(d, c, fn, gn, ux[k], uy[k]);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) f[r][i][k] = fn[i];
@@ -594,6 +595,31 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st) {
     size_t blocks = (n16 + BLOCK - 1) / BLOCK;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(BLOCK), 0, st, (uint4 *)p, n16);
+    return hipGetLastError();
+}
+
+// Per-node s_nu = 1 / (1/2 + 3 J nu) (Eq. 21, cs^2 = 1/3) from a [ny][nx]
+// plane of viscosity ratios J (or the constant J0 where J is NULL), in double
+// and rounded once, so a plane of constant J holds the uniform rate exactly.
+// With `bad` set the kernel only checks: any J that is not finite and > 0
+// stores 1 there (every such thread stores the same value), and out is untouched.
+__global__ __launch_bounds__(BLOCK) void k_snu_plane(const float *J, double J0, double nu,
+                                                     float *out, int pitch, int nx, int *bad) {
+    const int x = blockIdx.x * BLOCK + threadIdx.x, y = blockIdx.y;
+    if (x >= nx) return;
+    const double j = J ? (double)J[(int64_t)y * nx + x] : J0;
+    if (bad) {
+        if (!(j > 0.0 && j <= 3.4e38)) *bad = 1;
+        return;
+    }
+    const double tau = 0.5 + 3.0 * j * nu;
+    out[(int64_t)y * pitch + x] = (float)(1.0 / tau);
+}
+
+hipError_t launch_snu_plane(const float *J, double J0, double nu, float *out, int pitch, int nx,
+                            int ny, int *bad, hipStream_t st) {
+    const dim3 grid((unsigned)((nx + BLOCK - 1) / BLOCK), (unsigned)ny);
+    hipLaunchKernelGGL(k_snu_plane, grid, dim3(BLOCK), 0, st, J, J0, nu, out, pitch, nx, bad);
     return hipGetLastError();
 }
 

@@ -85,6 +85,8 @@ hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out
 // u(t) and u(t-1).
 hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
                                 const float *u_tm1, float *gphi, float *gkappa, hipStream_t st);
+hipError_t launch_snu_plane(const float *J, double J0, double nu, float *out, int pitch, int nx,
+                            int ny, int *bad, hipStream_t st);
 hipError_t launch_unpitch(const float *src, int pitch, float *dst, int nx, int ny,
                           hipStream_t st);
 

@@ -41,6 +41,8 @@ class Case:
     phi: Optional[np.ndarray] = None   # float32 [ny, nx] porosity field
     dp: Optional[float] = None   # particle diameter for Eq. (4) when phi varies
     Fphi: Optional[float] = None  # constant F_phi, or None for Eq. (4) per cell
+    kappa: Optional[np.ndarray] = None  # float32 [ny, nx] 1/K plane (0 = free fluid); with phi
+    Jfield: Optional[np.ndarray] = None  # float32 [ny, nx] per-node viscosity ratio
     Pi0: float = 1.0             # rest value of phi*p (initial state)
     steps: int = 0
     thermal: bool = False
@@ -106,6 +108,23 @@ def poiseuille_channel(ny: int = 64, nx: int = 8, phi: float = 0.1, Da: float = 
     return Case(name=f"poiseuille_{nx}x{ny}", nx=nx, ny=ny, bc_x=PERIODIC, bc_y=WALLS,
                 nu=nu, J=J, ax=ax, phi0=phi, K0=K, Fphi=ergun_F(phi) if forchheimer else 0.0,
                 Pi0=phi, meta=dict(L=L, u0=u0, Da=Da, Re=Re))
+
+
+def partial_couette(J: float = 4.0, ny: int = 80, nx: int = 2, phi: float = 0.1,
+                    Da: float = 1e-3, Re: float = 0.01, nu: float = 0.16) -> Case:
+    """Couette flow in a channel partially filled with a porous layer (Sec. 3.2,
+    Eq. 25): nodes with (y + 1/2)/L <= 1/2 are porous (porosity phi, K = Da L^2,
+    viscosity ratio J), the rest free fluid (phi = 1, no matrix, J = 1);
+    F_phi = 0, moving lid u0 = Re nu / L, L = ny."""
+    L = float(ny)
+    u0 = Re * nu / L
+    porous = ((np.arange(ny) + 0.5) / L <= 0.5)[:, None] & np.ones((1, nx), dtype=bool)
+    phif = np.where(porous, phi, 1.0).astype(np.float32)
+    kap = np.where(porous, 1.0 / (Da * L * L), 0.0).astype(np.float32)
+    Jf = np.where(porous, J, 1.0).astype(np.float32)
+    return Case(name=f"partial_couette_J{J:g}_{nx}x{ny}", nx=nx, ny=ny, bc_x=PERIODIC,
+                bc_y=WALLS, nu=nu, J=1.0, lid_ux=u0, phi=phif, kappa=kap, Fphi=0.0,
+                Jfield=Jf, Pi0=1.0, meta=dict(L=L, u0=u0, Da=Da, Re=Re, phi_p=phi, J_p=J))
 
 
 def couette_channel(ny: int = 64, nx: int = 2, phi: float = 0.1, Da: float = 1e-2,

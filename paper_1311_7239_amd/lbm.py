@@ -46,7 +46,8 @@ class Desc(ctypes.Structure):
                 ("kappa0", ctypes.c_double), ("dp", ctypes.c_double),
                 ("F_eps", ctypes.c_double), ("ax", ctypes.c_double), ("ay", ctypes.c_double),
                 ("Pi0", ctypes.c_double), ("storage", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32), ("thermal", Thermal)]
+                ("ckpt_every", ctypes.c_int32), ("j_plane", ctypes.c_int32),
+                ("thermal", Thermal)]
 
 
 _vp = ctypes.c_void_p
@@ -87,6 +88,7 @@ def lib():
         L.lbm_set_schedule.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_int32]
         L.lbm_set_graph_steps.argtypes = [_vp, ctypes.c_int32]
+        L.lbm_set_viscosity_ratio.argtypes = [_vp, ctypes.c_int32, _vp]
         L.lbm_set_time_blocking.argtypes = [_vp, ctypes.c_int32]
         L.lbm_set_two_cycle_tile.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32]
         L.lbm_time_blocking.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int32)] * 4
@@ -117,9 +119,12 @@ def desc_from_case(case, storage: int = FP32_DEV, ckpt_every: int = 0) -> Desc:
         d.medium = MEDIUM_UNIFORM
         d.phi0 = case.phi0
         d.kappa0 = 0.0 if math.isinf(case.K0) else 1.0 / case.K0
+    elif getattr(case, "kappa", None) is not None:
+        d.medium = MEDIUM_PHI_KAPPA
     else:
         d.medium = MEDIUM_PHI_ERGUN
         d.dp = case.dp
+    d.j_plane = 1 if getattr(case, "Jfield", None) is not None else 0
     d.storage = storage
     d.ckpt_every = ckpt_every
     if case.thermal:
@@ -243,6 +248,10 @@ class Solver:
     def set_graph_steps(self, steps: int):
         check(lib().lbm_set_graph_steps(self._ctx, int(steps)))
 
+    def set_viscosity_ratio(self, J: torch.Tensor):
+        """Per-node viscosity ratio J [ny, nx] (needs desc.j_plane = 1)."""
+        check(lib().lbm_set_viscosity_ratio(self._ctx, 0, _ptr(J.contiguous())))
+
     def set_time_blocking(self, cycles_per_pass: int):
         check(lib().lbm_set_time_blocking(self._ctx, int(cycles_per_pass)))
 
@@ -265,13 +274,19 @@ def _time_blocking(ctx):
     return {"cycles_per_pass": v[0].value, "threads": v[1].value, "rows": v[2].value, "grid": v[3].value}
 
 
+def _plane(a, device):
+    return None if a is None else torch.from_numpy(a.astype("float32")).to(device)
+
+
 def solver_for_case(case, storage: int = FP32_DEV, ckpt_every: int = 0, max_steps_recorded: int = 0,
                     device="cuda") -> Solver:
     desc = desc_from_case(case, storage=storage, ckpt_every=ckpt_every)
-    phi = None
-    if case.phi is not None:
-        phi = torch.from_numpy(case.phi.astype("float32")).to(device)
-    return Solver(desc, phi=phi, max_steps_recorded=max_steps_recorded, device=device)
+    kappa = _plane(getattr(case, "kappa", None), device)
+    s = Solver(desc, phi=_plane(case.phi, device), kappa=kappa,
+               max_steps_recorded=max_steps_recorded, device=device)
+    if getattr(case, "Jfield", None) is not None:
+        s.set_viscosity_ratio(_plane(case.Jfield, device))
+    return s
 
 
 class Batch:
@@ -328,6 +343,9 @@ class Batch:
     def set_time_blocking(self, cycles_per_pass: int):
         check(lib().lbm_set_time_blocking(self._ctx, int(cycles_per_pass)))
 
+    def set_viscosity_ratio(self, k: int, J: torch.Tensor):
+        check(lib().lbm_set_viscosity_ratio(self._ctx, int(k), _ptr(J.contiguous())))
+
     def time_blocking(self):
         return _time_blocking(self._ctx)
 
@@ -360,8 +378,13 @@ class Batch:
 
 def batch_for_cases(cases, storage: int = FP32_DEV, tune_cache=None, device="cuda") -> Batch:
     descs = [desc_from_case(c, storage=storage) for c in cases]
-    phis = None
+    phis = kappas = None
     if any(c.phi is not None for c in cases):
-        phis = [None if c.phi is None else torch.from_numpy(c.phi.astype("float32")).to(device)
-                for c in cases]
-    return Batch(descs, phis=phis, tune_cache=tune_cache, device=device)
+        phis = [_plane(c.phi, device) for c in cases]
+    if any(getattr(c, "kappa", None) is not None for c in cases):
+        kappas = [_plane(getattr(c, "kappa", None), device) for c in cases]
+    b = Batch(descs, phis=phis, kappas=kappas, tune_cache=tune_cache, device=device)
+    for k, c in enumerate(cases):
+        if getattr(c, "Jfield", None) is not None:
+            b.set_viscosity_ratio(k, _plane(c.Jfield, device))
+    return b

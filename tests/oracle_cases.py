@@ -8,11 +8,21 @@ def oracle_setup(case, nthreads=0):
     p = oracle.make_params(case.nx, case.ny, bc_x=case.bc_x, bc_y=case.bc_y, lid_ux=case.lid_ux,
                            nu=case.nu, J=case.J, ax=case.ax, ay=case.ay, thermal=case.thermal,
                            sigma=case.sigma, tau_T=case.tau_T, Th=case.Th, Tc=case.Tc,
-                           T0=case.T0, gbeta=case.gbeta, nthreads=nthreads)
+                           T0=case.T0, gbeta=case.gbeta, nthreads=nthreads,
+                           Jcell=getattr(case, "Jfield", None))
     shape = (case.ny, case.nx)
     if case.phi is None:
         phi = np.full(shape, case.phi0, dtype=np.float64)
         K = np.full(shape, case.K0, dtype=np.float64)
+        if case.Fphi is None:
+            _, F = oracle.ergun(phi, 1.0)
+        else:
+            F = np.full(shape, case.Fphi, dtype=np.float64)
+    elif getattr(case, "kappa", None) is not None:
+        phi = case.phi.astype(np.float64)
+        kap = case.kappa.astype(np.float64)
+        with np.errstate(divide="ignore"):
+            K = np.where(kap > 0.0, 1.0 / kap, np.inf)
         if case.Fphi is None:
             _, F = oracle.ergun(phi, 1.0)
         else:

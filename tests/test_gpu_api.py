@@ -1,0 +1,91 @@
+"""State handling of the C ABI on the GPU: snapshots, instability detection, argument
+checks that need a live context."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1311_7239_amd import inputs as I
+from paper_1311_7239_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+
+def test_save_load_round_trip_is_bitwise():
+    case = I.lid_cavity(n=96, heterogeneous=True, ell=8.0)
+    a = lbm.solver_for_case(case)
+    a.step(57)
+    blob = a.save()
+    a.step(40)
+    ref, _ = a.populations()
+    _, res_ref, _ = a.reduce()
+    b = lbm.solver_for_case(case)
+    b.load(blob)
+    assert b.time == 57
+    b.step(40)
+    got, _ = b.populations()
+    _, res, _ = b.reduce()
+    torch.cuda.synchronize()
+    assert torch.equal(ref, got) and res == res_ref
+
+
+def test_load_rejects_a_snapshot_of_another_descriptor():
+    a = lbm.solver_for_case(I.lid_cavity(n=64))
+    blob = a.save()
+    other = I.lid_cavity(n=64)
+    other.nu *= 2
+    b = lbm.solver_for_case(other)
+    with pytest.raises(lbm.LBMError) as e:
+        b.load(blob)
+    assert e.value.status == lbm.EINVAL
+    with pytest.raises(lbm.LBMError):
+        a.load(blob[:100])
+
+
+def test_non_finite_state_is_reported_unstable():
+    case = I.lid_cavity(n=64)
+    s = lbm.solver_for_case(case)
+    df = torch.zeros((8, 64, 64), device="cuda")
+    df[3, 10, 20] = float("nan")
+    s.set_populations(df)
+    s.step(3)
+    mass, res, st = s.reduce()
+    assert st == lbm.EUNSTABLE
+    assert not np.isfinite(mass)
+
+
+def test_thermal_populations_round_trip_and_time():
+    case = I.natural_convection(n=48)
+    s = lbm.solver_for_case(case)
+    dg = I.random_deviation_state(48, 48, 0.5, seed=3, channels=5)
+    s.set_populations(torch.zeros((8, 48, 48), device="cuda"), torch.from_numpy(dg).cuda())
+    assert s.time == 0
+    _, g = s.populations(thermal=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.cpu().numpy(), dg)
+    s.step(5)
+    assert s.time == 5
+
+
+def test_argument_checks_on_a_live_context():
+    case = I.lid_cavity(n=64)
+    s = lbm.solver_for_case(case)
+    for bad in (3, -2, 5000):
+        with pytest.raises(lbm.LBMError) as e:
+            s.set_graph_steps(bad)
+        assert e.value.status == lbm.EINVAL
+    with pytest.raises(lbm.LBMError) as e:
+        s.set_schedule(100, 1, 1)
+    assert e.value.status == lbm.EINVAL
+    with pytest.raises(lbm.LBMError) as e:
+        s.set_time_blocking(3)
+    assert e.value.status == lbm.EINVAL
+    with pytest.raises(lbm.LBMError) as e:
+        s.macroscopic(want_T=True)          # no thermal model
+    assert e.value.status == lbm.EINVAL
+    t = lbm.solver_for_case(I.natural_convection(n=32))
+    with pytest.raises(lbm.LBMError) as e:
+        t.set_time_blocking(2)
+    assert e.value.status == lbm.ENOTSUP
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lib().lbm_step and s.step(-1)
+    assert e.value.status == lbm.EINVAL

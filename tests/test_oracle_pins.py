@@ -245,6 +245,31 @@ def test_couette_matches_closed_form():
     assert 1.7 < np.log2(errs[0] / errs[1]) < 2.3
 
 
+@pytest.mark.parametrize("J", [1.0, 4.0])
+def test_partially_porous_couette_matches_eq25(J):
+    """Sec. 3.2, Eq. (25): porous layer (phi = 0.1, Da = 1e-3, viscosity ratio J)
+    under free fluid (phi = 1, J = 1), nu = 0.16, Re = 0.01, F_phi = 0. The
+    layer's own relaxation rate 1/(1/2 + 3 J nu) comes from the per-node J.
+    The steady profile converges to the exact finite-layer form at second
+    order and, at the paper's 80 nodes, lies within 3e-4 u0 of it."""
+    errs = []
+    for ny in (40, 80):
+        case = I.partial_couette(J=J, ny=ny)
+        p, phi, K, F = oracle_setup(case, nthreads=1)
+        f = oracle.rest_state(p, case.Pi0)
+        _, ux, uy = run_to_steady(p, phi, K, F, f, tol=1e-10, every=200)
+        y = np.arange(ny) + 0.5
+        ref = A.partial_couette(y, ny, case.lid_ux, 0.1, 1e-3, J)
+        errs.append(np.abs(ux[:, 0] - ref).max() / case.lid_ux)
+        assert np.abs(uy).max() < 1e-12 * case.lid_ux * 1e3
+    assert errs[1] < 3e-4
+    assert 1.7 < np.log2(errs[0] / errs[1]) < 2.3
+    if J != 1.0:
+        # the per-node J must matter: the J = 1 profile is far from this one
+        other = A.partial_couette(y, ny, case.lid_ux, 0.1, 1e-3, 1.0)
+        assert np.abs(other - ref).max() / case.lid_ux > 100 * errs[1]
+
+
 def test_free_fluid_limit_is_parabolic():
     """Sec. 2.2 end: phi = 1 and K -> infinity give the free-fluid model; plane
     Poiseuille flow is then the parabola a y (L - y) / (2 nu)."""
