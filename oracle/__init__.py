@@ -27,6 +27,7 @@ _lib = None
 
 PERIODIC = 0
 WALLS = 1
+NEE = 2
 
 
 def build(force: bool = True) -> pathlib.Path:

@@ -13,7 +13,8 @@
  *   f_i(x + e_i, t + 1) = f_i+(x, t) (Eq. 15).
  * Boundaries: periodic wrap, or halfway bounce-back on walls half a link
  * outside the edge nodes; a link that crosses the top wall y = ny picks up
- * the moving-wall term of the lid (corners included).
+ * the moving-wall term of the lid (corners included). Or on-node walls with
+ * non-equilibrium extrapolation (the paper's default, Sec. 3, Ref. [40]).
  */
 #include "oracle.h"
 
@@ -314,6 +315,9 @@ static double buoyancy_y(const orc_params *p, double T)
     return p->gbeta * (T - p->T0);
 }
 
+static void nee_walls(const orc_params *p, const double *phi, const double *K, const double *Fphi,
+                      double *f, double *g);
+
 void orc_step(const orc_params *p, const double *phi, const double *K, const double *Fphi,
               const double *f, double *fnew, const double *g, double *gnew)
 {
@@ -346,6 +350,9 @@ void orc_step(const orc_params *p, const double *phi, const double *K, const dou
                 if (out_y && p->bc_y == ORC_PERIODIC) { yt = (yt + ny) % ny; out_y = 0; }
                 if (!out_x && !out_y) {
                     fnew[((long)yt * nx + xt) * 8 + i] = fp[i];
+                } else if ((out_x && p->bc_x == ORC_NEE) || (out_y && p->bc_y == ORC_NEE)) {
+                    /* leaves through an on-node wall: the wall node's own
+                     * populations are rebuilt after streaming */
                 } else {
                     /* halfway bounce-back; the link returns to this node as
                      * the opposite population, with the moving-wall term
@@ -366,6 +373,8 @@ void orc_step(const orc_params *p, const double *phi, const double *K, const dou
                     if (out_y && p->bc_y == ORC_PERIODIC) { yt = (yt + ny) % ny; out_y = 0; }
                     if (!out_x && !out_y) {
                         gnew[((long)yt * nx + xt) * 5 + j] = gp[j];
+                    } else if ((out_x && p->bc_x == ORC_NEE) || (out_y && p->bc_y == ORC_NEE)) {
+                        /* rebuilt after streaming, as for f */
                     } else if (out_x) {
                         /* Dirichlet walls (hot x = 0, cold x = nx): anti-bounce-back */
                         double Tw = (xt < 0) ? p->Th : p->Tc;
@@ -375,6 +384,81 @@ void orc_step(const orc_params *p, const double *phi, const double *K, const dou
                         gnew[k * 5 + opposite5(j)] = gp[j];
                     }
                 }
+            }
+        }
+    }
+    if (p->bc_x == ORC_NEE || p->bc_y == ORC_NEE) nee_walls(p, phi, K, Fphi, fnew, thermal ? gnew : NULL);
+}
+
+/* Eq. (22): equilibrium populations at porosity phi, pressure pres, velocity u. */
+static void feq_eq22(const orc_params *p, double phi, double pres, double ux, double uy,
+                     double feq[8])
+{
+    const double r = p->rho0;
+    const double u2 = ux * ux + uy * uy;
+    for (int i = 0; i < 8; ++i) {
+        const double eu = EX[i] * ux + EY[i] * uy;
+        feq[i] = r * W[i] * (phi * pres / (r * CS2) + eu / CS2 + eu * eu / (2.0 * phi * CS2 * CS2) -
+                             u2 / (2.0 * phi * CS2));
+    }
+}
+
+/* Thermal equilibrium g^eq = N^-1 n^eq with n^eq of Eq. (B.6). */
+static void geq_b6(const orc_params *p, double T, double ux, double uy, double geq[5])
+{
+    const double neq[5] = {T, ux * T / p->sigma, uy * T / p->sigma, p->varpi * T, 0.0};
+    for (int j = 0; j < 5; ++j) {
+        double acc = 0.0;
+        for (int a = 0; a < 5; ++a) acc += NINV[j][a] * neq[a];
+        geq[j] = acc;
+    }
+}
+
+/* Non-equilibrium extrapolation at on-node walls (Sec. 3, Ref. [40]).
+ * Every population of a wall node O is the equilibrium at the wall's state
+ * plus the non-equilibrium part of the next node B inward along the normal
+ * (diagonally inward at a corner), all at the same time:
+ *   f(O) = f^eq(phi_O, p_O, u_w) + [f(B) - f^eq(phi_B, p_B, u_B)],
+ * f^eq from Eq. (22), u_B and p_B from Eqs. (18)-(20) at B (with B's force),
+ * the wall taking B's phi p (phi_O p_O = phi_B p_B) and the wall velocity
+ * u_w: the lid velocity on the top wall away from on-node x walls (the top
+ * corners of a cavity stay at rest), zero elsewhere. Temperature likewise:
+ *   g(O) = g^eq(T_w, u_w) + [g(B) - g^eq(T_B, u_B)],
+ * T_w = Th / Tc on the x walls (Dirichlet, corners included) and T_w = T_B
+ * on the y walls (adiabatic). B is never a wall node (>= 3 nodes per axis). */
+static void nee_walls(const orc_params *p, const double *phi, const double *K, const double *Fphi,
+                      double *f, double *g)
+{
+    const int nx = p->nx, ny = p->ny;
+    const int thermal = p->thermal && g;
+    for (int y = 0; y < ny; ++y) {
+        for (int x = 0; x < nx; ++x) {
+            const int wx = p->bc_x == ORC_NEE && (x == 0 || x == nx - 1);
+            const int wy = p->bc_y == ORC_NEE && (y == 0 || y == ny - 1);
+            if (!wx && !wy) continue;
+            const int bx = wx ? (x == 0 ? 1 : nx - 2) : x;
+            const int by = wy ? (y == 0 ? 1 : ny - 2) : y;
+            const long ko = (long)y * nx + x, kb = (long)by * nx + bx;
+            double ax = p->ax, ay = p->ay, TB = 0.0;
+            if (thermal) {
+                for (int j = 0; j < 5; ++j) TB += g[kb * 5 + j];
+                ay += buoyancy_y(p, TB);
+            }
+            double uB[2], FB[2];
+            orc_velocity(p, phi[kb], K[kb], Fphi[kb], ax, ay, &f[kb * 8], uB, FB);
+            const double pB = orc_pressure(p, phi[kb], &f[kb * 8], uB[0], uB[1]);
+            const double pO = phi[kb] * pB / phi[ko];
+            const double uwx = (wy && y == ny - 1 && !wx) ? p->lid_ux : 0.0;
+            double eO[8], eB[8];
+            feq_eq22(p, phi[ko], pO, uwx, 0.0, eO);
+            feq_eq22(p, phi[kb], pB, uB[0], uB[1], eB);
+            for (int i = 0; i < 8; ++i) f[ko * 8 + i] = eO[i] + (f[kb * 8 + i] - eB[i]);
+            if (thermal) {
+                const double Tw = wx ? (x == 0 ? p->Th : p->Tc) : TB;
+                double hO[5], hB[5];
+                geq_b6(p, Tw, uwx, 0.0, hO);
+                geq_b6(p, TB, uB[0], uB[1], hB);
+                for (int j = 0; j < 5; ++j) g[ko * 5 + j] = hO[j] + (g[kb * 5 + j] - hB[j]);
             }
         }
     }

@@ -28,13 +28,17 @@
 extern "C" {
 #endif
 
-enum { ORC_PERIODIC = 0, ORC_WALLS = 1 };
+/* ORC_WALLS: halfway bounce-back, walls half a link outside the edge nodes.
+ * ORC_NEE: the first and last node of the axis lie on the walls, treated by
+ * non-equilibrium extrapolation (Sec. 3, its Ref. [40]); an axis with ORC_NEE
+ * needs >= 3 nodes and the other axis ORC_PERIODIC or ORC_NEE. */
+enum { ORC_PERIODIC = 0, ORC_WALLS = 1, ORC_NEE = 2 };
 
 typedef struct {
     int nx, ny;
-    int bc_x;        /* ORC_PERIODIC, or ORC_WALLS at x = 0 and x = nx        */
-    int bc_y;        /* ORC_PERIODIC, or ORC_WALLS at y = 0 and y = ny        */
-    double lid_ux;   /* x-velocity of the wall y = ny (moving lid); 0 = rest  */
+    int bc_x;        /* ORC_PERIODIC, ORC_WALLS (x = 0, x = nx) or ORC_NEE    */
+    int bc_y;        /* ORC_PERIODIC, ORC_WALLS (y = 0, y = ny) or ORC_NEE    */
+    double lid_ux;   /* x-velocity of the top wall (moving lid); 0 = rest     */
     double rho0;     /* mean density (Eq. 2)                                  */
     double nu;       /* fluid kinematic viscosity (Eq. 3)                     */
     double J;        /* viscosity ratio nu_e / nu (Eq. 5)                     */
@@ -89,7 +93,9 @@ void orc_collide_node(const orc_params *p, double phi, double K, double Fphi,
 
 /* One collide-and-stream step (Eqs. 14-15), push scheme, f -> fnew
  * (and g -> gnew when p->thermal). Arrays are node-major as above.
- * phi, K, Fphi are per node; K may be +inf (free fluid). */
+ * phi, K, Fphi are per node; K may be +inf (free fluid). With ORC_NEE axes
+ * the wall nodes of fnew (and gnew) are rebuilt by non-equilibrium
+ * extrapolation after streaming, so every stored state past t = 0 is whole. */
 void orc_step(const orc_params *p, const double *phi, const double *K, const double *Fphi,
               const double *f, double *fnew, const double *g, double *gnew);
 /* nsteps steps in place (internal double buffer). Returns 0, or -1 on

@@ -20,7 +20,8 @@ from typing import Optional
 import numpy as np
 
 PERIODIC = 0
-WALLS = 1
+WALLS = 1   # halfway bounce-back: walls half a link outside the edge nodes, L = n
+NEE = 2     # on-node walls (non-equilibrium extrapolation): L = n - 1
 
 
 @dataclasses.dataclass
@@ -95,18 +96,19 @@ def grf(ny: int, nx: int, ell: float, seed: int) -> np.ndarray:
 
 def poiseuille_channel(ny: int = 64, nx: int = 8, phi: float = 0.1, Da: float = 1e-2,
                        Re: float = 0.01, tau: float = 0.6, J: float = 1.0,
-                       forchheimer: bool = True) -> Case:
-    """Porous Poiseuille channel (Sec. 3.1): x periodic, walls at y = 0 and y = ny,
-    L = ny, K = Da L^2; a_x chosen so that the Brinkman centreline velocity of
-    Eq. (24) equals u0 = Re nu / L."""
-    L = float(ny)
+                       forchheimer: bool = True, nee: bool = False) -> Case:
+    """Porous Poiseuille channel (Sec. 3.1): x periodic, walls at y = 0 and y = L
+    (L = ny with bounce-back walls, ny - 1 with on-node NEE walls), K = Da L^2;
+    a_x chosen so that the Brinkman centreline velocity of Eq. (24) equals
+    u0 = Re nu / L."""
+    L = float(ny - 1 if nee else ny)
     nu = (tau - 0.5) / (3.0 * J)
     K = Da * L * L
     u0 = Re * nu / L
     th = math.sqrt(phi * nu / (K * J * nu))
     ax = u0 * nu / (K * (1.0 - 1.0 / math.cosh(0.5 * th * L)))
-    return Case(name=f"poiseuille_{nx}x{ny}", nx=nx, ny=ny, bc_x=PERIODIC, bc_y=WALLS,
-                nu=nu, J=J, ax=ax, phi0=phi, K0=K, Fphi=ergun_F(phi) if forchheimer else 0.0,
+    return Case(name=f"poiseuille_{nx}x{ny}" + ("_nee" if nee else ""), nx=nx, ny=ny,
+                bc_x=PERIODIC, bc_y=NEE if nee else WALLS, nu=nu, J=J, ax=ax, phi0=phi, K0=K, Fphi=ergun_F(phi) if forchheimer else 0.0,
                 Pi0=phi, meta=dict(L=L, u0=u0, Da=Da, Re=Re))
 
 
@@ -128,26 +130,30 @@ def partial_couette(J: float = 4.0, ny: int = 80, nx: int = 2, phi: float = 0.1,
 
 
 def couette_channel(ny: int = 64, nx: int = 2, phi: float = 0.1, Da: float = 1e-2,
-                    Re: float = 0.01, nu: float = 0.1, J: float = 1.0) -> Case:
-    """Porous Couette flow (Sec. 3.2) with F_phi = 0: moving top wall, u0 = Re nu / L."""
-    L = float(ny)
+                    Re: float = 0.01, nu: float = 0.1, J: float = 1.0, nee: bool = False) -> Case:
+    """Porous Couette flow (Sec. 3.2) with F_phi = 0: moving top wall, u0 = Re nu / L
+    (L = ny, or ny - 1 with on-node NEE walls)."""
+    L = float(ny - 1 if nee else ny)
     u0 = Re * nu / L
-    return Case(name=f"couette_{nx}x{ny}", nx=nx, ny=ny, bc_x=PERIODIC, bc_y=WALLS, nu=nu,
+    return Case(name=f"couette_{nx}x{ny}" + ("_nee" if nee else ""), nx=nx, ny=ny, bc_x=PERIODIC,
+                bc_y=NEE if nee else WALLS, nu=nu,
                 J=J, lid_ux=u0, phi0=phi, K0=Da * L * L, Fphi=0.0, Pi0=phi,
                 meta=dict(L=L, u0=u0, Da=Da, Re=Re))
 
 
 def lid_cavity(n: int = 512, phi: float = 0.4, Da: float = 1e-2, Re: float = 100.0,
                U: float = 0.1, heterogeneous: bool = False, seed: int = 2,
-               ell: float = 32.0, steps: int = 50_000) -> Case:
+               ell: float = 32.0, steps: int = 50_000, nee: bool = False) -> Case:
     """Lid-driven porous cavity (Sec. 3.3 setting): walls all round, top wall moving at U,
-    nu = U L / Re, K = Da L^2. The heterogeneous variant draws
-    phi = clip(phi + 0.1 G, 0.2, 0.9) from a GRF G (correlation length ell) and keeps
-    a fixed particle diameter, so that K(phi) follows Eq. (4) through K(phi) = Da L^2."""
-    L = float(n)
+    nu = U L / Re, K = Da L^2 (L = n, or n - 1 with on-node NEE walls). The
+    heterogeneous variant draws phi = clip(phi + 0.1 G, 0.2, 0.9) from a GRF G
+    (correlation length ell) and keeps a fixed particle diameter, so that K(phi)
+    follows Eq. (4) through K(phi) = Da L^2."""
+    L = float(n - 1 if nee else n)
     nu = U * L / Re
     K = Da * L * L
-    case = Case(name=f"cavity_{n}", nx=n, ny=n, bc_x=WALLS, bc_y=WALLS, nu=nu, lid_ux=U,
+    bc = NEE if nee else WALLS
+    case = Case(name=f"cavity_{n}" + ("_nee" if nee else ""), nx=n, ny=n, bc_x=bc, bc_y=bc, nu=nu, lid_ux=U,
                 phi0=phi, K0=K, Fphi=ergun_F(phi), Pi0=phi, steps=steps,
                 meta=dict(L=L, Da=Da, Re=Re, U=U))
     if heterogeneous:
@@ -165,12 +171,12 @@ def lid_cavity(n: int = 512, phi: float = 0.4, Da: float = 1e-2, Re: float = 100
 def natural_convection(n: int = 1024, phi: float = 0.6, Da: float = 1e-4, Ra: float = 1e5,
                        Pr: float = 1.0, Ma: float = 0.1, J: float = 1.0, sigma: float = 1.0,
                        gamma: float = 1.0, Th: float = 21.0, Tc: float = 1.0,
-                       steps: int = 2000) -> Case:
+                       steps: int = 2000, nee: bool = False) -> Case:
     """Natural convection in a porous square cavity (Sec. 3.4): no-slip walls, hot wall
-    x = 0, cold wall x = L, adiabatic top and bottom. Relaxation times from Eq. (26)
-    with c_sT^2 = 2/5 (varpi = 0), the viscosity from Eq. (21), g*beta from the
-    definition of Ra."""
-    L = float(n)
+    x = 0, cold wall x = L, adiabatic top and bottom (L = n, or n - 1 with on-node
+    NEE walls). Relaxation times from Eq. (26) with c_sT^2 = 2/5 (varpi = 0), the
+    viscosity from Eq. (21), g*beta from the definition of Ra."""
+    L = float(n - 1 if nee else n)
     tau_v = 0.5 + Ma * J * L * math.sqrt(3.0 * Pr) / math.sqrt(Ra)
     nu_e = (tau_v - 0.5) / 3.0
     nu = nu_e / J
@@ -178,7 +184,9 @@ def natural_convection(n: int = 1024, phi: float = 0.6, Da: float = 1e-4, Ra: fl
     tau_T = 0.5 + gamma * (tau_v - 0.5) / 3.0 / (J * sigma * csT2 * Pr)
     dT = Th - Tc
     gbeta = Ra * nu * nu / (dT * L ** 3 * Pr)
-    return Case(name=f"convection_{n}", nx=n, ny=n, bc_x=WALLS, bc_y=WALLS, nu=nu, J=J,
+    bc = NEE if nee else WALLS
+    return Case(name=f"convection_{n}" + ("_nee" if nee else ""), nx=n, ny=n, bc_x=bc, bc_y=bc,
+                nu=nu, J=J,
                 phi0=phi, K0=Da * L * L, Fphi=ergun_F(phi), Pi0=phi, steps=steps,
                 thermal=True, sigma=sigma, tau_T=tau_T, Th=Th, Tc=Tc, T0=0.5 * (Th + Tc),
                 gbeta=gbeta, meta=dict(L=L, Da=Da, Ra=Ra, Pr=Pr, Ma=Ma, tau_v=tau_v))

@@ -270,6 +270,80 @@ def test_partially_porous_couette_matches_eq25(J):
         assert np.abs(other - ref).max() / case.lid_ux > 100 * errs[1]
 
 
+def _nee_profile(case, tol=1e-11):
+    p, phi, K, F = oracle_setup(case, nthreads=1)
+    f = oracle.rest_state(p, case.Pi0)
+    _, ux, uy = run_to_steady(p, phi, K, F, f, tol=tol)
+    return ux[:, 0], uy
+
+
+def test_nee_walls_brinkman_poiseuille():
+    """Sec. 3.1 with the paper's default on-node walls (non-equilibrium
+    extrapolation, Ref. [40]): nodes y = 0..N-1 with the walls on the first and
+    last node, L = N - 1. The Brinkman profile (Eq. 23 with F_phi = 0) is met at
+    second order and the wall nodes are at rest to O(1/N^3)."""
+    errs = []
+    for ny in (17, 33):
+        case = I.poiseuille_channel(ny=ny, nx=1, forchheimer=False, nee=True)
+        ux, uy = _nee_profile(case)
+        ref = A.brinkman_poiseuille(np.arange(ny, dtype=float), ny - 1, case.ax, case.phi0,
+                                    case.K0, case.nu)
+        errs.append(np.sqrt(np.sum((ux - ref) ** 2) / np.sum(ref ** 2)))
+        assert max(abs(ux[0]), abs(ux[-1])) < 2.0 / (ny - 1) ** 3 * ref.max()
+        assert np.abs(uy).max() < 1e-7 * ref.max()   # decaying acoustic remnant
+    assert errs[1] < 5e-3
+    assert 1.7 < np.log2(errs[0] / errs[1]) < 2.3
+
+
+def test_nee_walls_free_poiseuille_second_order():
+    """phi = 1, K -> infinity with on-node walls: the parabola a y (L - y)/(2 nu)
+    is met with a maximum error that falls exactly fourfold per halving of the
+    spacing (second order)."""
+    errs = []
+    for ny in (9, 17):
+        case = I.poiseuille_channel(ny=ny, nx=1, phi=1.0, forchheimer=False, nee=True)
+        case.K0 = math.inf
+        case.ax = 1e-6
+        ux, _ = _nee_profile(case, tol=1e-12)
+        ref = A.free_poiseuille(np.arange(ny, dtype=float), ny - 1, case.ax, case.nu)
+        errs.append(np.abs(ux - ref).max() / ref.max())
+    assert errs[1] < 0.02
+    assert abs(np.log2(errs[0] / errs[1]) - 2.0) < 0.05
+
+
+def test_nee_walls_couette():
+    """Sec. 3.2 with on-node walls: the lid node carries u0 and the profile
+    u0 sinh(th y)/sinh(th L), L = N - 1, is met at second order."""
+    errs = []
+    for ny in (33, 65):
+        case = I.couette_channel(ny=ny, nx=1, nee=True)
+        ux, _ = _nee_profile(case)
+        ref = A.porous_couette(np.arange(ny, dtype=float), ny - 1, case.lid_ux, case.phi0,
+                               case.K0, case.nu)
+        errs.append(np.sqrt(np.sum((ux - ref) ** 2) / np.sum(ref ** 2)))
+        assert abs(ux[-1] / case.lid_ux - 1.0) < 1e-4
+    assert errs[1] < 1e-3
+    assert 1.7 < np.log2(errs[0] / errs[1]) < 2.3
+
+
+def test_nee_walls_conduction_is_linear():
+    """Pure conduction (g beta = 0) between on-node Dirichlet walls T = Th at x = 0
+    and Tc at x = L with adiabatic on-node walls in y: the steady temperature is
+    linear in x to round-off (a linear profile has a uniform non-equilibrium part,
+    which the extrapolation carries exactly), and the fluid stays at rest."""
+    case = I.natural_convection(n=24, nee=True)
+    case.gbeta = 0.0
+    case.tau_T = 1.0
+    p, phi, K, F = oracle_setup(case, nthreads=1)
+    f = oracle.rest_state(p, case.Pi0)
+    g = oracle.thermal_rest_state(p, np.full((case.ny, case.nx), case.T0))
+    oracle.run(p, phi, K, F, f, g, nsteps=20000)
+    ux, uy, _, T = oracle.macroscopic(p, phi, K, F, f, g)
+    ref = case.Th + (case.Tc - case.Th) * np.arange(case.nx) / (case.nx - 1)
+    assert np.abs(T - ref[None, :]).max() < 1e-11
+    assert np.abs(ux).max() == 0.0 and np.abs(uy).max() == 0.0
+
+
 def test_free_fluid_limit_is_parabolic():
     """Sec. 2.2 end: phi = 1 and K -> infinity give the free-fluid model; plane
     Poiseuille flow is then the parabola a y (L - y) / (2 nu)."""
