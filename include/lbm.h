@@ -56,6 +56,17 @@ extern "C" {
 /* boundary kinds per axis */
 #define LBM_PERIODIC 0
 #define LBM_WALLS 1 /* halfway bounce-back; top wall y = ny moves at lid_ux */
+/* On-node walls with non-equilibrium extrapolation, the paper's default wall
+ * treatment (Sec. 3, its Ref. [40]): the first and last node of the axis lie
+ * on the walls (so a side L holds L + 1 nodes) and every population of a
+ * wall node is rebuilt each step as f^eq(phi p of the inner neighbour B,
+ * wall velocity) + f(B) - f^eq(state of B), f^eq from Eq. (22); the top row
+ * moves at lid_ux except at on-node x walls. Thermal: x walls are Dirichlet
+ * (Th at x = 0, Tc at x = nx - 1), y walls adiabatic (T of B). Needs >= 3
+ * nodes on the axis; the other axis is periodic or on-node (mixing with
+ * LBM_WALLS gives ENOTSUP). Such contexts advance one cycle per pass and
+ * have no adjoint (ENOTSUP). */
+#define LBM_WALLS_NEE 2
 
 /* population storage */
 #define LBM_FP32_DEV 0 /* IEEE binary32 deviations                      */
@@ -78,9 +89,10 @@ typedef struct {
 
 typedef struct {
     int32_t nx, ny;   /* nodes, >= 1 each (>= 2 along a walled axis)          */
-    int32_t bc_x;     /* LBM_PERIODIC or LBM_WALLS (walls at x = 0, x = nx)    */
-    int32_t bc_y;     /* LBM_PERIODIC or LBM_WALLS (walls at y = 0, y = ny)    */
-    double lid_ux;    /* x-velocity of the wall y = ny (needs bc_y = WALLS)    */
+    int32_t bc_x;     /* LBM_PERIODIC, LBM_WALLS (walls at x = 0, x = nx) or   */
+                      /* LBM_WALLS_NEE (walls on the nodes x = 0, x = nx - 1)  */
+    int32_t bc_y;     /* likewise along y                                      */
+    double lid_ux;    /* x-velocity of the top wall (needs walls in y)         */
     double nu;        /* fluid viscosity nu > 0; tau = 1/2 + 3 J nu (Eq. 21)   */
     double J;         /* viscosity ratio nu_e/nu > 0 (Eq. 5)                   */
     double s_e, s_q;  /* s_2 and s_4 = s_6 of Eq. (13): 1.1 and 1.2 (Sec. 3)   */

@@ -101,11 +101,16 @@ int validate(const lbm_desc *d) {
     if (d->nx < 1 || d->ny < 1) return fail(LBM_EINVAL, "nx and ny must be >= 1 (got %d, %d)", d->nx, d->ny);
     if ((int64_t)d->nx * d->ny > (int64_t)1 << 31)
         return fail(LBM_EINVAL, "nx*ny exceeds 2^31 nodes");
-    if (d->bc_x != LBM_PERIODIC && d->bc_x != LBM_WALLS) return fail(LBM_EINVAL, "bc_x must be LBM_PERIODIC or LBM_WALLS");
-    if (d->bc_y != LBM_PERIODIC && d->bc_y != LBM_WALLS) return fail(LBM_EINVAL, "bc_y must be LBM_PERIODIC or LBM_WALLS");
+    auto bc_ok = [](int32_t b) { return b == LBM_PERIODIC || b == LBM_WALLS || b == LBM_WALLS_NEE; };
+    if (!bc_ok(d->bc_x)) return fail(LBM_EINVAL, "bc_x must be LBM_PERIODIC, LBM_WALLS or LBM_WALLS_NEE");
+    if (!bc_ok(d->bc_y)) return fail(LBM_EINVAL, "bc_y must be LBM_PERIODIC, LBM_WALLS or LBM_WALLS_NEE");
     if (d->bc_x == LBM_WALLS && d->nx < 2) return fail(LBM_EINVAL, "a walled x axis needs nx >= 2");
     if (d->bc_y == LBM_WALLS && d->ny < 2) return fail(LBM_EINVAL, "a walled y axis needs ny >= 2");
-    if (d->lid_ux != 0.0 && d->bc_y != LBM_WALLS) return fail(LBM_EINVAL, "lid_ux needs bc_y = LBM_WALLS");
+    if (d->bc_x == LBM_WALLS_NEE && d->nx < 3) return fail(LBM_EINVAL, "an on-node walled x axis needs nx >= 3");
+    if (d->bc_y == LBM_WALLS_NEE && d->ny < 3) return fail(LBM_EINVAL, "an on-node walled y axis needs ny >= 3");
+    if ((d->bc_x == LBM_WALLS && d->bc_y == LBM_WALLS_NEE) || (d->bc_x == LBM_WALLS_NEE && d->bc_y == LBM_WALLS))
+        return fail(LBM_ENOTSUP, "bounce-back and on-node walls cannot be mixed");
+    if (d->lid_ux != 0.0 && d->bc_y == LBM_PERIODIC) return fail(LBM_EINVAL, "lid_ux needs walls in y");
     if (!std::isfinite(d->lid_ux)) return fail(LBM_EINVAL, "lid_ux must be finite");
     if (!(d->nu > 0.0) || !std::isfinite(d->nu)) return fail(LBM_EINVAL, "nu must be > 0 (tau > 1/2)");
     if (!(d->J > 0.0) || !std::isfinite(d->J)) return fail(LBM_EINVAL, "J must be > 0");
@@ -144,6 +149,7 @@ Dom make_dom(const lbm_desc &d, const Layout &L) {
     o.nx = d.nx; o.ny = d.ny; o.pitch = L.pitch; o.plane = L.plane;
     o.bc_x = d.bc_x; o.bc_y = d.bc_y;
     o.lid6 = (float)(d.lid_ux / 6.0);
+    o.lid_u = (float)d.lid_ux;
     const double tau = 0.5 + 3.0 * d.J * d.nu;  // Eq. (21), cs^2 = 1/3
     const double s_nu = 1.0 / tau;
     o.s_e = (float)d.s_e; o.s_q = (float)d.s_q; o.s_nu = (float)s_nu;
@@ -172,6 +178,8 @@ Dom make_dom(const lbm_desc &d, const Layout &L) {
         o.gbeta = (float)t.g_beta;
         o.abbh = (float)(0.4 * (t.Th - t.T0));  // 2 w_T (T_w - T0), w_T = 1/5
         o.abbc = (float)(0.4 * (t.Tc - t.T0));
+        o.dTh = (float)(t.Th - t.T0);
+        o.dTc = (float)(t.Tc - t.T0);
     }
     return o;
 }
@@ -220,6 +228,14 @@ struct lbm_ctx {
 };
 
 namespace {
+
+bool on_node_walls(const lbm_desc &d) { return d.bc_x == LBM_WALLS_NEE || d.bc_y == LBM_WALLS_NEE; }
+
+bool any_on_node_walls(const lbm_ctx *c) {
+    for (const Domain &D : c->dom)
+        if (on_node_walls(D.desc)) return true;
+    return false;
+}
 
 int device_fail(lbm_ctx *c, hipError_t e, const char *what) {
     if (c) c->poisoned = true;
@@ -446,7 +462,8 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     D.L = L;
     c->rec_cap = cap;
     // two cycles per pass pays once the domain fills the GPU several times over
-    c->tblock = (!d->thermal.enabled && (int64_t)d->nx * d->ny >= ((int64_t)1 << 21)) ? 2 : 1;
+    // (the two-cycle kernels implement bounce-back walls only)
+    c->tblock = (!d->thermal.enabled && !on_node_walls(*d) && (int64_t)d->nx * d->ny >= ((int64_t)1 << 21)) ? 2 : 1;
     if (d->storage == LBM_FP16_DEV) c->sched = Schedule{64, 2, 2, 1};
     hipError_t e = init_domain(D, 0, phi, kappa, c->stream);
     if (e != hipSuccess) {
@@ -767,6 +784,8 @@ int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
     if (cycles_per_pass != 1 && cycles_per_pass != 2) return fail(LBM_EINVAL, "cycles per pass must be 1 or 2");
     if (cycles_per_pass == 2 && c->dom[0].desc.thermal.enabled)
         return fail(LBM_ENOTSUP, "thermal domains advance one cycle per pass");
+    if (cycles_per_pass == 2 && any_on_node_walls(c))
+        return fail(LBM_ENOTSUP, "on-node (extrapolated) walls advance one cycle per pass");
     c->tblock = cycles_per_pass;
     reset_graphs(c);
     return LBM_OK;
@@ -1022,8 +1041,9 @@ hipError_t autotune(lbm_ctx *c, Tuned &best) {
         }
         if (e != hipSuccess) break;
     }
+    const bool two_cycle_ok = !any_on_node_walls(c);
     for (const auto &sh : kTwoCycleShapes) {
-        if (e != hipSuccess) break;
+        if (e != hipSuccess || !two_cycle_ok) break;
         if ((e = upload_tiles2(c, sh[1])) != hipSuccess) break;
         const int grids[4] = {2 * ncu, 4 * ncu, 8 * ncu, c->ntiles2};
         for (int g : grids) {
@@ -1135,6 +1155,7 @@ extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, floa
     if (!dL_du || !dL_dphi) return fail(LBM_EINVAL, "dL_du and dL_dphi are required");
     if (d.ckpt_every <= 0) return fail(LBM_ESTATE, "context was created without recording (ckpt_every = 0)");
     if (d.thermal.enabled) return fail(LBM_ENOTSUP, "adjoint of the thermal coupling is not implemented");
+    if (on_node_walls(d)) return fail(LBM_ENOTSUP, "adjoint of on-node (extrapolated) walls is not implemented");
     if (d.storage != LBM_FP32_DEV) return fail(LBM_ENOTSUP, "adjoint needs FP32 storage");
     if (d.medium == LBM_MEDIUM_UNIFORM) return fail(LBM_ENOTSUP, "adjoint needs a porosity plane");
     if (dL_dkappa && d.medium != LBM_MEDIUM_PHI_KAPPA) return fail(LBM_EINVAL, "dL_dkappa needs LBM_MEDIUM_PHI_KAPPA");

@@ -25,7 +25,10 @@ constexpr int TXv[5] = {0, 1, 0, -1, 0};
 constexpr int TYv[5] = {0, 0, 1, 0, -1};
 constexpr int TOPP[5] = {0, 3, 4, 1, 2};
 
-enum { BC_PERIODIC = 0, BC_WALLS = 1 };
+// BC_WALLS: halfway bounce-back, walls half a link outside the edge nodes.
+// BC_NEE: the first and last node of the axis lie on the walls
+// (non-equilibrium extrapolation); the other axis is periodic or BC_NEE.
+enum { BC_PERIODIC = 0, BC_WALLS = 1, BC_NEE = 2 };
 enum { MED_UNIFORM = 0, MED_PHI_ERGUN = 1, MED_PHI_KAPPA = 2 };
 
 // Everything a kernel needs to know about one domain. Passed by value as a
@@ -35,6 +38,7 @@ struct Dom {
     int32_t bc_x, bc_y;
     int64_t plane;          // elements between consecutive planes
     float lid6;             // 6 w_diag U_lid = U_lid / 6 (diagonal lid links)
+    float lid_u;            // U_lid (velocity of on-node lid nodes)
     // relaxation (Eq. 13) and the (1 - s/2) factors of Eq. (14)
     float s_e, s_q, s_nu, h_e, h_q, h_nu;
     // medium
@@ -52,6 +56,7 @@ struct Dom {
     float zT, z3, z4;                // 1/tau_T, zeta3, zeta4
     float inv_sigma, T0, gbeta;
     float abbh, abbc;                // 2 wT (Th - T0), 2 wT (Tc - T0)
+    float dTh, dTc;                  // Th - T0, Tc - T0 (on-node Dirichlet walls)
     // state buffers (storage type erased)
     const void *fin;
     void *fout;
@@ -388,6 +393,87 @@ __device__ __forceinline__ void load_own_thermal(const Dom &d, const float *__re
     const int64_t o = (int64_t)y * d.pitch + x;
 #pragma unroll
     for (int j = 0; j < 5; ++j) g[j] = gin[j * d.plane + o];
+}
+
+// ---- on-node walls: non-equilibrium extrapolation (Sec. 3, Ref. [40]) ----
+
+// Whether (x, y) lies on an on-node wall, and the next node inward along the
+// wall normal (diagonally inward at a corner), which is never a wall node
+// (>= 3 nodes per BC_NEE axis).
+__device__ __forceinline__ bool nee_wall(const Dom &d, int x, int y, int &bx, int &by) {
+    const bool wx = d.bc_x == BC_NEE && (x == 0 || x == d.nx - 1);
+    const bool wy = d.bc_y == BC_NEE && (y == 0 || y == d.ny - 1);
+    bx = wx ? (x == 0 ? 1 : d.nx - 2) : x;
+    by = wy ? (y == 0 ? 1 : d.ny - 2) : y;
+    return wx || wy;
+}
+
+// Deviation of the equilibrium of Eq. (22) from the rest state 3 w_i Pi0 at
+// phi p = Pi0 + dPi (rho0 = 1):
+//   w_i [3 dPi + 3 e.u + (9/2)(e.u)^2/phi - (3/2)|u|^2/phi].
+__device__ __forceinline__ void feq_dev(float dPi, float ux, float uy, float ip, float out[8]) {
+    const float u2 = 1.5f * (ux * ux + uy * uy) * ip;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float eu = (float)EX[i] * ux + (float)EY[i] * uy;
+        const float v = 3.0f * dPi + 3.0f * eu + 4.5f * eu * eu * ip - u2;
+        out[i] = (i < 4) ? v * (1.0f / 9.0f) : v * (1.0f / 36.0f);
+    }
+}
+
+// Deviation of g^eq = N^-1 n^eq (Eq. B.6, varpi = 0) from T0/5 per link:
+// dT/5 on every link plus +-u T/(2 sigma) along the axis links.
+__device__ __forceinline__ void geq_dev(const Dom &d, float dT, float ux, float uy, float out[5]) {
+    const float b = 0.2f * dT, T = d.T0 + dT;
+    const float hx = 0.5f * ux * T * d.inv_sigma, hy = 0.5f * uy * T * d.inv_sigma;
+    out[0] = b;
+    out[1] = b + hx;
+    out[2] = b + hy;
+    out[3] = b - hx;
+    out[4] = b - hy;
+}
+
+// Rebuilds the populations f(t) (and g(t)) of a wall node from those of its
+// inner neighbour B at the same time t >= 1 (B's own gather from the
+// post-collision buffer fin):
+//   f(O) = f^eq(Pi_B, u_w; phi_O) + [f(B) - f^eq(Pi_B, u_B; phi_B)],
+// with Pi = phi p taken over from B, u_B from Eqs. (18)-(19) with B's force,
+// u_w = (U_lid, 0) on the top wall away from on-node x walls and zero
+// elsewhere; g likewise with T_w = Th / Tc on x walls and T_B on y walls.
+template <typename S, bool THERMAL>
+__device__ __forceinline__ void nee_fixup(const Dom &d, const S *__restrict__ fin, int x, int y,
+                                          float f[8], float g[5]) {
+    int bx, by;
+    if (!nee_wall(d, x, y, bx, by)) return;
+    float fB[8], gB[5];
+    gather_general<S>(d, fin, bx, by, fB);
+    const Cell cB = load_cell(d, (int64_t)by * d.pitch + bx);
+    const Cell cO = load_cell(d, (int64_t)y * d.pitch + x);
+    float ay = d.ay, dTB = 0.0f;
+    if (THERMAL) {
+        gather_thermal(d, d.gin, bx, by, false, gB);
+        dTB = (gB[0] + gB[1]) + (gB[2] + gB[3]) + gB[4];
+        ay = d.ay + d.gbeta * dTB;
+    }
+    float uxB, uyB, m1B;
+    node_velocity(fB, cB, cB.phi * d.ax, cB.phi * ay, uxB, uyB, m1B);
+    // Eq. (20) on deviations: dPi = (3/5)(dm1 - (2/3)|u|^2/phi)
+    const float dPi = mulc(m1B, MRT_C3_5) - mulc((uxB * uxB + uyB * uyB) * cB.inv_phi, MRT_C2_5);
+    const bool wx = d.bc_x == BC_NEE && (x == 0 || x == d.nx - 1);
+    const float uw = (d.bc_y == BC_NEE && y == d.ny - 1 && !wx) ? d.lid_u : 0.0f;
+    float eO[8], eB[8];
+    feq_dev(dPi, uw, 0.0f, cO.inv_phi, eO);
+    feq_dev(dPi, uxB, uyB, cB.inv_phi, eB);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = eO[i] + (fB[i] - eB[i]);
+    if (THERMAL) {
+        const float dTw = wx ? (x == 0 ? d.dTh : d.dTc) : dTB;
+        float hO[5], hB[5];
+        geq_dev(d, dTw, uw, 0.0f, hO);
+        geq_dev(d, dTB, uxB, uyB, hB);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) g[j] = hO[j] + (gB[j] - hB[j]);
+    }
 }
 
 }  // namespace mrt

@@ -124,6 +124,7 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
             } else {
                 gather_general<S>(d, fin, x, y, fn);
                 if (THERMAL) gather_thermal(d, d.gin, x, y, false, gn);
+                nee_fixup<S, THERMAL>(d, fin, x, y, fn, gn);
             }
             const int64_t o = (int64_t)y * d.pitch + x;
             const Cell c = load_cell(d, o);
@@ -470,6 +471,7 @@ __device__ __forceinline__ void read_state(const Dom &d, int src, int x, int y, 
     } else {
         gather_general<S>(d, (const S *)d.fin, x, y, f);
         if (THERMAL) gather_thermal(d, d.gin, x, y, false, g);
+        nee_fixup<S, THERMAL>(d, (const S *)d.fin, x, y, f, g);
     }
 }
 

@@ -18,7 +18,7 @@ _LIB_PATH = pathlib.Path(__file__).resolve().parent / "libmrtlbm.so"
 _lib = None
 
 OK, EINVAL, ESTATE, EDEVICE, EUNSTABLE, ENOTSUP = 0, -1, -2, -3, -4, -5
-PERIODIC, WALLS = 0, 1
+PERIODIC, WALLS, WALLS_NEE = 0, 1, 2
 FP32_DEV, FP16_DEV = 0, 1
 MEDIUM_UNIFORM, MEDIUM_PHI_ERGUN, MEDIUM_PHI_KAPPA = 0, 1, 2
 
