@@ -133,6 +133,16 @@ def extras(args):
                              "bytes_per_node": 104, "note": "working set fits the 256 MB Infinity Cache"}
     del s
     torch.cuda.empty_cache()
+    log("bench: Table 1 sweep as one thermal batch (27 natural-convection cavities)")
+    from paper_1311_7239_amd import convection as C
+    cases = [c for _, c in C.table1_cases()]
+    b = lbm.batch_for_cases(cases)
+    ms = timed(b, 20000, 2000)
+    out["table1_batch27_thermal"] = {"mlups": round(b.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 5),
+                                     "nodes": b.nodes, "bytes_per_node": 104, "schedule": list(b.schedule()),
+                                     "note": "120^2, 200^2, 250^2 cavities of Sec. 3.4; D2Q8 + D2Q5"}
+    del b
+    torch.cuda.empty_cache()
     for storage, name, bpn in ((lbm.FP32_DEV, "batch256_f32", 64), (lbm.FP16_DEV, "batch256_f16", 32)):
         log(f"bench: ragged batch of 256 lid cavities ({name})")
         cases = I.cavity_batch()

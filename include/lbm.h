@@ -139,14 +139,15 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
  * launch per step (a tile table maps workgroups to (domain, tile)), replayed
  * from a HIP graph of graph_steps launches (default 32). descs, phis,
  * kappas: host arrays of n entries (phis[k]/kappas[k] device planes or
- * NULL). All domains must share the storage; thermal domains and
- * ckpt_every > 0 give ENOTSUP. The tile schedule and persistent grid size
- * are chosen by timing every compiled candidate on the stream (autotuning,
- * which synchronises the stream): the one-cycle shapes and grids, and the
- * two-cycle (temporal blocking) shapes and grids, keeping the faster mode,
- * unless tune_cache (host path, may be NULL) already holds a choice for the
- * same batch signature (sizes, boundaries, media, storage, device); a new
- * choice is appended there as a text line.
+ * NULL). All domains must share the storage and be all thermal or all
+ * isothermal (else ENOTSUP); ckpt_every > 0 gives ENOTSUP. The tile
+ * schedule and persistent grid size are chosen by timing every compiled
+ * candidate on the stream (autotuning, which synchronises the stream): the
+ * one-cycle shapes and grids, and, for isothermal batches with bounce-back
+ * walls, the two-cycle (temporal blocking) shapes and grids, keeping the
+ * faster mode, unless tune_cache (host path, may be NULL) already holds a
+ * choice for the same batch signature (sizes, boundaries, media, storage,
+ * thermal, device); a new choice is appended there as a text line.
  * Results are bitwise identical to stepping each domain alone. The
  * per-domain calls (lbm_macroscopic, lbm_get_populations, lbm_reduce) take
  * the domain index. */
@@ -186,7 +187,8 @@ int lbm_get_populations(lbm_ctx *c, int32_t domain, float *df, float *dg);
 
 /* Replaces the state with f(0) = f_ref + df (and g(0) = w_T T0 + dg) and
  * sets t = 0; df [8][ny][nx], dg [5][ny][nx] or NULL (keeps g at T0).
- * Values are rounded to the storage type. Clears any recording. */
+ * Values are rounded to the storage type. Clears any recording. A batch
+ * domain takes a new state only while the batch is at t = 0 (else ESTATE). */
 int lbm_set_populations(lbm_ctx *c, int32_t domain, const float *df, const float *dg);
 
 /* FP64 reductions of one domain at the current time, computed on the GPU

@@ -1,0 +1,133 @@
+"""Natural convection in a porous square cavity (Sec. 3.4) as batched thermal
+workloads: the Table 1 sweep over (Da, Ra, phi) stepped as one ragged batch.
+
+The stepping runs in the library (lbm_create_batch with thermal domains);
+this module builds the seeded cases, starts every domain from the
+conduction profile, steps in chunks and reads the hot-wall Nusselt number
+from the temperature field after each chunk.
+"""
+from __future__ import annotations
+
+import time
+from typing import Callable, Dict, Iterable, List, Optional, Tuple
+
+import numpy as np
+import torch
+
+from . import inputs as I
+from . import lbm
+
+# Grid per Darcy number (Sec. 3.4) and the (Da, Ra) pairs of Table 1.
+TABLE1_GRID = {1e-2: 120, 1e-4: 200, 1e-6: 250}
+TABLE1_PAIRS = [(1e-2, 1e3), (1e-2, 1e4), (1e-2, 1e5),
+                (1e-4, 1e5), (1e-4, 1e6), (1e-4, 1e7),
+                (1e-6, 1e7), (1e-6, 1e8), (1e-6, 1e9)]
+TABLE1_PHIS = (0.4, 0.6, 0.9)
+
+
+def table1_cases(pairs: Iterable[Tuple[float, float]] = TABLE1_PAIRS,
+                 phis: Iterable[float] = TABLE1_PHIS, nee: bool = False,
+                 grid: Optional[Dict[float, int]] = None) -> List[Tuple[tuple, I.Case]]:
+    """((Da, Ra, phi), Case) for every combination, Pr = 1, Ma = 0.1, J = sigma =
+    gamma = 1, Th = 21, Tc = 1 (Sec. 3.4), on the paper's grid per Da."""
+    grid = TABLE1_GRID if grid is None else grid
+    out = []
+    for Da, Ra in pairs:
+        for phi in phis:
+            c = I.natural_convection(n=grid[Da], phi=phi, Da=Da, Ra=Ra, nee=nee)
+            out.append(((Da, Ra, phi), c))
+    return out
+
+
+def conduction_state(case: I.Case) -> np.ndarray:
+    """Thermal deviations dg [5, ny, nx] of the pure-conduction profile between
+    the hot (x = 0) and cold (x = L) walls, every link at T/5 (varpi = 0)."""
+    if case.bc_x == I.NEE:
+        x = np.arange(case.nx, dtype=np.float64)
+        L = case.nx - 1.0
+    else:
+        x = np.arange(case.nx, dtype=np.float64) + 0.5
+        L = float(case.nx)
+    T = case.Th + (case.Tc - case.Th) * x / L
+    return np.broadcast_to(((T - case.T0) / 5.0)[None, None, :],
+                           (5, case.ny, case.nx)).astype(np.float32).copy()
+
+
+def nusselt_hot_wall(T: np.ndarray, case: I.Case) -> float:
+    """Average Nusselt number of the hot wall x = 0: -(L / dT) times the wall-mean
+    of dT/dx there. Bounce-back walls (wall half a node before the first node):
+    the quadratic through the wall value and the first two nodes,
+    dT/dx = (9 T_1/2 - T_3/2 - 8 T_w) / 3, mean over the rows, L = n.
+    On-node walls: the one-sided second-order difference (-3 T_0 + 4 T_1 - T_2)/2,
+    trapezoidal mean along the wall, L = n - 1."""
+    dT = case.Th - case.Tc
+    if case.bc_x == I.NEE:
+        g = (-3.0 * case.Th + 4.0 * T[:, 1] - T[:, 2]) / 2.0
+        w = np.ones(T.shape[0]); w[0] = w[-1] = 0.5
+        mean = float(np.sum(w * g) / np.sum(w))
+        return -mean * (case.nx - 1.0) / dT
+    g = (9.0 * T[:, 0] - T[:, 1] - 8.0 * case.Th) / 3.0
+    return -float(np.mean(g)) * case.nx / dT
+
+
+def run_sweep(keyed_cases: List[Tuple[tuple, I.Case]], chunk: int = 4000, tol: float = 1e-6,
+              max_steps: int = 2_000_000, time_limit: Optional[float] = None,
+              storage: int = lbm.FP32_DEV, log: Optional[Callable[[str], None]] = None,
+              device="cuda") -> Dict[tuple, dict]:
+    """Steps all cases as one thermal batch from the conduction profile until every
+    Nusselt number changes by less than tol over a chunk (or max_steps / the time
+    limit is reached). Returns {key: {"nu", "steps", "converged"}}."""
+    cases = [c for _, c in keyed_cases]
+    b = lbm.batch_for_cases(cases, storage=storage, device=device)
+    for k, c in enumerate(cases):
+        b.set_populations(k, torch.zeros((8, c.ny, c.nx), device=device),
+                          torch.from_numpy(conduction_state(c)).to(device))
+    prev = [None] * len(cases)
+    done = [False] * len(cases)
+    nu = [float("nan")] * len(cases)
+    when = [0] * len(cases)
+    t0 = time.time()
+    steps = 0
+    while steps < max_steps:
+        b.step(chunk)
+        steps += chunk
+        for k, c in enumerate(cases):
+            if done[k]:
+                continue
+            _, _, T = b.macroscopic(k, want_T=True)
+            nu[k] = nusselt_hot_wall(T.cpu().numpy().astype(np.float64), c)
+            if not np.isfinite(nu[k]):
+                done[k] = True
+                when[k] = steps
+            elif prev[k] is not None and abs(nu[k] - prev[k]) < tol:
+                done[k] = True
+                when[k] = steps
+            prev[k] = nu[k]
+        if log is not None:
+            log(f"t={steps} converged {sum(done)}/{len(cases)} elapsed {time.time() - t0:.1f}s")
+        if all(done) or (time_limit is not None and time.time() - t0 > time_limit):
+            break
+    return {key: {"nu": nu[k], "steps": when[k] if done[k] else steps, "converged": bool(done[k])}
+            for k, (key, _) in enumerate(keyed_cases)}
+
+
+def _main(argv=None):
+    """Runs the Table 1 sweep and prints the hot-wall Nusselt number of every case."""
+    import argparse
+    ap = argparse.ArgumentParser(description=_main.__doc__)
+    ap.add_argument("--walls", choices=["bounce-back", "on-node"], default="bounce-back")
+    ap.add_argument("--max-steps", type=int, default=3_000_000)
+    ap.add_argument("--chunk", type=int, default=5000)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--time-limit", type=float, default=None)
+    a = ap.parse_args(argv)
+    keyed = table1_cases(nee=a.walls == "on-node")
+    res = run_sweep(keyed, chunk=a.chunk, tol=a.tol, max_steps=a.max_steps, time_limit=a.time_limit,
+                    log=lambda m: print(m, flush=True))
+    print("Da Ra phi Nu steps converged")
+    for (Da, Ra, phi), r in res.items():
+        print(f"{Da:g} {Ra:g} {phi} {r['nu']:.4f} {r['steps']} {int(r['converged'])}")
+
+
+if __name__ == "__main__":
+    _main()

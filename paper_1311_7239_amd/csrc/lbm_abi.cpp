@@ -166,7 +166,11 @@ Dom make_dom(const lbm_desc &d, const Layout &L) {
         o.cd0 = (float)(d.phi0 * d.nu * d.kappa0);
         o.cf0 = (float)(d.phi0 * F * std::sqrt(d.kappa0));
     }
-    if (d.medium == LBM_MEDIUM_PHI_ERGUN) o.kcoef = (float)(150.0 / (d.dp * d.dp));
+    if (d.medium == LBM_MEDIUM_PHI_ERGUN) {
+        o.kcoef = (float)(150.0 / (d.dp * d.dp));
+        o.cdk = (float)(150.0 * d.nu / (d.dp * d.dp));
+        o.cfk = (float)(1.75 / d.dp);
+    }
     o.ax = (float)d.ax; o.ay = (float)d.ay;
     if (d.thermal.enabled) {
         const lbm_thermal &t = d.thermal;
@@ -200,6 +204,7 @@ struct lbm_ctx {
     int cur = 0;  // index of the buffer holding the state at t
     bool poisoned = false;
     bool batch = false;
+    bool batch_thermal = false;  // every batch domain carries the D2Q5 field
     Schedule sched{128, 1, 2, 1};
     // recording (single domain)
     bool rec_valid = false;
@@ -363,7 +368,7 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
             kp.blockDim = dim3((unsigned)c->tb_threads);
             kp.kernelParams = args_b2;
         } else if (c->batch) {
-            kp.func = (void *)batch_kernel_fn(c->storage, c->sched);
+            kp.func = (void *)batch_kernel_fn(c->storage, c->batch_thermal, c->sched);
             kp.gridDim = dim3((unsigned)c->grid);
             kp.kernelParams = args_b;
         } else if (c->tblock == 2) {
@@ -532,7 +537,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
             continue;
         }
         if (c->batch) {
-            e = launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, c->cur, c->storage, c->sched, c->grid,
+            e = launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, c->cur, c->storage, c->batch_thermal, c->sched, c->grid,
                                   c->stream);
         } else {
             Domain &D = c->dom[0];
@@ -588,7 +593,7 @@ int lbm_set_populations(lbm_ctx *c, int32_t k, const float *df, const float *dg)
     if (rc) return rc;
     if ((rc = check_domain(c, k))) return rc;
     if (!df) return fail(LBM_EINVAL, "df is NULL");
-    if (c->batch) return fail(LBM_ENOTSUP, "set_populations is not supported on batches");
+    if (c->batch && c->t != 0) return fail(LBM_ESTATE, "batch domains take a new state only at t = 0");
     Domain &D = c->dom[k];
     if (dg && !D.desc.thermal.enabled) return fail(LBM_EINVAL, "dg given without thermal model");
     // write f(0) into the buffer that becomes current at t = 0
@@ -855,7 +860,8 @@ int validate_batch(int32_t n, const lbm_desc *descs) {
     for (int32_t k = 0; k < n; ++k) {
         int rc = validate(&descs[k]);
         if (rc) return fail(rc, "domain %d: %s", k, g_last_error.c_str());
-        if (descs[k].thermal.enabled) return fail(LBM_ENOTSUP, "domain %d: thermal batches are not supported", k);
+        if ((descs[k].thermal.enabled != 0) != (descs[0].thermal.enabled != 0))
+            return fail(LBM_ENOTSUP, "domain %d: a batch is thermal in every domain or in none", k);
         if (descs[k].ckpt_every != 0) return fail(LBM_ENOTSUP, "domain %d: batches do not record for the adjoint", k);
         if (descs[k].storage != descs[0].storage) return fail(LBM_EINVAL, "domain %d: storage differs from domain 0", k);
     }
@@ -947,6 +953,7 @@ uint64_t batch_signature(const lbm_ctx *c) {
     };
     mix((int64_t)c->dom.size());
     mix(c->storage);
+    mix(c->batch_thermal ? 1 : 0);
     for (const Domain &D : c->dom) {
         mix(D.desc.nx); mix(D.desc.ny); mix(D.desc.bc_x); mix(D.desc.bc_y); mix(D.desc.medium);
     }
@@ -1034,14 +1041,15 @@ hipError_t autotune(lbm_ctx *c, Tuned &best) {
         for (int g : grids) {
             if (g > c->ntiles) g = c->ntiles;
             float ms = 0.0f;
-            e = time_it([&] { return launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, 0, c->storage, s, g,
+            e = time_it([&] { return launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, 0, c->storage,
+                                                       c->batch_thermal, s, g,
                                                        c->stream); }, ms);
             if (e != hipSuccess) break;
             if (ms < best1) { best1 = ms; best.s = s; best.grid = g; }
         }
         if (e != hipSuccess) break;
     }
-    const bool two_cycle_ok = !any_on_node_walls(c);
+    const bool two_cycle_ok = !any_on_node_walls(c) && !c->batch_thermal;
     for (const auto &sh : kTwoCycleShapes) {
         if (e != hipSuccess || !two_cycle_ok) break;
         if ((e = upload_tiles2(c, sh[1])) != hipSuccess) break;
@@ -1095,6 +1103,7 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
     c->stream = (hipStream_t)stream;
     c->batch = true;
     c->storage = descs[0].storage == LBM_FP16_DEV ? ST_F16 : ST_F32;
+    c->batch_thermal = descs[0].thermal.enabled != 0;
     c->dom.resize((size_t)n);
     char *base = (char *)workspace;
     hipError_t e = hipSuccess;

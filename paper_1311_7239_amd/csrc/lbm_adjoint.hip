@@ -84,10 +84,10 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
 
     // forward quantities on this node
     const float ip = c.inv_phi;
-    const float umag = hw_sqrt(ux * ux + uy * uy);
-    const float drag = c.cd + c.cf * umag;
-    const float Fx = pax - drag * ux, Fy = pay - drag * uy;
-    const float u2 = ux * ux + uy * uy, uF = ux * Fx + uy * Fy;
+    const float umag = hw_sqrt(fmaf(ux, ux, uy * uy));
+    const float drag = fmaf(c.cf, umag, c.cd);
+    const float Fx = fmaf(-drag, ux, pax), Fy = fmaf(-drag, uy, pay);
+    const float u2 = fmaf(ux, ux, uy * uy), uF = fmaf(ux, Fx, uy * Fy);
 
     float mb[8];
     mb[0] = P1 - 0.6f * d.s_e * P2;

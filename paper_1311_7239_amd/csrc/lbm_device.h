@@ -46,6 +46,7 @@ struct Dom {
     float phi0, inv_phi0, cd0, cf0;  // uniform: phi, 1/phi, phi nu kappa, phi F sqrt(kappa)
     float nu;                        // fluid viscosity (per-cell drag)
     float kcoef;                     // 150 / dp^2 (Eq. 4): kappa = kcoef (1-phi)^2 / phi^3
+    float cdk, cfk;                  // 150 nu / dp^2 and 1.75 / dp (Eq. 4 drag in closed form)
     float Fconst;                    // >= 0: constant F_phi; < 0: Eq. (4)
     float ax, ay;                    // uniform external acceleration
     const float *phi;                // [ny][pitch] (MED_PHI_*)
@@ -121,6 +122,16 @@ __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_p
         return c;
     }
     const float ip = hw_rcp(phi);
+    c.phi = phi; c.inv_phi = ip;
+    if (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f) {
+        // Eq. (4) substituted into Eq. (3): phi nu / K = (150 nu / dp^2)(1-phi)^2 / phi^2
+        // and phi F_phi / sqrt(K) = (1.75 / dp)(1-phi) / phi^2, without square roots
+        const float om = 1.0f - phi;
+        const float t = om * (ip * ip);
+        c.cd = (d.cdk * om) * t;
+        c.cf = d.cfk * t;
+        return c;
+    }
     float kappa;
     if (d.medium == MED_PHI_ERGUN) {
         const float om = 1.0f - phi;
@@ -129,7 +140,6 @@ __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_p
         kappa = kappa_plane;
     }
     const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
-    c.phi = phi; c.inv_phi = ip;
     c.cd = phi * d.nu * kappa;
     c.cf = phi * F * hw_sqrt(kappa);
     return c;
@@ -163,14 +173,14 @@ __device__ __forceinline__ void velocity(const Cell &c, float vx, float vy, floa
                                          float &uy) {
     const float dd = 0.5f * c.cd;
     const float l1 = 0.5f * c.cf;
-    const float l0 = 0.5f * (1.0f + dd);
-    const float vmag = hw_sqrt(vx * vx + vy * vy);
+    const float l0 = fmaf(0.5f, dd, 0.5f);
+    const float vmag = hw_sqrt(fmaf(vx, vx, vy * vy));
     const float t = l1 * vmag;
-    const float delta = t * hw_rcp(l0 + hw_sqrt(l0 * l0 + t));
+    const float delta = t * hw_rcp(l0 + hw_sqrt(fmaf(l0, l0, t)));
     const float qn = dd + delta;
     const float q = qn * hw_rcp(1.0f + qn);
-    ux = vx - vx * q;
-    uy = vy - vy * q;
+    ux = fmaf(-vx, q, vx);
+    uy = fmaf(-vy, q, vy);
 }
 
 // Moments m_1, m_3, m_5 of the deviations (rows 1, 3, 5 of Eq. 10).
@@ -189,7 +199,7 @@ __device__ __forceinline__ void node_velocity(const float f[8], const Cell &c, f
                                               float pay, float &ux, float &uy, float &m1) {
     float m3, m5;
     conserved_moments(f, m1, m3, m5);
-    velocity(c, m3 + 0.5f * pax, m5 + 0.5f * pay, ux, uy);
+    velocity(c, fmaf(0.5f, pax, m3), fmaf(0.5f, pay, m5), ux, uy);
 }
 
 // One node's collision (Eq. 14) followed by f+ = M^-1 m+, in place on the
@@ -204,36 +214,40 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
     const float m2 = cdg - ab;
     const float pmq = p57 - q68, ppq = p57 + q68;
     const float m3 = x13 + pmq;
-    const float m4 = pmq - 2.0f * x13;
+    const float m4 = fmaf(-2.0f, x13, pmq);
     const float m5 = y24 + ppq;
-    const float m6 = ppq - 2.0f * y24;
+    const float m6 = fmaf(-2.0f, y24, ppq);
     const float m7 = a - b;
     const float m8 = cc - dg;
 
     // velocity (Eqs. 18-19) and total force (Eq. 3)
-    velocity(c, m3 + 0.5f * pax, m5 + 0.5f * pay, ux, uy);
-    const float umag = hw_sqrt(ux * ux + uy * uy);
-    const float drag = c.cd + c.cf * umag;
-    const float Fx = pax - drag * ux;
-    const float Fy = pay - drag * uy;
+    velocity(c, fmaf(0.5f, pax, m3), fmaf(0.5f, pay, m5), ux, uy);
+    const float umag = hw_sqrt(fmaf(ux, ux, uy * uy));
+    const float drag = fmaf(c.cf, umag, c.cd);
+    const float Fx = fmaf(-drag, ux, pax);
+    const float Fy = fmaf(-drag, uy, pay);
 
     // relaxation toward m^eq (Eqs. 11-12) with forcing (Eq. 16)
     const float ip = c.inv_phi;
-    const float u2 = ux * ux + uy * uy;
-    const float uF = ux * Fx + uy * Fy;
-    // e - e^eq = dm2 + (3/5) dm1 - (2/5)|u|^2/phi  (Pi from Eq. 20, alpha2 = -1, gamma2 = 0)
-    const float m2p = m2 - d.s_e * (m2 + mulc(m1, MRT_C3_5) - mulc(u2 * ip, MRT_C2_5)) +
-                      d.h_e * mulc(uF * ip, MRT_C4_5);
+    const float u2 = fmaf(ux, ux, uy * uy);
+    const float uF = fmaf(ux, Fx, uy * Fy);
+    // e - e^eq = dm2 + (3/5) dm1 - (2/5)|u|^2/phi  (Pi from Eq. 20, alpha2 = -1, gamma2 = 0);
+    // e enters neither m1 nor j of f+, so single-rounded constants suffice here
+    const float ne = fmaf(0.6f, m1, m2) - 0.4f * (u2 * ip);
+    const float m2p = fmaf(d.h_e, 0.8f * (uF * ip), fmaf(-d.s_e, ne, m2));
     // s1 = s3 = s5 = 1: m1+ = m1, j+ = rho0 u + F/2
-    const float m3p = ux + 0.5f * Fx;
-    const float m5p = uy + 0.5f * Fy;
+    const float m3p = fmaf(0.5f, Fx, ux);
+    const float m5p = fmaf(0.5f, Fy, uy);
     // q^eq = -u (c1 = c2 = -2)
-    const float m4p = m4 - d.s_q * (m4 + ux) - d.h_q * Fx;
-    const float m6p = m6 - d.s_q * (m6 + uy) - d.h_q * Fy;
+    const float m4p = fmaf(-d.h_q, Fx, fmaf(-d.s_q, m4 + ux, m4));
+    const float m6p = fmaf(-d.h_q, Fy, fmaf(-d.s_q, m6 + uy, m6));
     // p_xx^eq = (ux^2 - uy^2)/phi, p_xy^eq = ux uy / phi (gamma1 = gamma3 = 2/3)
-    const float m7p = m7 - c.s_nu * (m7 - (ux * ux - uy * uy) * ip) +
-                      c.h_nu * (2.0f * (ux * Fx - uy * Fy) * ip);
-    const float m8p = m8 - c.s_nu * (m8 - ux * uy * ip) + c.h_nu * ((ux * Fy + uy * Fx) * ip);
+    const float pxx = fmaf(ux, ux, -(uy * uy)) * ip;
+    const float pxy = (ux * uy) * ip;
+    const float Sxx = 2.0f * fmaf(ux, Fx, -(uy * Fy)) * ip;
+    const float Sxy = fmaf(ux, Fy, uy * Fx) * ip;
+    const float m7p = fmaf(c.h_nu, Sxx, fmaf(-c.s_nu, m7 - pxx, m7));
+    const float m8p = fmaf(c.h_nu, Sxy, fmaf(-c.s_nu, m8 - pxy, m8));
 
     // f+ = M^T diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m+
     const float A = 0.125f * m1, B = 0.125f * m2p;
@@ -241,7 +255,7 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
     const float Y = mulc(m5p, MRT_C1_6), Qy = mulc(m6p, MRT_C1_12);
     const float P = 0.25f * m7p, R = 0.25f * m8p;
     const float amb = A - B, apb = A + B;
-    const float xa = X - 2.0f * Qx, ya = Y - 2.0f * Qy;
+    const float xa = fmaf(-2.0f, Qx, X), ya = fmaf(-2.0f, Qy, Y);
     const float xd = X + Qx, yd = Y + Qy;
     f[0] = (amb + xa) + P;
     f[2] = (amb - xa) + P;
@@ -264,8 +278,8 @@ __device__ __forceinline__ void thermal_collide(float g[5], const Dom &d, float 
     const float n4 = (g[1] - g[2]) + (g[3] - g[4]);
     const float T = d.T0 + n0;
     // n^eq = (T, ux T/sigma, uy T/sigma, varpi T, 0) with varpi = 0 (Eq. B.6)
-    const float n1p = n1 - d.zT * (n1 - ux * T * d.inv_sigma);
-    const float n2p = n2 - d.zT * (n2 - uy * T * d.inv_sigma);
+    const float n1p = fmaf(-d.zT, n1 - ux * T * d.inv_sigma, n1);
+    const float n2p = fmaf(-d.zT, n2 - uy * T * d.inv_sigma, n2);
     const float n3p = n3 - d.z3 * n3;
     const float n4p = n4 - d.z4 * n4;
     // g+ = N^T diag(1/5, 1/2, 1/2, 1/20, 1/4) n+

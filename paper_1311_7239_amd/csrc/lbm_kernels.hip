@@ -154,7 +154,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(Dom d, int tiles_x, int swz) {
 // Persistent batched step: block b walks a contiguous run of the tile table
 // (tiles of one domain row stay on one XCD and in order), so the grid size is
 // a free tuning parameter independent of the number of tiles.
-template <typename S, int TWT, int NX, int ROWS>
+template <typename S, bool THERMAL, int TWT, int NX, int ROWS>
 __global__ __launch_bounds__(BLOCK) void k_step_batch(const Dom *__restrict__ doms,
                                                       const int4 *__restrict__ tiles,
                                                       int ntiles, int parity) {
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_batch(const Dom *__restrict__ do
     for (int t = t0; t < t1; ++t) {
         const int4 tl = tiles[t];
         const Dom d = doms[2 * tl.x + parity];
-        step_tile<S, false, SRC_GATHER, false, TWT, NX, ROWS>(d, tl.y, tl.z);
+        step_tile<S, THERMAL, SRC_GATHER, false, TWT, NX, ROWS>(d, tl.y, tl.z);
     }
 }
 
@@ -243,27 +243,28 @@ const void *step_kernel_fn(int storage, bool thermal, const Schedule &s) {
     return thermal ? step_fn_t<_Float16, true, SRC_GATHER, false>(s) : step_fn_t<_Float16, false, SRC_GATHER, false>(s);
 }
 
-template <typename S>
+template <typename S, bool THERMAL>
 static const void *batch_fn_t(const Schedule &s) {
 #define MRT_BFN(T, V, R) \
-    if (s.tile_w == T && s.vec == V && s.rows == R) return (const void *)&k_step_batch<S, T, V, R>;
+    if (s.tile_w == T && s.vec == V && s.rows == R) return (const void *)&k_step_batch<S, THERMAL, T, V, R>;
     MRT_SCHEDULES(MRT_BFN)
 #undef MRT_BFN
     return nullptr;
 }
 
-const void *batch_kernel_fn(int storage, const Schedule &s) {
-    return storage == ST_F32 ? batch_fn_t<float>(s) : batch_fn_t<_Float16>(s);
+const void *batch_kernel_fn(int storage, bool thermal, const Schedule &s) {
+    if (storage == ST_F32) return thermal ? batch_fn_t<float, true>(s) : batch_fn_t<float, false>(s);
+    return thermal ? batch_fn_t<_Float16, true>(s) : batch_fn_t<_Float16, false>(s);
 }
 
-template <typename S>
+template <typename S, bool THERMAL>
 static hipError_t launch_batch_t(const Dom *doms, const int4 *tiles, int ntiles, int parity,
                                  const Schedule &s, int grid, hipStream_t st) {
     const dim3 g((unsigned)grid), b(BLOCK);
-#define MRT_BLAUNCH(T, V, R)                                                              \
-    if (s.tile_w == T && s.vec == V && s.rows == R) {                                     \
-        hipLaunchKernelGGL((k_step_batch<S, T, V, R>), g, b, 0, st, doms, tiles, ntiles, parity); \
-        return hipGetLastError();                                                         \
+#define MRT_BLAUNCH(T, V, R)                                                                       \
+    if (s.tile_w == T && s.vec == V && s.rows == R) {                                              \
+        hipLaunchKernelGGL((k_step_batch<S, THERMAL, T, V, R>), g, b, 0, st, doms, tiles, ntiles, parity); \
+        return hipGetLastError();                                                                  \
     }
     MRT_SCHEDULES(MRT_BLAUNCH)
 #undef MRT_BLAUNCH
@@ -271,10 +272,13 @@ static hipError_t launch_batch_t(const Dom *doms, const int4 *tiles, int ntiles,
 }
 
 hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity,
-                             int storage, const Schedule &s, int grid, hipStream_t st) {
+                             int storage, bool thermal, const Schedule &s, int grid, hipStream_t st) {
     if (grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
-    if (storage == ST_F32) return launch_batch_t<float>(doms, tiles, ntiles, parity, s, grid, st);
-    return launch_batch_t<_Float16>(doms, tiles, ntiles, parity, s, grid, st);
+    if (storage == ST_F32)
+        return thermal ? launch_batch_t<float, true>(doms, tiles, ntiles, parity, s, grid, st)
+                       : launch_batch_t<float, false>(doms, tiles, ntiles, parity, s, grid, st);
+    return thermal ? launch_batch_t<_Float16, true>(doms, tiles, ntiles, parity, s, grid, st)
+                   : launch_batch_t<_Float16, false>(doms, tiles, ntiles, parity, s, grid, st);
 }
 
 // ------------------------------------------------- two steps per pass
@@ -335,26 +339,31 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
         const int lx = q % TW, ly = q / TW;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= d.nx || gy >= d.ny) continue;
-        // one LDS read per link at a selected index (the neighbour's value, or the
-        // node's own opposite value across a wall); written as an index select
-        // rather than two guarded reads, a form the compiler got wrong here
         float f[8];
         const float *flat = &lds[0][0][0];
+        if (interior) {
+            // every source is the neighbour's value: one base, constant offsets
+            const int base = (ly + 1) * EW + lx + 1;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            bool out = false, top = false;
-            if (!interior) {
+            for (int i = 0; i < 8; ++i) f[i] = flat[base + i * EH * EW - EY[i] * EW - EX[i]];
+        } else {
+            // one LDS read per link at a selected index (the neighbour's value, or the
+            // node's own opposite value across a wall); written as an index select
+            // rather than two guarded reads, a form the compiler got wrong here
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                bool out = false, top = false;
                 const int sx = gx - EX[i], sy = gy - EY[i];
                 if (EX[i] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) out = true;
                 if (EY[i] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) {
                     out = true;
                     top = (sy >= d.ny);
                 }
+                const int src = out ? (OPP[i] * EH + ly + 1) * EW + lx + 1
+                                    : (i * EH + ly + 1 - EY[i]) * EW + lx + 1 - EX[i];
+                const float v = flat[src];
+                f[i] = top ? v + (float)EX[i] * d.lid6 : v;
             }
-            const int src = out ? (OPP[i] * EH + ly + 1) * EW + lx + 1
-                                : (i * EH + ly + 1 - EY[i]) * EW + lx + 1 - EX[i];
-            const float v = flat[src];
-            f[i] = top ? v + (float)EX[i] * d.lid6 : v;
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
         const Cell c = load_cell(d, o);

@@ -50,14 +50,15 @@ const void *step2_batch_kernel_fn(int storage, int threads, int rows);
 
 // Persistent batched step over a tile table: doms[2*k + parity] describes
 // domain k with its buffers for this parity; tiles[j] = (domain, tx, ty, 0).
+// thermal: every domain of the table carries the D2Q5 field (or none does).
 hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity,
-                             int storage, const Schedule &s, int grid, hipStream_t st);
+                             int storage, bool thermal, const Schedule &s, int grid, hipStream_t st);
 
 // Kernel entry points for building HIP graphs by hand (gather-layout step of
 // one domain: arguments (Dom, int tiles_x, int swizzle); batched step:
 // arguments (const Dom*, const int4*, int ntiles, int parity)).
 const void *step_kernel_fn(int storage, bool thermal, const Schedule &s);
-const void *batch_kernel_fn(int storage, const Schedule &s);
+const void *batch_kernel_fn(int storage, bool thermal, const Schedule &s);
 
 hipError_t launch_macroscopic(const Dom &d, int storage, Source src, float Pi0, float *p,
                               float *ux, float *uy, float *T, hipStream_t st);

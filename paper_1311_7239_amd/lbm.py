@@ -355,18 +355,33 @@ class Batch:
                                  ctypes.byref(c)))
         return a.value, v.value, b.value, c.value
 
-    def macroscopic(self, k: int):
+    def macroscopic(self, k: int, want_T: bool = False):
+        """(p, u) of domain k, or (p, u, T) with want_T."""
         d = self.descs[k]
         p = torch.empty((d.ny, d.nx), dtype=torch.float32, device=self.device)
         u = torch.empty((2, d.ny, d.nx), dtype=torch.float32, device=self.device)
-        check(lib().lbm_macroscopic(self._ctx, k, _ptr(p), _ptr(u), None))
-        return p, u
+        T = torch.empty((d.ny, d.nx), dtype=torch.float32, device=self.device) if want_T else None
+        check(lib().lbm_macroscopic(self._ctx, k, _ptr(p), _ptr(u), _ptr(T)))
+        return (p, u, T) if want_T else (p, u)
 
-    def populations(self, k: int):
+    def set_populations(self, k: int, df: torch.Tensor, dg: Optional[torch.Tensor] = None):
+        """Initial state f(0) (and g(0)) of domain k; only before the first step."""
+        check(lib().lbm_set_populations(self._ctx, int(k), _ptr(df.contiguous()),
+                                        _ptr(None if dg is None else dg.contiguous())))
+
+    @property
+    def time(self) -> int:
+        t = ctypes.c_int64()
+        check(lib().lbm_time(self._ctx, ctypes.byref(t)))
+        return t.value
+
+    def populations(self, k: int, thermal: bool = False):
+        """Deviations df of domain k, or (df, dg) with thermal."""
         d = self.descs[k]
         df = torch.empty((8, d.ny, d.nx), dtype=torch.float32, device=self.device)
-        check(lib().lbm_get_populations(self._ctx, k, _ptr(df), None))
-        return df
+        dg = torch.empty((5, d.ny, d.nx), dtype=torch.float32, device=self.device) if thermal else None
+        check(lib().lbm_get_populations(self._ctx, k, _ptr(df), _ptr(dg)))
+        return (df, dg) if thermal else df
 
     def reduce(self, k: int):
         m = ctypes.c_double(); r = ctypes.c_double()

@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_1311_7239_amd import inputs as I
 from paper_1311_7239_amd import lbm
 from tests.gpu_cases import Pair
@@ -91,7 +92,68 @@ def test_single_domain_graph_replays_match_eager():
 
 
 def test_batch_rejects_unsupported_domains():
-    c = I.natural_convection(n=32)
+    # thermal and isothermal domains do not mix
     with pytest.raises(lbm.LBMError) as e:
-        lbm.batch_for_cases([c])
+        lbm.batch_for_cases([I.natural_convection(n=32), I.lid_cavity(n=32)])
     assert e.value.status == lbm.ENOTSUP
+    # recording for the adjoint is per single context
+    d = lbm.desc_from_case(I.lid_cavity(n=32), ckpt_every=4)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.Batch([d])
+    assert e.value.status == lbm.ENOTSUP
+
+
+def _thermal_cases():
+    a = I.natural_convection(n=96, Ra=1e6)
+    a.gbeta *= 10.0
+    b = I.natural_convection(n=64, phi=0.4, Da=1e-2, Ra=1e4, nee=True)
+    c = I.natural_convection(n=150, Da=1e-6, Ra=1e8)
+    c.ny = 70
+    return [a, b, c]
+
+
+def test_thermal_batch_is_bitwise_equal_to_single_domains():
+    """Thermal batches (bounce-back and on-node walls mixed): f and g after 37 steps
+    from seeded random states equal those of each domain stepped alone."""
+    cases = _thermal_cases()
+    b = lbm.batch_for_cases(cases)
+    states = []
+    for k, c in enumerate(cases):
+        df = torch.from_numpy(I.random_deviation_state(c.ny, c.nx, 1e-3, seed=40 + k)).cuda()
+        dg = torch.from_numpy(I.random_deviation_state(c.ny, c.nx, 1e-1, seed=50 + k, channels=5)).cuda()
+        b.set_populations(k, df, dg)
+        states.append((df, dg))
+    b.step(37)
+    assert b.time == 37
+    with pytest.raises(lbm.LBMError) as e:
+        b.set_populations(0, *states[0])
+    assert e.value.status == lbm.ESTATE
+    for k, c in enumerate(cases):
+        s = lbm.solver_for_case(c)
+        s.set_populations(*states[k])
+        s.step(37)
+        bf, bg = b.populations(k, thermal=True)
+        sf, sg = s.populations(thermal=True)
+        assert torch.equal(bf, sf), k
+        assert torch.equal(bg, sg), k
+        _, _, T = b.macroscopic(k, want_T=True)
+        _, _, Ts = s.macroscopic(want_T=True)
+        assert torch.equal(T, Ts), k
+
+
+def test_thermal_batch_matches_oracle():
+    """One thermal batch domain against the FP64 oracle after 20 steps."""
+    cases = _thermal_cases()
+    b = lbm.batch_for_cases(cases)
+    c = cases[1]
+    dg0 = I.random_deviation_state(c.ny, c.nx, 1e-1, seed=51, channels=5)
+    df0 = I.random_deviation_state(c.ny, c.nx, 1e-3, seed=41)
+    b.set_populations(1, torch.from_numpy(df0).cuda(), torch.from_numpy(dg0).cuda())
+    pair = Pair(c, df0=df0, dg0=dg0)   # its own GPU context stays at t = 0
+    b.step(20)
+    oracle.run(pair.p, pair.phi, pair.K, pair.F, pair.f, pair.g, nsteps=20)
+    got, gg = b.populations(1, thermal=True)
+    ref = pair.oracle_dev()
+    assert np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max() < 8 * 2.0 ** -24 * 8 * 20
+    gref = np.transpose(pair.g, (2, 0, 1)) - c.T0 / 5.0
+    assert np.abs(gg.cpu().numpy() - gref).max() / np.abs(gref).max() < 8 * 2.0 ** -24 * 8 * 20
