@@ -242,6 +242,15 @@ bool any_on_node_walls(const lbm_ctx *c) {
     return false;
 }
 
+// The two-cycle kernels address a state buffer with 32-bit byte offsets.
+bool buffer_below_4gib(const Layout &L) { return L.f_bytes < ((size_t)1 << 32); }
+
+bool two_cycle_possible(const lbm_ctx *c) {
+    for (const Domain &D : c->dom)
+        if (D.desc.thermal.enabled || on_node_walls(D.desc) || !buffer_below_4gib(D.L)) return false;
+    return true;
+}
+
 int device_fail(lbm_ctx *c, hipError_t e, const char *what) {
     if (c) c->poisoned = true;
     return fail(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -468,7 +477,7 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     c->rec_cap = cap;
     // two cycles per pass pays once the domain fills the GPU several times over
     // (the two-cycle kernels implement bounce-back walls only)
-    c->tblock = (!d->thermal.enabled && !on_node_walls(*d) && (int64_t)d->nx * d->ny >= ((int64_t)1 << 21)) ? 2 : 1;
+    c->tblock = (two_cycle_possible(c) && (int64_t)d->nx * d->ny >= ((int64_t)1 << 21)) ? 2 : 1;
     if (d->storage == LBM_FP16_DEV) c->sched = Schedule{64, 2, 2, 1};
     hipError_t e = init_domain(D, 0, phi, kappa, c->stream);
     if (e != hipSuccess) {
@@ -791,6 +800,8 @@ int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
         return fail(LBM_ENOTSUP, "thermal domains advance one cycle per pass");
     if (cycles_per_pass == 2 && any_on_node_walls(c))
         return fail(LBM_ENOTSUP, "on-node (extrapolated) walls advance one cycle per pass");
+    if (cycles_per_pass == 2 && !two_cycle_possible(c))
+        return fail(LBM_ENOTSUP, "a population buffer of 4 GiB or more advances one cycle per pass");
     c->tblock = cycles_per_pass;
     reset_graphs(c);
     return LBM_OK;
@@ -1049,7 +1060,7 @@ hipError_t autotune(lbm_ctx *c, Tuned &best) {
         }
         if (e != hipSuccess) break;
     }
-    const bool two_cycle_ok = !any_on_node_walls(c) && !c->batch_thermal;
+    const bool two_cycle_ok = two_cycle_possible(c);
     for (const auto &sh : kTwoCycleShapes) {
         if (e != hipSuccess || !two_cycle_ok) break;
         if ((e = upload_tiles2(c, sh[1])) != hipSuccess) break;

@@ -324,6 +324,83 @@ __device__ __forceinline__ void store_row(S *p, const float in[NX]) {
     __builtin_memcpy(q, tmp, sizeof(S) * NX);
 }
 
+// ---- raw buffer access ------------------------------------------------
+
+// CDNA buffer instructions: a 128-bit resource (base and byte size) lives in
+// scalar registers, each lane adds a 32-bit byte offset and the wave a
+// uniform one, so a gather of eight planes costs one vector offset instead of
+// eight 64-bit address computations. Reads beyond the size return 0 and
+// stores beyond it are dropped. Only for arrays below 4 GiB.
+typedef __amdgpu_buffer_rsrc_t BufRes;
+
+__device__ __forceinline__ BufRes buf_res(const void *base, uint32_t bytes) {
+    // word 3 of the resource for gfx9-family raw (unformatted, unswizzled) access
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename S> struct BufIO;
+template <> struct BufIO<float> {
+    __device__ __forceinline__ static float ld(BufRes r, uint32_t vo, uint32_t so) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+    }
+    __device__ __forceinline__ static void st(BufRes r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, 0);
+    }
+};
+template <> struct BufIO<_Float16> {
+    __device__ __forceinline__ static float ld(BufRes r, uint32_t vo, uint32_t so) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0);
+        _Float16 x;
+        __builtin_memcpy(&x, &h, 2);
+        return (float)x;
+    }
+    __device__ __forceinline__ static void st(BufRes r, uint32_t vo, uint32_t so, float v) {
+        const _Float16 x = (_Float16)v;
+        unsigned short h;
+        __builtin_memcpy(&h, &x, 2);
+        __builtin_amdgcn_raw_buffer_store_b16(h, r, (int)vo, (int)so, 0);
+    }
+};
+
+// The cell of the node at byte offset o4 of the FP32 planes (same values as
+// load_cell).
+struct CellPlanes {
+    BufRes phi, kappa, snu;
+};
+
+__device__ __forceinline__ CellPlanes cell_planes(const Dom &d) {
+    const uint32_t pb = (uint32_t)(d.plane * 4);
+    CellPlanes r;
+    r.phi = buf_res(d.phi, d.phi ? pb : 0u);
+    r.kappa = buf_res(d.kappa, d.kappa ? pb : 0u);
+    r.snu = buf_res(d.snu, d.snu ? pb : 0u);
+    return r;
+}
+
+// The raw per-node medium values of a node (porosity, 1/K, s_nu plane entries),
+// fetched early so that the loads are in flight while other work runs.
+struct CellRaw {
+    float phi, kappa, snu;
+};
+
+__device__ __forceinline__ CellRaw load_cell_raw(const Dom &d, const CellPlanes &pl, uint32_t o4) {
+    CellRaw r{0.0f, 0.0f, 0.0f};
+    if (d.medium != MED_UNIFORM) r.phi = BufIO<float>::ld(pl.phi, o4, 0u);
+    if (d.medium == MED_PHI_KAPPA) r.kappa = BufIO<float>::ld(pl.kappa, o4, 0u);
+    if (d.snu) r.snu = BufIO<float>::ld(pl.snu, o4, 0u);
+    return r;
+}
+
+// Same values as load_cell.
+__device__ __forceinline__ Cell cell_of(const Dom &d, const CellRaw &r) {
+    Cell c = cell_from(d, r.phi, r.kappa);
+    if (d.snu) {
+        c.s_nu = r.snu;
+        c.h_nu = 1.0f - 0.5f * r.snu;
+    }
+    return c;
+}
+
 // ---- gather (pull streaming, Eq. 15, with boundaries) -----------------
 
 // f_i(x, t) = f_i+(x - e_i, t-1); a link whose source lies beyond a wall is

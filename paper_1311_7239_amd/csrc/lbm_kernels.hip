@@ -297,31 +297,31 @@ template <typename S, int TW, int TH, int NT, bool REC>
 __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *urec_next,
                                            float (&lds)[8][TH + 2][TW + 2]) {
     constexpr int EW = TW + 2, EH = TH + 2, EN = EW * EH;
+    constexpr int ES = (int)sizeof(S);
     const S *__restrict__ fin = (const S *)d.fin;
-    S *__restrict__ fout = (S *)d.fout;
+    // the state buffers are below 4 GiB (the host keeps larger domains on the
+    // one-cycle kernel), so every byte offset fits the buffer instructions
+    const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
+    const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
+    const CellPlanes pl = cell_planes(d);
     // every source of phase A inside the domain, no wrap needed
     const bool interior = x0 >= 2 && x0 + TW + 2 <= d.nx && y0 >= 2 && y0 + TH + 2 <= d.ny;
 
+    // medium values of this thread's phase-B nodes, fetched now so that they
+    // arrive during phase A
+    constexpr int NB = (TW * TH + NT - 1) / NT;
+    CellRaw rawB[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int q = threadIdx.x + k * NT;
+        const int gx = x0 + q % TW, gy = y0 + q / TW;
+        rawB[k] = CellRaw{0.0f, 0.0f, 0.0f};
+        if (q < TW * TH && gx < d.nx && gy < d.ny)
+            rawB[k] = load_cell_raw(d, pl, (uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
+    }
+
     // phase A: s_{t+1} on the extended tile (and u(t) on the tile when recording)
-    for (int e = threadIdx.x; e < EN; e += NT) {
-        const int ex = e % EW, ey = e / EW;
-        int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
-        float f[8];
-        if (interior) {
-            gather_interior<S>(d, fin, gx, gy, f);
-        } else {
-            if (gx < 0 || gx >= d.nx) {
-                if (d.bc_x != BC_PERIODIC) continue;
-                gx = ((gx % d.nx) + d.nx) % d.nx;
-            }
-            if (gy < 0 || gy >= d.ny) {
-                if (d.bc_y != BC_PERIODIC) continue;
-                gy = ((gy % d.ny) + d.ny) % d.ny;
-            }
-            gather_general<S>(d, fin, gx, gy, f);
-        }
-        const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = load_cell(d, o);
+    auto finish_a = [&](float (&f)[8], const Cell &c, int ex, int ey, int64_t o) {
         float ux, uy;
         collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy);
 #pragma unroll
@@ -331,11 +331,57 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
             d.urec[o] = ux;
             d.urec[d.plane + o] = uy;
         }
+    };
+    if (interior) {
+        // link i pulls from (gx - e_ix, gy - e_iy): the lane's offset of (gx - 1, gy - 1)
+        // plus a uniform, non-negative per-link offset. Software pipelined: the next
+        // node's loads are issued before this node collides.
+        auto fetch = [&](int e, float (&f)[8], CellRaw &r) {
+            const int gx = x0 - 1 + e % EW, gy = y0 - 1 + e / EW;
+            const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * ES);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                f[i] = BufIO<S>::ld(rin, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
+            r = load_cell_raw(d, pl, (uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
+        };
+        float fn[8];
+        CellRaw rn{0.0f, 0.0f, 0.0f};
+        if ((int)threadIdx.x < EN) fetch(threadIdx.x, fn, rn);
+        for (int e = threadIdx.x; e < EN; e += NT) {
+            float f[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) f[i] = fn[i];
+            const CellRaw r = rn;
+            if (e + NT < EN) fetch(e + NT, fn, rn);
+            const int ex = e % EW, ey = e / EW;
+            const int64_t o = (int64_t)(y0 - 1 + ey) * d.pitch + (x0 - 1 + ex);
+            finish_a(f, cell_of(d, r), ex, ey, o);
+        }
+    } else {
+        for (int e = threadIdx.x; e < EN; e += NT) {
+            const int ex = e % EW, ey = e / EW;
+            int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
+            if (gx < 0 || gx >= d.nx) {
+                if (d.bc_x != BC_PERIODIC) continue;
+                gx = ((gx % d.nx) + d.nx) % d.nx;
+            }
+            if (gy < 0 || gy >= d.ny) {
+                if (d.bc_y != BC_PERIODIC) continue;
+                gy = ((gy % d.ny) + d.ny) % d.ny;
+            }
+            float f[8];
+            gather_general<S>(d, fin, gx, gy, f);
+            const int64_t o = (int64_t)gy * d.pitch + gx;
+            finish_a(f, cell_of(d, load_cell_raw(d, pl, (uint32_t)(o * 4))), ex, ey, o);
+        }
     }
     __syncthreads();
 
     // phase B: s_{t+2} on the tile (and u(t+1) when recording)
-    for (int q = threadIdx.x; q < TW * TH; q += NT) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int q = threadIdx.x + k * NT;
+        if (q >= TW * TH) continue;
         const int lx = q % TW, ly = q / TW;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= d.nx || gy >= d.ny) continue;
@@ -366,11 +412,12 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
             }
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = load_cell(d, o);
+        const Cell c = cell_of(d, rawB[k]);
         float ux, uy;
         collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy);
+        const uint32_t vo = (uint32_t)(o * ES);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) Store<S>::st(fout + i * d.plane + o, f[i]);
+        for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
         if (REC) {
             urec_next[o] = ux;
             urec_next[d.plane + o] = uy;
