@@ -211,6 +211,19 @@ int lbm_reduce(lbm_ctx *c, int32_t domain, double *mass, double *residual);
  * is left at T. */
 int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa);
 
+/* As lbm_backward, and also the gradient of L with respect to the scalar
+ * parameters of the recorded pass: dL_dtheta (host, 4 doubles) receives
+ * dL/dnu (nu enters the linear drag of Eq. 3 and s_nu of Eqs. 13 and 21, J
+ * held fixed), dL/da_x and dL/da_y (the uniform acceleration of Eq. 3) and
+ * dL/dlid_ux (the moving-wall term of the bounce-back lid), each summed over
+ * every node and step in a fixed order in FP64 (bitwise reproducible).
+ * dL_dphi may be NULL (then MEDIUM_UNIFORM is allowed); dL_dkappa as for
+ * lbm_backward. The recomputation records two more FP32 planes per step (the
+ * non-equilibrium stress moments). Synchronises the stream. Errors as for
+ * lbm_backward; EINVAL if dL_dtheta is NULL. */
+int lbm_backward_params(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa,
+                        double *dL_dtheta);
+
 /* Snapshot of one context's state (host memory, synchronous). */
 int lbm_state_bytes(const lbm_ctx *c, size_t *bytes);
 int lbm_save(lbm_ctx *c, void *host_buf, size_t bytes);

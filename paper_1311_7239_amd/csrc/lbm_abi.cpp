@@ -50,6 +50,7 @@ struct Layout {
     // recording for the adjoint
     int64_t nck = 0, ring = 0;
     size_t off_ck = 0, off_urec = 0, off_lam[2] = {0, 0}, off_gphi = 0, off_gkappa = 0;
+    size_t off_theta = 0, theta_slots = 0;  // parameter-gradient slots (4 doubles each) + 4 results
     size_t off_rf[2] = {0, 0};  // recomputation buffers (the forward state stays put)
     size_t total = 0;
 };
@@ -84,13 +85,16 @@ Layout make_layout(const lbm_desc &d, int64_t max_rec) {
         L.nck = max_rec / d.ckpt_every + 1;
         L.ring = d.ckpt_every;
         L.off_ck = carve(L.f_bytes * (size_t)L.nck);
-        L.off_urec = carve(L.p_bytes * 2 * (size_t)L.ring);
+        // per recorded step: u_x, u_y and the two stress moments (parameter gradients)
+        L.off_urec = carve(L.p_bytes * 4 * (size_t)L.ring);
         L.off_lam[0] = carve(L.p_bytes * 8);
         L.off_lam[1] = carve(L.p_bytes * 8);
         L.off_gphi = carve(L.p_bytes);
         L.off_gkappa = carve(L.p_bytes);
         L.off_rf[0] = carve(L.f_bytes);
         L.off_rf[1] = carve(L.f_bytes);
+        L.theta_slots = (size_t)adjoint_theta_slots(d.nx, d.ny);
+        L.off_theta = carve(sizeof(double) * 4 * (L.theta_slots + 1));
     }
     L.total = o;
     return L;
@@ -158,6 +162,7 @@ Dom make_dom(const lbm_desc &d, const Layout &L) {
     o.h_nu = (float)(1.0 - 0.5 * (double)o.s_nu);
     o.medium = d.medium;
     o.nu = (float)d.nu;
+    o.inv_nu = (float)(1.0 / d.nu);
     o.Fconst = (float)d.F_eps;
     if (d.medium == LBM_MEDIUM_UNIFORM) {
         const double F = d.F_eps >= 0.0 ? d.F_eps : 1.75 / std::sqrt(150.0 * d.phi0 * d.phi0 * d.phi0);
@@ -1166,18 +1171,23 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
     return LBM_OK;
 }
 
-extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa) {
+namespace {
+
+// The backward pass shared by lbm_backward and lbm_backward_params; theta
+// (host, 4 doubles) receives dL/dnu, dL/da_x, dL/da_y, dL/dU_lid when non-NULL.
+int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa, double *theta) {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (c->batch) return fail(LBM_ENOTSUP, "the adjoint runs on single-domain contexts");
     Domain &D = c->dom[0];
     const lbm_desc &d = D.desc;
-    if (!dL_du || !dL_dphi) return fail(LBM_EINVAL, "dL_du and dL_dphi are required");
+    if (!dL_du) return fail(LBM_EINVAL, "dL_du is required");
+    if (!dL_dphi && !theta) return fail(LBM_EINVAL, "dL_dphi is required");
     if (d.ckpt_every <= 0) return fail(LBM_ESTATE, "context was created without recording (ckpt_every = 0)");
     if (d.thermal.enabled) return fail(LBM_ENOTSUP, "adjoint of the thermal coupling is not implemented");
     if (on_node_walls(d)) return fail(LBM_ENOTSUP, "adjoint of on-node (extrapolated) walls is not implemented");
     if (d.storage != LBM_FP32_DEV) return fail(LBM_ENOTSUP, "adjoint needs FP32 storage");
-    if (d.medium == LBM_MEDIUM_UNIFORM) return fail(LBM_ENOTSUP, "adjoint needs a porosity plane");
+    if (dL_dphi && d.medium == LBM_MEDIUM_UNIFORM) return fail(LBM_ENOTSUP, "dL/dphi needs a porosity plane");
     if (dL_dkappa && d.medium != LBM_MEDIUM_PHI_KAPPA) return fail(LBM_EINVAL, "dL_dkappa needs LBM_MEDIUM_PHI_KAPPA");
     if (!c->rec_valid) return fail(LBM_ESTATE, "no recorded trajectory leads to the current state");
     const int64_t T = c->t, k = d.ckpt_every;
@@ -1189,15 +1199,22 @@ extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, floa
     float *gphi = (float *)(D.base + L.off_gphi);
     float *gk = d.medium == LBM_MEDIUM_PHI_KAPPA ? (float *)(D.base + L.off_gkappa) : nullptr;
     float *urec = (float *)(D.base + L.off_urec);
+    const size_t rstride = 4 * (size_t)L.plane;  // floats per recorded step
+    double *acc = theta ? (double *)(D.base + L.off_theta) : nullptr;
+    double *acc_seed = acc ? acc + 4 * adjoint_theta_offset(d.nx, d.ny, 0) : nullptr;
+    double *acc_step = acc ? acc + 4 * adjoint_theta_offset(d.nx, d.ny, 1) : nullptr;
+    double *acc_step2 = acc ? acc + 4 * adjoint_theta_offset(d.nx, d.ny, 2) : nullptr;
     hipStream_t st = c->stream;
 
-    hipError_t e = launch_adjoint_seed(dom_for(D, c->cur), src_now(T), dL_du, lam[0], gphi, gk, st);
+    hipError_t e = hipSuccess;
+    if (acc) e = launch_fill_zero(acc, sizeof(double) * 4 * (L.theta_slots + 1), st);
+    if (e == hipSuccess) e = launch_adjoint_seed(dom_for(D, c->cur), src_now(T), dL_du, lam[0], gphi, gk, acc_seed, st);
     if (e != hipSuccess) return device_fail(c, e, "adjoint seed");
     int la = 0;  // lam[la] holds a(t + 1)
     if (T > 0) {
         for (int64_t s0 = ((T - 1) / k) * k; s0 >= 0; s0 -= k) {
             const int64_t s1 = (s0 + k < T) ? s0 + k : T;
-            // recompute the segment from its checkpoint, recording u(t)
+            // recompute the segment from its checkpoint, recording u(t) (and the stress moments)
             e = hipMemcpyAsync(D.base + L.off_rf[0], D.base + L.off_ck + (size_t)(s0 / k) * L.f_bytes,
                                L.f_bytes, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return device_fail(c, e, "checkpoint restore");
@@ -1206,11 +1223,11 @@ extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, floa
                 Dom dr = D.dom;
                 dr.fin = D.base + L.off_rf[p];
                 dr.fout = D.base + L.off_rf[p ^ 1];
-                dr.urec = urec + (size_t)(t - s0) * 2 * (size_t)L.plane;
+                dr.urec = urec + (size_t)(t - s0) * rstride;
+                dr.rec_stress = theta ? 1 : 0;
                 if (c->tblock == 2 && t > 0 && t + 1 < s1) {
-                    // two cycles in one pass, recording u(t) and u(t + 1)
-                    e = launch_step2(dr, ST_F32, c->sched.swizzle, c->tb_threads, c->tb_rows,
-                                     dr.urec + 2 * (size_t)L.plane, st);
+                    // two cycles in one pass, recording at t and t + 1
+                    e = launch_step2(dr, ST_F32, c->sched.swizzle, c->tb_threads, c->tb_rows, dr.urec + rstride, st);
                     t += 2;
                 } else {
                     e = launch_step(dr, ST_F32, t == 0 ? SRC_DIRECT : SRC_GATHER, true, c->sched, st);
@@ -1221,13 +1238,12 @@ extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, floa
             }
             // backward through the segment (two steps per pass in two-cycle mode)
             for (int64_t t = s1 - 1; t >= s0;) {
-                const float *ut = urec + (size_t)(t - s0) * 2 * (size_t)L.plane;
+                const float *ut = urec + (size_t)(t - s0) * rstride;
                 if (c->tblock == 2 && t - 1 >= s0) {
-                    e = launch_adjoint_step2(D.dom, lam[la], lam[la ^ 1], ut, ut - 2 * (size_t)L.plane, gphi, gk,
-                                             st);
+                    e = launch_adjoint_step2(D.dom, lam[la], lam[la ^ 1], ut, ut - rstride, gphi, gk, acc_step2, st);
                     t -= 2;
                 } else {
-                    e = launch_adjoint_step(D.dom, lam[la], lam[la ^ 1], ut, gphi, gk, st);
+                    e = launch_adjoint_step(D.dom, lam[la], lam[la ^ 1], ut, gphi, gk, acc_step, st);
                     t -= 1;
                 }
                 if (e != hipSuccess) return device_fail(c, e, "adjoint step");
@@ -1235,8 +1251,28 @@ extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, floa
             }
         }
     }
-    e = launch_unpitch(gphi, L.pitch, dL_dphi, d.nx, d.ny, st);
+    if (dL_dphi) e = launch_unpitch(gphi, L.pitch, dL_dphi, d.nx, d.ny, st);
     if (e == hipSuccess && dL_dkappa) e = launch_unpitch(gk, L.pitch, dL_dkappa, d.nx, d.ny, st);
     if (e != hipSuccess) return device_fail(c, e, "gradient copy");
+    if (theta) {
+        double *res = acc + 4 * (int64_t)L.theta_slots;
+        e = launch_theta_final(acc, (int64_t)L.theta_slots, res, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(theta, res, sizeof(double) * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return device_fail(c, e, "parameter gradients");
+    }
     return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa) {
+    if (c && !c->batch && !dL_dphi) return fail(LBM_EINVAL, "dL_du and dL_dphi are required");
+    return backward_impl(c, dL_du, dL_dphi, dL_dkappa, nullptr);
+}
+
+extern "C" int lbm_backward_params(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa,
+                                   double *dL_dtheta) {
+    if (!dL_dtheta) return fail(LBM_EINVAL, "dL_dtheta is required");
+    return backward_impl(c, dL_du, dL_dphi, dL_dkappa, dL_dtheta);
 }

@@ -24,7 +24,54 @@ constexpr int ABLOCK = 256;
 // cd = phi nu kappa, cf = phi F sqrt(kappa), and 1/phi.
 struct ParamBar {
     float pax, pay, cd, cf, ip;
+    float s;   // adjoint of the node's s_nu (s_7 = s_8)
 };
+
+// Per-thread sums of the adjoints of the scalar parameters: nu, a_x, a_y and
+// the lid velocity.
+struct ThetaSum {
+    float nu, ax, ay, lid;
+};
+
+// A node's share of dL/dnu, dL/da_x, dL/da_y at one step: a enters as phi a;
+// nu enters the linear drag cd = phi nu / K (Eq. 3) and s_nu = 1/(1/2 + 3 J nu)
+// (Eq. 21), whose derivative is -s_nu (1 - s_nu/2) / nu for any J.
+__device__ __forceinline__ void theta_add(const Dom &d, const Cell &c, const ParamBar &pb, ThetaSum &ts) {
+    ts.ax += c.phi * pb.pax;
+    ts.ay += c.phi * pb.pay;
+    ts.nu += (pb.cd * c.cd - pb.s * c.s_nu * c.h_nu) * d.inv_nu;
+}
+
+// The lid term of the bounce-back gather adds (U/6) e_ix to links 6 and 7
+// of a top-row node (e_iy = -1), so a(t) there carries (a_7 - a_6)/6 to dL/dU.
+__device__ __forceinline__ float lid_share(const Dom &d, int y, float a6, float a7) {
+    return (d.bc_y == BC_WALLS && y == d.ny - 1) ? (a7 - a6) * (1.0f / 6.0f) : 0.0f;
+}
+
+// Adds the block's sums of ts to slot[0..3] in a fixed order (bitwise
+// reproducible); every thread of the block calls it.
+template <int NT>
+__device__ __forceinline__ void block_theta_add(const ThetaSum &ts, double *slot) {
+    __shared__ double red[NT / 64][4];
+    double v[4] = {ts.nu, ts.ax, ts.ay, ts.lid};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[w][k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            double acc = 0.0;
+            for (int j = 0; j < NT / 64; ++j) acc += red[j][k];
+            slot[k] += acc;
+        }
+    }
+}
 
 // y -> M^T y with the paper's M (Eq. 10); y in moment order.
 __device__ __forceinline__ void apply_MT(const float y[8], float f[8]) {
@@ -66,9 +113,11 @@ __device__ __forceinline__ void velocity_adjoint(const Cell &c, float ux, float 
 // Reverse mode of one node's collision (Eq. 14 and f+ = M^-1 m+): given the
 // adjoint b of f+, returns the adjoint a of the pre-collision f and the
 // medium adjoints. u is the node's velocity at this time step.
+// n7, n8: the node's non-equilibrium stress moments before relaxation (only
+// the adjoint of s_nu uses them).
 __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, const Cell &c,
                                                 float pax, float pay, float ux, float uy,
-                                                float a[8], ParamBar &pb) {
+                                                float n7, float n8, float a[8], ParamBar &pb) {
     // mbar+ = diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) M b
     const float A1 = b[0] + b[2], B1 = b[1] + b[3], C1 = b[4] + b[6], D1 = b[5] + b[7];
     const float x13 = b[0] - b[2], y24 = b[1] - b[3], p57 = b[4] - b[6], q68 = b[5] - b[7];
@@ -108,6 +157,8 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
                       2.0f * c.h_nu * ux * ip * P7 + c.h_nu * uy * ip * P8;
     const float Fby = 0.8f * d.h_e * uy * ip * P2 + 0.5f * P5 - d.h_q * P6 -
                       2.0f * c.h_nu * uy * ip * P7 + c.h_nu * ux * ip * P8;
+    // m7+ = m7 - s (m7 - m7^eq) + (1 - s/2) S7 (and m8+ alike): d/ds = -n7 - S7/2
+    pb.s = P7 * (-n7 - (ux * Fx - uy * Fy) * ip) + P8 * (-n8 - 0.5f * (ux * Fy + uy * Fx) * ip);
     pb.ip = (0.4f * d.s_e * u2 + 0.8f * d.h_e * uF) * P2 +
             (c.s_nu * (ux * ux - uy * uy) + 2.0f * c.h_nu * (ux * Fx - uy * Fy)) * P7 +
             (c.s_nu * ux * uy + c.h_nu * (ux * Fy + uy * Fx)) * P8;
@@ -158,63 +209,79 @@ __device__ __forceinline__ float kappa_at(const Dom &d, int64_t o) {
     return d.medium == MED_PHI_KAPPA ? d.kappa[o] : 0.0f;
 }
 
-// a(T) and the direct medium gradient of u(T), from f(T) and dL/du(T).
-template <int SRC_T>
+// a(T) and the direct medium gradient of u(T), from f(T) and dL/du(T). With
+// THETA the block also adds its share of the parameter gradients to acc.
+template <int SRC_T, bool THETA>
 __global__ __launch_bounds__(ABLOCK) void k_adjoint_seed(Dom d, const float *__restrict__ dLdu,
                                                          float *__restrict__ lam,
                                                          float *__restrict__ gphi,
-                                                         float *__restrict__ gkappa) {
+                                                         float *__restrict__ gkappa,
+                                                         double *__restrict__ acc) {
     const int x = blockIdx.x * ABLOCK + threadIdx.x, y = blockIdx.y;
-    if (x >= d.nx) return;
-    float f[8];
-    if (SRC_T == SRC_DIRECT) load_own<float>(d, (const float *)d.fin, x, y, f);
-    else gather_general<float>(d, (const float *)d.fin, x, y, f);
-    const int64_t o = (int64_t)y * d.pitch + x;
-    const Cell c = load_cell(d, o);
-    const float pax = c.phi * d.ax, pay = c.phi * d.ay;
-    float ux, uy, m1;
-    node_velocity(f, c, pax, pay, ux, uy, m1);
-    const int64_t q = (int64_t)y * d.nx + x, n = (int64_t)d.nx * d.ny;
-    ParamBar pb{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    float vbx, vby;
-    velocity_adjoint(c, ux, uy, dLdu[q], dLdu[n + q], vbx, vby, pb);
+    ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
+    if (x < d.nx) {
+        float f[8];
+        if (SRC_T == SRC_DIRECT) load_own<float>(d, (const float *)d.fin, x, y, f);
+        else gather_general<float>(d, (const float *)d.fin, x, y, f);
+        const int64_t o = (int64_t)y * d.pitch + x;
+        const Cell c = load_cell(d, o);
+        const float pax = c.phi * d.ax, pay = c.phi * d.ay;
+        float ux, uy, m1;
+        node_velocity(f, c, pax, pay, ux, uy, m1);
+        const int64_t q = (int64_t)y * d.nx + x, n = (int64_t)d.nx * d.ny;
+        ParamBar pb{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        float vbx, vby;
+        velocity_adjoint(c, ux, uy, dLdu[q], dLdu[n + q], vbx, vby, pb);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lam[i * d.plane + o] = (float)EX[i] * vbx + (float)EY[i] * vby;
-    float gp, gk;
-    medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
-    gphi[o] = gp;
-    if (gkappa) gkappa[o] = gk;
+        for (int i = 0; i < 8; ++i) lam[i * d.plane + o] = (float)EX[i] * vbx + (float)EY[i] * vby;
+        float gp, gk;
+        medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
+        gphi[o] = gp;
+        if (gkappa) gkappa[o] = gk;
+        if (THETA) theta_add(d, c, pb, ts);
+    }
+    if (THETA) block_theta_add<ABLOCK>(ts, acc + 4 * ((int64_t)blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 __device__ __forceinline__ void gather_transposed(const Dom &d, const float *__restrict__ lam, int x,
                                                   int y, bool interior, float b[8]);
 
-// One backward step at time t: lam_out = a(t), lam_in = a(t+1), u_t = u(t).
+// One backward step at time t: lam_out = a(t), lam_in = a(t+1), u_t = u(t)
+// (with THETA also the stress moments n7, n8 in planes 2 and 3).
+template <bool THETA>
 __global__ __launch_bounds__(ABLOCK) void k_adjoint_step(Dom d, const float *__restrict__ lam_in,
                                                          float *__restrict__ lam_out,
                                                          const float *__restrict__ u_t,
                                                          float *__restrict__ gphi,
                                                          float *__restrict__ gkappa,
-                                                         int tiles_x) {
+                                                         int tiles_x, double *__restrict__ acc) {
     const int tx = blockIdx.x % tiles_x, y = blockIdx.x / tiles_x;
     const int x = tx * ABLOCK + threadIdx.x;
-    if (x >= d.nx) return;
-    const int64_t o = (int64_t)y * d.pitch + x;
-    const bool interior = tx * ABLOCK >= 1 && tx * ABLOCK + ABLOCK <= d.nx - 1 && y >= 1 &&
-                          y <= d.ny - 2;
-    float b[8];
-    gather_transposed(d, lam_in, x, y, interior, b);
-    const Cell c = load_cell(d, o);
-    const float ux = u_t[o], uy = u_t[d.plane + o];
-    float a[8];
-    ParamBar pb;
-    collide_adjoint(b, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, a, pb);
+    ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
+    if (x < d.nx) {
+        const int64_t o = (int64_t)y * d.pitch + x;
+        const bool interior = tx * ABLOCK >= 1 && tx * ABLOCK + ABLOCK <= d.nx - 1 && y >= 1 &&
+                              y <= d.ny - 2;
+        float b[8];
+        gather_transposed(d, lam_in, x, y, interior, b);
+        const Cell c = load_cell(d, o);
+        const float ux = u_t[o], uy = u_t[d.plane + o];
+        const float n7 = THETA ? u_t[2 * d.plane + o] : 0.0f, n8 = THETA ? u_t[3 * d.plane + o] : 0.0f;
+        float a[8];
+        ParamBar pb;
+        collide_adjoint(b, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8, a, pb);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lam_out[i * d.plane + o] = a[i];
-    float gp, gk;
-    medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
-    gphi[o] += gp;
-    if (gkappa) gkappa[o] += gk;
+        for (int i = 0; i < 8; ++i) lam_out[i * d.plane + o] = a[i];
+        float gp, gk;
+        medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
+        gphi[o] += gp;
+        if (gkappa) gkappa[o] += gk;
+        if (THETA) {
+            theta_add(d, c, pb, ts);
+            if (y == d.ny - 1) ts.lid += lid_share(d, y, lam_in[6 * d.plane + o], lam_in[7 * d.plane + o]);
+        }
+    }
+    if (THETA) block_theta_add<ABLOCK>(ts, acc + 4 * (int64_t)blockIdx.x);
 }
 
 // b_i(x) = a_i(x + e_i), or a_ibar(x) across a wall: the transpose of the
@@ -249,13 +316,14 @@ __device__ __forceinline__ void gather_transposed(const Dom &d, const float *__r
 // bitwise that of two k_adjoint_step launches.
 constexpr int ATW = 64, ATH = 16, ANT = 512;
 
+template <bool THETA>
 __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__restrict__ lam_in,
                                                        float *__restrict__ lam_out,
                                                        const float *__restrict__ u_t,
                                                        const float *__restrict__ u_tm1,
                                                        float *__restrict__ gphi,
                                                        float *__restrict__ gkappa, int tiles_x,
-                                                       int swz) {
+                                                       int swz, double *__restrict__ acc) {
     constexpr int EW = ATW + 2, EH = ATH + 2, EN = EW * EH;
     __shared__ float lds[8][EH][EW];
     __shared__ float gA[ATH][ATW];
@@ -264,6 +332,7 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
     if (swz) b = xcd_swizzle(b, gridDim.x);
     const int x0 = (b % tiles_x) * ATW, y0 = (b / tiles_x) * ATH;
     const bool interior = x0 >= 2 && x0 + ATW + 2 <= d.nx && y0 >= 2 && y0 + ATH + 2 <= d.ny;
+    ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
 
     for (int e = threadIdx.x; e < EN; e += ANT) {
         const int ex = e % EW, ey = e / EW;
@@ -282,9 +351,10 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
         gather_transposed(d, lam_in, gx, gy, interior, bb);
         const int64_t o = (int64_t)gy * d.pitch + gx;
         const Cell c = load_cell(d, o);
+        const float n7 = THETA ? u_t[2 * d.plane + o] : 0.0f, n8 = THETA ? u_t[3 * d.plane + o] : 0.0f;
         float a[8];
         ParamBar pb;
-        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, u_t[o], u_t[d.plane + o], a, pb);
+        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, u_t[o], u_t[d.plane + o], n7, n8, a, pb);
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[i][ey][ex] = a[i];
         if (ex >= 1 && ex <= ATW && ey >= 1 && ey <= ATH && x0 - 1 + ex < d.nx && y0 - 1 + ey < d.ny) {
@@ -292,6 +362,11 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
             medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
             gA[ey - 1][ex - 1] = gp;
             gkA[ey - 1][ex - 1] = gk;
+            if (THETA) {
+                theta_add(d, c, pb, ts);
+                if (gy == d.ny - 1)
+                    ts.lid += lid_share(d, gy, lam_in[6 * d.plane + o], lam_in[7 * d.plane + o]);
+            }
         }
     }
     __syncthreads();
@@ -316,43 +391,105 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
         const Cell c = load_cell(d, o);
+        const float n7 = THETA ? u_tm1[2 * d.plane + o] : 0.0f, n8 = THETA ? u_tm1[3 * d.plane + o] : 0.0f;
         float a[8];
         ParamBar pb;
-        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, u_tm1[o], u_tm1[d.plane + o], a, pb);
+        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, u_tm1[o], u_tm1[d.plane + o], n7, n8, a, pb);
 #pragma unroll
         for (int i = 0; i < 8; ++i) lam_out[i * d.plane + o] = a[i];
         float gp, gk;
         medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
         gphi[o] = (gphi[o] + gA[ly][lx]) + gp;
         if (gkappa) gkappa[o] = (gkappa[o] + gkA[ly][lx]) + gk;
+        if (THETA) {
+            theta_add(d, c, pb, ts);
+            if (gy == d.ny - 1)
+                ts.lid += lid_share(d, gy, lds[6][ly + 1][lx + 1], lds[7][ly + 1][lx + 1]);
+        }
+    }
+    if (THETA) {
+        __syncthreads();   // the block sum reuses shared memory after phase B's reads
+        block_theta_add<ANT>(ts, acc + 4 * (int64_t)b);
     }
 }
 
 hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
-                                const float *u_tm1, float *gphi, float *gkappa, hipStream_t st) {
+                                const float *u_tm1, float *gphi, float *gkappa, double *acc, hipStream_t st) {
     const int tiles_x = (d.nx + ATW - 1) / ATW, tiles_y = (d.ny + ATH - 1) / ATH;
-    hipLaunchKernelGGL(k_adjoint_step2, dim3((unsigned)(tiles_x * tiles_y)), dim3(ANT), 0, st, d, lam_in,
-                       lam_out, u_t, u_tm1, gphi, gkappa, tiles_x, 1);
+    const dim3 grid((unsigned)(tiles_x * tiles_y));
+    if (acc)
+        hipLaunchKernelGGL(k_adjoint_step2<true>, grid, dim3(ANT), 0, st, d, lam_in, lam_out, u_t, u_tm1,
+                           gphi, gkappa, tiles_x, 1, acc);
+    else
+        hipLaunchKernelGGL(k_adjoint_step2<false>, grid, dim3(ANT), 0, st, d, lam_in, lam_out, u_t, u_tm1,
+                           gphi, gkappa, tiles_x, 1, acc);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_seed(const Dom &d, Source src, const float *dLdu, float *lam,
-                               float *gphi, float *gkappa, hipStream_t st) {
+                               float *gphi, float *gkappa, double *acc, hipStream_t st) {
     const dim3 grid((unsigned)((d.nx + ABLOCK - 1) / ABLOCK), (unsigned)d.ny);
-    if (src == SRC_DIRECT)
-        hipLaunchKernelGGL(k_adjoint_seed<SRC_DIRECT>, grid, dim3(ABLOCK), 0, st, d, dLdu, lam, gphi, gkappa);
-    else
-        hipLaunchKernelGGL(k_adjoint_seed<SRC_GATHER>, grid, dim3(ABLOCK), 0, st, d, dLdu, lam, gphi, gkappa);
+    if (src == SRC_DIRECT) {
+        if (acc) hipLaunchKernelGGL((k_adjoint_seed<SRC_DIRECT, true>), grid, dim3(ABLOCK), 0, st, d, dLdu, lam, gphi, gkappa, acc);
+        else hipLaunchKernelGGL((k_adjoint_seed<SRC_DIRECT, false>), grid, dim3(ABLOCK), 0, st, d, dLdu, lam, gphi, gkappa, acc);
+    } else {
+        if (acc) hipLaunchKernelGGL((k_adjoint_seed<SRC_GATHER, true>), grid, dim3(ABLOCK), 0, st, d, dLdu, lam, gphi, gkappa, acc);
+        else hipLaunchKernelGGL((k_adjoint_seed<SRC_GATHER, false>), grid, dim3(ABLOCK), 0, st, d, dLdu, lam, gphi, gkappa, acc);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out,
-                               const float *u_t, float *gphi, float *gkappa, hipStream_t st) {
+                               const float *u_t, float *gphi, float *gkappa, double *acc, hipStream_t st) {
     const int tiles_x = (d.nx + ABLOCK - 1) / ABLOCK;
     const dim3 grid((unsigned)(tiles_x * d.ny));
-    hipLaunchKernelGGL(k_adjoint_step, grid, dim3(ABLOCK), 0, st, d, lam_in, lam_out, u_t, gphi,
-                       gkappa, tiles_x);
+    if (acc)
+        hipLaunchKernelGGL(k_adjoint_step<true>, grid, dim3(ABLOCK), 0, st, d, lam_in, lam_out, u_t, gphi,
+                           gkappa, tiles_x, acc);
+    else
+        hipLaunchKernelGGL(k_adjoint_step<false>, grid, dim3(ABLOCK), 0, st, d, lam_in, lam_out, u_t, gphi,
+                           gkappa, tiles_x, acc);
     return hipGetLastError();
+}
+
+// Sum of per-block parameter partials over n slots of 4 doubles, in a fixed
+// order (one workgroup): out[k] = sum_j slots[4 j + k].
+__global__ __launch_bounds__(256) void k_theta_final(const double *__restrict__ slots, int64_t n,
+                                                     double *__restrict__ out) {
+    __shared__ double red[256][4];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t j = threadIdx.x; j < n; j += 256) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] += slots[4 * j + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) red[threadIdx.x][k] = v[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red[threadIdx.x][k] += red[threadIdx.x + w][k];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = red[0][threadIdx.x];
+}
+
+hipError_t launch_theta_final(const double *slots, int64_t n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_theta_final, dim3(1), dim3(256), 0, st, slots, n, out);
+    return hipGetLastError();
+}
+
+int64_t adjoint_theta_slots(int nx, int ny) {
+    const int64_t seed = (int64_t)((nx + ABLOCK - 1) / ABLOCK) * ny;
+    const int64_t step = seed;
+    const int64_t step2 = (int64_t)((nx + ATW - 1) / ATW) * ((ny + ATH - 1) / ATH);
+    return seed + step + step2;
+}
+
+int64_t adjoint_theta_offset(int nx, int ny, int which) {
+    const int64_t seed = (int64_t)((nx + ABLOCK - 1) / ABLOCK) * ny;
+    return which == 0 ? 0 : (which == 1 ? seed : 2 * seed);
 }
 
 }  // namespace mrt

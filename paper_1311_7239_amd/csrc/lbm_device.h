@@ -63,7 +63,9 @@ struct Dom {
     void *fout;
     const float *gin;
     float *gout;
-    float *urec;                     // optional u(t) record: 2 planes
+    float *urec;                     // optional u(t) record: 2 planes (4 with rec_stress)
+    int32_t rec_stress;              // also record m7 - m7^eq and m8 - m8^eq (planes 2, 3)
+    float inv_nu;                    // 1 / nu (parameter gradients)
 };
 
 // Square root and reciprocal by the hardware instructions (v_sqrt_f32,
@@ -204,8 +206,10 @@ __device__ __forceinline__ void node_velocity(const float f[8], const Cell &c, f
 
 // One node's collision (Eq. 14) followed by f+ = M^-1 m+, in place on the
 // deviations. Returns u. pax/pay = phi * a (a may include buoyancy).
+// Also returns the non-equilibrium stress moments n7 = m7 - m7^eq and
+// n8 = m8 - m8^eq before relaxation (dropped by the compiler when unused).
 __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c, float pax,
-                                        float pay, float &ux, float &uy) {
+                                        float pay, float &ux, float &uy, float &n7, float &n8) {
     // m = M f (Eq. 8, rows of Eq. 10), shared sums first
     const float a = f[0] + f[2], b = f[1] + f[3], cc = f[4] + f[6], dg = f[5] + f[7];
     const float x13 = f[0] - f[2], y24 = f[1] - f[3], p57 = f[4] - f[6], q68 = f[5] - f[7];
@@ -246,8 +250,10 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
     const float pxy = (ux * uy) * ip;
     const float Sxx = 2.0f * fmaf(ux, Fx, -(uy * Fy)) * ip;
     const float Sxy = fmaf(ux, Fy, uy * Fx) * ip;
-    const float m7p = fmaf(c.h_nu, Sxx, fmaf(-c.s_nu, m7 - pxx, m7));
-    const float m8p = fmaf(c.h_nu, Sxy, fmaf(-c.s_nu, m8 - pxy, m8));
+    n7 = m7 - pxx;
+    n8 = m8 - pxy;
+    const float m7p = fmaf(c.h_nu, Sxx, fmaf(-c.s_nu, n7, m7));
+    const float m8p = fmaf(c.h_nu, Sxy, fmaf(-c.s_nu, n8, m8));
 
     // f+ = M^T diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m+
     const float A = 0.125f * m1, B = 0.125f * m2p;
@@ -265,6 +271,12 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
     f[5] = (apb - xd) + (yd - R);
     f[6] = (apb - xd) - (yd - R);
     f[7] = (apb + xd) - (yd + R);
+}
+
+__device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c, float pax,
+                                        float pay, float &ux, float &uy) {
+    float n7, n8;
+    collide(f, d, c, pax, pay, ux, uy, n7, n8);
 }
 
 // D2Q5 collision (Eq. B.2) on deviations dg = g - wT T0 (varpi = 0, so the

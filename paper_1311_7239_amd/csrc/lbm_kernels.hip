@@ -25,13 +25,13 @@ constexpr int BLOCK = 256;
 // paths below: collide, then return u.
 template <bool THERMAL>
 __device__ __forceinline__ void node_update(const Dom &d, const Cell &c, float f[8], float g[5],
-                                            float &ux, float &uy) {
+                                            float &ux, float &uy, float &n7, float &n8) {
     float ay = d.ay;
     if (THERMAL) {
         const float dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
         ay = d.ay + d.gbeta * dT;
     }
-    collide(f, d, c, c.phi * d.ax, c.phi * ay, ux, uy);
+    collide(f, d, c, c.phi * d.ax, c.phi * ay, ux, uy, n7, n8);
     if (THERMAL) thermal_collide(g, d, ux, uy);
 }
 
@@ -74,7 +74,7 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int64_t o = (int64_t)(y0 + ly + r * TH) * d.pitch + xb;
-            float ux[NX], uy[NX];
+            float ux[NX], uy[NX], n7[NX], n8[NX];
 #pragma unroll
             for (int k = 0; k < NX; ++k) {
                 float fn[8], gn[5];
@@ -86,7 +86,7 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
                 }
                 Cell c = cell_from(d, ph[r][k], kp[r][k]);
                 cell_viscosity(d, c, o + k);
-                node_update<THERMAL>(d, c, fn, gn, ux[k], uy[k]);
+                node_update<THERMAL>(d, c, fn, gn, ux[k], uy[k], n7[k], n8[k]);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) f[r][i][k] = fn[i];
                 if (THERMAL) {
@@ -103,6 +103,10 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
             if (REC) {
                 store_row<float, NX>(d.urec + o, ux);
                 store_row<float, NX>(d.urec + d.plane + o, uy);
+                if (d.rec_stress) {
+                    store_row<float, NX>(d.urec + 2 * d.plane + o, n7);
+                    store_row<float, NX>(d.urec + 3 * d.plane + o, n8);
+                }
             }
         }
         return;
@@ -128,8 +132,8 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
             }
             const int64_t o = (int64_t)y * d.pitch + x;
             const Cell c = load_cell(d, o);
-            float ux, uy;
-            node_update<THERMAL>(d, c, fn, gn, ux, uy);
+            float ux, uy, n7, n8;
+            node_update<THERMAL>(d, c, fn, gn, ux, uy, n7, n8);
 #pragma unroll
             for (int i = 0; i < 8; ++i) Store<S>::st(fout + i * d.plane + o, fn[i]);
             if (THERMAL) {
@@ -139,6 +143,10 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
             if (REC) {
                 d.urec[o] = ux;
                 d.urec[d.plane + o] = uy;
+                if (d.rec_stress) {
+                    d.urec[2 * d.plane + o] = n7;
+                    d.urec[3 * d.plane + o] = n8;
+                }
             }
         }
     }
@@ -322,14 +330,18 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
 
     // phase A: s_{t+1} on the extended tile (and u(t) on the tile when recording)
     auto finish_a = [&](float (&f)[8], const Cell &c, int ex, int ey, int64_t o) {
-        float ux, uy;
-        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy);
+        float ux, uy, n7, n8;
+        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[i][ey][ex] = (float)(S)f[i];
         if (REC && ex >= 1 && ex <= TW && ey >= 1 && ey <= TH && x0 - 1 + ex < d.nx &&
             y0 - 1 + ey < d.ny) {
             d.urec[o] = ux;
             d.urec[d.plane + o] = uy;
+            if (d.rec_stress) {
+                d.urec[2 * d.plane + o] = n7;
+                d.urec[3 * d.plane + o] = n8;
+            }
         }
     };
     if (interior) {
@@ -413,14 +425,18 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
         const Cell c = cell_of(d, rawB[k]);
-        float ux, uy;
-        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy);
+        float ux, uy, n7, n8;
+        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
         const uint32_t vo = (uint32_t)(o * ES);
 #pragma unroll
         for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
         if (REC) {
             urec_next[o] = ux;
             urec_next[d.plane + o] = uy;
+            if (d.rec_stress) {
+                urec_next[2 * d.plane + o] = n7;
+                urec_next[3 * d.plane + o] = n8;
+            }
         }
     }
 }

@@ -74,18 +74,27 @@ int reduce_blocks(int nx, int ny);
 hipError_t launch_reduce(const Dom &cur, Source src_cur, const Dom &prev, Source src_prev,
                          int storage, double *partials, double *result, hipStream_t st);
 
-// Discrete adjoint pieces (FP32 storage, isothermal).
+// Discrete adjoint pieces (FP32 storage, isothermal). acc (may be NULL):
+// per-workgroup FP64 slots of 4 (nu, a_x, a_y, U_lid) to which each launch
+// adds its share of the parameter gradients; with acc, the u record carries
+// the stress moments in planes 2 and 3.
 // Seed: lam(T) = (du/df)^T dL/du and g_phi = (du/dphi)^T dL/du at time T.
 hipError_t launch_adjoint_seed(const Dom &d, Source src, const float *dLdu, float *lam,
-                               float *gphi, float *gkappa, hipStream_t st);
+                               float *gphi, float *gkappa, double *acc, hipStream_t st);
 // One backward step: lam_out = J(t)^T G^T lam_in, g += (dC/dphi)^T G^T lam_in,
 // using u(t) from urec.
 hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out,
-                               const float *u_t, float *gphi, float *gkappa, hipStream_t st);
+                               const float *u_t, float *gphi, float *gkappa, double *acc, hipStream_t st);
 // Two backward steps per pass: lam_out = a(t-1) from lam_in = a(t+1), using
 // u(t) and u(t-1).
 hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
-                                const float *u_tm1, float *gphi, float *gkappa, hipStream_t st);
+                                const float *u_tm1, float *gphi, float *gkappa, double *acc, hipStream_t st);
+// Slots of 4 doubles the three adjoint kernels use for a domain (seed, step,
+// two-step regions, in that order) and the first slot of each region.
+int64_t adjoint_theta_slots(int nx, int ny);
+int64_t adjoint_theta_offset(int nx, int ny, int which);
+// out[0..3] = the sum of n slots, in a fixed order.
+hipError_t launch_theta_final(const double *slots, int64_t n, double *out, hipStream_t st);
 hipError_t launch_snu_plane(const float *J, double J0, double nu, float *out, int pitch, int nx,
                             int ny, int *bad, hipStream_t st);
 hipError_t launch_unpitch(const float *src, int pitch, float *dst, int nx, int ny,

@@ -76,6 +76,7 @@ def lib():
         L.lbm_reduce.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)]
         L.lbm_backward.argtypes = [_vp, _vp, _vp, _vp]
+        L.lbm_backward_params.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
         L.lbm_state_bytes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
         L.lbm_save.argtypes = [_vp, _vp, ctypes.c_size_t]
         L.lbm_load.argtypes = [_vp, _vp, ctypes.c_size_t]
@@ -230,6 +231,14 @@ class Solver:
         gk = torch.empty_like(g) if want_kappa else None
         check(lib().lbm_backward(self._ctx, _ptr(dL_du.contiguous()), _ptr(g), _ptr(gk)))
         return g, gk
+
+    def backward_params(self, dL_du: torch.Tensor, want_phi: bool = True, want_kappa: bool = False):
+        """(dL/dphi or None, dL/dkappa or None, {"nu", "ax", "ay", "lid_ux"}) of the recorded pass."""
+        g = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device) if want_phi else None
+        gk = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device) if want_kappa else None
+        th = (ctypes.c_double * 4)()
+        check(lib().lbm_backward_params(self._ctx, _ptr(dL_du.contiguous()), _ptr(g), _ptr(gk), th))
+        return g, gk, dict(zip(("nu", "ax", "ay", "lid_ux"), list(th)))
 
     def save(self) -> bytes:
         nb = ctypes.c_size_t()
