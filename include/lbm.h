@@ -224,6 +224,19 @@ int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkapp
 int lbm_backward_params(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa,
                         double *dL_dtheta);
 
+/* Tangent-linear (forward-mode) model of the recorded pass: reruns it from
+ * f(0) (the first checkpoint) to the current time T together with the
+ * derivative of the state along a direction of the inputs, and writes
+ * du = (d u(T) / d eps) at eps = 0 for phi + eps dphi and
+ * (nu, a_x, a_y, lid_ux) + eps dtheta, as device [2][ny][nx] (u_x plane then
+ * u_y). dphi: device [ny][nx] or NULL (no porosity change); dtheta: host 4
+ * doubles or NULL. The forward state is left at T; the checkpointed
+ * recording is required as for lbm_backward (ESTATE otherwise), and thermal,
+ * on-node walls, FP16 storage and batches give ENOTSUP. For any loss
+ * L(u(T)), <dL/du, du> equals <dL/dphi, dphi> + <dL/dtheta, dtheta> from
+ * lbm_backward_params up to rounding. */
+int lbm_tangent(lbm_ctx *c, const float *dphi, const double *dtheta, float *du);
+
 /* Snapshot of one context's state (host memory, synchronous). */
 int lbm_state_bytes(const lbm_ctx *c, size_t *bytes);
 int lbm_save(lbm_ctx *c, void *host_buf, size_t bytes);

@@ -1266,6 +1266,55 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
 
 }  // namespace
 
+extern "C" int lbm_tangent(lbm_ctx *c, const float *dphi, const double *dtheta, float *du) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (c->batch) return fail(LBM_ENOTSUP, "the tangent runs on single-domain contexts");
+    Domain &D = c->dom[0];
+    const lbm_desc &d = D.desc;
+    if (!du) return fail(LBM_EINVAL, "du is required");
+    if (d.ckpt_every <= 0) return fail(LBM_ESTATE, "context was created without recording (ckpt_every = 0)");
+    if (d.thermal.enabled) return fail(LBM_ENOTSUP, "tangent of the thermal coupling is not implemented");
+    if (on_node_walls(d)) return fail(LBM_ENOTSUP, "tangent of on-node (extrapolated) walls is not implemented");
+    if (d.storage != LBM_FP32_DEV) return fail(LBM_ENOTSUP, "the tangent needs FP32 storage");
+    if (dphi && d.medium == LBM_MEDIUM_UNIFORM) return fail(LBM_ENOTSUP, "a porosity direction needs a porosity plane");
+    if (!c->rec_valid) return fail(LBM_ESTATE, "no recorded trajectory leads to the current state");
+    const int64_t T = c->t;
+    const Layout &L = D.L;
+    hipStream_t st = c->stream;
+    float *tan[2] = {(float *)(D.base + L.off_lam[0]), (float *)(D.base + L.off_lam[1])};
+    float *dphi_p = nullptr;
+    hipError_t e = hipSuccess;
+    if (dphi) {
+        dphi_p = (float *)(D.base + L.off_gphi);
+        e = launch_fill_zero(dphi_p, align_up(L.p_bytes, 16), st);
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(dphi_p, (size_t)L.pitch * 4, dphi, (size_t)d.nx * 4, (size_t)d.nx * 4,
+                                 (size_t)d.ny, hipMemcpyDeviceToDevice, st);
+    }
+    // f(0) from the first checkpoint; the tangent of f(0) is zero
+    if (e == hipSuccess) e = hipMemcpyAsync(D.base + L.off_rf[0], D.base + L.off_ck, L.f_bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = launch_fill_zero(tan[0], (size_t)L.p_bytes * 8, st);
+    if (e != hipSuccess) return device_fail(c, e, "tangent set-up");
+    const float dnu = dtheta ? (float)dtheta[0] : 0.0f, dax = dtheta ? (float)dtheta[1] : 0.0f;
+    const float day = dtheta ? (float)dtheta[2] : 0.0f, dU = dtheta ? (float)dtheta[3] : 0.0f;
+    int p = 0;
+    for (int64_t t = 0; t <= T; ++t) {
+        Dom ds = D.dom, dtn = D.dom;
+        ds.fin = D.base + L.off_rf[p];
+        ds.fout = D.base + L.off_rf[p ^ 1];
+        dtn.fin = tan[p];
+        dtn.fout = tan[p ^ 1];
+        dtn.lid6 = dU / 6.0f;
+        const Source src = t == 0 ? SRC_DIRECT : SRC_GATHER;
+        if (t == T) e = launch_tangent_u(ds, dtn, src, dphi_p, dnu, dax, day, du, st);
+        else e = launch_tangent_step(ds, dtn, src, dphi_p, dnu, dax, day, st);
+        if (e != hipSuccess) return device_fail(c, e, "tangent step");
+        p ^= 1;
+    }
+    return LBM_OK;
+}
+
 extern "C" int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa) {
     if (c && !c->batch && !dL_dphi) return fail(LBM_EINVAL, "dL_du and dL_dphi are required");
     return backward_impl(c, dL_du, dL_dphi, dL_dkappa, nullptr);

@@ -180,13 +180,10 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
     apply_MT(mb, a);
 }
 
-// Medium adjoints -> dL/dphi (and dL/dkappa with a kappa plane).
-__device__ __forceinline__ void medium_gradient(const Dom &d, const Cell &c, float kappa,
-                                                const ParamBar &pb, float ax, float ay,
-                                                float &gphi, float &gkappa) {
+// d cd / d phi and d cf / d phi of a node (Eqs. 3-4; zero without a porosity plane).
+__device__ __forceinline__ void cell_phi_derivs(const Dom &d, const Cell &c, float kappa, float &dcd,
+                                                float &dcf) {
     const float phi = c.phi, ip = c.inv_phi;
-    float dcd, dcf;
-    gkappa = 0.0f;
     if (d.medium == MED_PHI_ERGUN) {
         // kappa = kcoef (1-phi)^2 / phi^3; sqrt(kappa) = sk (1 - phi)
         const float om = 1.0f - phi;
@@ -194,11 +191,27 @@ __device__ __forceinline__ void medium_gradient(const Dom &d, const Cell &c, flo
         const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
         dcd = -2.0f * d.nu * d.kcoef * om * (ip * ip * ip);
         dcf = ((d.Fconst >= 0.0f) ? -0.5f : -2.0f) * c.cf * ip - phi * F * sk;
+    } else if (d.medium == MED_PHI_KAPPA) {
+        const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
+        dcd = d.nu * kappa;
+        dcf = ((d.Fconst >= 0.0f) ? 1.0f : -0.5f) * F * hw_sqrt(kappa);
     } else {
+        dcd = 0.0f;
+        dcf = 0.0f;
+    }
+}
+
+// Medium adjoints -> dL/dphi (and dL/dkappa with a kappa plane).
+__device__ __forceinline__ void medium_gradient(const Dom &d, const Cell &c, float kappa,
+                                                const ParamBar &pb, float ax, float ay,
+                                                float &gphi, float &gkappa) {
+    const float phi = c.phi, ip = c.inv_phi;
+    float dcd, dcf;
+    cell_phi_derivs(d, c, kappa, dcd, dcf);
+    gkappa = 0.0f;
+    if (d.medium == MED_PHI_KAPPA) {
         const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
         const float sq = hw_sqrt(kappa);
-        dcd = d.nu * kappa;
-        dcf = ((d.Fconst >= 0.0f) ? 1.0f : -0.5f) * F * sq;
         const float dcf_dk = (kappa > 0.0f) ? 0.5f * phi * F * hw_rcp(sq) : 0.0f;
         gkappa = pb.cd * phi * d.nu + pb.cf * dcf_dk;
     }
@@ -449,6 +462,178 @@ hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out
     else
         hipLaunchKernelGGL(k_adjoint_step<false>, grid, dim3(ABLOCK), 0, st, d, lam_in, lam_out, u_t, gphi,
                            gkappa, tiles_x, acc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- tangent
+
+// Forward mode of the velocity recovery (Eqs. 18-19) on the solution: with
+// D = 2 l0 + l1 |u| and R = l0 + l1 |u|, du/dv = (I - (l1 / (2 R |u|)) u u^T) / D,
+// du/dcd = -u / (4 R) and du/dcf = -|u| u / (4 R) (the transposes of the maps
+// velocity_adjoint applies).
+__device__ __forceinline__ void velocity_tangent(const Cell &c, float ux, float uy, float vdx, float vdy,
+                                                 float dcd, float dcf, float &udx, float &udy) {
+    const float umag = hw_sqrt(ux * ux + uy * uy);
+    const float l0 = 0.5f * (1.0f + 0.5f * c.cd);
+    const float l1 = 0.5f * c.cf;
+    const float R = l0 + l1 * umag;
+    const float D = l0 + R;
+    const float rR = hw_rcp(R), rD = hw_rcp(D);
+    const float corr = (umag > 0.0f) ? (0.5f * l1 * rR) * (ux * vdx + uy * vdy) * hw_rcp(umag) : 0.0f;
+    const float w = 0.25f * (dcd + umag * dcf) * rR;
+    udx = (vdx - corr * ux) * rD - w * ux;
+    udy = (vdy - corr * uy) * rD - w * uy;
+}
+
+// Tangents of the node's inputs: phi a (per component), cd, cf, 1/phi and s_nu.
+struct TanIn {
+    float dpax, dpay, dcd, dcf, dip, ds;
+};
+
+__device__ __forceinline__ TanIn tangent_inputs(const Dom &d, const Cell &c, float kappa, float dphi,
+                                                float dnu, float dax, float day) {
+    float dcd_dphi, dcf_dphi;
+    cell_phi_derivs(d, c, kappa, dcd_dphi, dcf_dphi);
+    TanIn t;
+    t.dpax = dphi * d.ax + c.phi * dax;
+    t.dpay = dphi * d.ay + c.phi * day;
+    t.dcd = dcd_dphi * dphi + c.cd * dnu * d.inv_nu;
+    t.dcf = dcf_dphi * dphi;
+    t.dip = -c.inv_phi * c.inv_phi * dphi;
+    t.ds = -c.s_nu * c.h_nu * dnu * d.inv_nu;   // s_nu = 1/(1/2 + 3 J nu)
+    return t;
+}
+
+// Forward mode of one node's collision (Eq. 14 and f+ = M^-1 m+): given f and
+// its tangent ft, returns the tangent of f+.
+__device__ __forceinline__ void collide_tangent(const float f[8], const float ft[8], const Dom &d,
+                                                const Cell &c, float pax, float pay, const TanIn &ti,
+                                                float out[8]) {
+    auto moments = [](const float g[8], float m[8]) {
+        const float a = g[0] + g[2], b = g[1] + g[3], cc = g[4] + g[6], dg = g[5] + g[7];
+        const float x13 = g[0] - g[2], y24 = g[1] - g[3], p57 = g[4] - g[6], q68 = g[5] - g[7];
+        const float pmq = p57 - q68, ppq = p57 + q68;
+        m[0] = (a + b) + (cc + dg);
+        m[1] = (cc + dg) - (a + b);
+        m[2] = x13 + pmq;
+        m[3] = fmaf(-2.0f, x13, pmq);
+        m[4] = y24 + ppq;
+        m[5] = fmaf(-2.0f, y24, ppq);
+        m[6] = a - b;
+        m[7] = cc - dg;
+    };
+    float m[8], dm[8];
+    moments(f, m);
+    moments(ft, dm);
+    // forward quantities, as in collide
+    float ux, uy;
+    velocity(c, fmaf(0.5f, pax, m[2]), fmaf(0.5f, pay, m[4]), ux, uy);
+    const float umag = hw_sqrt(fmaf(ux, ux, uy * uy));
+    const float drag = fmaf(c.cf, umag, c.cd);
+    const float Fx = fmaf(-drag, ux, pax), Fy = fmaf(-drag, uy, pay);
+    const float ip = c.inv_phi;
+    // tangents of u, |u| and F (Eq. 3)
+    float udx, udy;
+    velocity_tangent(c, ux, uy, dm[2] + 0.5f * ti.dpax, dm[4] + 0.5f * ti.dpay, ti.dcd, ti.dcf, udx, udy);
+    const float dumag = (umag > 0.0f) ? (ux * udx + uy * udy) * hw_rcp(umag) : 0.0f;
+    const float ddrag = ti.dcd + ti.dcf * umag + c.cf * dumag;
+    const float dFx = ti.dpax - ddrag * ux - drag * udx;
+    const float dFy = ti.dpay - ddrag * uy - drag * udy;
+    // relaxation (Eq. 14) differentiated term by term
+    const float u2 = ux * ux + uy * uy, uF = ux * Fx + uy * Fy;
+    const float du2 = 2.0f * (ux * udx + uy * udy);
+    const float duF = (udx * Fx + ux * dFx) + (udy * Fy + uy * dFy);
+    float mp[8];
+    mp[0] = dm[0];
+    mp[1] = dm[1] - d.s_e * (dm[1] + 0.6f * dm[0] - 0.4f * (du2 * ip + u2 * ti.dip)) +
+            0.8f * d.h_e * (duF * ip + uF * ti.dip);
+    mp[2] = udx + 0.5f * dFx;
+    mp[4] = udy + 0.5f * dFy;
+    mp[3] = dm[3] - d.s_q * (dm[3] + udx) - d.h_q * dFx;
+    mp[5] = dm[5] - d.s_q * (dm[5] + udy) - d.h_q * dFy;
+    const float pxx = (ux * ux - uy * uy) * ip, pxy = ux * uy * ip;
+    const float Sxx = 2.0f * (ux * Fx - uy * Fy) * ip, Sxy = (ux * Fy + uy * Fx) * ip;
+    const float dpxx = 2.0f * (ux * udx - uy * udy) * ip + (ux * ux - uy * uy) * ti.dip;
+    const float dpxy = (udx * uy + ux * udy) * ip + ux * uy * ti.dip;
+    const float dSxx = 2.0f * ((udx * Fx + ux * dFx) - (udy * Fy + uy * dFy)) * ip +
+                       2.0f * (ux * Fx - uy * Fy) * ti.dip;
+    const float dSxy = ((udx * Fy + ux * dFy) + (udy * Fx + uy * dFx)) * ip + (ux * Fy + uy * Fx) * ti.dip;
+    mp[6] = dm[6] - c.s_nu * (dm[6] - dpxx) + c.h_nu * dSxx - ti.ds * ((m[6] - pxx) + 0.5f * Sxx);
+    mp[7] = dm[7] - c.s_nu * (dm[7] - dpxy) + c.h_nu * dSxy - ti.ds * ((m[7] - pxy) + 0.5f * Sxy);
+    // f+ tangent = M^T diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m+ tangent
+    const float y[8] = {0.125f * mp[0], 0.125f * mp[1], mp[2] * (1.0f / 6.0f), mp[3] * (1.0f / 12.0f),
+                        mp[4] * (1.0f / 6.0f), mp[5] * (1.0f / 12.0f), 0.25f * mp[6], 0.25f * mp[7]};
+    apply_MT(y, out);
+}
+
+// One cycle of the state and its tangent: d streams the state (fin -> fout),
+// dt the tangent (same geometry, its own buffers, lid6 = dU/6 so that the
+// moving-wall term's tangent enters the bounce-back). dphi: tangent porosity
+// plane (pitched, may be NULL); dnu, dax, day: tangent parameters.
+__global__ __launch_bounds__(ABLOCK) void k_tangent_step(Dom d, Dom dt, int src, const float *__restrict__ dphi,
+                                                         float dnu, float dax, float day) {
+    const int x = blockIdx.x * ABLOCK + threadIdx.x, y = blockIdx.y;
+    if (x >= d.nx) return;
+    float f[8], ft[8];
+    if (src == SRC_DIRECT) {
+        load_own<float>(d, (const float *)d.fin, x, y, f);
+        load_own<float>(dt, (const float *)dt.fin, x, y, ft);
+    } else {
+        gather_general<float>(d, (const float *)d.fin, x, y, f);
+        gather_general<float>(dt, (const float *)dt.fin, x, y, ft);
+    }
+    const int64_t o = (int64_t)y * d.pitch + x;
+    const Cell c = load_cell(d, o);
+    const TanIn ti = tangent_inputs(d, c, kappa_at(d, o), dphi ? dphi[o] : 0.0f, dnu, dax, day);
+    float fpt[8];
+    collide_tangent(f, ft, d, c, c.phi * d.ax, c.phi * d.ay, ti, fpt);
+    float ux, uy;
+    collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy);
+    float *fo = (float *)d.fout, *fto = (float *)dt.fout;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        fo[i * d.plane + o] = f[i];
+        fto[i * d.plane + o] = fpt[i];
+    }
+}
+
+// Tangent of u at the state's time into du [2][ny][nx] (unpitched).
+__global__ __launch_bounds__(ABLOCK) void k_tangent_u(Dom d, Dom dt, int src, const float *__restrict__ dphi,
+                                                      float dnu, float dax, float day, float *__restrict__ du) {
+    const int x = blockIdx.x * ABLOCK + threadIdx.x, y = blockIdx.y;
+    if (x >= d.nx) return;
+    float f[8], ft[8];
+    if (src == SRC_DIRECT) {
+        load_own<float>(d, (const float *)d.fin, x, y, f);
+        load_own<float>(dt, (const float *)dt.fin, x, y, ft);
+    } else {
+        gather_general<float>(d, (const float *)d.fin, x, y, f);
+        gather_general<float>(dt, (const float *)dt.fin, x, y, ft);
+    }
+    const int64_t o = (int64_t)y * d.pitch + x;
+    const Cell c = load_cell(d, o);
+    const TanIn ti = tangent_inputs(d, c, kappa_at(d, o), dphi ? dphi[o] : 0.0f, dnu, dax, day);
+    float ux, uy, m1, dux, duy, dm1;
+    node_velocity(f, c, c.phi * d.ax, c.phi * d.ay, ux, uy, m1);
+    float dm3, dm5;
+    conserved_moments(ft, dm1, dm3, dm5);
+    velocity_tangent(c, ux, uy, dm3 + 0.5f * ti.dpax, dm5 + 0.5f * ti.dpay, ti.dcd, ti.dcf, dux, duy);
+    const int64_t q = (int64_t)y * d.nx + x, n = (int64_t)d.nx * d.ny;
+    du[q] = dux;
+    du[n + q] = duy;
+}
+
+hipError_t launch_tangent_step(const Dom &d, const Dom &dt, Source src, const float *dphi, float dnu,
+                               float dax, float day, hipStream_t st) {
+    const dim3 grid((unsigned)((d.nx + ABLOCK - 1) / ABLOCK), (unsigned)d.ny);
+    hipLaunchKernelGGL(k_tangent_step, grid, dim3(ABLOCK), 0, st, d, dt, (int)src, dphi, dnu, dax, day);
+    return hipGetLastError();
+}
+
+hipError_t launch_tangent_u(const Dom &d, const Dom &dt, Source src, const float *dphi, float dnu, float dax,
+                            float day, float *du, hipStream_t st) {
+    const dim3 grid((unsigned)((d.nx + ABLOCK - 1) / ABLOCK), (unsigned)d.ny);
+    hipLaunchKernelGGL(k_tangent_u, grid, dim3(ABLOCK), 0, st, d, dt, (int)src, dphi, dnu, dax, day, du);
     return hipGetLastError();
 }
 

@@ -93,6 +93,13 @@ hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_ou
 // two-step regions, in that order) and the first slot of each region.
 int64_t adjoint_theta_slots(int nx, int ny);
 int64_t adjoint_theta_offset(int nx, int ny, int which);
+// Tangent-linear (forward mode): one cycle of the state (d) and its tangent
+// (dt: the tangent buffers, lid6 = dU/6), and the tangent of u at the
+// state's time into du [2][ny][nx].
+hipError_t launch_tangent_step(const Dom &d, const Dom &dt, Source src, const float *dphi, float dnu,
+                               float dax, float day, hipStream_t st);
+hipError_t launch_tangent_u(const Dom &d, const Dom &dt, Source src, const float *dphi, float dnu, float dax,
+                            float day, float *du, hipStream_t st);
 // out[0..3] = the sum of n slots, in a fixed order.
 hipError_t launch_theta_final(const double *slots, int64_t n, double *out, hipStream_t st);
 hipError_t launch_snu_plane(const float *J, double J0, double nu, float *out, int pitch, int nx,

@@ -77,6 +77,7 @@ def lib():
                                  ctypes.POINTER(ctypes.c_double)]
         L.lbm_backward.argtypes = [_vp, _vp, _vp, _vp]
         L.lbm_backward_params.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
+        L.lbm_tangent.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
         L.lbm_state_bytes.argtypes = [_vp, ctypes.POINTER(ctypes.c_size_t)]
         L.lbm_save.argtypes = [_vp, _vp, ctypes.c_size_t]
         L.lbm_load.argtypes = [_vp, _vp, ctypes.c_size_t]
@@ -239,6 +240,14 @@ class Solver:
         th = (ctypes.c_double * 4)()
         check(lib().lbm_backward_params(self._ctx, _ptr(dL_du.contiguous()), _ptr(g), _ptr(gk), th))
         return g, gk, dict(zip(("nu", "ax", "ay", "lid_ux"), list(th)))
+
+    def tangent(self, dphi: Optional[torch.Tensor] = None, dtheta=None) -> torch.Tensor:
+        """Directional derivative of u(T) [2, ny, nx] along dphi [ny, nx] and
+        dtheta (nu, ax, ay, lid_ux) of the recorded pass."""
+        du = torch.empty((2, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        th = None if dtheta is None else (ctypes.c_double * 4)(*[float(v) for v in dtheta])
+        check(lib().lbm_tangent(self._ctx, _ptr(None if dphi is None else dphi.contiguous()), th, _ptr(du)))
+        return du
 
     def save(self) -> bytes:
         nb = ctypes.c_size_t()
