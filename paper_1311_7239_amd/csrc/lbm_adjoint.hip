@@ -338,6 +338,7 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
                                                        float *__restrict__ gkappa, int tiles_x,
                                                        int swz, double *__restrict__ acc) {
     constexpr int EW = ATW + 2, EH = ATH + 2, EN = EW * EH;
+    constexpr int NB = (ATW * ATH + ANT - 1) / ANT;
     __shared__ float lds[8][EH][EW];
     __shared__ float gA[ATH][ATW];
     __shared__ float gkA[ATH][ATW];
@@ -345,12 +346,98 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
     if (swz) b = xcd_swizzle(b, gridDim.x);
     const int x0 = (b % tiles_x) * ATW, y0 = (b / tiles_x) * ATH;
     const bool interior = x0 >= 2 && x0 + ATW + 2 <= d.nx && y0 >= 2 && y0 + ATH + 2 <= d.ny;
+    // every buffer is below 4 GiB (the host runs two steps per pass only then):
+    // byte offsets go through buffer resources
+    const uint32_t pb4 = (uint32_t)(d.plane * 4);
+    const BufRes rlin = buf_res(lam_in, 8 * pb4), rlout = buf_res(lam_out, 8 * pb4);
+    const BufRes rut = buf_res(u_t, 4 * pb4), rutm = buf_res(u_tm1, 4 * pb4);
+    const BufRes rg = buf_res(gphi, pb4), rgk = buf_res(gkappa, gkappa ? pb4 : 0u);
+    const CellPlanes pl = cell_planes(d);
     ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
 
-    for (int e = threadIdx.x; e < EN; e += ANT) {
-        const int ex = e % EW, ey = e / EW;
-        int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
-        if (!interior) {
+    // inputs of this thread's phase-B nodes, fetched now so that they arrive during phase A
+    CellRaw rawB[NB];
+    float uB[NB][4], gB[NB], gkB[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int q = threadIdx.x + k * ANT;
+        const int gx = x0 + q % ATW, gy = y0 + q / ATW;
+        rawB[k] = CellRaw{0.0f, 0.0f, 0.0f};
+        uB[k][0] = uB[k][1] = uB[k][2] = uB[k][3] = 0.0f;
+        gB[k] = gkB[k] = 0.0f;
+        if (q < ATW * ATH && gx < d.nx && gy < d.ny) {
+            const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+            rawB[k] = load_cell_raw(d, pl, o4);
+            uB[k][0] = BufIO<float>::ld(rutm, o4, 0u);
+            uB[k][1] = BufIO<float>::ld(rutm, o4, pb4);
+            if (THETA) {
+                uB[k][2] = BufIO<float>::ld(rutm, o4, 2 * pb4);
+                uB[k][3] = BufIO<float>::ld(rutm, o4, 3 * pb4);
+            }
+            gB[k] = BufIO<float>::ld(rg, o4, 0u);
+            if (gkappa) gkB[k] = BufIO<float>::ld(rgk, o4, 0u);
+        }
+    }
+
+    // phase A: a(t) on the tile plus a one-node ring, from a(t+1) in HBM
+    auto finish_a = [&](float (&bb)[8], const CellRaw &r, const float (&uu)[4], int ex, int ey, int gx,
+                        int gy) {
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = cell_of(d, r);
+        float a[8];
+        ParamBar pb;
+        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, uu[0], uu[1], uu[2], uu[3], a, pb);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[i][ey][ex] = a[i];
+        if (ex >= 1 && ex <= ATW && ey >= 1 && ey <= ATH && x0 - 1 + ex < d.nx && y0 - 1 + ey < d.ny) {
+            float gp, gk;
+            medium_gradient(d, c, r.kappa, pb, d.ax, d.ay, gp, gk);
+            gA[ey - 1][ex - 1] = gp;
+            gkA[ey - 1][ex - 1] = gk;
+            if (THETA) {
+                theta_add(d, c, pb, ts);
+                if (gy == d.ny - 1) {
+                    const uint32_t o4 = (uint32_t)(o * 4);
+                    ts.lid += lid_share(d, gy, BufIO<float>::ld(rlin, o4, 6 * pb4), BufIO<float>::ld(rlin, o4, 7 * pb4));
+                }
+            }
+        }
+    };
+    if (interior) {
+        // b_i(x) = a_i(x + e_i): the lane's offset of (gx - 1, gy - 1) plus a uniform,
+        // non-negative per-link offset; the next node's loads are issued before this
+        // node's reverse-mode collision (software pipeline)
+        auto fetch = [&](int e, float (&bb)[8], CellRaw &r, float (&uu)[4]) {
+            const int gx = x0 - 1 + e % EW, gy = y0 - 1 + e / EW;
+            const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * 4);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                bb[i] = BufIO<float>::ld(rlin, vo, (uint32_t)((i * d.plane + (1 + EY[i]) * d.pitch + (1 + EX[i])) * 4));
+            const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+            r = load_cell_raw(d, pl, o4);
+            uu[0] = BufIO<float>::ld(rut, o4, 0u);
+            uu[1] = BufIO<float>::ld(rut, o4, pb4);
+            uu[2] = THETA ? BufIO<float>::ld(rut, o4, 2 * pb4) : 0.0f;
+            uu[3] = THETA ? BufIO<float>::ld(rut, o4, 3 * pb4) : 0.0f;
+        };
+        float bn[8], un[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        CellRaw rn{0.0f, 0.0f, 0.0f};
+        if ((int)threadIdx.x < EN) fetch(threadIdx.x, bn, rn, un);
+        for (int e = threadIdx.x; e < EN; e += ANT) {
+            float bb[8], uu[4];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bb[i] = bn[i];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) uu[k] = un[k];
+            const CellRaw r = rn;
+            if (e + ANT < EN) fetch(e + ANT, bn, rn, un);
+            const int ex = e % EW, ey = e / EW;
+            finish_a(bb, r, uu, ex, ey, x0 - 1 + ex, y0 - 1 + ey);
+        }
+    } else {
+        for (int e = threadIdx.x; e < EN; e += ANT) {
+            const int ex = e % EW, ey = e / EW;
+            int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
             if (gx < 0 || gx >= d.nx) {
                 if (d.bc_x != BC_PERIODIC) continue;
                 gx = ((gx % d.nx) + d.nx) % d.nx;
@@ -359,71 +446,63 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
                 if (d.bc_y != BC_PERIODIC) continue;
                 gy = ((gy % d.ny) + d.ny) % d.ny;
             }
-        }
-        float bb[8];
-        gather_transposed(d, lam_in, gx, gy, interior, bb);
-        const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = load_cell(d, o);
-        const float n7 = THETA ? u_t[2 * d.plane + o] : 0.0f, n8 = THETA ? u_t[3 * d.plane + o] : 0.0f;
-        float a[8];
-        ParamBar pb;
-        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, u_t[o], u_t[d.plane + o], n7, n8, a, pb);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) lds[i][ey][ex] = a[i];
-        if (ex >= 1 && ex <= ATW && ey >= 1 && ey <= ATH && x0 - 1 + ex < d.nx && y0 - 1 + ey < d.ny) {
-            float gp, gk;
-            medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
-            gA[ey - 1][ex - 1] = gp;
-            gkA[ey - 1][ex - 1] = gk;
+            float bb[8];
+            gather_transposed(d, lam_in, gx, gy, false, bb);
+            const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+            float uu[4] = {BufIO<float>::ld(rut, o4, 0u), BufIO<float>::ld(rut, o4, pb4), 0.0f, 0.0f};
             if (THETA) {
-                theta_add(d, c, pb, ts);
-                if (gy == d.ny - 1)
-                    ts.lid += lid_share(d, gy, lam_in[6 * d.plane + o], lam_in[7 * d.plane + o]);
+                uu[2] = BufIO<float>::ld(rut, o4, 2 * pb4);
+                uu[3] = BufIO<float>::ld(rut, o4, 3 * pb4);
             }
+            finish_a(bb, load_cell_raw(d, pl, o4), uu, ex, ey, gx, gy);
         }
     }
     __syncthreads();
 
+    // phase B: a(t-1) on the tile from LDS
     const float *flat = &lds[0][0][0];
-    for (int q = threadIdx.x; q < ATW * ATH; q += ANT) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int q = threadIdx.x + k * ANT;
+        if (q >= ATW * ATH) continue;
         const int lx = q % ATW, ly = q / ATW;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= d.nx || gy >= d.ny) continue;
         float bb[8];
+        if (interior) {
+            const int base = (ly + 1) * EW + lx + 1;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            bool out = false;
-            if (!interior) {
+            for (int i = 0; i < 8; ++i) bb[i] = flat[base + i * EH * EW + EY[i] * EW + EX[i]];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                bool out = false;
                 const int sx = gx + EX[i], sy = gy + EY[i];
                 if (EX[i] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) out = true;
                 if (EY[i] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) out = true;
+                const int src = out ? (OPP[i] * EH + ly + 1) * EW + lx + 1
+                                    : (i * EH + ly + 1 + EY[i]) * EW + lx + 1 + EX[i];
+                bb[i] = flat[src];
             }
-            const int src = out ? (OPP[i] * EH + ly + 1) * EW + lx + 1
-                                : (i * EH + ly + 1 + EY[i]) * EW + lx + 1 + EX[i];
-            bb[i] = flat[src];
         }
-        const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = load_cell(d, o);
-        const float n7 = THETA ? u_tm1[2 * d.plane + o] : 0.0f, n8 = THETA ? u_tm1[3 * d.plane + o] : 0.0f;
+        const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+        const Cell c = cell_of(d, rawB[k]);
         float a[8];
         ParamBar pb;
-        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, u_tm1[o], u_tm1[d.plane + o], n7, n8, a, pb);
+        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, uB[k][0], uB[k][1], uB[k][2], uB[k][3], a, pb);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) lam_out[i * d.plane + o] = a[i];
+        for (int i = 0; i < 8; ++i) BufIO<float>::st(rlout, o4, (uint32_t)i * pb4, a[i]);
         float gp, gk;
-        medium_gradient(d, c, kappa_at(d, o), pb, d.ax, d.ay, gp, gk);
-        gphi[o] = (gphi[o] + gA[ly][lx]) + gp;
-        if (gkappa) gkappa[o] = (gkappa[o] + gkA[ly][lx]) + gk;
+        medium_gradient(d, c, rawB[k].kappa, pb, d.ax, d.ay, gp, gk);
+        BufIO<float>::st(rg, o4, 0u, (gB[k] + gA[ly][lx]) + gp);
+        if (gkappa) BufIO<float>::st(rgk, o4, 0u, (gkB[k] + gkA[ly][lx]) + gk);
         if (THETA) {
             theta_add(d, c, pb, ts);
             if (gy == d.ny - 1)
                 ts.lid += lid_share(d, gy, lds[6][ly + 1][lx + 1], lds[7][ly + 1][lx + 1]);
         }
     }
-    if (THETA) {
-        __syncthreads();   // the block sum reuses shared memory after phase B's reads
-        block_theta_add<ANT>(ts, acc + 4 * (int64_t)b);
-    }
+    if (THETA) block_theta_add<ANT>(ts, acc + 4 * (int64_t)b);
 }
 
 hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
