@@ -374,8 +374,8 @@ template <> struct BufIO<_Float16> {
     }
 };
 
-// The cell of the node at byte offset o4 of the FP32 planes (same values as
-// load_cell).
+// Buffer resources over a domain's per-node medium planes (porosity, 1/K,
+// s_nu), each NULL plane given size 0.
 struct CellPlanes {
     BufRes phi, kappa, snu;
 };
@@ -441,15 +441,6 @@ __device__ __forceinline__ void gather_general(const Dom &d, const S *__restrict
             f[i] = v;
         }
     }
-}
-
-template <typename S>
-__device__ __forceinline__ void gather_interior(const Dom &d, const S *__restrict__ fin, int x,
-                                                int y, float f[8]) {
-    const int64_t o = (int64_t)y * d.pitch + x;
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-        f[i] = Store<S>::ld(fin + i * d.plane + o - EY[i] * d.pitch - EX[i]);
 }
 
 template <typename S>
