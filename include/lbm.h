@@ -65,7 +65,7 @@ extern "C" {
  * (Th at x = 0, Tc at x = nx - 1), y walls adiabatic (T of B). Needs >= 3
  * nodes on the axis; the other axis is periodic or on-node (mixing with
  * LBM_WALLS gives ENOTSUP). Such contexts advance one cycle per pass and
- * have no adjoint (ENOTSUP). */
+ * have no adjoint or tangent (ENOTSUP). */
 #define LBM_WALLS_NEE 2
 
 /* population storage */
@@ -205,10 +205,12 @@ int lbm_reduce(lbm_ctx *c, int32_t domain, double *mass, double *residual);
  * (u_x plane then u_y; zeros where L does not look). Writes dL/dphi
  * [ny][nx] (device) and, for MEDIUM_PHI_KAPPA, dL/dkappa (device, may be
  * NULL). In MEDIUM_PHI_ERGUN, kappa and F_phi follow phi through Eq. (4).
- * ESTATE if the context was not created with ckpt_every > 0, if the state
- * was replaced since t = 0, or if T exceeds the recorded capacity; ENOTSUP
- * for thermal, FP16 storage, batches or MEDIUM_UNIFORM. The forward state
- * is left at T. */
+ * With the thermal model the adjoint runs through the coupling (the
+ * buoyancy of Sec. 3.4 and the D2Q5 equilibrium's dependence on u, App. B;
+ * checkpoints then hold g too), one step per pass. ESTATE if the context was
+ * not created with ckpt_every > 0, if the state was replaced since t = 0, or
+ * if T exceeds the recorded capacity; ENOTSUP for on-node walls, FP16
+ * storage, batches or MEDIUM_UNIFORM. The forward state is left at T. */
 int lbm_backward(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkappa);
 
 /* As lbm_backward, and also the gradient of L with respect to the scalar

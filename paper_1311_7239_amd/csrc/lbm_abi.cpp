@@ -52,6 +52,8 @@ struct Layout {
     size_t off_ck = 0, off_urec = 0, off_lam[2] = {0, 0}, off_gphi = 0, off_gkappa = 0;
     size_t off_theta = 0, theta_slots = 0;  // parameter-gradient slots (4 doubles each) + 4 results
     size_t off_rf[2] = {0, 0};  // recomputation buffers (the forward state stays put)
+    size_t ck_slot = 0;         // bytes per checkpoint: populations (+ thermal populations)
+    size_t off_lamg[2] = {0, 0}, off_rg[2] = {0, 0};  // thermal adjoint and recomputation
     size_t total = 0;
 };
 
@@ -84,15 +86,23 @@ Layout make_layout(const lbm_desc &d, int64_t max_rec) {
     if (d.ckpt_every > 0) {
         L.nck = max_rec / d.ckpt_every + 1;
         L.ring = d.ckpt_every;
-        L.off_ck = carve(L.f_bytes * (size_t)L.nck);
-        // per recorded step: u_x, u_y and the two stress moments (parameter gradients)
-        L.off_urec = carve(L.p_bytes * 4 * (size_t)L.ring);
+        L.ck_slot = L.f_bytes + (d.thermal.enabled ? L.g_bytes : 0);
+        L.off_ck = carve(L.ck_slot * (size_t)L.nck);
+        // per recorded step: u_x, u_y, the two stress moments (parameter gradients)
+        // and the temperature deviation (thermal coupling)
+        L.off_urec = carve(L.p_bytes * 5 * (size_t)L.ring);
         L.off_lam[0] = carve(L.p_bytes * 8);
         L.off_lam[1] = carve(L.p_bytes * 8);
         L.off_gphi = carve(L.p_bytes);
         L.off_gkappa = carve(L.p_bytes);
         L.off_rf[0] = carve(L.f_bytes);
         L.off_rf[1] = carve(L.f_bytes);
+        if (d.thermal.enabled) {
+            L.off_lamg[0] = carve(L.g_bytes);
+            L.off_lamg[1] = carve(L.g_bytes);
+            L.off_rg[0] = carve(L.g_bytes);
+            L.off_rg[1] = carve(L.g_bytes);
+        }
         L.theta_slots = (size_t)adjoint_theta_slots(d.nx, d.ny);
         L.off_theta = carve(sizeof(double) * 4 * (L.theta_slots + 1));
     }
@@ -337,8 +347,12 @@ hipError_t checkpoint(lbm_ctx *c) {
     if (!c->rec_valid || k <= 0 || c->t % k != 0) return hipSuccess;
     const int64_t slot = c->t / k;
     if (slot >= D.L.nck) return hipSuccess;  // beyond capacity: backward will refuse
-    return hipMemcpyAsync(D.base + D.L.off_ck + (size_t)slot * D.L.f_bytes, D.base + D.L.off_f[c->cur],
-                          D.L.f_bytes, hipMemcpyDeviceToDevice, c->stream);
+    char *dst = D.base + D.L.off_ck + (size_t)slot * D.L.ck_slot;
+    hipError_t e = hipMemcpyAsync(dst, D.base + D.L.off_f[c->cur], D.L.f_bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess && D.desc.thermal.enabled)
+        e = hipMemcpyAsync(dst + D.L.f_bytes, D.base + D.L.off_g[c->cur], D.L.g_bytes, hipMemcpyDeviceToDevice,
+                           c->stream);
+    return e;
 }
 
 }  // namespace
@@ -1184,10 +1198,10 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
     if (!dL_du) return fail(LBM_EINVAL, "dL_du is required");
     if (!dL_dphi && !theta) return fail(LBM_EINVAL, "dL_dphi is required");
     if (d.ckpt_every <= 0) return fail(LBM_ESTATE, "context was created without recording (ckpt_every = 0)");
-    if (d.thermal.enabled) return fail(LBM_ENOTSUP, "adjoint of the thermal coupling is not implemented");
     if (on_node_walls(d)) return fail(LBM_ENOTSUP, "adjoint of on-node (extrapolated) walls is not implemented");
     if (d.storage != LBM_FP32_DEV) return fail(LBM_ENOTSUP, "adjoint needs FP32 storage");
     if (dL_dphi && d.medium == LBM_MEDIUM_UNIFORM) return fail(LBM_ENOTSUP, "dL/dphi needs a porosity plane");
+    const bool th = d.thermal.enabled != 0;
     if (dL_dkappa && d.medium != LBM_MEDIUM_PHI_KAPPA) return fail(LBM_EINVAL, "dL_dkappa needs LBM_MEDIUM_PHI_KAPPA");
     if (!c->rec_valid) return fail(LBM_ESTATE, "no recorded trajectory leads to the current state");
     const int64_t T = c->t, k = d.ckpt_every;
@@ -1199,7 +1213,8 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
     float *gphi = (float *)(D.base + L.off_gphi);
     float *gk = d.medium == LBM_MEDIUM_PHI_KAPPA ? (float *)(D.base + L.off_gkappa) : nullptr;
     float *urec = (float *)(D.base + L.off_urec);
-    const size_t rstride = 4 * (size_t)L.plane;  // floats per recorded step
+    const size_t rstride = 5 * (size_t)L.plane;  // floats per recorded step
+    float *lamg[2] = {th ? (float *)(D.base + L.off_lamg[0]) : nullptr, th ? (float *)(D.base + L.off_lamg[1]) : nullptr};
     double *acc = theta ? (double *)(D.base + L.off_theta) : nullptr;
     double *acc_seed = acc ? acc + 4 * adjoint_theta_offset(d.nx, d.ny, 0) : nullptr;
     double *acc_step = acc ? acc + 4 * adjoint_theta_offset(d.nx, d.ny, 1) : nullptr;
@@ -1208,15 +1223,19 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
 
     hipError_t e = hipSuccess;
     if (acc) e = launch_fill_zero(acc, sizeof(double) * 4 * (L.theta_slots + 1), st);
-    if (e == hipSuccess) e = launch_adjoint_seed(dom_for(D, c->cur), src_now(T), dL_du, lam[0], gphi, gk, acc_seed, st);
+    if (e == hipSuccess)
+        e = th ? launch_adjoint_seed_thermal(dom_for(D, c->cur), src_now(T), dL_du, lam[0], lamg[0], gphi, gk, acc_seed, st)
+               : launch_adjoint_seed(dom_for(D, c->cur), src_now(T), dL_du, lam[0], gphi, gk, acc_seed, st);
     if (e != hipSuccess) return device_fail(c, e, "adjoint seed");
     int la = 0;  // lam[la] holds a(t + 1)
     if (T > 0) {
         for (int64_t s0 = ((T - 1) / k) * k; s0 >= 0; s0 -= k) {
             const int64_t s1 = (s0 + k < T) ? s0 + k : T;
             // recompute the segment from its checkpoint, recording u(t) (and the stress moments)
-            e = hipMemcpyAsync(D.base + L.off_rf[0], D.base + L.off_ck + (size_t)(s0 / k) * L.f_bytes,
-                               L.f_bytes, hipMemcpyDeviceToDevice, st);
+            const char *slot = D.base + L.off_ck + (size_t)(s0 / k) * L.ck_slot;
+            e = hipMemcpyAsync(D.base + L.off_rf[0], slot, L.f_bytes, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess && th)
+                e = hipMemcpyAsync(D.base + L.off_rg[0], slot + L.f_bytes, L.g_bytes, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return device_fail(c, e, "checkpoint restore");
             int p = 0;
             for (int64_t t = s0; t < s1;) {
@@ -1225,6 +1244,10 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
                 dr.fout = D.base + L.off_rf[p ^ 1];
                 dr.urec = urec + (size_t)(t - s0) * rstride;
                 dr.rec_stress = theta ? 1 : 0;
+                if (th) {
+                    dr.gin = (const float *)(D.base + L.off_rg[p]);
+                    dr.gout = (float *)(D.base + L.off_rg[p ^ 1]);
+                }
                 if (c->tblock == 2 && t > 0 && t + 1 < s1) {
                     // two cycles in one pass, recording at t and t + 1
                     e = launch_step2(dr, ST_F32, c->sched.swizzle, c->tb_threads, c->tb_rows, dr.urec + rstride, st);
@@ -1239,7 +1262,11 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
             // backward through the segment (two steps per pass in two-cycle mode)
             for (int64_t t = s1 - 1; t >= s0;) {
                 const float *ut = urec + (size_t)(t - s0) * rstride;
-                if (c->tblock == 2 && t - 1 >= s0) {
+                if (th) {
+                    e = launch_adjoint_step_thermal(D.dom, lam[la], lam[la ^ 1], lamg[la], lamg[la ^ 1], ut, gphi, gk,
+                                                    acc_step, st);
+                    t -= 1;
+                } else if (c->tblock == 2 && t - 1 >= s0) {
                     e = launch_adjoint_step2(D.dom, lam[la], lam[la ^ 1], ut, ut - rstride, gphi, gk, acc_step2, st);
                     t -= 2;
                 } else {
@@ -1293,7 +1320,7 @@ extern "C" int lbm_tangent(lbm_ctx *c, const float *dphi, const double *dtheta, 
                                  (size_t)d.ny, hipMemcpyDeviceToDevice, st);
     }
     // f(0) from the first checkpoint; the tangent of f(0) is zero
-    if (e == hipSuccess) e = hipMemcpyAsync(D.base + L.off_rf[0], D.base + L.off_ck, L.f_bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(D.base + L.off_rf[0], D.base + L.off_ck, L.f_bytes, hipMemcpyDeviceToDevice, st);   // slot 0
     if (e == hipSuccess) e = launch_fill_zero(tan[0], (size_t)L.p_bytes * 8, st);
     if (e != hipSuccess) return device_fail(c, e, "tangent set-up");
     const float dnu = dtheta ? (float)dtheta[0] : 0.0f, dax = dtheta ? (float)dtheta[1] : 0.0f;

@@ -115,9 +115,12 @@ __device__ __forceinline__ void velocity_adjoint(const Cell &c, float ux, float 
 // medium adjoints. u is the node's velocity at this time step.
 // n7, n8: the node's non-equilibrium stress moments before relaxation (only
 // the adjoint of s_nu uses them).
+// ubx0, uby0: adjoint of u from outside the flow collision (the thermal
+// equilibrium), added before the velocity recovery.
 __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, const Cell &c,
                                                 float pax, float pay, float ux, float uy,
-                                                float n7, float n8, float a[8], ParamBar &pb) {
+                                                float n7, float n8, float a[8], ParamBar &pb,
+                                                float ubx0 = 0.0f, float uby0 = 0.0f) {
     // mbar+ = diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) M b
     const float A1 = b[0] + b[2], B1 = b[1] + b[3], C1 = b[4] + b[6], D1 = b[5] + b[7];
     const float x13 = b[0] - b[2], y24 = b[1] - b[3], p57 = b[4] - b[6], q68 = b[5] - b[7];
@@ -166,8 +169,8 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
     // F = phi a - (cd + cf |u|) u  (Eq. 3)
     const float uFb = ux * Fbx + uy * Fby;
     const float nl = (umag > 0.0f) ? c.cf * uFb * hw_rcp(umag) : 0.0f;
-    ubx += -drag * Fbx - nl * ux;
-    uby += -drag * Fby - nl * uy;
+    ubx += -drag * Fbx - nl * ux + ubx0;
+    uby += -drag * Fby - nl * uy + uby0;
     pb.pax = Fbx;
     pb.pay = Fby;
     pb.cd = -uFb;
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
     // byte offsets go through buffer resources
     const uint32_t pb4 = (uint32_t)(d.plane * 4);
     const BufRes rlin = buf_res(lam_in, 8 * pb4), rlout = buf_res(lam_out, 8 * pb4);
-    const BufRes rut = buf_res(u_t, 4 * pb4), rutm = buf_res(u_tm1, 4 * pb4);
+    const BufRes rut = buf_res(u_t, 5 * pb4), rutm = buf_res(u_tm1, 5 * pb4);
     const BufRes rg = buf_res(gphi, pb4), rgk = buf_res(gkappa, gkappa ? pb4 : 0u);
     const CellPlanes pl = cell_planes(d);
     ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
@@ -541,6 +544,179 @@ hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out
     else
         hipLaunchKernelGGL(k_adjoint_step<false>, grid, dim3(ABLOCK), 0, st, d, lam_in, lam_out, u_t, gphi,
                            gkappa, tiles_x, acc);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ thermal coupling
+
+// Reverse mode of the D2Q5 collision (Eq. B.2 with varpi = 0, deviations from
+// T0/5): given the adjoint bg of g+, the adjoint ag of the pre-collision g
+// (through n = N g, T = T0 + n_0 and n^eq of Eq. B.6) and the adjoint of the
+// flow velocity it uses, added to ubx, uby.
+__device__ __forceinline__ void thermal_collide_adjoint(const float bg[5], const Dom &d, float ux, float uy,
+                                                        float dT, float ag[5], float &ubx, float &uby) {
+    // adjoint of n+: diag(1/5, 1/2, 1/2, 1/20, 1/4) N bg (g+ = N^T diag(...) n+)
+    const float nb0 = 0.2f * ((bg[0] + bg[1]) + (bg[2] + bg[3]) + bg[4]);
+    const float nb1 = 0.5f * (bg[1] - bg[3]);
+    const float nb2 = 0.5f * (bg[2] - bg[4]);
+    const float nb3 = 0.05f * ((bg[1] + bg[2]) + (bg[3] + bg[4]) - 4.0f * bg[0]);
+    const float nb4 = 0.25f * ((bg[1] - bg[2]) + (bg[3] - bg[4]));
+    const float T = d.T0 + dT;
+    // n1+ = n1 - zT (n1 - ux T / sigma), T = T0 + n0; n0+ = n0; n3, n4 relax to 0
+    const float nbar0 = nb0 + d.zT * (ux * nb1 + uy * nb2) * d.inv_sigma;
+    const float nbar1 = (1.0f - d.zT) * nb1, nbar2 = (1.0f - d.zT) * nb2;
+    const float nbar3 = (1.0f - d.z3) * nb3, nbar4 = (1.0f - d.z4) * nb4;
+    ubx += d.zT * T * d.inv_sigma * nb1;
+    uby += d.zT * T * d.inv_sigma * nb2;
+    // ag = N^T nbar
+    ag[0] = nbar0 - 4.0f * nbar3;
+    ag[1] = (nbar0 + nbar1) + (nbar3 + nbar4);
+    ag[2] = (nbar0 + nbar2) + (nbar3 - nbar4);
+    ag[3] = (nbar0 - nbar1) + (nbar3 + nbar4);
+    ag[4] = (nbar0 - nbar2) + (nbar3 - nbar4);
+}
+
+// Transpose of the D2Q5 gather: b_j(x) = a_j(x + e_j), or across a wall the
+// node's own a of the opposite link, negated on the Dirichlet walls
+// (anti-bounce-back g = const - g+) and kept on the adiabatic ones.
+__device__ __forceinline__ void gather_thermal_transposed(const Dom &d, const float *__restrict__ lamg, int x,
+                                                          int y, float b[5]) {
+    const int64_t o = (int64_t)y * d.pitch + x;
+    b[0] = lamg[o];
+#pragma unroll
+    for (int j = 1; j < 5; ++j) {
+        int sx = x + TXv[j], sy = y + TYv[j];
+        int kind = 0;  // 0 stream, 1 bounce-back, 2 anti-bounce-back
+        if (TXv[j] != 0 && (sx < 0 || sx >= d.nx)) {
+            if (d.bc_x == BC_PERIODIC) sx = (sx < 0) ? d.nx - 1 : 0;
+            else kind = 2;
+        }
+        if (TYv[j] != 0 && (sy < 0 || sy >= d.ny)) {
+            if (d.bc_y == BC_PERIODIC) sy = (sy < 0) ? d.ny - 1 : 0;
+            else kind = 1;
+        }
+        if (kind == 0) {
+            b[j] = lamg[j * d.plane + (int64_t)sy * d.pitch + sx];
+        } else {
+            const float v = lamg[TOPP[j] * d.plane + o];
+            b[j] = (kind == 1) ? v : -v;
+        }
+    }
+}
+
+// Seed of the coupled adjoint: a_f(T) and a_g(T) from dL/du(T) (u(T) depends on
+// g(T) through the buoyancy of Sec. 3.4), and the direct medium gradient.
+template <int SRC_T, bool THETA>
+__global__ __launch_bounds__(ABLOCK) void k_adjoint_seed_thermal(Dom d, const float *__restrict__ dLdu,
+                                                                 float *__restrict__ lam, float *__restrict__ lamg,
+                                                                 float *__restrict__ gphi,
+                                                                 float *__restrict__ gkappa,
+                                                                 double *__restrict__ acc) {
+    const int x = blockIdx.x * ABLOCK + threadIdx.x, y = blockIdx.y;
+    ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
+    if (x < d.nx) {
+        float f[8], g[5];
+        if (SRC_T == SRC_DIRECT) {
+            load_own<float>(d, (const float *)d.fin, x, y, f);
+            load_own_thermal(d, d.gin, x, y, g);
+        } else {
+            gather_general<float>(d, (const float *)d.fin, x, y, f);
+            gather_thermal(d, d.gin, x, y, false, g);
+        }
+        const float dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+        const int64_t o = (int64_t)y * d.pitch + x;
+        const Cell c = load_cell(d, o);
+        const float ay = d.ay + d.gbeta * dT;
+        float ux, uy, m1;
+        node_velocity(f, c, c.phi * d.ax, c.phi * ay, ux, uy, m1);
+        const int64_t q = (int64_t)y * d.nx + x, n = (int64_t)d.nx * d.ny;
+        ParamBar pb{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        float vbx, vby;
+        velocity_adjoint(c, ux, uy, dLdu[q], dLdu[n + q], vbx, vby, pb);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lam[i * d.plane + o] = (float)EX[i] * vbx + (float)EY[i] * vby;
+        const float Tb = c.phi * d.gbeta * pb.pay;   // pay = phi (a_y + g beta dT)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) lamg[j * d.plane + o] = Tb;
+        float gp, gk;
+        medium_gradient(d, c, kappa_at(d, o), pb, d.ax, ay, gp, gk);
+        gphi[o] = gp;
+        if (gkappa) gkappa[o] = gk;
+        if (THETA) theta_add(d, c, pb, ts);
+    }
+    if (THETA) block_theta_add<ABLOCK>(ts, acc + 4 * ((int64_t)blockIdx.y * gridDim.x + blockIdx.x));
+}
+
+// One backward step of the coupled D2Q8 + D2Q5 scheme at time t: a(t) from
+// a(t+1) for both distributions, using u(t) and dT(t) recorded in planes 0, 1
+// and 4 of u_t (n7, n8 in planes 2, 3 with THETA).
+template <bool THETA>
+__global__ __launch_bounds__(ABLOCK) void k_adjoint_step_thermal(Dom d, const float *__restrict__ lam_in,
+                                                                 float *__restrict__ lam_out,
+                                                                 const float *__restrict__ lamg_in,
+                                                                 float *__restrict__ lamg_out,
+                                                                 const float *__restrict__ u_t,
+                                                                 float *__restrict__ gphi,
+                                                                 float *__restrict__ gkappa,
+                                                                 int tiles_x, double *__restrict__ acc) {
+    const int tx = blockIdx.x % tiles_x, y = blockIdx.x / tiles_x;
+    const int x = tx * ABLOCK + threadIdx.x;
+    ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
+    if (x < d.nx) {
+        const int64_t o = (int64_t)y * d.pitch + x;
+        float b[8], bg[5];
+        gather_transposed(d, lam_in, x, y, false, b);
+        gather_thermal_transposed(d, lamg_in, x, y, bg);
+        const Cell c = load_cell(d, o);
+        const float ux = u_t[o], uy = u_t[d.plane + o], dT = u_t[4 * d.plane + o];
+        const float n7 = THETA ? u_t[2 * d.plane + o] : 0.0f, n8 = THETA ? u_t[3 * d.plane + o] : 0.0f;
+        float ag[5], ubx = 0.0f, uby = 0.0f;
+        thermal_collide_adjoint(bg, d, ux, uy, dT, ag, ubx, uby);
+        const float ay = d.ay + d.gbeta * dT;
+        float a[8];
+        ParamBar pb;
+        collide_adjoint(b, d, c, c.phi * d.ax, c.phi * ay, ux, uy, n7, n8, a, pb, ubx, uby);
+        const float Tb = c.phi * d.gbeta * pb.pay;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lam_out[i * d.plane + o] = a[i];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) lamg_out[j * d.plane + o] = ag[j] + Tb;
+        float gp, gk;
+        medium_gradient(d, c, kappa_at(d, o), pb, d.ax, ay, gp, gk);
+        gphi[o] += gp;
+        if (gkappa) gkappa[o] += gk;
+        if (THETA) {
+            theta_add(d, c, pb, ts);
+            if (y == d.ny - 1) ts.lid += lid_share(d, y, lam_in[6 * d.plane + o], lam_in[7 * d.plane + o]);
+        }
+    }
+    if (THETA) block_theta_add<ABLOCK>(ts, acc + 4 * (int64_t)blockIdx.x);
+}
+
+hipError_t launch_adjoint_seed_thermal(const Dom &d, Source src, const float *dLdu, float *lam, float *lamg,
+                                       float *gphi, float *gkappa, double *acc, hipStream_t st) {
+    const dim3 grid((unsigned)((d.nx + ABLOCK - 1) / ABLOCK), (unsigned)d.ny);
+    if (src == SRC_DIRECT) {
+        if (acc) hipLaunchKernelGGL((k_adjoint_seed_thermal<SRC_DIRECT, true>), grid, dim3(ABLOCK), 0, st, d, dLdu, lam, lamg, gphi, gkappa, acc);
+        else hipLaunchKernelGGL((k_adjoint_seed_thermal<SRC_DIRECT, false>), grid, dim3(ABLOCK), 0, st, d, dLdu, lam, lamg, gphi, gkappa, acc);
+    } else {
+        if (acc) hipLaunchKernelGGL((k_adjoint_seed_thermal<SRC_GATHER, true>), grid, dim3(ABLOCK), 0, st, d, dLdu, lam, lamg, gphi, gkappa, acc);
+        else hipLaunchKernelGGL((k_adjoint_seed_thermal<SRC_GATHER, false>), grid, dim3(ABLOCK), 0, st, d, dLdu, lam, lamg, gphi, gkappa, acc);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step_thermal(const Dom &d, const float *lam_in, float *lam_out, const float *lamg_in,
+                                       float *lamg_out, const float *u_t, float *gphi, float *gkappa, double *acc,
+                                       hipStream_t st) {
+    const int tiles_x = (d.nx + ABLOCK - 1) / ABLOCK;
+    const dim3 grid((unsigned)(tiles_x * d.ny));
+    if (acc)
+        hipLaunchKernelGGL(k_adjoint_step_thermal<true>, grid, dim3(ABLOCK), 0, st, d, lam_in, lam_out, lamg_in,
+                           lamg_out, u_t, gphi, gkappa, tiles_x, acc);
+    else
+        hipLaunchKernelGGL(k_adjoint_step_thermal<false>, grid, dim3(ABLOCK), 0, st, d, lam_in, lam_out, lamg_in,
+                           lamg_out, u_t, gphi, gkappa, tiles_x, acc);
     return hipGetLastError();
 }
 

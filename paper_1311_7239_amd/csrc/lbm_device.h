@@ -63,7 +63,8 @@ struct Dom {
     void *fout;
     const float *gin;
     float *gout;
-    float *urec;                     // optional u(t) record: 2 planes (4 with rec_stress)
+    float *urec;                     // optional record of step t: planes u_x, u_y, then
+                                     // n7, n8 (with rec_stress) and dT (thermal)
     int32_t rec_stress;              // also record m7 - m7^eq and m8 - m8^eq (planes 2, 3)
     float inv_nu;                    // 1 / nu (parameter gradients)
 };

@@ -25,10 +25,11 @@ constexpr int BLOCK = 256;
 // paths below: collide, then return u.
 template <bool THERMAL>
 __device__ __forceinline__ void node_update(const Dom &d, const Cell &c, float f[8], float g[5],
-                                            float &ux, float &uy, float &n7, float &n8) {
+                                            float &ux, float &uy, float &n7, float &n8, float &dT) {
     float ay = d.ay;
+    dT = 0.0f;
     if (THERMAL) {
-        const float dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+        dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
         ay = d.ay + d.gbeta * dT;
     }
     collide(f, d, c, c.phi * d.ax, c.phi * ay, ux, uy, n7, n8);
@@ -74,7 +75,7 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) {
             const int64_t o = (int64_t)(y0 + ly + r * TH) * d.pitch + xb;
-            float ux[NX], uy[NX], n7[NX], n8[NX];
+            float ux[NX], uy[NX], n7[NX], n8[NX], dT[NX];
 #pragma unroll
             for (int k = 0; k < NX; ++k) {
                 float fn[8], gn[5];
@@ -86,7 +87,7 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
                 }
                 Cell c = cell_from(d, ph[r][k], kp[r][k]);
                 cell_viscosity(d, c, o + k);
-                node_update<THERMAL>(d, c, fn, gn, ux[k], uy[k], n7[k], n8[k]);
+                node_update<THERMAL>(d, c, fn, gn, ux[k], uy[k], n7[k], n8[k], dT[k]);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) f[r][i][k] = fn[i];
                 if (THERMAL) {
@@ -107,6 +108,7 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
                     store_row<float, NX>(d.urec + 2 * d.plane + o, n7);
                     store_row<float, NX>(d.urec + 3 * d.plane + o, n8);
                 }
+                if (THERMAL) store_row<float, NX>(d.urec + 4 * d.plane + o, dT);
             }
         }
         return;
@@ -132,8 +134,8 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
             }
             const int64_t o = (int64_t)y * d.pitch + x;
             const Cell c = load_cell(d, o);
-            float ux, uy, n7, n8;
-            node_update<THERMAL>(d, c, fn, gn, ux, uy, n7, n8);
+            float ux, uy, n7, n8, dT;
+            node_update<THERMAL>(d, c, fn, gn, ux, uy, n7, n8, dT);
 #pragma unroll
             for (int i = 0; i < 8; ++i) Store<S>::st(fout + i * d.plane + o, fn[i]);
             if (THERMAL) {
@@ -147,6 +149,7 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
                     d.urec[2 * d.plane + o] = n7;
                     d.urec[3 * d.plane + o] = n8;
                 }
+                if (THERMAL) d.urec[4 * d.plane + o] = dT;
             }
         }
     }
@@ -217,10 +220,11 @@ hipError_t launch_step(const Dom &d, int storage, Source src, bool rec, const Sc
     // the collide-only first cycle always runs with the plain schedule
     static const Schedule flat{256, 1, 1, 0};
     const bool th = d.thermal != 0;
-    if (rec && (storage != ST_F32 || th)) return hipErrorInvalidValue;
+    if (rec && storage != ST_F32) return hipErrorInvalidValue;
     if (src == SRC_DIRECT) {
         if (storage == ST_F32) {
-            if (th) return launch_step_t<float, true, SRC_DIRECT, false>(d, flat, st);
+            if (th) return rec ? launch_step_t<float, true, SRC_DIRECT, true>(d, flat, st)
+                               : launch_step_t<float, true, SRC_DIRECT, false>(d, flat, st);
             return rec ? launch_step_t<float, false, SRC_DIRECT, true>(d, flat, st)
                        : launch_step_t<float, false, SRC_DIRECT, false>(d, flat, st);
         }
@@ -228,7 +232,8 @@ hipError_t launch_step(const Dom &d, int storage, Source src, bool rec, const Sc
         return launch_step_t<_Float16, false, SRC_DIRECT, false>(d, flat, st);
     }
     if (storage == ST_F32) {
-        if (th) return launch_step_t<float, true, SRC_GATHER, false>(d, s, st);
+        if (th) return rec ? launch_step_t<float, true, SRC_GATHER, true>(d, s, st)
+                           : launch_step_t<float, true, SRC_GATHER, false>(d, s, st);
         return rec ? launch_step_t<float, false, SRC_GATHER, true>(d, s, st)
                    : launch_step_t<float, false, SRC_GATHER, false>(d, s, st);
     }

@@ -89,6 +89,13 @@ hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out
 // u(t) and u(t-1).
 hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
                                 const float *u_tm1, float *gphi, float *gkappa, double *acc, hipStream_t st);
+// The coupled D2Q8 + D2Q5 adjoint (one step per pass): lamg holds the
+// adjoint of the thermal populations (5 planes); u_t carries dT in plane 4.
+hipError_t launch_adjoint_seed_thermal(const Dom &d, Source src, const float *dLdu, float *lam, float *lamg,
+                                       float *gphi, float *gkappa, double *acc, hipStream_t st);
+hipError_t launch_adjoint_step_thermal(const Dom &d, const float *lam_in, float *lam_out, const float *lamg_in,
+                                       float *lamg_out, const float *u_t, float *gphi, float *gkappa, double *acc,
+                                       hipStream_t st);
 // Slots of 4 doubles the three adjoint kernels use for a domain (seed, step,
 // two-step regions, in that order) and the first slot of each region.
 int64_t adjoint_theta_slots(int nx, int ny);

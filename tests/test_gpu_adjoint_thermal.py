@@ -1,0 +1,96 @@
+"""Adjoint of the coupled D2Q8 + D2Q5 scheme (natural convection, Sec. 3.4 and
+App. B): dL/dphi and the parameter gradients against central differences of
+the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1311_7239_amd import inputs as I
+from paper_1311_7239_amd import lbm
+from tests.oracle_cases import oracle_setup
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 300
+
+
+def _case():
+    """48^2 porous convection cell over an Ergun GRF medium, buoyancy strong enough
+    that the temperature field steers the flow within a few hundred steps."""
+    c = I.natural_convection(n=48, phi=0.6, Da=1e-2, Ra=1e5)
+    G = I.grf(48, 48, 6.0, 77)
+    c.phi = np.clip(0.6 + 0.1 * G, 0.3, 0.9).astype(np.float32)
+    c.dp = I.ergun_dp(c.K0, 0.6)
+    c.Fphi = None
+    c.gbeta *= 50.0
+    c.ay = 1e-7
+    return c
+
+
+def _conduction(c):
+    x = np.arange(c.nx) + 0.5
+    return np.tile(c.Th + (c.Tc - c.Th) * x / c.nx, (c.ny, 1))
+
+
+def _oracle_loss(c, phi, col, **over):
+    for k, v in over.items():
+        setattr(c, k, v)
+    p, _, K, F = oracle_setup(c, nthreads=8)
+    phi = np.asarray(phi, dtype=np.float64)
+    K, F = oracle.ergun(phi, c.dp)
+    f = oracle.rest_state(p, c.Pi0)
+    g = oracle.thermal_rest_state(p, _conduction(c))
+    oracle.run(p, phi, K, F, f, g, nsteps=STEPS)
+    ux, uy, _, _ = oracle.macroscopic(p, phi, K, F, f, g)
+    return 0.5 * float(np.sum(ux[:, col] ** 2 + uy[:, col] ** 2))
+
+
+def _gpu(c, col):
+    s = lbm.solver_for_case(c, ckpt_every=64, max_steps_recorded=STEPS)
+    T = _conduction(c)
+    dg = np.broadcast_to(((T - c.T0) / 5.0)[None], (5, c.ny, c.nx)).astype(np.float32).copy()
+    s.set_populations(torch.zeros((8, c.ny, c.nx), device="cuda"), torch.from_numpy(dg).cuda())
+    s.step(STEPS)
+    _, u, _ = s.macroscopic()
+    dLdu = torch.zeros_like(u)
+    dLdu[:, :, col] = u[:, :, col]
+    g, _ = s.backward(dLdu)
+    g2, _, th = s.backward_params(dLdu)
+    torch.cuda.synchronize()
+    assert torch.equal(g, g2)
+    return g.cpu().numpy().astype(np.float64), th
+
+
+def test_thermal_adjoint_matches_oracle_differences():
+    c = _case()
+    col = c.nx // 2
+    g, th = _gpu(c, col)
+    phi0 = c.phi.astype(np.float64)
+    order = np.argsort(-np.abs(g).ravel())
+    worst = 0.0
+    for idx in [int(i) for i in order[:8]]:
+        j, i = divmod(idx, c.nx)
+        h = 1e-4 * phi0[j, i]
+        pp = phi0.copy(); pp[j, i] += h
+        pm = phi0.copy(); pm[j, i] -= h
+        fd = (_oracle_loss(_case(), pp, col) - _oracle_loss(_case(), pm, col)) / (2 * h)
+        worst = max(worst, abs(g[j, i] - fd) / abs(fd))
+    print(f"thermal adjoint, 8 largest cells: worst relative error {worst:.2e}")
+    assert worst < 1e-4
+    # random direction over the whole field
+    rng = np.random.default_rng(9)
+    d = 0.05 * phi0 * rng.uniform(-1.0, 1.0, phi0.shape)
+    hd = 1e-3
+    fd = (_oracle_loss(_case(), phi0 + hd * d, col) - _oracle_loss(_case(), phi0 - hd * d, col)) / (2 * hd)
+    ad = float(np.sum(g * d))
+    print(f"thermal adjoint, random direction: {ad:.8e} vs oracle {fd:.8e}")
+    assert abs(ad - fd) <= 1e-4 * abs(fd)
+    # parameters (a_y acts together with the buoyancy; nu through drag and s_nu)
+    for name in ("nu", "ay"):
+        base = getattr(c, name)
+        hh = 1e-4 * abs(base)
+        fd = (_oracle_loss(_case(), phi0, col, **{name: base + hh}) -
+              _oracle_loss(_case(), phi0, col, **{name: base - hh})) / (2 * hh)
+        print(f"thermal dL/d{name}: adjoint {th[name]:.6e}  FD {fd:.6e}")
+        assert abs(th[name] - fd) <= 1e-4 * abs(fd), name
