@@ -106,6 +106,11 @@ def extras(args):
     out["one_cycle_per_pass_f32"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4),
                                      "bytes_per_node": 68, "kernel": "k_step<float, 128x1x2>",
                                      "roofline": roofline(case.nodes, 68, ms)}
+    s.set_time_blocking(2)
+    ms = timed(s, args.steps, args.warmup)
+    out["two_cycles_per_pass_f32"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+                                      "bytes_per_node_per_launch": 68, "kernel": "k_step2<float, 64, 16>",
+                                      "roofline": roofline(case.nodes, 68, 2 * ms)}
     del s
     torch.cuda.empty_cache()
     # FP16-deviation storage on the headline workload (two cycles per pass by default)
@@ -218,17 +223,21 @@ def main():
     n = args.n
     log(f"bench: generating the {n}x{n} log-normal porosity field")
     case = I.lognormal_channel(n=n, seed=5, K_ref=1e-6 * 2048.0 ** 2)
-    solver = lbm.solver_for_case(case, storage=lbm.FP32_DEV)   # two cycles per HBM pass (default)
-    log(f"bench: stepping ({args.warmup} warmup + {args.steps} timed)")
+    solver = lbm.solver_for_case(case, storage=lbm.FP32_DEV)   # the default cycles per HBM pass
+    cycles = solver.time_blocking()["cycles_per_pass"]
+    log(f"bench: stepping ({args.warmup} warmup + {args.steps} timed, {cycles} cycles per pass)")
     ms = timed(solver, args.steps, args.warmup)
     mlups = case.nodes / (ms * 1e-3) / 1e6
     bytes_per_node = 68  # per pass: 8 FP32 loads + 8 FP32 stores + the FP32 porosity load
-    launch_ms = 2.0 * ms  # one launch advances two cycles
+    launch_ms = cycles * ms  # one launch advances `cycles` cycles
     rl = roofline(case.nodes, bytes_per_node, launch_ms)
-    traffic = profiling.traffic_bytes(COUNTERS) if n == 8192 else None
+    kname = {3: ("void mrt::k_step3<float", "k_step3<float, 64, 16>: three collide-stream cycles per launch"),
+             2: ("void mrt::k_step2<float", "k_step2<float, 64, 16>: two collide-stream cycles per launch"),
+             1: ("void mrt::k_step<float, false, 0", "k_step<float>: one collide-stream cycle per launch")}[cycles]
+    traffic = profiling.traffic_bytes(COUNTERS, kname[0]) if n == 8192 else None
     rl["traffic"] = None if traffic is None else round(traffic / 1e9, 4)
     rl["traffic_unit"] = "GB per launch"
-    rl["kernel"] = "k_step2<float, 64, 16>: two collide-stream cycles per launch"
+    rl["kernel"] = kname[1]
     rl["algorithmic_bytes_per_launch"] = case.nodes * bytes_per_node
     rl["one_cycle_equivalent_gbs"] = round(case.nodes * bytes_per_node / (ms * 1e-3) / 1e9, 1)
     mass, res, _ = solver.reduce()
@@ -248,7 +257,7 @@ def main():
         "config": {"time_blocking": solver.time_blocking(),
                    "workload": f"log-normal porous channel {n}x{n}: x periodic, walls in y, per-cell "
                                "porosity (log-normal, sigma 0.5, correlation 64, seed 5) with Ergun K and "
-                               "F_phi, tau 0.8, FP32 deviation storage, forward steps, two cycles per "
+                               f"F_phi, tau 0.8, FP32 deviation storage, forward steps, {cycles} cycles per "
                                "HBM pass",
                    "nodes": case.nodes, "schedule": list(solver.schedule())},
         "roofline": rl,

@@ -267,17 +267,21 @@ int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows,
  * autotuned). */
 int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int32_t swizzle);
 
-/* Cycles per HBM pass of a single-domain isothermal context: 1, or 2
- * (temporal blocking: one launch gathers, collides on its tile plus a
+/* Cycles per HBM pass of an isothermal context with bounce-back walls: 1,
+ * 2 (temporal blocking: one launch gathers, collides on its tile plus a
  * one-node ring kept in LDS, then collides again, so each population crosses
- * HBM about once per two cycles). Results are bitwise identical either way.
- * Two-cycle passes are skipped for t = 0, while recording for lbm_backward,
- * and for the last cycle of each lbm_step call (so lbm_reduce's residual
- * always compares u(t) with u(t-1)). The recomputation inside lbm_backward
- * also uses two-cycle passes (recording u at both cycles). Default: 2 for
- * isothermal single domains of at least 2^21 nodes, 1 otherwise; for
- * batches, the autotuner's choice. ENOTSUP for thermal domains, EINVAL for
- * another value. */
+ * HBM about once per two cycles) or 3 (a two-node ring, three collisions per
+ * launch; single domains only). Results are bitwise identical in every mode.
+ * Multi-cycle passes are skipped for t = 0, while recording for
+ * lbm_backward, and for the last cycle of each lbm_step call (so
+ * lbm_reduce's residual always compares u(t) with u(t-1)); a call finishes
+ * with shorter passes where fewer cycles remain. The recomputation inside
+ * lbm_backward uses passes of the same length (recording u at every cycle)
+ * and its adjoint sweep two steps per pass in modes 2 and 3. Default for
+ * single domains of at least 2^20 nodes that allow it: 3 (FP32) or 2 (FP16),
+ * else 1; for batches, the autotuner's choice. ENOTSUP for thermal domains, on-node
+ * walls, population buffers of 4 GiB or more, and mode 3 on batches; EINVAL
+ * for another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
 
 /* Current cycles per pass and the two-cycle kernel's workgroup size, tile
@@ -291,7 +295,8 @@ int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threa
 int lbm_set_two_cycle_tile(lbm_ctx *c, int32_t threads, int32_t rows);
 
 /* Number of steps lbm_step replays from one hand-built HIP graph of kernel
- * nodes (an even number up to 4096; 0 launches every step separately).
+ * nodes (up to 4096, rounded down to a whole number of passes; 0 launches
+ * every step separately).
  * Defaults: 0 for single domains, 32 for batches. Graphs are not used while
  * a trajectory is recorded for lbm_backward. Results do not depend on it. */
 int lbm_set_graph_steps(lbm_ctx *c, int32_t steps);

@@ -360,7 +360,12 @@ hipError_t checkpoint(lbm_ctx *c) {
 namespace {
 
 // cycles advanced by one kernel node of the step graph
-int graph_node_steps(const lbm_ctx *c) { return c->tblock == 2 ? 2 : 1; }
+int graph_node_steps(const lbm_ctx *c) { return c->tblock; }
+
+// cycles one graph replay advances (a whole number of kernel nodes)
+int64_t graph_cycles(const lbm_ctx *c) {
+    return (int64_t)(c->graph_steps / graph_node_steps(c)) * graph_node_steps(c);
+}
 
 void reset_graphs(lbm_ctx *c) {
     for (auto &g : c->gexec) {
@@ -389,6 +394,7 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         void *args_s[3] = {&d, &tx, &swz};
         float *no_rec = nullptr;
         void *args_s2[4] = {&d, &tx, &swz, &no_rec};
+        void *args_s3[5] = {&d, &tx, &swz, &no_rec, &no_rec};
         void *args_b2[4] = {&c->d_doms, &c->d_tiles2, &c->ntiles2, &p};
         if (c->batch && c->tblock == 2) {
             kp.func = (void *)step2_batch_kernel_fn(c->storage, c->tb_threads, c->tb_rows);
@@ -399,6 +405,14 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
             kp.func = (void *)batch_kernel_fn(c->storage, c->batch_thermal, c->sched);
             kp.gridDim = dim3((unsigned)c->grid);
             kp.kernelParams = args_b;
+        } else if (c->tblock == 3) {
+            Domain &D = c->dom[0];
+            d = dom_for(D, p);
+            step3_tiles(D.desc.nx, D.desc.ny, &tx, &ty);
+            kp.func = (void *)step3_kernel_fn(D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, false);
+            kp.gridDim = dim3((unsigned)(tx * ty));
+            kp.blockDim = dim3(512);
+            kp.kernelParams = args_s3;
         } else if (c->tblock == 2) {
             Domain &D = c->dom[0];
             d = dom_for(D, p);
@@ -494,9 +508,13 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     if (rc) { delete c; return rc; }
     D.L = L;
     c->rec_cap = cap;
-    // two cycles per pass pays once the domain fills the GPU several times over
-    // (the two-cycle kernels implement bounce-back walls only)
-    c->tblock = (two_cycle_possible(c) && (int64_t)d->nx * d->ny >= ((int64_t)1 << 21)) ? 2 : 1;
+    // several cycles per pass pay once the domain fills the GPU a few times over
+    // (measured from 1024^2 up; the multi-cycle kernels implement bounce-back
+    // walls only); FP32 takes three, FP16 two (its third cycle is compute-bound)
+    if (two_cycle_possible(c) && (int64_t)d->nx * d->ny >= ((int64_t)1 << 20))
+        c->tblock = d->storage == LBM_FP16_DEV ? 2 : 3;
+    else
+        c->tblock = 1;
     if (d->storage == LBM_FP16_DEV) c->sched = Schedule{64, 2, 2, 1};
     hipError_t e = init_domain(D, 0, phi, kappa, c->stream);
     if (e != hipSuccess) {
@@ -537,8 +555,9 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         const bool recording = c->rec_valid && c->dom[0].desc.ckpt_every > 0;
         // two cycles per pass while at least one single cycle remains for the end of
         // this call (so the previous buffer always holds f+(t-2) -> u(t-1) for the residual)
-        const bool fused = c->tblock == 2 && !recording && !c->dom[0].desc.thermal.enabled;
-        if (c->graph_steps > 0 && !recording && n - (fused ? 1 : 0) >= c->graph_steps) {
+        const bool fused = c->tblock >= 2 && !recording && !c->dom[0].desc.thermal.enabled;
+        const int64_t gcyc = graph_cycles(c);
+        if (gcyc > 0 && !recording && n - (fused ? 1 : 0) >= gcyc) {
             if (!c->gexec[c->cur]) {
                 if ((e = build_graph(c, c->cur)) != hipSuccess) return device_fail(c, e, "graph build");
             }
@@ -546,8 +565,18 @@ int lbm_step(lbm_ctx *c, int64_t n) {
                 return device_fail(c, e, "graph launch");
             const int nodes = c->graph_steps / graph_node_steps(c);
             c->cur ^= (nodes & 1);
-            c->t += c->graph_steps;
-            n -= c->graph_steps;
+            c->t += gcyc;
+            n -= gcyc;
+            continue;
+        }
+        if (fused && c->tblock == 3 && !c->batch && n >= 4) {
+            Domain &D = c->dom[0];
+            e = launch_step3(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
+                             c->sched.swizzle, nullptr, nullptr, c->stream);
+            if (e != hipSuccess) return device_fail(c, e, "step launch");
+            c->cur ^= 1;
+            c->t += 3;
+            n -= 3;
             continue;
         }
         if (fused && n >= 3) {
@@ -814,12 +843,13 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (cycles_per_pass != 1 && cycles_per_pass != 2) return fail(LBM_EINVAL, "cycles per pass must be 1 or 2");
-    if (cycles_per_pass == 2 && c->dom[0].desc.thermal.enabled)
+    if (cycles_per_pass < 1 || cycles_per_pass > 3) return fail(LBM_EINVAL, "cycles per pass must be 1, 2 or 3");
+    if (cycles_per_pass == 3 && c->batch) return fail(LBM_ENOTSUP, "batches advance one or two cycles per pass");
+    if (cycles_per_pass >= 2 && c->dom[0].desc.thermal.enabled)
         return fail(LBM_ENOTSUP, "thermal domains advance one cycle per pass");
-    if (cycles_per_pass == 2 && any_on_node_walls(c))
+    if (cycles_per_pass >= 2 && any_on_node_walls(c))
         return fail(LBM_ENOTSUP, "on-node (extrapolated) walls advance one cycle per pass");
-    if (cycles_per_pass == 2 && !two_cycle_possible(c))
+    if (cycles_per_pass >= 2 && !two_cycle_possible(c))
         return fail(LBM_ENOTSUP, "a population buffer of 4 GiB or more advances one cycle per pass");
     c->tblock = cycles_per_pass;
     reset_graphs(c);
@@ -867,8 +897,7 @@ int lbm_set_viscosity_ratio(lbm_ctx *c, int32_t k, const float *J) {
 int lbm_set_graph_steps(lbm_ctx *c, int32_t steps) {
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (steps < 0 || (steps & 1) || steps > 4096)
-        return fail(LBM_EINVAL, "graph steps must be an even number in [0, 4096]");
+    if (steps < 0 || steps > 4096) return fail(LBM_EINVAL, "graph steps must lie in [0, 4096]");
     c->graph_steps = steps;
     reset_graphs(c);
     return LBM_OK;
@@ -1248,7 +1277,11 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
                     dr.gin = (const float *)(D.base + L.off_rg[p]);
                     dr.gout = (float *)(D.base + L.off_rg[p ^ 1]);
                 }
-                if (c->tblock == 2 && t > 0 && t + 1 < s1) {
+                if (c->tblock == 3 && t > 0 && t + 2 < s1) {
+                    // three cycles in one pass, recording at t, t + 1 and t + 2
+                    e = launch_step3(dr, ST_F32, c->sched.swizzle, dr.urec + rstride, dr.urec + 2 * rstride, st);
+                    t += 3;
+                } else if (c->tblock >= 2 && t > 0 && t + 1 < s1) {
                     // two cycles in one pass, recording at t and t + 1
                     e = launch_step2(dr, ST_F32, c->sched.swizzle, c->tb_threads, c->tb_rows, dr.urec + rstride, st);
                     t += 2;
@@ -1266,7 +1299,7 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
                     e = launch_adjoint_step_thermal(D.dom, lam[la], lam[la ^ 1], lamg[la], lamg[la ^ 1], ut, gphi, gk,
                                                     acc_step, st);
                     t -= 1;
-                } else if (c->tblock == 2 && t - 1 >= s0) {
+                } else if (c->tblock >= 2 && t - 1 >= s0) {
                     e = launch_adjoint_step2(D.dom, lam[la], lam[la ^ 1], ut, ut - rstride, gphi, gk, acc_step2, st);
                     t -= 2;
                 } else {

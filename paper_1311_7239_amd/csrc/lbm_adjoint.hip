@@ -94,20 +94,21 @@ __device__ __forceinline__ void apply_MT(const float y[8], float f[8]) {
 __device__ __forceinline__ void velocity_adjoint(const Cell &c, float ux, float uy, float ubx,
                                                  float uby, float &vbx, float &vby,
                                                  ParamBar &pb) {
-    const float umag = hw_sqrt(ux * ux + uy * uy);
-    const float l0 = 0.5f * (1.0f + 0.5f * c.cd);
+    const float umag = hw_sqrt(fmaf(ux, ux, uy * uy));
+    const float l0 = fmaf(0.25f, c.cd, 0.5f);
     const float l1 = 0.5f * c.cf;
-    const float R = l0 + l1 * umag;   // sqrt(l0^2 + l1|v|) on the solution
-    const float D = l0 + R;           // = 2 l0 + l1 |u|
-    const float uub = ux * ubx + uy * uby;
+    const float R = fmaf(l1, umag, l0);   // sqrt(l0^2 + l1|v|) on the solution
+    const float D = l0 + R;               // = 2 l0 + l1 |u|
+    const float uub = fmaf(ux, ubx, uy * uby);
     const float rR = hw_rcp(R), rD = hw_rcp(D);
     const float corr = (umag > 0.0f) ? (0.5f * l1 * rR) * uub * hw_rcp(umag) : 0.0f;
-    vbx = (ubx - corr * ux) * rD;
-    vby = (uby - corr * uy) * rD;
-    pb.cd += 0.25f * (-uub * rR);
-    pb.cf += 0.5f * (-0.5f * uub * umag * rR);
-    pb.pax += 0.5f * vbx;
-    pb.pay += 0.5f * vby;
+    vbx = fmaf(-corr, ux, ubx) * rD;
+    vby = fmaf(-corr, uy, uby) * rD;
+    const float w = -0.25f * uub * rR;
+    pb.cd += w;
+    pb.cf += w * umag;
+    pb.pax = fmaf(0.5f, vbx, pb.pax);
+    pb.pay = fmaf(0.5f, vby, pb.pay);
 }
 
 // Reverse mode of one node's collision (Eq. 14 and f+ = M^-1 m+): given the
@@ -142,35 +143,34 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
     const float u2 = fmaf(ux, ux, uy * uy), uF = fmaf(ux, Fx, uy * Fy);
 
     float mb[8];
-    mb[0] = P1 - 0.6f * d.s_e * P2;
+    mb[0] = fmaf(-0.6f * d.s_e, P2, P1);
     mb[1] = (1.0f - d.s_e) * P2;
     mb[3] = (1.0f - d.s_q) * P4;
     mb[5] = (1.0f - d.s_q) * P6;
     mb[6] = (1.0f - c.s_nu) * P7;
     mb[7] = (1.0f - c.s_nu) * P8;
 
-    // u and F enter m2+, m3+..m8+ directly
-    float ubx = (0.8f * d.s_e * ux + 0.8f * d.h_e * Fx) * ip * P2 + P3 - d.s_q * P4 +
-                (2.0f * c.s_nu * ux + 2.0f * c.h_nu * Fx) * ip * P7 +
-                (c.s_nu * uy + c.h_nu * Fy) * ip * P8;
-    float uby = (0.8f * d.s_e * uy + 0.8f * d.h_e * Fy) * ip * P2 + P5 - d.s_q * P6 -
-                (2.0f * c.s_nu * uy + 2.0f * c.h_nu * Fy) * ip * P7 +
-                (c.s_nu * ux + c.h_nu * Fx) * ip * P8;
-    const float Fbx = 0.8f * d.h_e * ux * ip * P2 + 0.5f * P3 - d.h_q * P4 +
-                      2.0f * c.h_nu * ux * ip * P7 + c.h_nu * uy * ip * P8;
-    const float Fby = 0.8f * d.h_e * uy * ip * P2 + 0.5f * P5 - d.h_q * P6 -
-                      2.0f * c.h_nu * uy * ip * P7 + c.h_nu * ux * ip * P8;
+    // u and F enter m2+, m3+..m8+ directly (Eqs. 11-12, 16)
+    const float se8 = 0.8f * d.s_e, he8 = 0.8f * d.h_e, s = c.s_nu, h = c.h_nu;
+    const float Q2 = P2 * ip, Q7 = P7 * ip, Q8 = P8 * ip;
+    float ubx = fmaf(Q2, fmaf(se8, ux, he8 * Fx),
+                     fmaf(Q7, fmaf(2.0f * s, ux, 2.0f * h * Fx), fmaf(Q8, fmaf(s, uy, h * Fy), fmaf(-d.s_q, P4, P3))));
+    float uby = fmaf(Q2, fmaf(se8, uy, he8 * Fy),
+                     fmaf(-Q7, fmaf(2.0f * s, uy, 2.0f * h * Fy), fmaf(Q8, fmaf(s, ux, h * Fx), fmaf(-d.s_q, P6, P5))));
+    const float hQ8 = h * Q8;
+    const float Fbx = fmaf(ux, fmaf(he8, Q2, 2.0f * h * Q7), fmaf(hQ8, uy, fmaf(0.5f, P3, -d.h_q * P4)));
+    const float Fby = fmaf(uy, fmaf(he8, Q2, -2.0f * h * Q7), fmaf(hQ8, ux, fmaf(0.5f, P5, -d.h_q * P6)));
+    const float sxx = fmaf(ux, Fx, -(uy * Fy)), sxy = fmaf(ux, Fy, uy * Fx);
     // m7+ = m7 - s (m7 - m7^eq) + (1 - s/2) S7 (and m8+ alike): d/ds = -n7 - S7/2
-    pb.s = P7 * (-n7 - (ux * Fx - uy * Fy) * ip) + P8 * (-n8 - 0.5f * (ux * Fy + uy * Fx) * ip);
-    pb.ip = (0.4f * d.s_e * u2 + 0.8f * d.h_e * uF) * P2 +
-            (c.s_nu * (ux * ux - uy * uy) + 2.0f * c.h_nu * (ux * Fx - uy * Fy)) * P7 +
-            (c.s_nu * ux * uy + c.h_nu * (ux * Fy + uy * Fx)) * P8;
+    pb.s = fmaf(P7, -n7 - sxx * ip, P8 * (-n8 - 0.5f * sxy * ip));
+    pb.ip = fmaf(fmaf(0.4f * d.s_e, u2, he8 * uF), P2,
+                 fmaf(fmaf(s, fmaf(ux, ux, -(uy * uy)), 2.0f * h * sxx), P7, fmaf(s, ux * uy, h * sxy) * P8));
 
     // F = phi a - (cd + cf |u|) u  (Eq. 3)
-    const float uFb = ux * Fbx + uy * Fby;
+    const float uFb = fmaf(ux, Fbx, uy * Fby);
     const float nl = (umag > 0.0f) ? c.cf * uFb * hw_rcp(umag) : 0.0f;
-    ubx += -drag * Fbx - nl * ux + ubx0;
-    uby += -drag * Fby - nl * uy + uby0;
+    ubx = fmaf(-drag, Fbx, fmaf(-nl, ux, ubx)) + ubx0;
+    uby = fmaf(-drag, Fby, fmaf(-nl, uy, uby)) + uby0;
     pb.pax = Fbx;
     pb.pay = Fby;
     pb.cd = -uFb;
@@ -187,7 +187,12 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
 __device__ __forceinline__ void cell_phi_derivs(const Dom &d, const Cell &c, float kappa, float &dcd,
                                                 float &dcf) {
     const float phi = c.phi, ip = c.inv_phi;
-    if (d.medium == MED_PHI_ERGUN) {
+    if (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f) {
+        // the closed forms cd = (150 nu/dp^2)(1-phi)^2/phi^2, cf = (1.75/dp)(1-phi)/phi^2
+        const float om = 1.0f - phi, ip2 = ip * ip;
+        dcd = -2.0f * d.cdk * om * ip2 * ip;
+        dcf = -fmaf(2.0f * c.cf, ip, d.cfk * ip2);
+    } else if (d.medium == MED_PHI_ERGUN) {
         // kappa = kcoef (1-phi)^2 / phi^3; sqrt(kappa) = sk (1 - phi)
         const float om = 1.0f - phi;
         const float sk = hw_sqrt(d.kcoef) * ip * hw_sqrt(ip);

@@ -92,6 +92,13 @@ __device__ __forceinline__ float mulc(float x, float hi, float lo) { return fmaf
 #define MRT_C1_5 0x1.99999ap-3f, -0x1.99999ap-29f
 #define MRT_C1_20 0x1.99999ap-5f, -0x1.99999ap-31f
 
+// Workgroup barrier for LDS exchange only: waits for this wave's LDS accesses
+// (lgkmcnt) but not for its outstanding global stores, which no other wave of
+// the workgroup reads (__syncthreads also drains those, stalling the
+// recording kernels on their u stores). The memory clobber keeps the compiler
+// from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // Workgroups are dispatched round-robin over the 8 XCDs; this remaps the
 // block id so that each XCD walks a contiguous run of tiles (neighbouring
 // tiles share cache lines at the x-shifted loads and the halo rows).

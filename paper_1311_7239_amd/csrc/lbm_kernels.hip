@@ -294,6 +294,23 @@ hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int
                    : launch_batch_t<_Float16, false>(doms, tiles, ntiles, parity, s, grid, st);
 }
 
+// Item -> node of a (TW + 2R) x H tile that has R ring columns on each side:
+// the TW-wide interior of every row first, row-major (with TW = 64 each wave
+// covers one whole row: aligned, coalesced accesses and no division by the
+// padded width), then the 2R ring columns of every row.
+template <int TW, int H, int R>
+__device__ __forceinline__ void tile_item(int item, int &cx, int &cy) {
+    if (item < TW * H) {
+        cy = item / TW;
+        cx = R + item % TW;
+    } else {
+        const int r = item - TW * H;
+        cy = r / (2 * R);
+        const int c = r % (2 * R);
+        cx = c < R ? c : TW + c;
+    }
+}
+
 // ------------------------------------------------- two steps per pass
 
 // Temporal blocking: one launch advances t -> t + 2 with a single HBM pass.
@@ -354,7 +371,9 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
         // plus a uniform, non-negative per-link offset. Software pipelined: the next
         // node's loads are issued before this node collides.
         auto fetch = [&](int e, float (&f)[8], CellRaw &r) {
-            const int gx = x0 - 1 + e % EW, gy = y0 - 1 + e / EW;
+            int ex, ey;
+            tile_item<TW, EH, 1>(e, ex, ey);
+            const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
             const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * ES);
 #pragma unroll
             for (int i = 0; i < 8; ++i)
@@ -370,13 +389,15 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
             for (int i = 0; i < 8; ++i) f[i] = fn[i];
             const CellRaw r = rn;
             if (e + NT < EN) fetch(e + NT, fn, rn);
-            const int ex = e % EW, ey = e / EW;
+            int ex, ey;
+            tile_item<TW, EH, 1>(e, ex, ey);
             const int64_t o = (int64_t)(y0 - 1 + ey) * d.pitch + (x0 - 1 + ex);
             finish_a(f, cell_of(d, r), ex, ey, o);
         }
     } else {
         for (int e = threadIdx.x; e < EN; e += NT) {
-            const int ex = e % EW, ey = e / EW;
+            int ex, ey;
+            tile_item<TW, EH, 1>(e, ex, ey);
             int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
             if (gx < 0 || gx >= d.nx) {
                 if (d.bc_x != BC_PERIODIC) continue;
@@ -392,7 +413,7 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
             finish_a(f, cell_of(d, load_cell_raw(d, pl, (uint32_t)(o * 4))), ex, ey, o);
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     // phase B: s_{t+2} on the tile (and u(t+1) when recording)
 #pragma unroll
@@ -468,7 +489,7 @@ __global__ __launch_bounds__(NT) void k_step2_batch(const Dom *__restrict__ doms
         const int4 tl = tiles[t];
         const Dom d = doms[2 * tl.x + parity];
         step2_tile<S, TW, TH, NT, false>(d, tl.y * TW, tl.z * TH, nullptr, lds);
-        __syncthreads();   // the next tile's phase A rewrites the LDS
+        lds_barrier();   // the next tile's phase A rewrites the LDS
     }
 }
 
@@ -487,6 +508,184 @@ bool step2_shape_supported(int threads, int rows) {
 void step2_tiles(int nx, int ny, int rows, int *tiles_x, int *tiles_y) {
     *tiles_x = (nx + STEP2_TW - 1) / STEP2_TW;
     *tiles_y = (ny + rows - 1) / rows;
+}
+
+// ------------------------------------------------ three steps per pass
+
+// One LDS gather of a node whose own values sit at (cx, cy) of a W x H tile
+// layout (plane stride W H): the neighbour's post-collision value per link,
+// or across a wall the node's own opposite value plus the lid term. With
+// `interior` every source is a neighbour (constant offsets).
+template <int W, int H>
+__device__ __forceinline__ void lds_gather(const Dom &d, const float *flat, bool interior, int gx, int gy,
+                                           int cx, int cy, float f[8]) {
+    if (interior) {
+        const int base = cy * W + cx;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) f[i] = flat[base + i * W * H - EY[i] * W - EX[i]];
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        bool out = false, top = false;
+        const int sx = gx - EX[i], sy = gy - EY[i];
+        if (EX[i] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) out = true;
+        if (EY[i] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) {
+            out = true;
+            top = (sy >= d.ny);
+        }
+        const int src = out ? (OPP[i] * H + cy) * W + cx : (i * H + cy - EY[i]) * W + cx - EX[i];
+        const float v = flat[src];
+        f[i] = top ? v + (float)EX[i] * d.lid6 : v;
+    }
+}
+
+// Wraps (gx, gy) on periodic axes; false for a node beyond a wall.
+__device__ __forceinline__ bool wrap_node(const Dom &d, int &gx, int &gy) {
+    if (gx < 0 || gx >= d.nx) {
+        if (d.bc_x != BC_PERIODIC) return false;
+        gx = ((gx % d.nx) + d.nx) % d.nx;
+    }
+    if (gy < 0 || gy >= d.ny) {
+        if (d.bc_y != BC_PERIODIC) return false;
+        gy = ((gy % d.ny) + d.ny) % d.ny;
+    }
+    return true;
+}
+
+// Temporal blocking over three cycles: a workgroup owns a TW x TH tile. Phase A
+// gathers f(t) from HBM on the tile plus a two-node ring and collides into LDS;
+// phase B gathers f(t+1) from LDS on the tile plus a one-node ring, collides and
+// keeps the results in registers; after a barrier they replace phase A's values
+// in the same LDS (a smaller layout), and phase C gathers f(t+2), collides and
+// stores f+(t+2). Same per-node function and FP16 rounding of every
+// intermediate as three one-cycle passes, so the result is bitwise theirs.
+// With REC (FP32 recomputation for the adjoint) u and, with rec_stress, the
+// stress moments of the tile nodes are recorded at t (d.urec), t + 1 (urec1)
+// and t + 2 (urec2).
+__device__ __forceinline__ void record_node(const Dom &d, float *rec, int64_t o, float ux, float uy, float n7,
+                                            float n8) {
+    rec[o] = ux;
+    rec[d.plane + o] = uy;
+    if (d.rec_stress) {
+        rec[2 * d.plane + o] = n7;
+        rec[3 * d.plane + o] = n8;
+    }
+}
+
+template <typename S, int TW, int TH, int NT, bool REC>
+__global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
+    constexpr int AW = TW + 4, AH = TH + 4, AN = AW * AH;
+    constexpr int BW = TW + 2, BH = TH + 2, BN = BW * BH;
+    constexpr int ES = (int)sizeof(S);
+    constexpr int NBB = (BN + NT - 1) / NT;
+    __shared__ float lds[8 * AH * AW];
+    int b = blockIdx.x;
+    if (swz) b = xcd_swizzle(b, gridDim.x);
+    const int x0 = (b % tiles_x) * TW, y0 = (b / tiles_x) * TH;
+    const S *__restrict__ fin = (const S *)d.fin;
+    const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
+    const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
+    const CellPlanes pl = cell_planes(d);
+    const bool interior = x0 >= 3 && x0 + TW + 3 <= d.nx && y0 >= 3 && y0 + TH + 3 <= d.ny;
+
+    // phase A: s_{t+1} on the tile + 2 ring
+    for (int e = threadIdx.x; e < AN; e += NT) {
+        const int ex = e % AW, ey = e / AW;
+        int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
+        float f[8];
+        if (interior) {
+            const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * ES);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                f[i] = BufIO<S>::ld(rin, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
+        } else {
+            if (!wrap_node(d, gx, gy)) continue;
+            gather_general<S>(d, fin, gx, gy, f);
+        }
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = cell_of(d, load_cell_raw(d, pl, (uint32_t)(o * 4)));
+        float ux, uy, n7, n8;
+        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[(i * AH + ey) * AW + ex] = (float)(S)f[i];
+        if (REC && ex >= 2 && ex < TW + 2 && ey >= 2 && ey < TH + 2 && x0 - 2 + ex < d.nx && y0 - 2 + ey < d.ny)
+            record_node(d, d.urec, o, ux, uy, n7, n8);
+    }
+    lds_barrier();
+
+    // phase B: s_{t+2} on the tile + 1 ring, kept in registers
+    float fb[NBB][8];
+    int slot[NBB];
+#pragma unroll
+    for (int k = 0; k < NBB; ++k) {
+        slot[k] = -1;
+        const int e = threadIdx.x + k * NT;
+        if (e >= BN) continue;
+        const int bx = e % BW, by = e / BW;
+        int gx = x0 - 1 + bx, gy = y0 - 1 + by;
+        if (!interior && !wrap_node(d, gx, gy)) continue;
+        lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fb[k]);
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = cell_of(d, load_cell_raw(d, pl, (uint32_t)(o * 4)));
+        float ux, uy, n7, n8;
+        collide(fb[k], d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
+        if (REC && bx >= 1 && bx <= TW && by >= 1 && by <= TH && x0 - 1 + bx < d.nx && y0 - 1 + by < d.ny)
+            record_node(d, urec1, o, ux, uy, n7, n8);
+        slot[k] = e;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < NBB; ++k) {
+        if (slot[k] < 0) continue;
+        const int bx = slot[k] % BW, by = slot[k] / BW;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[(i * BH + by) * BW + bx] = (float)(S)fb[k][i];
+    }
+    lds_barrier();
+
+    // phase C: s_{t+3} on the tile, to HBM
+    for (int q = threadIdx.x; q < TW * TH; q += NT) {
+        const int lx = q % TW, ly = q / TW;
+        const int gx = x0 + lx, gy = y0 + ly;
+        if (gx >= d.nx || gy >= d.ny) continue;
+        float f[8];
+        lds_gather<BW, BH>(d, lds, interior, gx, gy, lx + 1, ly + 1, f);
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = cell_of(d, load_cell_raw(d, pl, (uint32_t)(o * 4)));
+        float ux, uy, n7, n8;
+        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
+        const uint32_t vo = (uint32_t)(o * ES);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+        if (REC) record_node(d, urec2, o, ux, uy, n7, n8);
+    }
+}
+
+constexpr int STEP3_TW = 64, STEP3_TH = 16, STEP3_NT = 512;
+
+void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y) {
+    *tiles_x = (nx + STEP3_TW - 1) / STEP3_TW;
+    *tiles_y = (ny + STEP3_TH - 1) / STEP3_TH;
+}
+
+const void *step3_kernel_fn(int storage, bool rec) {
+    if (rec) return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, true> : nullptr;
+    return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, false>
+                             : (const void *)&k_step3<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, false>;
+}
+
+hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, float *urec2, hipStream_t st) {
+    if (d.thermal) return hipErrorInvalidValue;
+    const bool rec = urec1 != nullptr;
+    const void *fn = step3_kernel_fn(storage, rec);
+    if (!fn || (rec && (!d.urec || !urec2))) return hipErrorInvalidValue;
+    int tx, ty;
+    step3_tiles(d.nx, d.ny, &tx, &ty);
+    Dom dd = d;
+    int swz = swizzle;
+    void *args[5] = {&dd, &tx, &swz, &urec1, &urec2};
+    return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3(STEP3_NT), args, 0, st);
 }
 
 template <typename S, bool REC>

@@ -76,15 +76,20 @@ def counters_summary(fetch_csv, write_csv, out_json, command, kernel_prefix="voi
 
 def traffic_bytes(summary_json, kernel_name=None):
     """HBM bytes per dispatch of the step kernel from a counters summary, or None if the
-    kernel sources changed since the counters were taken."""
+    kernel sources changed since the counters were taken. kernel_name: the full name or a
+    prefix of it (the first match); None takes the most dispatched kernel."""
     p = pathlib.Path(summary_json)
     if not p.exists():
         return None
     s = json.loads(p.read_text())
     if s.get("kernel_source_hash") != kernel_source_hash() or not s.get("kernels"):
         return None
-    k = s["kernels"].get(kernel_name) if kernel_name else max(s["kernels"].values(),
-                                                              key=lambda v: v["dispatches"])
+    if kernel_name:
+        k = s["kernels"].get(kernel_name)
+        if k is None:
+            k = next((v for n, v in s["kernels"].items() if n.startswith(kernel_name)), None)
+    else:
+        k = max(s["kernels"].values(), key=lambda v: v["dispatches"])
     if not k or k["write_kib"] is None or not s["fetch_scale"] or not s["write_scale"]:
         return None
     return 1024.0 * (k["fetch_kib"] * s["fetch_scale"] + k["write_kib"] * s["write_scale"])

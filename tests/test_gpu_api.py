@@ -69,7 +69,7 @@ def test_thermal_populations_round_trip_and_time():
 def test_argument_checks_on_a_live_context():
     case = I.lid_cavity(n=64)
     s = lbm.solver_for_case(case)
-    for bad in (3, -2, 5000):
+    for bad in (-2, 5000):
         with pytest.raises(lbm.LBMError) as e:
             s.set_graph_steps(bad)
         assert e.value.status == lbm.EINVAL
@@ -77,7 +77,7 @@ def test_argument_checks_on_a_live_context():
         s.set_schedule(100, 1, 1)
     assert e.value.status == lbm.EINVAL
     with pytest.raises(lbm.LBMError) as e:
-        s.set_time_blocking(3)
+        s.set_time_blocking(4)
     assert e.value.status == lbm.EINVAL
     with pytest.raises(lbm.LBMError) as e:
         s.macroscopic(want_T=True)          # no thermal model

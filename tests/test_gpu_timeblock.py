@@ -40,6 +40,29 @@ def cases():
 
 @pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
 @pytest.mark.parametrize("name,case", cases(), ids=[n for n, _ in cases()])
+@pytest.mark.parametrize("graph", [0, 9, 8])
+def test_three_cycles_per_pass_is_bitwise_equal(name, case, storage, graph):
+    """Three cycles per pass (two-node LDS ring), alone and mixed with the two- and
+    one-cycle passes that finish a call, equal one cycle per pass bit for bit."""
+    ref = lbm.solver_for_case(case, storage=storage)
+    ref.set_time_blocking(1)
+    tb = lbm.solver_for_case(case, storage=storage)
+    tb.set_time_blocking(3)
+    tb.set_graph_steps(graph)
+    df0 = I.random_deviation_state(case.ny, case.nx, 1e-3, seed=5)
+    for s in (ref, tb):
+        s.set_populations(torch.from_numpy(df0).cuda())
+    for chunk in (1, 7, 10, 2, 5, 19, 4):
+        ref.step(chunk)
+        tb.step(chunk)
+        a, _ = ref.populations()
+        b, _ = tb.populations()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), (name, chunk)
+
+
+@pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
+@pytest.mark.parametrize("name,case", cases(), ids=[n for n, _ in cases()])
 @pytest.mark.parametrize("graph,shape", [(0, (512, 16)), (8, (256, 16)), (0, (256, 8)), (8, (512, 8))])
 def test_two_cycles_per_pass_is_bitwise_equal(name, case, storage, graph, shape):
     ref = lbm.solver_for_case(case, storage=storage)
@@ -74,7 +97,7 @@ def test_backward_with_two_cycle_passes_is_bitwise_equal(kappa_plane):
         kap = torch.from_numpy((150.0 * (1 - case.phi) ** 2 / (case.phi ** 3 * case.dp ** 2))
                                .astype(np.float32)).cuda()
     grads = []
-    for tblock in (1, 2):
+    for tblock in (1, 2, 3):
         desc = lbm.desc_from_case(case, ckpt_every=50)
         if kappa_plane:
             desc.medium = lbm.MEDIUM_PHI_KAPPA
@@ -87,6 +110,7 @@ def test_backward_with_two_cycle_passes_is_bitwise_equal(kappa_plane):
         g, gk = s.backward(dLdu, want_kappa=kappa_plane)
         torch.cuda.synchronize()
         grads.append((g.cpu().numpy(), None if gk is None else gk.cpu().numpy()))
-    assert np.array_equal(grads[0][0], grads[1][0])
-    if kappa_plane:
-        assert np.array_equal(grads[0][1], grads[1][1])
+    for k in (1, 2):
+        assert np.array_equal(grads[0][0], grads[k][0]), k
+        if kappa_plane:
+            assert np.array_equal(grads[0][1], grads[k][1]), k
