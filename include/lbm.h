@@ -272,10 +272,10 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * one-node ring kept in LDS, then collides again, so each population crosses
  * HBM about once per two cycles) or 3 (a two-node ring, three collisions per
  * launch; single domains only). Results are bitwise identical in every mode.
- * Multi-cycle passes are skipped for t = 0, while recording for
- * lbm_backward, and for the last cycle of each lbm_step call (so
- * lbm_reduce's residual always compares u(t) with u(t-1)); a call finishes
- * with shorter passes where fewer cycles remain. The recomputation inside
+ * Multi-cycle passes are skipped for t = 0 and for the last cycle of each
+ * lbm_step call (so lbm_reduce's residual always compares u(t) with u(t-1));
+ * while recording for lbm_backward no pass steps over a checkpoint time.
+ * Shorter passes fill in where fewer cycles remain. The recomputation inside
  * lbm_backward uses passes of the same length (recording u at every cycle)
  * and its adjoint sweep two steps per pass in modes 2 and 3. Default for
  * single domains of at least 2^20 nodes that allow it: 3 (FP32) or 2 (FP16),

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -553,9 +554,13 @@ int lbm_step(lbm_ctx *c, int64_t n) {
             continue;
         }
         const bool recording = c->rec_valid && c->dom[0].desc.ckpt_every > 0;
-        // two cycles per pass while at least one single cycle remains for the end of
-        // this call (so the previous buffer always holds f+(t-2) -> u(t-1) for the residual)
-        const bool fused = c->tblock >= 2 && !recording && !c->dom[0].desc.thermal.enabled;
+        // several cycles per pass while at least one single cycle remains for the end of
+        // this call (so the previous buffer always holds f+(t-2) -> u(t-1) for the residual);
+        // when recording, a pass never steps over a checkpoint time (the checkpoint
+        // needs the state there)
+        const bool fused = c->tblock >= 2 && !c->dom[0].desc.thermal.enabled;
+        const int64_t next_ck = recording ? (c->t / c->dom[0].desc.ckpt_every + 1) * c->dom[0].desc.ckpt_every
+                                          : INT64_MAX;
         const int64_t gcyc = graph_cycles(c);
         if (gcyc > 0 && !recording && n - (fused ? 1 : 0) >= gcyc) {
             if (!c->gexec[c->cur]) {
@@ -569,7 +574,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
             n -= gcyc;
             continue;
         }
-        if (fused && c->tblock == 3 && !c->batch && n >= 4) {
+        if (fused && c->tblock == 3 && !c->batch && n >= 4 && c->t + 3 <= next_ck) {
             Domain &D = c->dom[0];
             e = launch_step3(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
                              c->sched.swizzle, nullptr, nullptr, c->stream);
@@ -577,9 +582,10 @@ int lbm_step(lbm_ctx *c, int64_t n) {
             c->cur ^= 1;
             c->t += 3;
             n -= 3;
+            if ((e = checkpoint(c)) != hipSuccess) return device_fail(c, e, "checkpoint copy");
             continue;
         }
-        if (fused && n >= 3) {
+        if (fused && n >= 3 && c->t + 2 <= next_ck) {
             Domain &D = c->dom[0];
             if (c->batch)
                 e = launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->tb_threads,
@@ -591,6 +597,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
             c->cur ^= 1;
             c->t += 2;
             n -= 2;
+            if ((e = checkpoint(c)) != hipSuccess) return device_fail(c, e, "checkpoint copy");
             continue;
         }
         if (c->batch) {

@@ -338,7 +338,7 @@ __device__ __forceinline__ void gather_transposed(const Dom &d, const float *__r
 constexpr int ATW = 64, ATH = 16, ANT = 512;
 
 template <bool THETA>
-__global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__restrict__ lam_in,
+__global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k_adjoint_step2(Dom d, const float *__restrict__ lam_in,
                                                        float *__restrict__ lam_out,
                                                        const float *__restrict__ u_t,
                                                        const float *__restrict__ u_tm1,
@@ -362,30 +362,6 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
     const BufRes rg = buf_res(gphi, pb4), rgk = buf_res(gkappa, gkappa ? pb4 : 0u);
     const CellPlanes pl = cell_planes(d);
     ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
-
-    // inputs of this thread's phase-B nodes, fetched now so that they arrive during phase A
-    CellRaw rawB[NB];
-    float uB[NB][4], gB[NB], gkB[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        const int q = threadIdx.x + k * ANT;
-        const int gx = x0 + q % ATW, gy = y0 + q / ATW;
-        rawB[k] = CellRaw{0.0f, 0.0f, 0.0f};
-        uB[k][0] = uB[k][1] = uB[k][2] = uB[k][3] = 0.0f;
-        gB[k] = gkB[k] = 0.0f;
-        if (q < ATW * ATH && gx < d.nx && gy < d.ny) {
-            const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
-            rawB[k] = load_cell_raw(d, pl, o4);
-            uB[k][0] = BufIO<float>::ld(rutm, o4, 0u);
-            uB[k][1] = BufIO<float>::ld(rutm, o4, pb4);
-            if (THETA) {
-                uB[k][2] = BufIO<float>::ld(rutm, o4, 2 * pb4);
-                uB[k][3] = BufIO<float>::ld(rutm, o4, 3 * pb4);
-            }
-            gB[k] = BufIO<float>::ld(rg, o4, 0u);
-            if (gkappa) gkB[k] = BufIO<float>::ld(rgk, o4, 0u);
-        }
-    }
 
     // phase A: a(t) on the tile plus a one-node ring, from a(t+1) in HBM
     auto finish_a = [&](float (&bb)[8], const CellRaw &r, const float (&uu)[4], int ex, int ey, int gx,
@@ -467,8 +443,26 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
     }
     __syncthreads();
 
-    // phase B: a(t-1) on the tile from LDS
+    // phase B: a(t-1) on the tile from LDS. The vector-memory counter retires
+    // loads and stores in order, so both nodes' inputs are fetched before the
+    // first node's stores.
     const float *flat = &lds[0][0][0];
+    CellRaw rawB[NB];
+    float uB[NB][4], gB[NB], gkB[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int q = threadIdx.x + k * ANT;
+        const int gx = x0 + q % ATW, gy = y0 + q / ATW;
+        if (q >= ATW * ATH || gx >= d.nx || gy >= d.ny) continue;
+        const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+        rawB[k] = load_cell_raw(d, pl, o4);
+        uB[k][0] = BufIO<float>::ld(rutm, o4, 0u);
+        uB[k][1] = BufIO<float>::ld(rutm, o4, pb4);
+        uB[k][2] = THETA ? BufIO<float>::ld(rutm, o4, 2 * pb4) : 0.0f;
+        uB[k][3] = THETA ? BufIO<float>::ld(rutm, o4, 3 * pb4) : 0.0f;
+        gB[k] = BufIO<float>::ld(rg, o4, 0u);
+        gkB[k] = gkappa ? BufIO<float>::ld(rgk, o4, 0u) : 0.0f;
+    }
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
         const int q = threadIdx.x + k * ANT;
@@ -476,6 +470,7 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
         const int lx = q % ATW, ly = q / ATW;
         const int gx = x0 + lx, gy = y0 + ly;
         if (gx >= d.nx || gy >= d.ny) continue;
+        const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
         float bb[8];
         if (interior) {
             const int base = (ly + 1) * EW + lx + 1;
@@ -493,7 +488,6 @@ __global__ __launch_bounds__(ANT) void k_adjoint_step2(Dom d, const float *__res
                 bb[i] = flat[src];
             }
         }
-        const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
         const Cell c = cell_of(d, rawB[k]);
         float a[8];
         ParamBar pb;

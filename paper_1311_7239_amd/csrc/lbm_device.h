@@ -391,24 +391,26 @@ struct CellPlanes {
 __device__ __forceinline__ CellPlanes cell_planes(const Dom &d) {
     const uint32_t pb = (uint32_t)(d.plane * 4);
     CellPlanes r;
-    r.phi = buf_res(d.phi, d.phi ? pb : 0u);
-    r.kappa = buf_res(d.kappa, d.kappa ? pb : 0u);
-    r.snu = buf_res(d.snu, d.snu ? pb : 0u);
+    // an absent plane gets a zero-size resource over a valid base: its loads are
+    // out of range and return 0 without a memory access
+    const void *any = d.fin;
+    r.phi = d.phi ? buf_res(d.phi, pb) : buf_res(any, 0u);
+    r.kappa = d.kappa ? buf_res(d.kappa, pb) : buf_res(any, 0u);
+    r.snu = d.snu ? buf_res(d.snu, pb) : buf_res(any, 0u);
     return r;
 }
 
 // The raw per-node medium values of a node (porosity, 1/K, s_nu plane entries),
-// fetched early so that the loads are in flight while other work runs.
+// fetched early so that the loads are in flight while other work runs. The
+// loads are unconditional (an absent plane reads 0), so that they issue
+// back to back and a later wait covers exactly them.
 struct CellRaw {
     float phi, kappa, snu;
 };
 
-__device__ __forceinline__ CellRaw load_cell_raw(const Dom &d, const CellPlanes &pl, uint32_t o4) {
-    CellRaw r{0.0f, 0.0f, 0.0f};
-    if (d.medium != MED_UNIFORM) r.phi = BufIO<float>::ld(pl.phi, o4, 0u);
-    if (d.medium == MED_PHI_KAPPA) r.kappa = BufIO<float>::ld(pl.kappa, o4, 0u);
-    if (d.snu) r.snu = BufIO<float>::ld(pl.snu, o4, 0u);
-    return r;
+__device__ __forceinline__ CellRaw load_cell_raw(const Dom &, const CellPlanes &pl, uint32_t o4) {
+    return CellRaw{BufIO<float>::ld(pl.phi, o4, 0u), BufIO<float>::ld(pl.kappa, o4, 0u),
+                   BufIO<float>::ld(pl.snu, o4, 0u)};
 }
 
 // Same values as load_cell.

@@ -563,15 +563,32 @@ __device__ __forceinline__ bool wrap_node(const Dom &d, int &gx, int &gy) {
 // With REC (FP32 recomputation for the adjoint) u and, with rec_stress, the
 // stress moments of the tile nodes are recorded at t (d.urec), t + 1 (urec1)
 // and t + 2 (urec2).
-__device__ __forceinline__ void record_node(const Dom &d, float *rec, int64_t o, float ux, float uy, float n7,
+// The records go through buffer stores: a recorded step spans at most five
+// planes, below 4 GiB whenever multi-cycle passes run.
+__device__ __forceinline__ void record_node(const Dom &d, BufRes rec, uint32_t o4, float ux, float uy, float n7,
                                             float n8) {
-    rec[o] = ux;
-    rec[d.plane + o] = uy;
+    const uint32_t pb4 = (uint32_t)(d.plane * 4);
+    BufIO<float>::st(rec, o4, 0u, ux);
+    BufIO<float>::st(rec, o4, pb4, uy);
     if (d.rec_stress) {
-        rec[2 * d.plane + o] = n7;
-        rec[3 * d.plane + o] = n8;
+        BufIO<float>::st(rec, o4, 2 * pb4, n7);
+        BufIO<float>::st(rec, o4, 3 * pb4, n8);
     }
 }
+
+// One node's record held back until the next node's loads have been issued.
+struct Pending {
+    uint32_t o4 = 0u;
+    float ux = 0.0f, uy = 0.0f, n7 = 0.0f, n8 = 0.0f;
+    bool on = false;
+    __device__ __forceinline__ void hold(uint32_t o, float a, float b, float c, float e) {
+        o4 = o; ux = a; uy = b; n7 = c; n8 = e; on = true;
+    }
+    __device__ __forceinline__ void flush(const Dom &d, BufRes rec) {
+        if (on) record_node(d, rec, o4, ux, uy, n7, n8);
+        on = false;
+    }
+};
 
 template <typename S, int TW, int TH, int NT, bool REC>
 __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
@@ -588,6 +605,16 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
     const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
     const CellPlanes pl = cell_planes(d);
     const bool interior = x0 >= 3 && x0 + TW + 3 <= d.nx && y0 >= 3 && y0 + TH + 3 <= d.ny;
+    const uint32_t rbytes = REC ? (uint32_t)((d.rec_stress ? 4 : 2) * d.plane * 4) : 0u;
+    const BufRes rr0 = buf_res(REC ? d.urec : nullptr, rbytes), rr1 = buf_res(urec1, rbytes),
+                 rr2 = buf_res(urec2, rbytes);
+
+    // CDNA's vector-memory counter retires loads and stores in order, so a wait
+    // for a load also waits for every store issued before it. Each phase
+    // therefore issues its global loads before the stores that belong to the
+    // previous node: records are held one node (Pending) and phase C fetches
+    // its medium values before its first store.
+    Pending pend;
 
     // phase A: s_{t+1} on the tile + 2 ring
     for (int e = threadIdx.x; e < AN; e += NT) {
@@ -604,14 +631,17 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
             gather_general<S>(d, fin, gx, gy, f);
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = cell_of(d, load_cell_raw(d, pl, (uint32_t)(o * 4)));
+        const CellRaw raw = load_cell_raw(d, pl, (uint32_t)(o * 4));
+        if (REC) pend.flush(d, rr0);
+        const Cell c = cell_of(d, raw);
         float ux, uy, n7, n8;
         collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[(i * AH + ey) * AW + ex] = (float)(S)f[i];
         if (REC && ex >= 2 && ex < TW + 2 && ey >= 2 && ey < TH + 2 && x0 - 2 + ex < d.nx && y0 - 2 + ey < d.ny)
-            record_node(d, d.urec, o, ux, uy, n7, n8);
+            pend.hold((uint32_t)(o * 4), ux, uy, n7, n8);
     }
+    if (REC) pend.flush(d, rr0);
     lds_barrier();
 
     // phase B: s_{t+2} on the tile + 1 ring, kept in registers
@@ -625,15 +655,18 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
         const int bx = e % BW, by = e / BW;
         int gx = x0 - 1 + bx, gy = y0 - 1 + by;
         if (!interior && !wrap_node(d, gx, gy)) continue;
-        lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fb[k]);
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = cell_of(d, load_cell_raw(d, pl, (uint32_t)(o * 4)));
+        const CellRaw raw = load_cell_raw(d, pl, (uint32_t)(o * 4));
+        if (REC) pend.flush(d, rr1);
+        lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fb[k]);
+        const Cell c = cell_of(d, raw);
         float ux, uy, n7, n8;
         collide(fb[k], d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
         if (REC && bx >= 1 && bx <= TW && by >= 1 && by <= TH && x0 - 1 + bx < d.nx && y0 - 1 + by < d.ny)
-            record_node(d, urec1, o, ux, uy, n7, n8);
+            pend.hold((uint32_t)(o * 4), ux, uy, n7, n8);
         slot[k] = e;
     }
+    if (REC) pend.flush(d, rr1);
     lds_barrier();
 #pragma unroll
     for (int k = 0; k < NBB; ++k) {
@@ -645,20 +678,31 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
     lds_barrier();
 
     // phase C: s_{t+3} on the tile, to HBM
-    for (int q = threadIdx.x; q < TW * TH; q += NT) {
+    constexpr int NC = (TW * TH + NT - 1) / NT;
+    CellRaw rawC[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const int q = threadIdx.x + k * NT;
+        const int gx = x0 + q % TW, gy = y0 + q / TW;
+        if (q < TW * TH && gx < d.nx && gy < d.ny)
+            rawC[k] = load_cell_raw(d, pl, (uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
+    }
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+        const int q = threadIdx.x + k * NT;
         const int lx = q % TW, ly = q / TW;
         const int gx = x0 + lx, gy = y0 + ly;
-        if (gx >= d.nx || gy >= d.ny) continue;
+        if (q >= TW * TH || gx >= d.nx || gy >= d.ny) continue;
         float f[8];
         lds_gather<BW, BH>(d, lds, interior, gx, gy, lx + 1, ly + 1, f);
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = cell_of(d, load_cell_raw(d, pl, (uint32_t)(o * 4)));
+        const Cell c = cell_of(d, rawC[k]);
         float ux, uy, n7, n8;
         collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
         const uint32_t vo = (uint32_t)(o * ES);
 #pragma unroll
         for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
-        if (REC) record_node(d, urec2, o, ux, uy, n7, n8);
+        if (REC) record_node(d, rr2, (uint32_t)(o * 4), ux, uy, n7, n8);
     }
 }
 
