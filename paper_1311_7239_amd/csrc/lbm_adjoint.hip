@@ -398,7 +398,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
             for (int i = 0; i < 8; ++i)
                 bb[i] = BufIO<float>::ld(rlin, vo, (uint32_t)((i * d.plane + (1 + EY[i]) * d.pitch + (1 + EX[i])) * 4));
             const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
-            r = load_cell_raw(d, pl, o4);
+            r = load_cell_raw_all(pl, o4);
             uu[0] = BufIO<float>::ld(rut, o4, 0u);
             uu[1] = BufIO<float>::ld(rut, o4, pb4);
             uu[2] = THETA ? BufIO<float>::ld(rut, o4, 2 * pb4) : 0.0f;
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
                 uu[2] = BufIO<float>::ld(rut, o4, 2 * pb4);
                 uu[3] = BufIO<float>::ld(rut, o4, 3 * pb4);
             }
-            finish_a(bb, load_cell_raw(d, pl, o4), uu, ex, ey, gx, gy);
+            finish_a(bb, load_cell_raw_all(pl, o4), uu, ex, ey, gx, gy);
         }
     }
     __syncthreads();
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
         const int gx = x0 + q % ATW, gy = y0 + q / ATW;
         if (q >= ATW * ATH || gx >= d.nx || gy >= d.ny) continue;
         const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
-        rawB[k] = load_cell_raw(d, pl, o4);
+        rawB[k] = load_cell_raw_all(pl, o4);
         uB[k][0] = BufIO<float>::ld(rutm, o4, 0u);
         uB[k][1] = BufIO<float>::ld(rutm, o4, pb4);
         uB[k][2] = THETA ? BufIO<float>::ld(rutm, o4, 2 * pb4) : 0.0f;

@@ -631,7 +631,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
             gather_general<S>(d, fin, gx, gy, f);
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const CellRaw raw = load_cell_raw(d, pl, (uint32_t)(o * 4));
+        const CellRaw raw = load_cell_raw_all(pl, (uint32_t)(o * 4));
         if (REC) pend.flush(d, rr0);
         const Cell c = cell_of(d, raw);
         float ux, uy, n7, n8;
@@ -656,7 +656,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
         int gx = x0 - 1 + bx, gy = y0 - 1 + by;
         if (!interior && !wrap_node(d, gx, gy)) continue;
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const CellRaw raw = load_cell_raw(d, pl, (uint32_t)(o * 4));
+        const CellRaw raw = load_cell_raw_all(pl, (uint32_t)(o * 4));
         if (REC) pend.flush(d, rr1);
         lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fb[k]);
         const Cell c = cell_of(d, raw);
@@ -685,7 +685,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
         const int q = threadIdx.x + k * NT;
         const int gx = x0 + q % TW, gy = y0 + q / TW;
         if (q < TW * TH && gx < d.nx && gy < d.ny)
-            rawC[k] = load_cell_raw(d, pl, (uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
+            rawC[k] = load_cell_raw_all(pl, (uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
     }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {

@@ -32,6 +32,10 @@ def _rows(path):
         return list(csv.DictReader(fh))
 
 
+def _short(name, width=150):
+    return name if len(name) <= width else name[:width] + " ..."
+
+
 def stats_summary(stats_csv, out_txt, command):
     rows = _rows(stats_csv)
     lines = [f"# rocprofv3 --kernel-trace --stats summary", f"# command: {command}",
@@ -39,7 +43,7 @@ def stats_summary(stats_csv, out_txt, command):
              "calls  avg_us  min_us  max_us  pct  kernel"]
     for r in rows:
         lines.append(f"{int(r['Calls']):5d} {float(r['AverageNs']) / 1e3:8.1f} {float(r['MinNs']) / 1e3:8.1f} "
-                     f"{float(r['MaxNs']) / 1e3:8.1f} {float(r['Percentage']):5.1f}  {r['Name']}")
+                     f"{float(r['MaxNs']) / 1e3:8.1f} {float(r['Percentage']):5.1f}  {_short(r['Name'])}")
     pathlib.Path(out_txt).write_text("\n".join(lines) + "\n")
 
 
