@@ -410,7 +410,7 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
             Domain &D = c->dom[0];
             d = dom_for(D, p);
             step3_tiles(D.desc.nx, D.desc.ny, &tx, &ty);
-            kp.func = (void *)step3_kernel_fn(D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, false);
+            kp.func = (void *)step3_kernel_fn(D.dom, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, false);
             kp.gridDim = dim3((unsigned)(tx * ty));
             kp.blockDim = dim3(512);
             kp.kernelParams = args_s3;

@@ -184,10 +184,11 @@ __device__ __forceinline__ void collide_adjoint(const float b[8], const Dom &d, 
 }
 
 // d cd / d phi and d cf / d phi of a node (Eqs. 3-4; zero without a porosity plane).
+template <int MK = MK_ANY>
 __device__ __forceinline__ void cell_phi_derivs(const Dom &d, const Cell &c, float kappa, float &dcd,
                                                 float &dcf) {
     const float phi = c.phi, ip = c.inv_phi;
-    if (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f) {
+    if (MK == MK_ERGUN || (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f)) {
         // the closed forms cd = (150 nu/dp^2)(1-phi)^2/phi^2, cf = (1.75/dp)(1-phi)/phi^2
         const float om = 1.0f - phi, ip2 = ip * ip;
         dcd = -2.0f * d.cdk * om * ip2 * ip;
@@ -210,14 +211,15 @@ __device__ __forceinline__ void cell_phi_derivs(const Dom &d, const Cell &c, flo
 }
 
 // Medium adjoints -> dL/dphi (and dL/dkappa with a kappa plane).
+template <int MK = MK_ANY>
 __device__ __forceinline__ void medium_gradient(const Dom &d, const Cell &c, float kappa,
                                                 const ParamBar &pb, float ax, float ay,
                                                 float &gphi, float &gkappa) {
     const float phi = c.phi, ip = c.inv_phi;
     float dcd, dcf;
-    cell_phi_derivs(d, c, kappa, dcd, dcf);
+    cell_phi_derivs<MK>(d, c, kappa, dcd, dcf);
     gkappa = 0.0f;
-    if (d.medium == MED_PHI_KAPPA) {
+    if (MK == MK_ANY && d.medium == MED_PHI_KAPPA) {
         const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
         const float sq = hw_sqrt(kappa);
         const float dcf_dk = (kappa > 0.0f) ? 0.5f * phi * F * hw_rcp(sq) : 0.0f;
@@ -330,6 +332,27 @@ __device__ __forceinline__ void gather_transposed(const Dom &d, const float *__r
     }
 }
 
+// gather_transposed's edge form through a buffer resource over the eight
+// planes of a (below 4 GiB): 32-bit offsets, no per-plane base pointers.
+__device__ __forceinline__ void gather_transposed_buf(const Dom &d, BufRes rlam, int x, int y, float b[8]) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        int sx = x + EX[i], sy = y + EY[i];
+        bool out = false;
+        if (EX[i] != 0 && (sx < 0 || sx >= d.nx)) {
+            if (d.bc_x == BC_PERIODIC) sx = (sx < 0) ? d.nx - 1 : 0;
+            else out = true;
+        }
+        if (EY[i] != 0 && (sy < 0 || sy >= d.ny)) {
+            if (d.bc_y == BC_PERIODIC) sy = (sy < 0) ? d.ny - 1 : 0;
+            else out = true;
+        }
+        const uint32_t idx = out ? (uint32_t)(OPP[i] * d.plane + y * d.pitch + x)
+                                 : (uint32_t)(i * d.plane + sy * d.pitch + sx);
+        b[i] = BufIO<float>::ld(rlam, idx * 4u, 0u);
+    }
+}
+
 // Two backward steps per pass: a(t) on a 64 x 16 tile plus a one-node ring
 // from a(t+1) in HBM into LDS (phase A), then a(t-1) on the tile from LDS
 // (phase B); the medium gradient of both steps is added in one
@@ -337,7 +360,7 @@ __device__ __forceinline__ void gather_transposed(const Dom &d, const float *__r
 // bitwise that of two k_adjoint_step launches.
 constexpr int ATW = 64, ATH = 16, ANT = 512;
 
-template <bool THETA>
+template <bool THETA, int MK>
 __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k_adjoint_step2(Dom d, const float *__restrict__ lam_in,
                                                        float *__restrict__ lam_out,
                                                        const float *__restrict__ u_t,
@@ -360,14 +383,14 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
     const BufRes rlin = buf_res(lam_in, 8 * pb4), rlout = buf_res(lam_out, 8 * pb4);
     const BufRes rut = buf_res(u_t, 5 * pb4), rutm = buf_res(u_tm1, 5 * pb4);
     const BufRes rg = buf_res(gphi, pb4), rgk = buf_res(gkappa, gkappa ? pb4 : 0u);
-    const CellPlanes pl = cell_planes(d);
+    const MediumSrc<MK> med(d);
     ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
 
     // phase A: a(t) on the tile plus a one-node ring, from a(t+1) in HBM
     auto finish_a = [&](float (&bb)[8], const CellRaw &r, const float (&uu)[4], int ex, int ey, int gx,
                         int gy) {
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = cell_of(d, r);
+        const Cell c = med.cell(d, r);
         float a[8];
         ParamBar pb;
         collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, uu[0], uu[1], uu[2], uu[3], a, pb);
@@ -375,7 +398,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
         for (int i = 0; i < 8; ++i) lds[i][ey][ex] = a[i];
         if (ex >= 1 && ex <= ATW && ey >= 1 && ey <= ATH && x0 - 1 + ex < d.nx && y0 - 1 + ey < d.ny) {
             float gp, gk;
-            medium_gradient(d, c, r.kappa, pb, d.ax, d.ay, gp, gk);
+            medium_gradient<MK>(d, c, r.kappa, pb, d.ax, d.ay, gp, gk);
             gA[ey - 1][ex - 1] = gp;
             gkA[ey - 1][ex - 1] = gk;
             if (THETA) {
@@ -398,7 +421,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
             for (int i = 0; i < 8; ++i)
                 bb[i] = BufIO<float>::ld(rlin, vo, (uint32_t)((i * d.plane + (1 + EY[i]) * d.pitch + (1 + EX[i])) * 4));
             const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
-            r = load_cell_raw_all(pl, o4);
+            r = med.load(o4);
             uu[0] = BufIO<float>::ld(rut, o4, 0u);
             uu[1] = BufIO<float>::ld(rut, o4, pb4);
             uu[2] = THETA ? BufIO<float>::ld(rut, o4, 2 * pb4) : 0.0f;
@@ -431,14 +454,14 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
                 gy = ((gy % d.ny) + d.ny) % d.ny;
             }
             float bb[8];
-            gather_transposed(d, lam_in, gx, gy, false, bb);
+            gather_transposed_buf(d, rlin, gx, gy, bb);
             const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
             float uu[4] = {BufIO<float>::ld(rut, o4, 0u), BufIO<float>::ld(rut, o4, pb4), 0.0f, 0.0f};
             if (THETA) {
                 uu[2] = BufIO<float>::ld(rut, o4, 2 * pb4);
                 uu[3] = BufIO<float>::ld(rut, o4, 3 * pb4);
             }
-            finish_a(bb, load_cell_raw_all(pl, o4), uu, ex, ey, gx, gy);
+            finish_a(bb, med.load(o4), uu, ex, ey, gx, gy);
         }
     }
     __syncthreads();
@@ -455,7 +478,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
         const int gx = x0 + q % ATW, gy = y0 + q / ATW;
         if (q >= ATW * ATH || gx >= d.nx || gy >= d.ny) continue;
         const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
-        rawB[k] = load_cell_raw_all(pl, o4);
+        rawB[k] = med.load(o4);
         uB[k][0] = BufIO<float>::ld(rutm, o4, 0u);
         uB[k][1] = BufIO<float>::ld(rutm, o4, pb4);
         uB[k][2] = THETA ? BufIO<float>::ld(rutm, o4, 2 * pb4) : 0.0f;
@@ -488,14 +511,14 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
                 bb[i] = flat[src];
             }
         }
-        const Cell c = cell_of(d, rawB[k]);
+        const Cell c = med.cell(d, rawB[k]);
         float a[8];
         ParamBar pb;
         collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, uB[k][0], uB[k][1], uB[k][2], uB[k][3], a, pb);
 #pragma unroll
         for (int i = 0; i < 8; ++i) BufIO<float>::st(rlout, o4, (uint32_t)i * pb4, a[i]);
         float gp, gk;
-        medium_gradient(d, c, rawB[k].kappa, pb, d.ax, d.ay, gp, gk);
+        medium_gradient<MK>(d, c, rawB[k].kappa, pb, d.ax, d.ay, gp, gk);
         BufIO<float>::st(rg, o4, 0u, (gB[k] + gA[ly][lx]) + gp);
         if (gkappa) BufIO<float>::st(rgk, o4, 0u, (gkB[k] + gkA[ly][lx]) + gk);
         if (THETA) {
@@ -511,12 +534,15 @@ hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_ou
                                 const float *u_tm1, float *gphi, float *gkappa, double *acc, hipStream_t st) {
     const int tiles_x = (d.nx + ATW - 1) / ATW, tiles_y = (d.ny + ATH - 1) / ATH;
     const dim3 grid((unsigned)(tiles_x * tiles_y));
-    if (acc)
-        hipLaunchKernelGGL(k_adjoint_step2<true>, grid, dim3(ANT), 0, st, d, lam_in, lam_out, u_t, u_tm1,
-                           gphi, gkappa, tiles_x, 1, acc);
-    else
-        hipLaunchKernelGGL(k_adjoint_step2<false>, grid, dim3(ANT), 0, st, d, lam_in, lam_out, u_t, u_tm1,
-                           gphi, gkappa, tiles_x, 1, acc);
+    const bool ergun = medium_kind(d) == MK_ERGUN;
+#define MRT_ADJ2(TH, MK) \
+    hipLaunchKernelGGL((k_adjoint_step2<TH, MK>), grid, dim3(ANT), 0, st, d, lam_in, lam_out, u_t, u_tm1, gphi, \
+                       gkappa, tiles_x, 1, acc)
+    if (acc && ergun) MRT_ADJ2(true, MK_ERGUN);
+    else if (acc) MRT_ADJ2(true, MK_ANY);
+    else if (ergun) MRT_ADJ2(false, MK_ERGUN);
+    else MRT_ADJ2(false, MK_ANY);
+#undef MRT_ADJ2
     return hipGetLastError();
 }
 

@@ -122,6 +122,17 @@ __device__ __forceinline__ float ergun_F(float inv_phi) {
     return 0.14288690166235206f * inv_phi * hw_sqrt(inv_phi);
 }
 
+// Eq. (4) substituted into Eq. (3): phi nu / K = (150 nu / dp^2)(1-phi)^2 / phi^2
+// and phi F_phi / sqrt(K) = (1.75 / dp)(1-phi) / phi^2, without square roots.
+__device__ __forceinline__ void ergun_closed(const Dom &d, float phi, Cell &c) {
+    const float ip = hw_rcp(phi);
+    c.phi = phi; c.inv_phi = ip;
+    const float om = 1.0f - phi;
+    const float t = om * (ip * ip);
+    c.cd = (d.cdk * om) * t;
+    c.cf = d.cfk * t;
+}
+
 // Per-cell drag coefficients from the porosity (and 1/K when it has its own
 // plane); kappa is ignored unless the medium is MED_PHI_KAPPA.
 __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_plane) {
@@ -131,17 +142,12 @@ __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_p
         c.phi = d.phi0; c.inv_phi = d.inv_phi0; c.cd = d.cd0; c.cf = d.cf0;
         return c;
     }
-    const float ip = hw_rcp(phi);
-    c.phi = phi; c.inv_phi = ip;
     if (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f) {
-        // Eq. (4) substituted into Eq. (3): phi nu / K = (150 nu / dp^2)(1-phi)^2 / phi^2
-        // and phi F_phi / sqrt(K) = (1.75 / dp)(1-phi) / phi^2, without square roots
-        const float om = 1.0f - phi;
-        const float t = om * (ip * ip);
-        c.cd = (d.cdk * om) * t;
-        c.cf = d.cfk * t;
+        ergun_closed(d, phi, c);
         return c;
     }
+    const float ip = hw_rcp(phi);
+    c.phi = phi; c.inv_phi = ip;
     float kappa;
     if (d.medium == MED_PHI_ERGUN) {
         const float om = 1.0f - phi;
@@ -434,6 +440,39 @@ __device__ __forceinline__ Cell cell_of(const Dom &d, const CellRaw &r) {
     return c;
 }
 
+// Where a kernel gets its per-node medium values, fixed at compile time.
+// MK_ANY: every medium, with an optional per-node s_nu plane (branch-free loads,
+// absent planes read 0). MK_ERGUN: the Ergun medium with the closed-form drag
+// and one s_nu for all nodes; only the porosity plane is read, and the kernel
+// holds fewer scalars (with MK_ANY the other medium parameters and plane
+// resources spill to vector lanes in the three-cycle kernel). Both give the
+// same values for an Ergun medium.
+enum { MK_ANY = 0, MK_ERGUN = 1 };
+
+__host__ __device__ inline int medium_kind(const Dom &d) {
+    return (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f && !d.snu) ? MK_ERGUN : MK_ANY;
+}
+
+template <int MK> struct MediumSrc;
+template <> struct MediumSrc<MK_ANY> {
+    CellPlanes pl;
+    __device__ explicit MediumSrc(const Dom &d) : pl(cell_planes(d)) {}
+    __device__ CellRaw load(uint32_t o4) const { return load_cell_raw_all(pl, o4); }
+    __device__ Cell cell(const Dom &d, const CellRaw &r) const { return cell_of(d, r); }
+};
+template <> struct MediumSrc<MK_ERGUN> {
+    BufRes phi;
+    __device__ explicit MediumSrc(const Dom &d) : phi(buf_res(d.phi, (uint32_t)(d.plane * 4))) {}
+    __device__ CellRaw load(uint32_t o4) const { return CellRaw{BufIO<float>::ld(phi, o4, 0u), 0.0f, 0.0f}; }
+    __device__ Cell cell(const Dom &d, const CellRaw &r) const {
+        Cell c;
+        c.s_nu = d.s_nu;
+        c.h_nu = d.h_nu;
+        ergun_closed(d, r.phi, c);
+        return c;
+    }
+};
+
 // ---- gather (pull streaming, Eq. 15, with boundaries) -----------------
 
 // f_i(x, t) = f_i+(x - e_i, t-1); a link whose source lies beyond a wall is
@@ -461,6 +500,32 @@ __device__ __forceinline__ void gather_general(const Dom &d, const S *__restrict
             if (top) v += (float)EX[i] * d.lid6;
             f[i] = v;
         }
+    }
+}
+
+// gather_general through a buffer resource over the eight planes: one 32-bit
+// offset per link instead of a 64-bit address, so no per-plane base pointers
+// stay live in scalar registers (the state buffer is below 4 GiB).
+template <typename S>
+__device__ __forceinline__ void gather_general_buf(const Dom &d, BufRes rin, int x, int y, float f[8]) {
+    constexpr uint32_t ES = sizeof(S);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        int sx = x - EX[i], sy = y - EY[i];
+        bool out = false, top = false;
+        if (EX[i] != 0 && (sx < 0 || sx >= d.nx)) {
+            if (d.bc_x == BC_PERIODIC) sx = (sx < 0) ? d.nx - 1 : 0;
+            else out = true;
+        }
+        if (EY[i] != 0 && (sy < 0 || sy >= d.ny)) {
+            if (d.bc_y == BC_PERIODIC) sy = (sy < 0) ? d.ny - 1 : 0;
+            else { out = true; top = (sy >= d.ny); }
+        }
+        const uint32_t idx = out ? (uint32_t)(OPP[i] * d.plane + y * d.pitch + x)
+                                 : (uint32_t)(i * d.plane + sy * d.pitch + sx);
+        float v = BufIO<S>::ld(rin, idx * ES, 0u);
+        if (top) v += (float)EX[i] * d.lid6;
+        f[i] = v;
     }
 }
 

@@ -590,7 +590,7 @@ struct Pending {
     }
 };
 
-template <typename S, int TW, int TH, int NT, bool REC>
+template <typename S, int TW, int TH, int NT, bool REC, int MK>
 __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
     constexpr int AW = TW + 4, AH = TH + 4, AN = AW * AH;
     constexpr int BW = TW + 2, BH = TH + 2, BN = BW * BH;
@@ -600,14 +600,12 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
     int b = blockIdx.x;
     if (swz) b = xcd_swizzle(b, gridDim.x);
     const int x0 = (b % tiles_x) * TW, y0 = (b / tiles_x) * TH;
-    const S *__restrict__ fin = (const S *)d.fin;
     const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
     const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
-    const CellPlanes pl = cell_planes(d);
+    const MediumSrc<MK> med(d);
     const bool interior = x0 >= 3 && x0 + TW + 3 <= d.nx && y0 >= 3 && y0 + TH + 3 <= d.ny;
+    // resources of the three recorded steps, each built where its phase starts
     const uint32_t rbytes = REC ? (uint32_t)((d.rec_stress ? 4 : 2) * d.plane * 4) : 0u;
-    const BufRes rr0 = buf_res(REC ? d.urec : nullptr, rbytes), rr1 = buf_res(urec1, rbytes),
-                 rr2 = buf_res(urec2, rbytes);
 
     // CDNA's vector-memory counter retires loads and stores in order, so a wait
     // for a load also waits for every store issued before it. Each phase
@@ -617,6 +615,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
     Pending pend;
 
     // phase A: s_{t+1} on the tile + 2 ring
+    const BufRes rr0 = buf_res(REC ? d.urec : nullptr, rbytes);
     for (int e = threadIdx.x; e < AN; e += NT) {
         const int ex = e % AW, ey = e / AW;
         int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
@@ -628,12 +627,12 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
                 f[i] = BufIO<S>::ld(rin, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
         } else {
             if (!wrap_node(d, gx, gy)) continue;
-            gather_general<S>(d, fin, gx, gy, f);
+            gather_general_buf<S>(d, rin, gx, gy, f);
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const CellRaw raw = load_cell_raw_all(pl, (uint32_t)(o * 4));
+        const CellRaw raw = med.load((uint32_t)(o * 4));
         if (REC) pend.flush(d, rr0);
-        const Cell c = cell_of(d, raw);
+        const Cell c = med.cell(d, raw);
         float ux, uy, n7, n8;
         collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
 #pragma unroll
@@ -645,6 +644,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
     lds_barrier();
 
     // phase B: s_{t+2} on the tile + 1 ring, kept in registers
+    const BufRes rr1 = buf_res(urec1, rbytes);
     float fb[NBB][8];
     int slot[NBB];
 #pragma unroll
@@ -656,10 +656,10 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
         int gx = x0 - 1 + bx, gy = y0 - 1 + by;
         if (!interior && !wrap_node(d, gx, gy)) continue;
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const CellRaw raw = load_cell_raw_all(pl, (uint32_t)(o * 4));
+        const CellRaw raw = med.load((uint32_t)(o * 4));
         if (REC) pend.flush(d, rr1);
         lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fb[k]);
-        const Cell c = cell_of(d, raw);
+        const Cell c = med.cell(d, raw);
         float ux, uy, n7, n8;
         collide(fb[k], d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
         if (REC && bx >= 1 && bx <= TW && by >= 1 && by <= TH && x0 - 1 + bx < d.nx && y0 - 1 + by < d.ny)
@@ -678,6 +678,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
     lds_barrier();
 
     // phase C: s_{t+3} on the tile, to HBM
+    const BufRes rr2 = buf_res(urec2, rbytes);
     constexpr int NC = (TW * TH + NT - 1) / NT;
     CellRaw rawC[NC];
 #pragma unroll
@@ -685,7 +686,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
         const int q = threadIdx.x + k * NT;
         const int gx = x0 + q % TW, gy = y0 + q / TW;
         if (q < TW * TH && gx < d.nx && gy < d.ny)
-            rawC[k] = load_cell_raw_all(pl, (uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
+            rawC[k] = med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
     }
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
@@ -696,7 +697,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
         float f[8];
         lds_gather<BW, BH>(d, lds, interior, gx, gy, lx + 1, ly + 1, f);
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = cell_of(d, rawC[k]);
+        const Cell c = med.cell(d, rawC[k]);
         float ux, uy, n7, n8;
         collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
         const uint32_t vo = (uint32_t)(o * ES);
@@ -713,16 +714,21 @@ void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y) {
     *tiles_y = (ny + STEP3_TH - 1) / STEP3_TH;
 }
 
-const void *step3_kernel_fn(int storage, bool rec) {
-    if (rec) return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, true> : nullptr;
-    return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, false>
-                             : (const void *)&k_step3<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, false>;
+template <int MK>
+static const void *step3_fn_t(int storage, bool rec) {
+    if (rec) return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, true, MK> : nullptr;
+    return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, false, MK>
+                             : (const void *)&k_step3<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, false, MK>;
+}
+
+const void *step3_kernel_fn(const Dom &d, int storage, bool rec) {
+    return medium_kind(d) == MK_ERGUN ? step3_fn_t<MK_ERGUN>(storage, rec) : step3_fn_t<MK_ANY>(storage, rec);
 }
 
 hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, float *urec2, hipStream_t st) {
     if (d.thermal) return hipErrorInvalidValue;
     const bool rec = urec1 != nullptr;
-    const void *fn = step3_kernel_fn(storage, rec);
+    const void *fn = step3_kernel_fn(d, storage, rec);
     if (!fn || (rec && (!d.urec || !urec2))) return hipErrorInvalidValue;
     int tx, ty;
     step3_tiles(d.nx, d.ny, &tx, &ty);
