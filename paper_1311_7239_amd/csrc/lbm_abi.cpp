@@ -418,7 +418,7 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
             Domain &D = c->dom[0];
             d = dom_for(D, p);
             step2_tiles(D.desc.nx, D.desc.ny, c->tb_rows, &tx, &ty);
-            kp.func = (void *)step2_kernel_fn(D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, c->tb_threads,
+            kp.func = (void *)step2_kernel_fn(D.dom, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, c->tb_threads,
                                               c->tb_rows, false);
             kp.gridDim = dim3((unsigned)(tx * ty));
             kp.blockDim = dim3((unsigned)c->tb_threads);

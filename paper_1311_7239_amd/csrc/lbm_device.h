@@ -447,7 +447,9 @@ __device__ __forceinline__ Cell cell_of(const Dom &d, const CellRaw &r) {
 // holds fewer scalars (with MK_ANY the other medium parameters and plane
 // resources spill to vector lanes in the three-cycle kernel). Both give the
 // same values for an Ergun medium.
-enum { MK_ANY = 0, MK_ERGUN = 1 };
+// MK_BRANCHED: every medium with the loads of load_cell_raw (branches; uniform
+// media load nothing), which the one- and two-cycle kernels measured faster.
+enum { MK_ANY = 0, MK_ERGUN = 1, MK_BRANCHED = 2 };
 
 __host__ __device__ inline int medium_kind(const Dom &d) {
     return (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f && !d.snu) ? MK_ERGUN : MK_ANY;
@@ -458,6 +460,20 @@ template <> struct MediumSrc<MK_ANY> {
     CellPlanes pl;
     __device__ explicit MediumSrc(const Dom &d) : pl(cell_planes(d)) {}
     __device__ CellRaw load(uint32_t o4) const { return load_cell_raw_all(pl, o4); }
+    __device__ Cell cell(const Dom &d, const CellRaw &r) const { return cell_of(d, r); }
+};
+template <> struct MediumSrc<MK_BRANCHED> {
+    CellPlanes pl;
+    int32_t medium;
+    bool snu;
+    __device__ explicit MediumSrc(const Dom &d) : pl(cell_planes(d)), medium(d.medium), snu(d.snu != nullptr) {}
+    __device__ CellRaw load(uint32_t o4) const {
+        CellRaw r{0.0f, 0.0f, 0.0f};
+        if (medium != MED_UNIFORM) r.phi = BufIO<float>::ld(pl.phi, o4, 0u);
+        if (medium == MED_PHI_KAPPA) r.kappa = BufIO<float>::ld(pl.kappa, o4, 0u);
+        if (snu) r.snu = BufIO<float>::ld(pl.snu, o4, 0u);
+        return r;
+    }
     __device__ Cell cell(const Dom &d, const CellRaw &r) const { return cell_of(d, r); }
 };
 template <> struct MediumSrc<MK_ERGUN> {

@@ -323,17 +323,44 @@ __device__ __forceinline__ void tile_item(int item, int &cx, int &cy) {
 // the same per-node code as the one-step kernel, and FP16 storage rounds the
 // intermediate state exactly as a store/reload would, so the result is
 // bitwise that of two one-step launches.
-template <typename S, int TW, int TH, int NT, bool REC>
+// The records go through buffer stores: a recorded step spans at most five
+// planes, below 4 GiB whenever multi-cycle passes run.
+__device__ __forceinline__ void record_node(const Dom &d, BufRes rec, uint32_t o4, float ux, float uy, float n7,
+                                            float n8) {
+    const uint32_t pb4 = (uint32_t)(d.plane * 4);
+    BufIO<float>::st(rec, o4, 0u, ux);
+    BufIO<float>::st(rec, o4, pb4, uy);
+    if (d.rec_stress) {
+        BufIO<float>::st(rec, o4, 2 * pb4, n7);
+        BufIO<float>::st(rec, o4, 3 * pb4, n8);
+    }
+}
+
+// One node's record held back until the next node's loads have been issued.
+struct Pending {
+    uint32_t o4 = 0u;
+    float ux = 0.0f, uy = 0.0f, n7 = 0.0f, n8 = 0.0f;
+    bool on = false;
+    __device__ __forceinline__ void hold(uint32_t o, float a, float b, float c, float e) {
+        o4 = o; ux = a; uy = b; n7 = c; n8 = e; on = true;
+    }
+    __device__ __forceinline__ void flush(const Dom &d, BufRes rec) {
+        if (on) record_node(d, rec, o4, ux, uy, n7, n8);
+        on = false;
+    }
+};
+
+template <typename S, int TW, int TH, int NT, bool REC, int MK>
 __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *urec_next,
                                            float (&lds)[8][TH + 2][TW + 2]) {
     constexpr int EW = TW + 2, EH = TH + 2, EN = EW * EH;
     constexpr int ES = (int)sizeof(S);
-    const S *__restrict__ fin = (const S *)d.fin;
     // the state buffers are below 4 GiB (the host keeps larger domains on the
     // one-cycle kernel), so every byte offset fits the buffer instructions
     const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
     const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
-    const CellPlanes pl = cell_planes(d);
+    const uint32_t rbytes = REC ? (uint32_t)((d.rec_stress ? 4 : 2) * d.plane * 4) : 0u;
+    const MediumSrc<MK> med(d);
     // every source of phase A inside the domain, no wrap needed
     const bool interior = x0 >= 2 && x0 + TW + 2 <= d.nx && y0 >= 2 && y0 + TH + 2 <= d.ny;
 
@@ -347,7 +374,7 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
         const int gx = x0 + q % TW, gy = y0 + q / TW;
         rawB[k] = CellRaw{0.0f, 0.0f, 0.0f};
         if (q < TW * TH && gx < d.nx && gy < d.ny)
-            rawB[k] = load_cell_raw(d, pl, (uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
+            rawB[k] = med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
     }
 
     // phase A: s_{t+1} on the extended tile (and u(t) on the tile when recording)
@@ -357,14 +384,8 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[i][ey][ex] = (float)(S)f[i];
         if (REC && ex >= 1 && ex <= TW && ey >= 1 && ey <= TH && x0 - 1 + ex < d.nx &&
-            y0 - 1 + ey < d.ny) {
-            d.urec[o] = ux;
-            d.urec[d.plane + o] = uy;
-            if (d.rec_stress) {
-                d.urec[2 * d.plane + o] = n7;
-                d.urec[3 * d.plane + o] = n8;
-            }
-        }
+            y0 - 1 + ey < d.ny)
+            record_node(d, buf_res(d.urec, rbytes), (uint32_t)(o * 4), ux, uy, n7, n8);
     };
     if (interior) {
         // link i pulls from (gx - e_ix, gy - e_iy): the lane's offset of (gx - 1, gy - 1)
@@ -378,7 +399,7 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 f[i] = BufIO<S>::ld(rin, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
-            r = load_cell_raw(d, pl, (uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
+            r = med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
         };
         float fn[8];
         CellRaw rn{0.0f, 0.0f, 0.0f};
@@ -392,7 +413,7 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
             int ex, ey;
             tile_item<TW, EH, 1>(e, ex, ey);
             const int64_t o = (int64_t)(y0 - 1 + ey) * d.pitch + (x0 - 1 + ex);
-            finish_a(f, cell_of(d, r), ex, ey, o);
+            finish_a(f, med.cell(d, r), ex, ey, o);
         }
     } else {
         for (int e = threadIdx.x; e < EN; e += NT) {
@@ -408,9 +429,9 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
                 gy = ((gy % d.ny) + d.ny) % d.ny;
             }
             float f[8];
-            gather_general<S>(d, fin, gx, gy, f);
+            gather_general_buf<S>(d, rin, gx, gy, f);
             const int64_t o = (int64_t)gy * d.pitch + gx;
-            finish_a(f, cell_of(d, load_cell_raw(d, pl, (uint32_t)(o * 4))), ex, ey, o);
+            finish_a(f, med.cell(d, med.load((uint32_t)(o * 4))), ex, ey, o);
         }
     }
     lds_barrier();
@@ -450,30 +471,23 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
             }
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = cell_of(d, rawB[k]);
+        const Cell c = med.cell(d, rawB[k]);
         float ux, uy, n7, n8;
         collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
         const uint32_t vo = (uint32_t)(o * ES);
 #pragma unroll
         for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
-        if (REC) {
-            urec_next[o] = ux;
-            urec_next[d.plane + o] = uy;
-            if (d.rec_stress) {
-                urec_next[2 * d.plane + o] = n7;
-                urec_next[3 * d.plane + o] = n8;
-            }
-        }
+        if (REC) record_node(d, buf_res(urec_next, rbytes), (uint32_t)(o * 4), ux, uy, n7, n8);
     }
 }
 
 
-template <typename S, int TW, int TH, int NT, bool REC>
+template <typename S, int TW, int TH, int NT, bool REC, int MK>
 __global__ __launch_bounds__(NT) void k_step2(Dom d, int tiles_x, int swz, float *urec_next) {
     __shared__ float lds[8][TH + 2][TW + 2];
     int b = blockIdx.x;
     if (swz) b = xcd_swizzle(b, gridDim.x);
-    step2_tile<S, TW, TH, NT, REC>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec_next, lds);
+    step2_tile<S, TW, TH, NT, REC, MK>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec_next, lds);
 }
 
 // Persistent batched two-cycle pass over a table of 64 x TH tiles.
@@ -488,7 +502,7 @@ __global__ __launch_bounds__(NT) void k_step2_batch(const Dom *__restrict__ doms
     for (int t = t0; t < t1; ++t) {
         const int4 tl = tiles[t];
         const Dom d = doms[2 * tl.x + parity];
-        step2_tile<S, TW, TH, NT, false>(d, tl.y * TW, tl.z * TH, nullptr, lds);
+        step2_tile<S, TW, TH, NT, false, MK_BRANCHED>(d, tl.y * TW, tl.z * TH, nullptr, lds);
         lds_barrier();   // the next tile's phase A rewrites the LDS
     }
 }
@@ -563,33 +577,6 @@ __device__ __forceinline__ bool wrap_node(const Dom &d, int &gx, int &gy) {
 // With REC (FP32 recomputation for the adjoint) u and, with rec_stress, the
 // stress moments of the tile nodes are recorded at t (d.urec), t + 1 (urec1)
 // and t + 2 (urec2).
-// The records go through buffer stores: a recorded step spans at most five
-// planes, below 4 GiB whenever multi-cycle passes run.
-__device__ __forceinline__ void record_node(const Dom &d, BufRes rec, uint32_t o4, float ux, float uy, float n7,
-                                            float n8) {
-    const uint32_t pb4 = (uint32_t)(d.plane * 4);
-    BufIO<float>::st(rec, o4, 0u, ux);
-    BufIO<float>::st(rec, o4, pb4, uy);
-    if (d.rec_stress) {
-        BufIO<float>::st(rec, o4, 2 * pb4, n7);
-        BufIO<float>::st(rec, o4, 3 * pb4, n8);
-    }
-}
-
-// One node's record held back until the next node's loads have been issued.
-struct Pending {
-    uint32_t o4 = 0u;
-    float ux = 0.0f, uy = 0.0f, n7 = 0.0f, n8 = 0.0f;
-    bool on = false;
-    __device__ __forceinline__ void hold(uint32_t o, float a, float b, float c, float e) {
-        o4 = o; ux = a; uy = b; n7 = c; n8 = e; on = true;
-    }
-    __device__ __forceinline__ void flush(const Dom &d, BufRes rec) {
-        if (on) record_node(d, rec, o4, ux, uy, n7, n8);
-        on = false;
-    }
-};
-
 template <typename S, int TW, int TH, int NT, bool REC, int MK>
 __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
     constexpr int AW = TW + 4, AH = TH + 4, AN = AW * AH;
@@ -738,9 +725,9 @@ hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, fl
     return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3(STEP3_NT), args, 0, st);
 }
 
-template <typename S, bool REC>
+template <typename S, bool REC, int MK>
 static const void *step2_fn_t(int threads, int rows) {
-#define MRT_S2FN(N, H) if (threads == N && rows == H) return (const void *)&k_step2<S, STEP2_TW, H, N, REC>;
+#define MRT_S2FN(N, H) if (threads == N && rows == H) return (const void *)&k_step2<S, STEP2_TW, H, N, REC, MK>;
     MRT_STEP2_SHAPES(MRT_S2FN)
 #undef MRT_S2FN
     return nullptr;
@@ -766,16 +753,23 @@ hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, in
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)threads), args, 0, st);
 }
 
-const void *step2_kernel_fn(int storage, int threads, int rows, bool rec) {
-    if (storage == ST_F32) return rec ? step2_fn_t<float, true>(threads, rows) : step2_fn_t<float, false>(threads, rows);
-    return rec ? nullptr : step2_fn_t<_Float16, false>(threads, rows);
+template <int MK>
+static const void *step2_fn_mk(int storage, int threads, int rows, bool rec) {
+    if (storage == ST_F32)
+        return rec ? step2_fn_t<float, true, MK>(threads, rows) : step2_fn_t<float, false, MK>(threads, rows);
+    return rec ? nullptr : step2_fn_t<_Float16, false, MK>(threads, rows);
+}
+
+const void *step2_kernel_fn(const Dom &d, int storage, int threads, int rows, bool rec) {
+    return medium_kind(d) == MK_ERGUN ? step2_fn_mk<MK_ERGUN>(storage, threads, rows, rec)
+                                      : step2_fn_mk<MK_BRANCHED>(storage, threads, rows, rec);
 }
 
 hipError_t launch_step2(const Dom &d, int storage, int swizzle, int threads, int rows,
                         float *urec_next, hipStream_t st) {
     if (d.thermal) return hipErrorInvalidValue;
     const bool rec = urec_next != nullptr;
-    const void *fn = step2_kernel_fn(storage, threads, rows, rec);
+    const void *fn = step2_kernel_fn(d, storage, threads, rows, rec);
     if (!fn || (rec && !d.urec)) return hipErrorInvalidValue;
     int tx, ty;
     step2_tiles(d.nx, d.ny, rows, &tx, &ty);

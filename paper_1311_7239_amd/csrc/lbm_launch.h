@@ -41,7 +41,7 @@ hipError_t launch_step2(const Dom &d, int storage, int swizzle, int threads, int
                         float *urec_next, hipStream_t st);
 bool step2_shape_supported(int threads, int rows);
 void step2_tiles(int nx, int ny, int rows, int *tiles_x, int *tiles_y);
-const void *step2_kernel_fn(int storage, int threads, int rows, bool rec);
+const void *step2_kernel_fn(const Dom &d, int storage, int threads, int rows, bool rec);
 // Three collide-stream cycles in one HBM pass (64 x 16 tiles, 512 threads;
 // kernel arguments (Dom, int tiles_x, int swizzle, float *urec1, float *urec2)).
 // With urec1/urec2 (FP32 only) the pass records at t (d.urec), t + 1, t + 2.
