@@ -267,7 +267,7 @@ int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows,
  * autotuned). */
 int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int32_t swizzle);
 
-/* Cycles per HBM pass of an isothermal context with bounce-back walls: 1,
+/* Cycles per HBM pass of a context with bounce-back walls: 1,
  * 2 (temporal blocking: one launch gathers, collides on its tile plus a
  * one-node ring kept in LDS, then collides again, so each population crosses
  * HBM about once per two cycles) or 3 (a two-node ring, three collisions per
@@ -277,11 +277,13 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * while recording for lbm_backward no pass steps over a checkpoint time.
  * Shorter passes fill in where fewer cycles remain. The recomputation inside
  * lbm_backward uses passes of the same length (recording u at every cycle)
- * and its adjoint sweep two steps per pass in modes 2 and 3. Default for
- * single domains of at least 2^20 nodes that allow it: 3 (FP32) or 2 (FP16),
- * else 1; for batches, the autotuner's choice. ENOTSUP for thermal domains, on-node
- * walls, population buffers of 4 GiB or more, and mode 3 on batches; EINVAL
- * for another value. */
+ * and its adjoint sweep two steps per pass in modes 2 and 3; for thermal
+ * runs both stay one cycle per pass. Default for
+ * single domains of at least 2^20 nodes that allow it: 3 (isothermal FP32) or 2
+ * (FP16, and thermal domains, whose D2Q5 field is kept in LDS beside the
+ * populations), else 1; for batches, the autotuner's choice. ENOTSUP for on-node
+ * walls, population or thermal buffers of 4 GiB or more, mode 3 on thermal
+ * domains and on batches; EINVAL for another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
 
 /* Current cycles per pass and the two-cycle kernel's workgroup size, tile

@@ -258,13 +258,23 @@ bool any_on_node_walls(const lbm_ctx *c) {
     return false;
 }
 
-// The two-cycle kernels address a state buffer with 32-bit byte offsets.
-bool buffer_below_4gib(const Layout &L) { return L.f_bytes < ((size_t)1 << 32); }
+// The multi-cycle kernels address a state buffer (and a thermal buffer) with
+// 32-bit byte offsets.
+bool buffer_below_4gib(const Layout &L) {
+    return L.f_bytes < ((size_t)1 << 32) && L.g_bytes < ((size_t)1 << 32);
+}
 
+// Two cycles per pass: halfway walls, buffers below 4 GiB, with or without the
+// D2Q5 field.
 bool two_cycle_possible(const lbm_ctx *c) {
     for (const Domain &D : c->dom)
-        if (D.desc.thermal.enabled || on_node_walls(D.desc) || !buffer_below_4gib(D.L)) return false;
+        if (on_node_walls(D.desc) || !buffer_below_4gib(D.L)) return false;
     return true;
+}
+
+// Three cycles per pass: single isothermal domains only.
+bool three_cycle_possible(const lbm_ctx *c) {
+    return !c->batch && two_cycle_possible(c) && !c->dom[0].desc.thermal.enabled;
 }
 
 int device_fail(lbm_ctx *c, hipError_t e, const char *what) {
@@ -398,7 +408,7 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         void *args_s3[5] = {&d, &tx, &swz, &no_rec, &no_rec};
         void *args_b2[4] = {&c->d_doms, &c->d_tiles2, &c->ntiles2, &p};
         if (c->batch && c->tblock == 2) {
-            kp.func = (void *)step2_batch_kernel_fn(c->storage, c->tb_threads, c->tb_rows);
+            kp.func = (void *)step2_batch_kernel_fn(c->storage, c->batch_thermal, c->tb_threads, c->tb_rows);
             kp.gridDim = dim3((unsigned)c->grid2);
             kp.blockDim = dim3((unsigned)c->tb_threads);
             kp.kernelParams = args_b2;
@@ -511,9 +521,9 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     c->rec_cap = cap;
     // several cycles per pass pay once the domain fills the GPU a few times over
     // (measured from 1024^2 up; the multi-cycle kernels implement bounce-back
-    // walls only); FP32 takes three, FP16 two (its third cycle is compute-bound)
+    // walls only); isothermal FP32 takes three, FP16 and thermal domains two
     if (two_cycle_possible(c) && (int64_t)d->nx * d->ny >= ((int64_t)1 << 20))
-        c->tblock = d->storage == LBM_FP16_DEV ? 2 : 3;
+        c->tblock = (d->storage == LBM_FP16_DEV || !three_cycle_possible(c)) ? 2 : 3;
     else
         c->tblock = 1;
     if (d->storage == LBM_FP16_DEV) c->sched = Schedule{64, 2, 2, 1};
@@ -558,7 +568,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         // this call (so the previous buffer always holds f+(t-2) -> u(t-1) for the residual);
         // when recording, a pass never steps over a checkpoint time (the checkpoint
         // needs the state there)
-        const bool fused = c->tblock >= 2 && !c->dom[0].desc.thermal.enabled;
+        const bool fused = c->tblock >= 2;
         const int64_t next_ck = recording ? (c->t / c->dom[0].desc.ckpt_every + 1) * c->dom[0].desc.ckpt_every
                                           : INT64_MAX;
         const int64_t gcyc = graph_cycles(c);
@@ -588,7 +598,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         if (fused && n >= 3 && c->t + 2 <= next_ck) {
             Domain &D = c->dom[0];
             if (c->batch)
-                e = launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->tb_threads,
+                e = launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_thermal, c->tb_threads,
                                        c->tb_rows, c->grid2, c->stream);
             else
                 e = launch_step2(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
@@ -852,12 +862,14 @@ int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
     if (rc) return rc;
     if (cycles_per_pass < 1 || cycles_per_pass > 3) return fail(LBM_EINVAL, "cycles per pass must be 1, 2 or 3");
     if (cycles_per_pass == 3 && c->batch) return fail(LBM_ENOTSUP, "batches advance one or two cycles per pass");
-    if (cycles_per_pass >= 2 && c->dom[0].desc.thermal.enabled)
-        return fail(LBM_ENOTSUP, "thermal domains advance one cycle per pass");
+    if (cycles_per_pass == 3 && c->dom[0].desc.thermal.enabled)
+        return fail(LBM_ENOTSUP, "thermal domains advance one or two cycles per pass");
     if (cycles_per_pass >= 2 && any_on_node_walls(c))
         return fail(LBM_ENOTSUP, "on-node (extrapolated) walls advance one cycle per pass");
     if (cycles_per_pass >= 2 && !two_cycle_possible(c))
         return fail(LBM_ENOTSUP, "a population buffer of 4 GiB or more advances one cycle per pass");
+    if (cycles_per_pass == 2 && c->batch && c->grid2 <= 0)
+        return fail(LBM_ENOTSUP, "this batch has no tuned two-cycle schedule");
     c->tblock = cycles_per_pass;
     reset_graphs(c);
     return LBM_OK;
@@ -1123,7 +1135,7 @@ hipError_t autotune(lbm_ctx *c, Tuned &best) {
         for (int g : grids) {
             if (g > c->ntiles2) g = c->ntiles2;
             float ms = 0.0f;
-            e = time_it([&] { return launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, 0, c->storage, sh[0],
+            e = time_it([&] { return launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, 0, c->storage, c->batch_thermal, sh[0],
                                                         sh[1], g, c->stream); }, ms);
             if (e != hipSuccess) break;
             if (0.5f * ms < best2) {
@@ -1288,8 +1300,9 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
                     // three cycles in one pass, recording at t, t + 1 and t + 2
                     e = launch_step3(dr, ST_F32, c->sched.swizzle, dr.urec + rstride, dr.urec + 2 * rstride, st);
                     t += 3;
-                } else if (c->tblock >= 2 && t > 0 && t + 1 < s1) {
-                    // two cycles in one pass, recording at t and t + 1
+                } else if (c->tblock >= 2 && !th && t > 0 && t + 1 < s1) {
+                    // two cycles in one pass, recording at t and t + 1 (a thermal
+                    // recomputation also records dT and stays one cycle per pass)
                     e = launch_step2(dr, ST_F32, c->sched.swizzle, c->tb_threads, c->tb_rows, dr.urec + rstride, st);
                     t += 2;
                 } else {

@@ -449,10 +449,16 @@ __device__ __forceinline__ Cell cell_of(const Dom &d, const CellRaw &r) {
 // same values for an Ergun medium.
 // MK_BRANCHED: every medium with the loads of load_cell_raw (branches; uniform
 // media load nothing), which the one- and two-cycle kernels measured faster.
-enum { MK_ANY = 0, MK_ERGUN = 1, MK_BRANCHED = 2 };
+// MK_UNIFORM: a uniform medium and one s_nu; nothing is loaded.
+enum { MK_ANY = 0, MK_ERGUN = 1, MK_BRANCHED = 2, MK_UNIFORM = 3 };
 
+// The specialised kind a domain allows (MK_ANY when none applies); kernels
+// without an instantiation for it use their generic kind.
 __host__ __device__ inline int medium_kind(const Dom &d) {
-    return (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f && !d.snu) ? MK_ERGUN : MK_ANY;
+    if (d.snu) return MK_ANY;
+    if (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f) return MK_ERGUN;
+    if (d.medium == MED_UNIFORM) return MK_UNIFORM;
+    return MK_ANY;
 }
 
 template <int MK> struct MediumSrc;
@@ -475,6 +481,11 @@ template <> struct MediumSrc<MK_BRANCHED> {
         return r;
     }
     __device__ Cell cell(const Dom &d, const CellRaw &r) const { return cell_of(d, r); }
+};
+template <> struct MediumSrc<MK_UNIFORM> {
+    __device__ explicit MediumSrc(const Dom &) {}
+    __device__ CellRaw load(uint32_t) const { return CellRaw{0.0f, 0.0f, 0.0f}; }
+    __device__ Cell cell(const Dom &d, const CellRaw &) const { return cell_from(d, 0.0f, 0.0f); }
 };
 template <> struct MediumSrc<MK_ERGUN> {
     BufRes phi;
@@ -581,6 +592,30 @@ __device__ __forceinline__ void gather_thermal(const Dom &d, const float *__rest
             const float v = gin[TOPP[j] * d.plane + o];
             g[j] = (kind == 1) ? v : ((kind == 2) ? d.abbh - v : d.abbc - v);
         }
+    }
+}
+
+// gather_thermal's edge form through a buffer resource over the five planes
+// (below 4 GiB).
+__device__ __forceinline__ void gather_thermal_buf(const Dom &d, BufRes rg, int x, int y, float g[5]) {
+    const uint32_t o = (uint32_t)(y * d.pitch + x);
+    g[0] = BufIO<float>::ld(rg, o * 4u, 0u);
+#pragma unroll
+    for (int j = 1; j < 5; ++j) {
+        int sx = x - TXv[j], sy = y - TYv[j];
+        int kind = 0;  // 0 stream, 1 bounce-back, 2 hot ABB, 3 cold ABB
+        if (TXv[j] != 0 && (sx < 0 || sx >= d.nx)) {
+            if (d.bc_x == BC_PERIODIC) sx = (sx < 0) ? d.nx - 1 : 0;
+            else kind = (sx < 0) ? 2 : 3;
+        }
+        if (TYv[j] != 0 && (sy < 0 || sy >= d.ny)) {
+            if (d.bc_y == BC_PERIODIC) sy = (sy < 0) ? d.ny - 1 : 0;
+            else kind = 1;
+        }
+        const uint32_t idx = kind == 0 ? (uint32_t)(j * d.plane + sy * d.pitch + sx)
+                                       : (uint32_t)(TOPP[j] * d.plane) + o;
+        const float v = BufIO<float>::ld(rg, idx * 4u, 0u);
+        g[j] = (kind <= 1) ? v : ((kind == 2) ? d.abbh - v : d.abbc - v);
     }
 }
 

@@ -350,9 +350,10 @@ struct Pending {
     }
 };
 
-template <typename S, int TW, int TH, int NT, bool REC, int MK>
+template <typename S, int TW, int TH, int NT, bool REC, int MK, bool THERMAL>
 __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *urec_next,
-                                           float (&lds)[8][TH + 2][TW + 2]) {
+                                           float (&lds)[8][TH + 2][TW + 2], float *ldsg) {
+    static_assert(!(REC && THERMAL), "the recomputation of thermal runs is one cycle per pass");
     constexpr int EW = TW + 2, EH = TH + 2, EN = EW * EH;
     constexpr int ES = (int)sizeof(S);
     // the state buffers are below 4 GiB (the host keeps larger domains on the
@@ -360,6 +361,9 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
     const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
     const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
     const uint32_t rbytes = REC ? (uint32_t)((d.rec_stress ? 4 : 2) * d.plane * 4) : 0u;
+    // D2Q5 buffers (FP32, five planes, also below 4 GiB)
+    const uint32_t gbytes = THERMAL ? (uint32_t)(5 * d.plane * 4) : 0u;
+    const BufRes rgin = buf_res(THERMAL ? d.gin : nullptr, gbytes), rgout = buf_res(THERMAL ? d.gout : nullptr, gbytes);
     const MediumSrc<MK> med(d);
     // every source of phase A inside the domain, no wrap needed
     const bool interior = x0 >= 2 && x0 + TW + 2 <= d.nx && y0 >= 2 && y0 + TH + 2 <= d.ny;
@@ -378,11 +382,15 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
     }
 
     // phase A: s_{t+1} on the extended tile (and u(t) on the tile when recording)
-    auto finish_a = [&](float (&f)[8], const Cell &c, int ex, int ey, int64_t o) {
-        float ux, uy, n7, n8;
-        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
+    auto finish_a = [&](float (&f)[8], float (&g)[5], const Cell &c, int ex, int ey, int64_t o) {
+        float ux, uy, n7, n8, dT;
+        node_update<THERMAL>(d, c, f, g, ux, uy, n7, n8, dT);
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[i][ey][ex] = (float)(S)f[i];
+        if (THERMAL) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) ldsg[(j * EH + ey) * EW + ex] = g[j];
+        }
         if (REC && ex >= 1 && ex <= TW && ey >= 1 && ey <= TH && x0 - 1 + ex < d.nx &&
             y0 - 1 + ey < d.ny)
             record_node(d, buf_res(d.urec, rbytes), (uint32_t)(o * 4), ux, uy, n7, n8);
@@ -391,7 +399,7 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
         // link i pulls from (gx - e_ix, gy - e_iy): the lane's offset of (gx - 1, gy - 1)
         // plus a uniform, non-negative per-link offset. Software pipelined: the next
         // node's loads are issued before this node collides.
-        auto fetch = [&](int e, float (&f)[8], CellRaw &r) {
+        auto fetch = [&](int e, float (&f)[8], float (&g)[5], CellRaw &r) {
             int ex, ey;
             tile_item<TW, EH, 1>(e, ex, ey);
             const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
@@ -399,21 +407,29 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 f[i] = BufIO<S>::ld(rin, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
+            if (THERMAL) {
+                const uint32_t vg = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * 4);
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                    g[j] = BufIO<float>::ld(rgin, vg, (uint32_t)((j * d.plane + (1 - TYv[j]) * d.pitch + (1 - TXv[j])) * 4));
+            }
             r = med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
         };
-        float fn[8];
+        float fn[8], gn[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         CellRaw rn{0.0f, 0.0f, 0.0f};
-        if ((int)threadIdx.x < EN) fetch(threadIdx.x, fn, rn);
+        if ((int)threadIdx.x < EN) fetch(threadIdx.x, fn, gn, rn);
         for (int e = threadIdx.x; e < EN; e += NT) {
-            float f[8];
+            float f[8], g[5];
 #pragma unroll
             for (int i = 0; i < 8; ++i) f[i] = fn[i];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) g[j] = gn[j];
             const CellRaw r = rn;
-            if (e + NT < EN) fetch(e + NT, fn, rn);
+            if (e + NT < EN) fetch(e + NT, fn, gn, rn);
             int ex, ey;
             tile_item<TW, EH, 1>(e, ex, ey);
             const int64_t o = (int64_t)(y0 - 1 + ey) * d.pitch + (x0 - 1 + ex);
-            finish_a(f, med.cell(d, r), ex, ey, o);
+            finish_a(f, g, med.cell(d, r), ex, ey, o);
         }
     } else {
         for (int e = threadIdx.x; e < EN; e += NT) {
@@ -428,10 +444,11 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
                 if (d.bc_y != BC_PERIODIC) continue;
                 gy = ((gy % d.ny) + d.ny) % d.ny;
             }
-            float f[8];
+            float f[8], g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             gather_general_buf<S>(d, rin, gx, gy, f);
+            if (THERMAL) gather_thermal_buf(d, rgin, gx, gy, g);
             const int64_t o = (int64_t)gy * d.pitch + gx;
-            finish_a(f, med.cell(d, med.load((uint32_t)(o * 4))), ex, ey, o);
+            finish_a(f, g, med.cell(d, med.load((uint32_t)(o * 4))), ex, ey, o);
         }
     }
     lds_barrier();
@@ -470,39 +487,65 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
                 f[i] = top ? v + (float)EX[i] * d.lid6 : v;
             }
         }
+        float g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (THERMAL) {
+            // the D2Q5 links: the neighbour's value, or across a wall the node's own
+            // opposite value (bounce-back on y walls, anti-bounce-back on x walls),
+            // again as one read at a selected index
+            g[0] = ldsg[(ly + 1) * EW + lx + 1];
+#pragma unroll
+            for (int j = 1; j < 5; ++j) {
+                int kind = 0;
+                if (!interior) {
+                    const int sx = gx - TXv[j], sy = gy - TYv[j];
+                    if (TXv[j] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) kind = (sx < 0) ? 2 : 3;
+                    if (TYv[j] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) kind = 1;
+                }
+                const int src = kind == 0 ? (j * EH + ly + 1 - TYv[j]) * EW + lx + 1 - TXv[j]
+                                          : (TOPP[j] * EH + ly + 1) * EW + lx + 1;
+                const float v = ldsg[src];
+                g[j] = (kind <= 1) ? v : ((kind == 2) ? d.abbh - v : d.abbc - v);
+            }
+        }
         const int64_t o = (int64_t)gy * d.pitch + gx;
         const Cell c = med.cell(d, rawB[k]);
-        float ux, uy, n7, n8;
-        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
+        float ux, uy, n7, n8, dT;
+        node_update<THERMAL>(d, c, f, g, ux, uy, n7, n8, dT);
         const uint32_t vo = (uint32_t)(o * ES);
 #pragma unroll
         for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+        if (THERMAL) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) BufIO<float>::st(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
+        }
         if (REC) record_node(d, buf_res(urec_next, rbytes), (uint32_t)(o * 4), ux, uy, n7, n8);
     }
 }
 
 
-template <typename S, int TW, int TH, int NT, bool REC, int MK>
+template <typename S, int TW, int TH, int NT, bool REC, int MK, bool THERMAL>
 __global__ __launch_bounds__(NT) void k_step2(Dom d, int tiles_x, int swz, float *urec_next) {
     __shared__ float lds[8][TH + 2][TW + 2];
+    __shared__ float ldsg[THERMAL ? 5 * (TH + 2) * (TW + 2) : 1];
     int b = blockIdx.x;
     if (swz) b = xcd_swizzle(b, gridDim.x);
-    step2_tile<S, TW, TH, NT, REC, MK>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec_next, lds);
+    step2_tile<S, TW, TH, NT, REC, MK, THERMAL>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec_next, lds, ldsg);
 }
 
 // Persistent batched two-cycle pass over a table of 64 x TH tiles.
-template <typename S, int TW, int TH, int NT>
+template <typename S, int TW, int TH, int NT, bool THERMAL>
 __global__ __launch_bounds__(NT) void k_step2_batch(const Dom *__restrict__ doms,
                                                     const int4 *__restrict__ tiles, int ntiles,
                                                     int parity) {
     __shared__ float lds[8][TH + 2][TW + 2];
+    __shared__ float ldsg[THERMAL ? 5 * (TH + 2) * (TW + 2) : 1];
     const int64_t nb = gridDim.x;
     const int t0 = (int)((int64_t)blockIdx.x * ntiles / nb);
     const int t1 = (int)(((int64_t)blockIdx.x + 1) * ntiles / nb);
     for (int t = t0; t < t1; ++t) {
         const int4 tl = tiles[t];
         const Dom d = doms[2 * tl.x + parity];
-        step2_tile<S, TW, TH, NT, false, MK_BRANCHED>(d, tl.y * TW, tl.z * TH, nullptr, lds);
+        step2_tile<S, TW, TH, NT, false, MK_BRANCHED, THERMAL>(d, tl.y * TW, tl.z * TH, nullptr, lds, ldsg);
         lds_barrier();   // the next tile's phase A rewrites the LDS
     }
 }
@@ -725,49 +768,61 @@ hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, fl
     return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3(STEP3_NT), args, 0, st);
 }
 
-template <typename S, bool REC, int MK>
+template <typename S, bool REC, int MK, bool THERMAL>
 static const void *step2_fn_t(int threads, int rows) {
-#define MRT_S2FN(N, H) if (threads == N && rows == H) return (const void *)&k_step2<S, STEP2_TW, H, N, REC, MK>;
+#define MRT_S2FN(N, H) if (threads == N && rows == H) return (const void *)&k_step2<S, STEP2_TW, H, N, REC, MK, THERMAL>;
     MRT_STEP2_SHAPES(MRT_S2FN)
 #undef MRT_S2FN
     return nullptr;
 }
 
-template <typename S>
+template <typename S, bool THERMAL>
 static const void *step2_batch_fn_t(int threads, int rows) {
-#define MRT_S2BFN(N, H) if (threads == N && rows == H) return (const void *)&k_step2_batch<S, STEP2_TW, H, N>;
+#define MRT_S2BFN(N, H) if (threads == N && rows == H) return (const void *)&k_step2_batch<S, STEP2_TW, H, N, THERMAL>;
     MRT_STEP2_SHAPES(MRT_S2BFN)
 #undef MRT_S2BFN
     return nullptr;
 }
 
-const void *step2_batch_kernel_fn(int storage, int threads, int rows) {
-    return storage == ST_F32 ? step2_batch_fn_t<float>(threads, rows) : step2_batch_fn_t<_Float16>(threads, rows);
+const void *step2_batch_kernel_fn(int storage, bool thermal, int threads, int rows) {
+    if (thermal)
+        return storage == ST_F32 ? step2_batch_fn_t<float, true>(threads, rows)
+                                 : step2_batch_fn_t<_Float16, true>(threads, rows);
+    return storage == ST_F32 ? step2_batch_fn_t<float, false>(threads, rows)
+                             : step2_batch_fn_t<_Float16, false>(threads, rows);
 }
 
 hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage,
-                              int threads, int rows, int grid, hipStream_t st) {
-    const void *fn = step2_batch_kernel_fn(storage, threads, rows);
+                              bool thermal, int threads, int rows, int grid, hipStream_t st) {
+    const void *fn = step2_batch_kernel_fn(storage, thermal, threads, rows);
     if (!fn || grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
     void *args[4] = {&doms, &tiles, &ntiles, &parity};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)threads), args, 0, st);
 }
 
 template <int MK>
-static const void *step2_fn_mk(int storage, int threads, int rows, bool rec) {
+static const void *step2_fn_mk(int storage, int threads, int rows, bool rec, bool thermal) {
+    if (thermal) {
+        if (rec) return nullptr;
+        return storage == ST_F32 ? step2_fn_t<float, false, MK, true>(threads, rows)
+                                 : step2_fn_t<_Float16, false, MK, true>(threads, rows);
+    }
     if (storage == ST_F32)
-        return rec ? step2_fn_t<float, true, MK>(threads, rows) : step2_fn_t<float, false, MK>(threads, rows);
-    return rec ? nullptr : step2_fn_t<_Float16, false, MK>(threads, rows);
+        return rec ? step2_fn_t<float, true, MK, false>(threads, rows) : step2_fn_t<float, false, MK, false>(threads, rows);
+    return rec ? nullptr : step2_fn_t<_Float16, false, MK, false>(threads, rows);
 }
 
 const void *step2_kernel_fn(const Dom &d, int storage, int threads, int rows, bool rec) {
-    return medium_kind(d) == MK_ERGUN ? step2_fn_mk<MK_ERGUN>(storage, threads, rows, rec)
-                                      : step2_fn_mk<MK_BRANCHED>(storage, threads, rows, rec);
+    const bool th = d.thermal != 0;
+    switch (medium_kind(d)) {
+    case MK_ERGUN: return step2_fn_mk<MK_ERGUN>(storage, threads, rows, rec, th);
+    case MK_UNIFORM: return step2_fn_mk<MK_UNIFORM>(storage, threads, rows, rec, th);
+    default: return step2_fn_mk<MK_BRANCHED>(storage, threads, rows, rec, th);
+    }
 }
 
 hipError_t launch_step2(const Dom &d, int storage, int swizzle, int threads, int rows,
                         float *urec_next, hipStream_t st) {
-    if (d.thermal) return hipErrorInvalidValue;
     const bool rec = urec_next != nullptr;
     const void *fn = step2_kernel_fn(d, storage, threads, rows, rec);
     if (!fn || (rec && !d.urec)) return hipErrorInvalidValue;

@@ -51,8 +51,8 @@ const void *step3_kernel_fn(const Dom &d, int storage, bool rec);
 // Batched two-cycle pass over a table of 64 x rows tiles (domain, tx, ty, 0);
 // entry arguments (const Dom*, const int4*, int ntiles, int parity).
 hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage,
-                              int threads, int rows, int grid, hipStream_t st);
-const void *step2_batch_kernel_fn(int storage, int threads, int rows);
+                              bool thermal, int threads, int rows, int grid, hipStream_t st);
+const void *step2_batch_kernel_fn(int storage, bool thermal, int threads, int rows);
 
 // Persistent batched step over a tile table: doms[2*k + parity] describes
 // domain k with its buffers for this parity; tiles[j] = (domain, tx, ty, 0).

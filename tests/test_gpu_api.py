@@ -83,8 +83,9 @@ def test_argument_checks_on_a_live_context():
         s.macroscopic(want_T=True)          # no thermal model
     assert e.value.status == lbm.EINVAL
     t = lbm.solver_for_case(I.natural_convection(n=32))
+    t.set_time_blocking(2)
     with pytest.raises(lbm.LBMError) as e:
-        t.set_time_blocking(2)
+        t.set_time_blocking(3)
     assert e.value.status == lbm.ENOTSUP
     with pytest.raises(lbm.LBMError) as e:
         lbm.lib().lbm_step and s.step(-1)

@@ -116,3 +116,87 @@ def test_backward_with_two_cycle_passes_is_bitwise_equal(kappa_plane):
         assert np.array_equal(grads[0][0], grads[k][0]), k
         if kappa_plane:
             assert np.array_equal(grads[0][1], grads[k][1]), k
+
+
+def thermal_cases():
+    """Natural-convection domains (D2Q8 + D2Q5): hot and cold x walls (anti-bounce-back),
+    adiabatic y walls, ragged sizes, a periodic y axis, an Ergun GRF medium, and a
+    buoyancy strong enough that the temperature field moves within the test."""
+    out = []
+    c = I.natural_convection(n=130, Ra=1e6)
+    c.ny = 77
+    c.gbeta *= 20.0
+    out.append(("convection_130x77", c))
+    c = I.natural_convection(n=70, phi=0.4, Da=1e-2, Ra=1e5)
+    c.nx = 201
+    c.bc_y = I.PERIODIC
+    c.gbeta *= 20.0
+    out.append(("convection_201x70_periodic_y", c))
+    c = I.natural_convection(n=96, phi=0.6, Da=1e-2, Ra=1e5)
+    G = I.grf(96, 96, 6.0, 77)
+    c.phi = np.clip(0.6 + 0.1 * G, 0.3, 0.9).astype(np.float32)
+    c.dp = I.ergun_dp(c.K0, 0.6)
+    c.Fphi = None
+    c.gbeta *= 50.0
+    out.append(("convection_96_ergun_grf", c))
+    return out
+
+
+def _thermal_state(case, seed):
+    rng = np.random.default_rng(seed)
+    df = I.random_deviation_state(case.ny, case.nx, 1e-3, seed=seed)
+    x = (np.arange(case.nx) + 0.5) / case.nx
+    T = case.Th + (case.Tc - case.Th) * x
+    dg = np.broadcast_to(((T - case.T0) / 5.0)[None, None, :], (5, case.ny, case.nx)).astype(np.float32)
+    dg = (dg + rng.uniform(-0.05, 0.05, dg.shape)).astype(np.float32)
+    return df, dg
+
+
+@pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
+@pytest.mark.parametrize("name,case", thermal_cases(), ids=[n for n, _ in thermal_cases()])
+@pytest.mark.parametrize("graph,shape", [(0, (512, 16)), (8, (256, 16)), (9, (256, 8)), (0, (512, 8))])
+def test_thermal_two_cycles_per_pass_is_bitwise_equal(name, case, storage, graph, shape):
+    """The coupled D2Q8 + D2Q5 step two cycles per pass (both fields kept in LDS for the
+    ring) equals one cycle per pass bit for bit, for flow and temperature."""
+    ref = lbm.solver_for_case(case, storage=storage)
+    ref.set_time_blocking(1)
+    tb = lbm.solver_for_case(case, storage=storage)
+    tb.set_time_blocking(2)
+    tb.set_two_cycle_tile(*shape)
+    tb.set_graph_steps(graph)
+    df0, dg0 = _thermal_state(case, 6)
+    for s in (ref, tb):
+        s.set_populations(torch.from_numpy(df0).cuda(), torch.from_numpy(dg0).cuda())
+    for chunk in (1, 7, 10, 2, 5, 19, 4):
+        ref.step(chunk)
+        tb.step(chunk)
+        fa, ga = ref.populations(thermal=True)
+        fb, gb = tb.populations(thermal=True)
+        torch.cuda.synchronize()
+        assert torch.equal(fa, fb), (name, chunk)
+        assert torch.equal(ga, gb), (name, chunk)
+    with pytest.raises(lbm.LBMError) as e:
+        tb.set_time_blocking(3)
+    assert e.value.status == lbm.ENOTSUP
+
+
+@pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
+def test_thermal_batch_two_cycles_per_pass_is_bitwise_equal(storage):
+    cases = [c for _, c in thermal_cases()]
+    a = lbm.batch_for_cases(cases, storage=storage)
+    a.set_time_blocking(1)
+    b = lbm.batch_for_cases(cases, storage=storage)
+    b.set_time_blocking(2)
+    for k, c in enumerate(cases):
+        df0, dg0 = _thermal_state(c, 10 + k)
+        for s in (a, b):
+            s.set_populations(k, torch.from_numpy(df0).cuda(), torch.from_numpy(dg0).cuda())
+    for chunk in (3, 8, 1, 12):
+        a.step(chunk)
+        b.step(chunk)
+        for k in range(len(cases)):
+            fa, ga = a.populations(k, thermal=True)
+            fb, gb = b.populations(k, thermal=True)
+            torch.cuda.synchronize()
+            assert torch.equal(fa, fb), (k, chunk)
+            assert torch.equal(ga, gb), (k, chunk)
