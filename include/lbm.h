@@ -293,7 +293,8 @@ int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threa
 
 /* Workgroup shape of the two-cycle kernel: threads in {256, 512} and tile
  * rows in {8, 16} (tiles are 64 nodes wide). Results do not depend on it.
- * Default 512 threads, 16 rows. ENOTSUP on batches (autotuned). */
+ * Default 512 threads, 16 rows (8 rows for thermal domains). ENOTSUP on
+ * batches (autotuned). */
 int lbm_set_two_cycle_tile(lbm_ctx *c, int32_t threads, int32_t rows);
 
 /* Number of steps lbm_step replays from one hand-built HIP graph of kernel
