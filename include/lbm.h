@@ -278,10 +278,11 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * Shorter passes fill in where fewer cycles remain. The recomputation inside
  * lbm_backward uses passes of the same length (recording u at every cycle)
  * and its adjoint sweep two steps per pass in modes 2 and 3; for thermal
- * runs both stay one cycle per pass. Default for
- * single domains of at least 2^20 nodes that allow it: 3 (isothermal FP32) or 2
- * (FP16, and thermal domains, whose D2Q5 field is kept in LDS beside the
- * populations), else 1; for batches, the autotuner's choice. ENOTSUP for on-node
+ * runs both stay one cycle per pass. Default for single domains that allow it:
+ * 3 for isothermal FP32 domains of at least 2^20 nodes, 2 for FP16, for thermal
+ * domains (whose D2Q5 field is kept in LDS beside the populations) and for
+ * smaller domains (with 8-row tiles), 1 for the others; for batches, the
+ * autotuner's choice. ENOTSUP for on-node
  * walls, population or thermal buffers of 4 GiB or more, mode 3 on thermal
  * domains and on batches; EINVAL for another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
@@ -293,8 +294,8 @@ int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threa
 
 /* Workgroup shape of the two-cycle kernel: threads in {256, 512} and tile
  * rows in {8, 16} (tiles are 64 nodes wide). Results do not depend on it.
- * Default 512 threads, 16 rows (8 rows for thermal domains). ENOTSUP on
- * batches (autotuned). */
+ * Default 512 threads, 16 rows (8 rows for thermal domains and for domains
+ * below 2^20 nodes). ENOTSUP on batches (autotuned). */
 int lbm_set_two_cycle_tile(lbm_ctx *c, int32_t threads, int32_t rows);
 
 /* Number of steps lbm_step replays from one hand-built HIP graph of kernel

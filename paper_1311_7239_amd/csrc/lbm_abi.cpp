@@ -519,13 +519,19 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     if (rc) { delete c; return rc; }
     D.L = L;
     c->rec_cap = cap;
-    // several cycles per pass pay once the domain fills the GPU a few times over
-    // (measured from 1024^2 up; the multi-cycle kernels implement bounce-back
-    // walls only); isothermal FP32 takes three, FP16 and thermal domains two
-    if (two_cycle_possible(c) && (int64_t)d->nx * d->ny >= ((int64_t)1 << 20))
-        c->tblock = (d->storage == LBM_FP16_DEV || !three_cycle_possible(c)) ? 2 : 3;
-    else
+    // several cycles per pass (the multi-cycle kernels implement bounce-back walls
+    // only): from 2^20 nodes isothermal FP32 takes three, FP16 and thermal domains
+    // two; smaller domains take two with 64 x 8 tiles, which keep more workgroups
+    // in flight (512^2 cavity: 81 GLUPS against 52 for one cycle per pass and 71
+    // for three)
+    if (!two_cycle_possible(c)) {
         c->tblock = 1;
+    } else if ((int64_t)d->nx * d->ny >= ((int64_t)1 << 20)) {
+        c->tblock = (d->storage == LBM_FP16_DEV || !three_cycle_possible(c)) ? 2 : 3;
+    } else {
+        c->tblock = 2;
+        c->tb_rows = 8;
+    }
     // thermal tiles carry 13 LDS planes: 8-row tiles keep four workgroups per CU
     // (measured 86 against 75 GLUPS for 16 rows at 1024^2)
     if (d->thermal.enabled) c->tb_rows = 8;
