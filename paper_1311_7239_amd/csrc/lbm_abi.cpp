@@ -1321,13 +1321,17 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
                 if (e != hipSuccess) return device_fail(c, e, "recompute step");
                 p ^= 1;
             }
-            // backward through the segment (two steps per pass in two-cycle mode)
+            // backward through the segment (two or three steps per pass in the multi-cycle modes)
             for (int64_t t = s1 - 1; t >= s0;) {
                 const float *ut = urec + (size_t)(t - s0) * rstride;
                 if (th) {
                     e = launch_adjoint_step_thermal(D.dom, lam[la], lam[la ^ 1], lamg[la], lamg[la ^ 1], ut, gphi, gk,
                                                     acc_step, st);
                     t -= 1;
+                } else if (c->tblock == 3 && t - 2 >= s0) {
+                    e = launch_adjoint_step3(D.dom, lam[la], lam[la ^ 1], ut, ut - rstride, ut - 2 * rstride, gphi,
+                                             gk, acc_step2, st);
+                    t -= 3;
                 } else if (c->tblock >= 2 && t - 1 >= s0) {
                     e = launch_adjoint_step2(D.dom, lam[la], lam[la ^ 1], ut, ut - rstride, gphi, gk, acc_step2, st);
                     t -= 2;

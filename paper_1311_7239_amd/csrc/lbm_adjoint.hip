@@ -530,6 +530,271 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
     if (THETA) block_theta_add<ANT>(ts, acc + 4 * (int64_t)b);
 }
 
+// Three backward steps per pass, the adjoint of the three-cycle forward pass:
+// a(t) on a 64 x 16 tile plus a two-node ring from a(t+1) in HBM into LDS
+// (phase A), a(t-1) on the tile plus a one-node ring from LDS, kept in
+// registers and written back to the same LDS in a smaller layout (phase B),
+// then a(t-2) on the tile to HBM (phase C). The three steps' medium gradients
+// of a tile node are added in one read-modify-write, in the order of three
+// single steps, so the result is bitwise that of three k_adjoint_step
+// launches. KAPPA: the gradient with respect to a 1/K plane is accumulated too.
+template <bool THETA, int MK, bool KAPPA>
+__global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(KAPPA ? 4 : 6))) void k_adjoint_step3(
+    Dom d, const float *__restrict__ lam_in, float *__restrict__ lam_out, const float *__restrict__ u_t,
+    const float *__restrict__ u_tm1, const float *__restrict__ u_tm2, float *__restrict__ gphi,
+    float *__restrict__ gkappa, int tiles_x, int swz, double *__restrict__ acc) {
+    constexpr int AW = ATW + 4, AH = ATH + 4, AN = AW * AH;
+    constexpr int BW = ATW + 2, BH = ATH + 2, BN = BW * BH;
+    constexpr int NBB = (BN + ANT - 1) / ANT;
+    constexpr int NC = (ATW * ATH + ANT - 1) / ANT;
+    constexpr int NG = KAPPA ? 4 : 2;   // gradient partials of steps t and t-1 (phi, then 1/K)
+    __shared__ float lds[8 * AH * AW];
+    __shared__ float gpart[NG][ATH][ATW];
+    int b = blockIdx.x;
+    if (swz) b = xcd_swizzle(b, gridDim.x);
+    const int x0 = (b % tiles_x) * ATW, y0 = (b / tiles_x) * ATH;
+    const bool interior = x0 >= 3 && x0 + ATW + 3 <= d.nx && y0 >= 3 && y0 + ATH + 3 <= d.ny;
+    // every buffer is below 4 GiB (the host runs multi-step passes only then)
+    const uint32_t pb4 = (uint32_t)(d.plane * 4);
+    const BufRes rlin = buf_res(lam_in, 8 * pb4), rlout = buf_res(lam_out, 8 * pb4);
+    const BufRes rg = buf_res(gphi, pb4), rgk = buf_res(KAPPA ? gkappa : nullptr, KAPPA ? pb4 : 0u);
+    const MediumSrc<MK> med(d);
+    ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
+
+    // phase A: a(t) on the tile plus a two-node ring, from a(t+1) in HBM
+    {
+        const BufRes rut = buf_res(u_t, 5 * pb4);
+        auto finish_a = [&](float (&bb)[8], const CellRaw &r, const float (&uu)[4], int ex, int ey, int gx,
+                            int gy) {
+            const Cell c = med.cell(d, r);
+            float a[8];
+            ParamBar pb;
+            collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, uu[0], uu[1], uu[2], uu[3], a, pb);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) lds[(i * AH + ey) * AW + ex] = a[i];
+            if (ex >= 2 && ex < ATW + 2 && ey >= 2 && ey < ATH + 2 && x0 - 2 + ex < d.nx && y0 - 2 + ey < d.ny) {
+                float gp, gk;
+                medium_gradient<MK>(d, c, r.kappa, pb, d.ax, d.ay, gp, gk);
+                gpart[0][ey - 2][ex - 2] = gp;
+                if (KAPPA) gpart[KAPPA ? 2 : 0][ey - 2][ex - 2] = gk;
+                if (THETA) {
+                    theta_add(d, c, pb, ts);
+                    if (gy == d.ny - 1) {
+                        const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+                        ts.lid += lid_share(d, gy, BufIO<float>::ld(rlin, o4, 6 * pb4),
+                                            BufIO<float>::ld(rlin, o4, 7 * pb4));
+                    }
+                }
+            }
+        };
+        if (interior) {
+            // b_i(x) = a_i(x + e_i) at constant per-link offsets; the next node's loads
+            // are issued before this node's reverse-mode collision
+            auto fetch = [&](int e, float (&bb)[8], CellRaw &r, float (&uu)[4]) {
+                const int gx = x0 - 2 + e % AW, gy = y0 - 2 + e / AW;
+                const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * 4);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    bb[i] = BufIO<float>::ld(rlin, vo, (uint32_t)((i * d.plane + (1 + EY[i]) * d.pitch + (1 + EX[i])) * 4));
+                const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+                r = med.load(o4);
+                uu[0] = BufIO<float>::ld(rut, o4, 0u);
+                uu[1] = BufIO<float>::ld(rut, o4, pb4);
+                uu[2] = THETA ? BufIO<float>::ld(rut, o4, 2 * pb4) : 0.0f;
+                uu[3] = THETA ? BufIO<float>::ld(rut, o4, 3 * pb4) : 0.0f;
+            };
+            float bn[8], un[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            CellRaw rn{0.0f, 0.0f, 0.0f};
+            if ((int)threadIdx.x < AN) fetch(threadIdx.x, bn, rn, un);
+            for (int e = threadIdx.x; e < AN; e += ANT) {
+                float bb[8], uu[4];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bb[i] = bn[i];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) uu[k] = un[k];
+                const CellRaw r = rn;
+                if (e + ANT < AN) fetch(e + ANT, bn, rn, un);
+                const int ex = e % AW, ey = e / AW;
+                finish_a(bb, r, uu, ex, ey, x0 - 2 + ex, y0 - 2 + ey);
+            }
+        } else {
+            for (int e = threadIdx.x; e < AN; e += ANT) {
+                const int ex = e % AW, ey = e / AW;
+                int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
+                if (!wrap_node(d, gx, gy)) continue;
+                float bb[8];
+                gather_transposed_buf(d, rlin, gx, gy, bb);
+                const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+                float uu[4] = {BufIO<float>::ld(rut, o4, 0u), BufIO<float>::ld(rut, o4, pb4), 0.0f, 0.0f};
+                if (THETA) {
+                    uu[2] = BufIO<float>::ld(rut, o4, 2 * pb4);
+                    uu[3] = BufIO<float>::ld(rut, o4, 3 * pb4);
+                }
+                finish_a(bb, med.load(o4), uu, ex, ey, gx, gy);
+            }
+        }
+    }
+    __syncthreads();
+
+    // phase B: a(t-1) on the tile plus a one-node ring, from LDS, kept in registers
+    float ab[NBB][8];
+    int slot[NBB];
+    {
+        const BufRes rutm = buf_res(u_tm1, 5 * pb4);
+        CellRaw rawB[NBB];
+        float uB[NBB][4];
+#pragma unroll
+        for (int k = 0; k < NBB; ++k) {
+            slot[k] = -1;
+            const int e = threadIdx.x + k * ANT;
+            if (e >= BN) continue;
+            int gx = x0 - 1 + e % BW, gy = y0 - 1 + e / BW;
+            if (!interior && !wrap_node(d, gx, gy)) continue;
+            const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+            rawB[k] = med.load(o4);
+            uB[k][0] = BufIO<float>::ld(rutm, o4, 0u);
+            uB[k][1] = BufIO<float>::ld(rutm, o4, pb4);
+            uB[k][2] = THETA ? BufIO<float>::ld(rutm, o4, 2 * pb4) : 0.0f;
+            uB[k][3] = THETA ? BufIO<float>::ld(rutm, o4, 3 * pb4) : 0.0f;
+            slot[k] = e;
+        }
+#pragma unroll
+        for (int k = 0; k < NBB; ++k) {
+            if (slot[k] < 0) continue;
+            const int bx = slot[k] % BW, by = slot[k] / BW;
+            const int gx = x0 - 1 + bx, gy = y0 - 1 + by;   // unwrapped: wall tests only
+            const int cx = bx + 1, cy = by + 1;              // position in the phase-A layout
+            float bb[8];
+            if (interior) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bb[i] = lds[(i * AH + cy + EY[i]) * AW + cx + EX[i]];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    bool out = false;
+                    const int sx = gx + EX[i], sy = gy + EY[i];
+                    if (EX[i] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) out = true;
+                    if (EY[i] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) out = true;
+                    const int src = out ? (OPP[i] * AH + cy) * AW + cx : (i * AH + cy + EY[i]) * AW + cx + EX[i];
+                    bb[i] = lds[src];
+                }
+            }
+            const Cell c = med.cell(d, rawB[k]);
+            ParamBar pb;
+            collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, uB[k][0], uB[k][1], uB[k][2], uB[k][3], ab[k], pb);
+            if (bx >= 1 && bx <= ATW && by >= 1 && by <= ATH && gx < d.nx && gy < d.ny) {
+                float gp, gk;
+                medium_gradient<MK>(d, c, rawB[k].kappa, pb, d.ax, d.ay, gp, gk);
+                gpart[1][by - 1][bx - 1] = gp;
+                if (KAPPA) gpart[KAPPA ? 3 : 1][by - 1][bx - 1] = gk;
+                if (THETA) {
+                    theta_add(d, c, pb, ts);
+                    if (gy == d.ny - 1)
+                        ts.lid += lid_share(d, gy, lds[(6 * AH + cy) * AW + cx], lds[(7 * AH + cy) * AW + cx]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NBB; ++k) {
+        if (slot[k] < 0) continue;
+        const int bx = slot[k] % BW, by = slot[k] / BW;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[(i * BH + by) * BW + bx] = ab[k][i];
+    }
+    __syncthreads();
+
+    // phase C: a(t-2) on the tile, to HBM. The vector-memory counter retires loads
+    // and stores in order, so every input is fetched before the first store.
+    {
+        const BufRes rutm2 = buf_res(u_tm2, 5 * pb4);
+        CellRaw rawC[NC];
+        float uC[NC][4], gC[NC], gkC[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int q = threadIdx.x + k * ANT;
+            const int gx = x0 + q % ATW, gy = y0 + q / ATW;
+            if (q >= ATW * ATH || gx >= d.nx || gy >= d.ny) continue;
+            const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+            rawC[k] = med.load(o4);
+            uC[k][0] = BufIO<float>::ld(rutm2, o4, 0u);
+            uC[k][1] = BufIO<float>::ld(rutm2, o4, pb4);
+            uC[k][2] = THETA ? BufIO<float>::ld(rutm2, o4, 2 * pb4) : 0.0f;
+            uC[k][3] = THETA ? BufIO<float>::ld(rutm2, o4, 3 * pb4) : 0.0f;
+            gC[k] = BufIO<float>::ld(rg, o4, 0u);
+            gkC[k] = KAPPA ? BufIO<float>::ld(rgk, o4, 0u) : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+            const int q = threadIdx.x + k * ANT;
+            if (q >= ATW * ATH) continue;
+            const int lx = q % ATW, ly = q / ATW;
+            const int gx = x0 + lx, gy = y0 + ly;
+            if (gx >= d.nx || gy >= d.ny) continue;
+            const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
+            const int cx = lx + 1, cy = ly + 1;
+            float bb[8];
+            if (interior) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) bb[i] = lds[(i * BH + cy + EY[i]) * BW + cx + EX[i]];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    bool out = false;
+                    const int sx = gx + EX[i], sy = gy + EY[i];
+                    if (EX[i] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) out = true;
+                    if (EY[i] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) out = true;
+                    const int src = out ? (OPP[i] * BH + cy) * BW + cx : (i * BH + cy + EY[i]) * BW + cx + EX[i];
+                    bb[i] = lds[src];
+                }
+            }
+            const Cell c = med.cell(d, rawC[k]);
+            float a[8];
+            ParamBar pb;
+            collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, uC[k][0], uC[k][1], uC[k][2], uC[k][3], a, pb);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) BufIO<float>::st(rlout, o4, (uint32_t)i * pb4, a[i]);
+            float gp, gk;
+            medium_gradient<MK>(d, c, rawC[k].kappa, pb, d.ax, d.ay, gp, gk);
+            BufIO<float>::st(rg, o4, 0u, ((gC[k] + gpart[0][ly][lx]) + gpart[1][ly][lx]) + gp);
+            if (KAPPA)
+                BufIO<float>::st(rgk, o4, 0u,
+                                 ((gkC[k] + gpart[KAPPA ? 2 : 0][ly][lx]) + gpart[KAPPA ? 3 : 1][ly][lx]) + gk);
+            if (THETA) {
+                theta_add(d, c, pb, ts);
+                if (gy == d.ny - 1)
+                    ts.lid += lid_share(d, gy, lds[(6 * BH + cy) * BW + cx], lds[(7 * BH + cy) * BW + cx]);
+            }
+        }
+    }
+    if (THETA) block_theta_add<ANT>(ts, acc + 4 * (int64_t)b);
+}
+
+hipError_t launch_adjoint_step3(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
+                                const float *u_tm1, const float *u_tm2, float *gphi, float *gkappa, double *acc,
+                                hipStream_t st) {
+    const int tiles_x = (d.nx + ATW - 1) / ATW, tiles_y = (d.ny + ATH - 1) / ATH;
+    const dim3 grid((unsigned)(tiles_x * tiles_y));
+    const int mk = medium_kind(d) == MK_ERGUN ? MK_ERGUN : MK_ANY;
+    const bool kap = gkappa != nullptr;
+#define MRT_ADJ3(TH, MK, KP) \
+    hipLaunchKernelGGL((k_adjoint_step3<TH, MK, KP>), grid, dim3(ANT), 0, st, d, lam_in, lam_out, u_t, u_tm1, \
+                       u_tm2, gphi, gkappa, tiles_x, 1, acc)
+    if (kap) {
+        if (acc) MRT_ADJ3(true, MK_ANY, true);
+        else MRT_ADJ3(false, MK_ANY, true);
+    } else if (mk == MK_ERGUN) {
+        if (acc) MRT_ADJ3(true, MK_ERGUN, false);
+        else MRT_ADJ3(false, MK_ERGUN, false);
+    } else {
+        if (acc) MRT_ADJ3(true, MK_ANY, false);
+        else MRT_ADJ3(false, MK_ANY, false);
+    }
+#undef MRT_ADJ3
+    return hipGetLastError();
+}
+
 hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
                                 const float *u_tm1, float *gphi, float *gkappa, double *acc, hipStream_t st) {
     const int tiles_x = (d.nx + ATW - 1) / ATW, tiles_y = (d.ny + ATH - 1) / ATH;

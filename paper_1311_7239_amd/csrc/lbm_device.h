@@ -502,6 +502,20 @@ template <> struct MediumSrc<MK_ERGUN> {
 
 // ---- gather (pull streaming, Eq. 15, with boundaries) -----------------
 
+// Wraps (gx, gy) on periodic axes; false for a node beyond a wall.
+__device__ __forceinline__ bool wrap_node(const Dom &d, int &gx, int &gy) {
+    if (gx < 0 || gx >= d.nx) {
+        if (d.bc_x != BC_PERIODIC) return false;
+        gx = ((gx % d.nx) + d.nx) % d.nx;
+    }
+    if (gy < 0 || gy >= d.ny) {
+        if (d.bc_y != BC_PERIODIC) return false;
+        gy = ((gy % d.ny) + d.ny) % d.ny;
+    }
+    return true;
+}
+
+
 // f_i(x, t) = f_i+(x - e_i, t-1); a link whose source lies beyond a wall is
 // replaced by the node's own opposite post-collision population plus the
 // moving-wall term 6 w_i (e_i . u_w) when the wall crossed is the top one.

@@ -311,18 +311,7 @@ __device__ __forceinline__ void tile_item(int item, int &cx, int &cy) {
     }
 }
 
-// ------------------------------------------------- two steps per pass
-
-// Temporal blocking: one launch advances t -> t + 2 with a single HBM pass.
-// A workgroup owns a TW x TH output tile. Phase A gathers f(t) (from the
-// post-collision state s_t in HBM) and collides on the tile plus a one-node
-// ring, keeping s_{t+1} in LDS; phase B gathers f(t+1) from LDS (periodic
-// neighbours are in the ring, walls bounce back), collides, and stores
-// s_{t+2}. Per output node the pass reads (TW+2)(TH+2)/(TW TH) populations and
-// writes one, instead of reading and writing one per step. Every node runs
-// the same per-node code as the one-step kernel, and FP16 storage rounds the
-// intermediate state exactly as a store/reload would, so the result is
-// bitwise that of two one-step launches.
+// Recorded u (and stress moments) of the multi-cycle passes.
 // The records go through buffer stores: a recorded step spans at most five
 // planes, below 4 GiB whenever multi-cycle passes run.
 __device__ __forceinline__ void record_node(const Dom &d, BufRes rec, uint32_t o4, float ux, float uy, float n7,
@@ -350,6 +339,20 @@ struct Pending {
     }
 };
 
+// ------------------------------------------------- two steps per pass
+
+// Temporal blocking: one launch advances t -> t + 2 with a single HBM pass.
+// A workgroup owns a TW x TH output tile. Phase A gathers f(t) (from the
+// post-collision state s_t in HBM) and collides on the tile plus a one-node
+// ring, keeping s_{t+1} in LDS; phase B gathers f(t+1) from LDS (periodic
+// neighbours are in the ring, walls bounce back), collides, and stores
+// s_{t+2}. Per output node the pass reads (TW+2)(TH+2)/(TW TH) populations and
+// writes one, instead of reading and writing one per step. Every node runs
+// the same per-node code as the one-step kernel, and FP16 storage rounds the
+// intermediate state exactly as a store/reload would, so the result is
+// bitwise that of two one-step launches. With THERMAL the D2Q5 field takes the
+// same path: phase A keeps g beside f in LDS (ldsg, five planes), phase B
+// gathers it with bounce-back and anti-bounce-back across the walls.
 template <typename S, int TW, int TH, int NT, bool REC, int MK, bool THERMAL>
 __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *urec_next,
                                            float (&lds)[8][TH + 2][TW + 2], float *ldsg) {
@@ -597,18 +600,6 @@ __device__ __forceinline__ void lds_gather(const Dom &d, const float *flat, bool
     }
 }
 
-// Wraps (gx, gy) on periodic axes; false for a node beyond a wall.
-__device__ __forceinline__ bool wrap_node(const Dom &d, int &gx, int &gy) {
-    if (gx < 0 || gx >= d.nx) {
-        if (d.bc_x != BC_PERIODIC) return false;
-        gx = ((gx % d.nx) + d.nx) % d.nx;
-    }
-    if (gy < 0 || gy >= d.ny) {
-        if (d.bc_y != BC_PERIODIC) return false;
-        gy = ((gy % d.ny) + d.ny) % d.ny;
-    }
-    return true;
-}
 
 // Temporal blocking over three cycles: a workgroup owns a TW x TH tile. Phase A
 // gathers f(t) from HBM on the tile plus a two-node ring and collides into LDS;

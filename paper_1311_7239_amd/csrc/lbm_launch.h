@@ -95,6 +95,9 @@ hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out
 // u(t) and u(t-1).
 hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
                                 const float *u_tm1, float *gphi, float *gkappa, double *acc, hipStream_t st);
+hipError_t launch_adjoint_step3(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
+                                const float *u_tm1, const float *u_tm2, float *gphi, float *gkappa, double *acc,
+                                hipStream_t st);
 // The coupled D2Q8 + D2Q5 adjoint (one step per pass): lamg holds the
 // adjoint of the thermal populations (5 planes); u_t carries dT in plane 4.
 hipError_t launch_adjoint_seed_thermal(const Dom &d, Source src, const float *dLdu, float *lam, float *lamg,

@@ -80,7 +80,7 @@ def test_tangent_matches_oracle_differences(kind):
         assert err < 1e-4, name
 
 
-@pytest.mark.parametrize("cycles", [1, 2])
+@pytest.mark.parametrize("cycles", [1, 2, 3])
 def test_dot_product_identity_with_the_adjoint(cycles):
     """<w, du> = <dL/dphi, dphi> + <dL/dtheta, dtheta> for L = <w, u(T)>."""
     case = _cavity()

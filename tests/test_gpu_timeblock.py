@@ -88,9 +88,10 @@ def test_two_cycles_per_pass_is_bitwise_equal(name, case, storage, graph, shape)
 
 @pytest.mark.parametrize("kappa_plane", [False, True])
 def test_backward_with_two_cycle_passes_is_bitwise_equal(kappa_plane):
-    """In two-cycle mode the adjoint's recomputation runs two cycles per pass (recording u
-    at both) and the backward sweep runs two adjoint steps per pass; gradients are
-    bitwise those of the one-cycle path (odd step count: segments of both parities)."""
+    """In the multi-cycle modes the adjoint's recomputation runs two or three cycles per
+    pass (recording u at each) and the backward sweep two or three adjoint steps per pass;
+    gradients are bitwise those of the one-cycle path (odd step count: segments of every
+    length modulo 2 and 3)."""
     case = I.lognormal_channel(n=160, seed=9, ell=10.0, K_ref=40.0, drive=0.02)
     kap = None
     if kappa_plane:
