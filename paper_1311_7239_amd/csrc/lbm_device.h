@@ -364,6 +364,9 @@ __device__ __forceinline__ BufRes buf_res(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+// Cache-policy operand of the buffer instructions: the non-temporal bit.
+constexpr int CPOL_NT = 2;
+
 template <typename S> struct BufIO;
 template <> struct BufIO<float> {
     __device__ __forceinline__ static float ld(BufRes r, uint32_t vo, uint32_t so) {
@@ -371,6 +374,10 @@ template <> struct BufIO<float> {
     }
     __device__ __forceinline__ static void st(BufRes r, uint32_t vo, uint32_t so, float v) {
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, 0);
+    }
+    // non-temporal (streaming) store: the line is not kept in the caches
+    __device__ __forceinline__ static void st_nt(BufRes r, uint32_t vo, uint32_t so, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)vo, (int)so, CPOL_NT);
     }
 };
 template <> struct BufIO<_Float16> {
@@ -385,6 +392,12 @@ template <> struct BufIO<_Float16> {
         unsigned short h;
         __builtin_memcpy(&h, &x, 2);
         __builtin_amdgcn_raw_buffer_store_b16(h, r, (int)vo, (int)so, 0);
+    }
+    __device__ __forceinline__ static void st_nt(BufRes r, uint32_t vo, uint32_t so, float v) {
+        const _Float16 x = (_Float16)v;
+        unsigned short h;
+        __builtin_memcpy(&h, &x, 2);
+        __builtin_amdgcn_raw_buffer_store_b16(h, r, (int)vo, (int)so, CPOL_NT);
     }
 };
 

@@ -1,0 +1,105 @@
+"""The headline workload at its full size: the 8192^2 log-normal porous channel
+(x periodic, walls in y, Ergun medium, FP32) in the launch configuration the
+benchmark times (three cycles per HBM pass, non-temporal state stores at this
+size). Every population is bitwise that of one cycle per pass, and sampled
+nodes agree with the FP64 oracle run on windows around them: after T steps a
+node depends only on the initial state within T nodes, so a window of radius
+T + 1 (its own edges closed by any boundary) reproduces the node exactly."""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1311_7239_amd import inputs as I
+from paper_1311_7239_amd import lbm
+from tests.gpu_cases import f_ref
+from tests.oracle_cases import oracle_setup
+
+pytestmark = pytest.mark.gpu
+
+N = 8192
+CHUNKS = (7, 5)            # 12 steps: collide-only, three-, two- and one-cycle passes
+T = sum(CHUNKS)
+STEP_TOL = 8 * 2.0 ** -24 * 8
+
+
+def _case():
+    return I.lognormal_channel(n=N, seed=5, K_ref=1e-6 * 2048.0 ** 2)
+
+
+@pytest.fixture(scope="module")
+def headline():
+    case = _case()
+    df0 = I.random_deviation_state(N, N, 1e-3, seed=31)
+    dft = torch.from_numpy(df0).cuda()
+    s = lbm.solver_for_case(case)
+    assert s.time_blocking()["cycles_per_pass"] == 3
+    s.set_populations(dft)
+    for n in CHUNKS:
+        s.step(n)
+    df, _ = s.populations()
+    _, u, _ = s.macroscopic()
+    torch.cuda.synchronize()
+    del s
+    yield case, df0, dft, df, u
+    torch.cuda.empty_cache()
+
+
+def test_headline_is_bitwise_one_cycle_per_pass(headline):
+    case, _, dft, df, _ = headline
+    ref = lbm.solver_for_case(case)
+    ref.set_time_blocking(1)
+    ref.set_populations(dft)
+    for n in CHUNKS:
+        ref.step(n)
+    dr, _ = ref.populations()
+    torch.cuda.synchronize()
+    assert torch.equal(df, dr)
+
+
+def _window(case, df0, x, y):
+    """Oracle inputs on the (2R+1)^2 window centred on (x, y), R = T + 1; rows start
+    at a real wall when the node is within R of it."""
+    R = T + 1
+    w = 2 * R + 1
+    if y < R:
+        y0 = 0
+    elif y > N - 1 - R:
+        y0 = N - w
+    else:
+        y0 = y - R
+    cols = np.arange(x - R, x + R + 1) % N
+    rows = np.arange(y0, y0 + w)
+    sub = copy.copy(case)
+    sub.nx, sub.ny = w, w
+    sub.phi = np.ascontiguousarray(case.phi[np.ix_(rows, cols)])
+    dfw = df0[:, rows][:, :, cols].astype(np.float64)
+    return sub, dfw, R, y - y0
+
+
+def test_headline_sampled_nodes_match_oracle(headline):
+    case, df0, _, df, u = headline
+    rng = np.random.default_rng(41)
+    xs = list(rng.integers(0, N, 10)) + [0, N - 1, 5, N - 3, 4000, 123]
+    ys = list(rng.integers(0, N, 10)) + [0, N - 1, N - 2, 1, 3, 8190]
+    worst_f = worst_u = 0.0
+    for x, y in zip(xs, ys):
+        x, y = int(x), int(y)
+        sub, dfw, cx, cy = _window(case, df0, x, y)
+        p, phi, K, F = oracle_setup(sub, nthreads=8)
+        f = np.ascontiguousarray(np.transpose(dfw, (1, 2, 0)) + f_ref(case.Pi0))
+        oracle.run(p, phi, K, F, f, nsteps=T)
+        ref = f[cy, cx] - f_ref(case.Pi0)
+        got = df[:, y, x].cpu().numpy().astype(np.float64)
+        err_f = np.abs(got - ref).max() / np.abs(ref).max()
+        ux, uy, _, _ = oracle.macroscopic(p, phi, K, F, f)
+        uref = np.array([ux[cy, cx], uy[cy, cx]])
+        ugot = u[:, y, x].cpu().numpy().astype(np.float64)
+        err_u = np.abs(ugot - uref).max() / np.abs(uref).max()
+        worst_f, worst_u = max(worst_f, err_f), max(worst_u, err_u)
+        assert err_f < STEP_TOL * T, (x, y, err_f)
+        assert err_u < 1e-5, (x, y, err_u)
+    print(f"8192^2 headline after {T} steps, {len(xs)} sampled nodes: populations {worst_f:.2e}, "
+          f"velocity {worst_u:.2e} (relative)")
