@@ -335,11 +335,18 @@ hipError_t init_domain(Domain &D, int cur, const float *phi, const float *kappa,
     return e;
 }
 
+// The multi-cycle passes store the state non-temporally once a state buffer
+// outgrows the 256 MB Infinity Cache (8192^2 FP32: about 2% faster; with two
+// 134 MB buffers at 2048^2 the cached stores are 5% faster). A batch decides
+// on the sum over its domains.
+constexpr size_t kCacheBytes = (size_t)256 << 20;
+
 int setup_domain(Domain &D, const lbm_desc *d, const float *phi, const float *kappa, char *base) {
     D.desc = *d;
     D.L = make_layout(*d, 0);
     D.base = base;
     D.dom = make_dom(*d, D.L);
+    D.dom.nt_store = D.L.f_bytes + D.L.g_bytes >= kCacheBytes ? 1 : 0;
     if (d->medium != LBM_MEDIUM_UNIFORM) {
         if (!phi) return fail(LBM_EINVAL, "phi plane required for this medium");
         D.dom.phi = (const float *)(base + D.L.off_phi);
@@ -1204,8 +1211,11 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
     }
     c->d_doms = (Dom *)(base + B.off_doms);
     c->d_tiles = (int4 *)(base + B.off_tiles);
+    size_t state_bytes = 0;
+    for (const Domain &D : c->dom) state_bytes += D.L.f_bytes + D.L.g_bytes;
     c->h_doms.resize(2 * (size_t)n);
     for (int32_t k = 0; k < n; ++k) {
+        c->dom[(size_t)k].dom.nt_store = state_bytes >= kCacheBytes ? 1 : 0;
         c->h_doms[2 * (size_t)k] = dom_for(c->dom[(size_t)k], 0);
         c->h_doms[2 * (size_t)k + 1] = dom_for(c->dom[(size_t)k], 1);
     }

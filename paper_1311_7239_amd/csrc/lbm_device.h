@@ -66,6 +66,8 @@ struct Dom {
     float *urec;                     // optional record of step t: planes u_x, u_y, then
                                      // n7, n8 (with rec_stress) and dT (thermal)
     int32_t rec_stress;              // also record m7 - m7^eq and m8 - m8^eq (planes 2, 3)
+    int32_t nt_store;                // multi-cycle passes store the state non-temporally
+                                     // (state buffers larger than the Infinity Cache)
     float inv_nu;                    // 1 / nu (parameter gradients)
 };
 

@@ -518,11 +518,19 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
         float ux, uy, n7, n8, dT;
         node_update<THERMAL>(d, c, f, g, ux, uy, n7, n8, dT);
         const uint32_t vo = (uint32_t)(o * ES);
+        if (d.nt_store) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+            for (int i = 0; i < 8; ++i) BufIO<S>::st_nt(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+        }
         if (THERMAL) {
 #pragma unroll
-            for (int j = 0; j < 5; ++j) BufIO<float>::st(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
+            for (int j = 0; j < 5; ++j) {
+                if (d.nt_store) BufIO<float>::st_nt(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
+                else BufIO<float>::st(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
+            }
         }
         if (REC) record_node(d, buf_res(urec_next, rbytes), (uint32_t)(o * 4), ux, uy, n7, n8);
     }
@@ -614,7 +622,7 @@ __device__ __forceinline__ void lds_gather(const Dom &d, const float *flat, bool
 // With REC (FP32 recomputation for the adjoint) u and, with rec_stress, the
 // stress moments of the tile nodes are recorded at t (d.urec), t + 1 (urec1)
 // and t + 2 (urec2).
-template <typename S, int TW, int TH, int NT, bool REC, int MK, bool NTS>
+template <typename S, int TW, int TH, int NT, bool REC, int MK>
 __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
     constexpr int AW = TW + 4, AH = TH + 4, AN = AW * AH;
     constexpr int BW = TW + 2, BH = TH + 2, BN = BW * BH;
@@ -727,7 +735,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
         const uint32_t vo = (uint32_t)(o * ES);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            if (NTS) BufIO<S>::st_nt(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+            if (d.nt_store) BufIO<S>::st_nt(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
             else BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
         }
         if (REC) record_node(d, rr2, (uint32_t)(o * 4), ux, uy, n7, n8);
@@ -741,22 +749,15 @@ void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y) {
     *tiles_y = (ny + STEP3_TH - 1) / STEP3_TH;
 }
 
-template <int MK, bool NTS>
+template <int MK>
 static const void *step3_fn_t(int storage, bool rec) {
-    if (rec)
-        return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, true, MK, NTS> : nullptr;
-    return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, false, MK, NTS>
-                             : (const void *)&k_step3<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, false, MK, NTS>;
+    if (rec) return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, true, MK> : nullptr;
+    return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, false, MK>
+                             : (const void *)&k_step3<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, false, MK>;
 }
 
-// The populations are stored non-temporally once a state buffer is too large
-// for the 256 MB Infinity Cache to hold both buffers: 8192^2 FP32 about 2% faster,
-// while at 2048^2 (two 134 MB buffers) the cached stores are 5% faster.
 const void *step3_kernel_fn(const Dom &d, int storage, bool rec) {
-    const size_t fbytes = (size_t)8 * (size_t)d.plane * (storage == ST_F32 ? 4 : 2);
-    const bool nts = fbytes >= ((size_t)256 << 20);
-    if (medium_kind(d) == MK_ERGUN) return nts ? step3_fn_t<MK_ERGUN, true>(storage, rec) : step3_fn_t<MK_ERGUN, false>(storage, rec);
-    return nts ? step3_fn_t<MK_ANY, true>(storage, rec) : step3_fn_t<MK_ANY, false>(storage, rec);
+    return medium_kind(d) == MK_ERGUN ? step3_fn_t<MK_ERGUN>(storage, rec) : step3_fn_t<MK_ANY>(storage, rec);
 }
 
 hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, float *urec2, hipStream_t st) {
