@@ -66,8 +66,8 @@ struct Dom {
     float *urec;                     // optional record of step t: planes u_x, u_y, then
                                      // n7, n8 (with rec_stress) and dT (thermal)
     int32_t rec_stress;              // also record m7 - m7^eq and m8 - m8^eq (planes 2, 3)
-    int32_t nt_store;                // multi-cycle passes store the state non-temporally
-                                     // (state buffers larger than the Infinity Cache)
+    int32_t nt_store;                // store the state non-temporally (state buffers
+                                     // larger than the Infinity Cache)
     float inv_nu;                    // 1 / nu (parameter gradients)
 };
 
@@ -350,6 +350,14 @@ __device__ __forceinline__ void store_row(S *p, const float in[NX]) {
     for (int k = 0; k < NX; ++k) tmp[k] = (S)in[k];
     S *q = (S *)__builtin_assume_aligned(p, sizeof(S) * NX);
     __builtin_memcpy(q, tmp, sizeof(S) * NX);
+}
+
+// The same values stored non-temporally (streaming past the caches).
+template <typename S, int NX>
+__device__ __forceinline__ void store_row_nt(S *p, const float in[NX]) {
+    S *q = (S *)__builtin_assume_aligned(p, sizeof(S) * NX);
+#pragma unroll
+    for (int k = 0; k < NX; ++k) __builtin_nontemporal_store((S)in[k], q + k);
 }
 
 // ---- raw buffer access ------------------------------------------------

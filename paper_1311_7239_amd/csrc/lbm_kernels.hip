@@ -95,11 +95,19 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
                     for (int j = 0; j < 5; ++j) g[THERMAL ? r : 0][j][k] = gn[j];
                 }
             }
+            if (d.nt_store) {
 #pragma unroll
-            for (int i = 0; i < 8; ++i) store_row<S, NX>(fout + i * d.plane + o, f[r][i]);
+                for (int i = 0; i < 8; ++i) store_row_nt<S, NX>(fout + i * d.plane + o, f[r][i]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) store_row<S, NX>(fout + i * d.plane + o, f[r][i]);
+            }
             if (THERMAL) {
 #pragma unroll
-                for (int j = 0; j < 5; ++j) store_row<float, NX>(d.gout + j * d.plane + o, g[THERMAL ? r : 0][j]);
+                for (int j = 0; j < 5; ++j) {
+                    if (d.nt_store) store_row_nt<float, NX>(d.gout + j * d.plane + o, g[THERMAL ? r : 0][j]);
+                    else store_row<float, NX>(d.gout + j * d.plane + o, g[THERMAL ? r : 0][j]);
+                }
             }
             if (REC) {
                 store_row<float, NX>(d.urec + o, ux);
