@@ -103,3 +103,25 @@ def test_headline_sampled_nodes_match_oracle(headline):
         assert err_u < 1e-5, (x, y, err_u)
     print(f"8192^2 headline after {T} steps, {len(xs)} sampled nodes: populations {worst_f:.2e}, "
           f"velocity {worst_u:.2e} (relative)")
+
+
+def test_headline_fp16_two_cycles_bitwise_one_cycle():
+    """The same workload with FP16-deviation storage in its default mode (two cycles per
+    pass, non-temporal stores) equals one cycle per pass bit for bit."""
+    case = _case()
+    df0 = torch.from_numpy(I.random_deviation_state(N, N, 1e-3, seed=33)).cuda()
+    out = []
+    for cycles in (None, 1):
+        s = lbm.solver_for_case(case, storage=lbm.FP16_DEV)
+        if cycles is None:
+            assert s.time_blocking()["cycles_per_pass"] == 2
+        else:
+            s.set_time_blocking(cycles)
+        s.set_populations(df0)
+        for n in CHUNKS:
+            s.step(n)
+        df, _ = s.populations()
+        torch.cuda.synchronize()
+        out.append(df)
+        del s
+    assert torch.equal(out[0], out[1])
