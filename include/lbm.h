@@ -143,9 +143,10 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
  * isothermal (else ENOTSUP); ckpt_every > 0 gives ENOTSUP. The tile
  * schedule and persistent grid size are chosen by timing every compiled
  * candidate on the stream (autotuning, which synchronises the stream): the
- * one-cycle shapes and grids, and, for isothermal batches with bounce-back
- * walls, the two-cycle (temporal blocking) shapes and grids, keeping the
- * faster mode, unless tune_cache (host path, may be NULL) already holds a
+ * one-cycle shapes and grids, and, for batches with bounce-back walls, the
+ * two-cycle (temporal blocking) shapes and grids and, when isothermal, the
+ * three-cycle grids, keeping the fastest mode, unless tune_cache (host path,
+ * may be NULL) already holds a
  * choice for the same batch signature (sizes, boundaries, media, storage,
  * thermal, device); a new choice is appended there as a text line.
  * Results are bitwise identical to stepping each domain alone. The
@@ -271,7 +272,7 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * 2 (temporal blocking: one launch gathers, collides on its tile plus a
  * one-node ring kept in LDS, then collides again, so each population crosses
  * HBM about once per two cycles) or 3 (a two-node ring, three collisions per
- * launch; single domains only). Results are bitwise identical in every mode.
+ * launch; isothermal domains). Results are bitwise identical in every mode.
  * Multi-cycle passes are skipped for t = 0 and for the last cycle of each
  * lbm_step call (so lbm_reduce's residual always compares u(t) with u(t-1));
  * while recording for lbm_backward no pass steps over a checkpoint time.
@@ -282,9 +283,10 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * 3 for isothermal FP32 domains of at least 2^20 nodes, 2 for FP16, for thermal
  * domains (whose D2Q5 field is kept in LDS beside the populations) and for
  * smaller domains (with 8-row tiles), 1 for the others; for batches, the
- * autotuner's choice. ENOTSUP for on-node
- * walls, population or thermal buffers of 4 GiB or more, mode 3 on thermal
- * domains and on batches; EINVAL for another value. */
+ * autotuner's choice among 1, 2 and 3 (a batch switched to 3 walks 64 x 16
+ * tiles, which its two-cycle passes then use too). ENOTSUP for on-node walls,
+ * population or thermal buffers of 4 GiB or more, mode 3 on thermal domains, a
+ * mode a batch has no tuned schedule for; EINVAL for another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
 
 /* Current cycles per pass and the two-cycle kernel's workgroup size, tile

@@ -236,6 +236,7 @@ struct lbm_ctx {
     int4 *d_tiles2 = nullptr;   // tiles of the two-cycle kernel (64 x tb_rows)
     int ntiles2 = 0;
     int grid2 = 0;
+    int grid3 = 0;              // grid of the batched three-cycle kernel (64 x 16 tiles of d_tiles2)
     std::vector<int4> h_tiles2;
     // steps replayed from one hand-built HIP graph (0: launch each step);
     // one executable graph per starting buffer parity
@@ -414,7 +415,12 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         void *args_s2[4] = {&d, &tx, &swz, &no_rec};
         void *args_s3[5] = {&d, &tx, &swz, &no_rec, &no_rec};
         void *args_b2[4] = {&c->d_doms, &c->d_tiles2, &c->ntiles2, &p};
-        if (c->batch && c->tblock == 2) {
+        if (c->batch && c->tblock == 3) {
+            kp.func = (void *)step3_batch_kernel_fn(c->storage);
+            kp.gridDim = dim3((unsigned)c->grid3);
+            kp.blockDim = dim3((unsigned)step3_threads());
+            kp.kernelParams = args_b2;
+        } else if (c->batch && c->tblock == 2) {
             kp.func = (void *)step2_batch_kernel_fn(c->storage, c->batch_thermal, c->tb_threads, c->tb_rows);
             kp.gridDim = dim3((unsigned)c->grid2);
             kp.blockDim = dim3((unsigned)c->tb_threads);
@@ -429,7 +435,7 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
             step3_tiles(D.desc.nx, D.desc.ny, &tx, &ty);
             kp.func = (void *)step3_kernel_fn(D.dom, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, false);
             kp.gridDim = dim3((unsigned)(tx * ty));
-            kp.blockDim = dim3(512);
+            kp.blockDim = dim3((unsigned)step3_threads());
             kp.kernelParams = args_s3;
         } else if (c->tblock == 2) {
             Domain &D = c->dom[0];
@@ -600,10 +606,13 @@ int lbm_step(lbm_ctx *c, int64_t n) {
             n -= gcyc;
             continue;
         }
-        if (fused && c->tblock == 3 && !c->batch && n >= 4 && c->t + 3 <= next_ck) {
+        if (fused && c->tblock == 3 && n >= 4 && c->t + 3 <= next_ck) {
             Domain &D = c->dom[0];
-            e = launch_step3(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
-                             c->sched.swizzle, nullptr, nullptr, c->stream);
+            if (c->batch)
+                e = launch_step3_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->grid3, c->stream);
+            else
+                e = launch_step3(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
+                                 c->sched.swizzle, nullptr, nullptr, c->stream);
             if (e != hipSuccess) return device_fail(c, e, "step launch");
             c->cur ^= 1;
             c->t += 3;
@@ -851,7 +860,7 @@ int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threa
     if (threads) *threads = c->tb_threads;
     if (rows) *rows = c->tb_rows;
     if (grid) {
-        if (c->batch) *grid = c->grid2;
+        if (c->batch) *grid = c->tblock == 3 ? c->grid3 : c->grid2;
         else {
             int tx, ty;
             step2_tiles(c->dom[0].desc.nx, c->dom[0].desc.ny, c->tb_rows, &tx, &ty);
@@ -873,11 +882,14 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
     return LBM_OK;
 }
 
+namespace {
+hipError_t upload_tiles2(lbm_ctx *c, int rows);
+}  // namespace
+
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (cycles_per_pass < 1 || cycles_per_pass > 3) return fail(LBM_EINVAL, "cycles per pass must be 1, 2 or 3");
-    if (cycles_per_pass == 3 && c->batch) return fail(LBM_ENOTSUP, "batches advance one or two cycles per pass");
     if (cycles_per_pass == 3 && c->dom[0].desc.thermal.enabled)
         return fail(LBM_ENOTSUP, "thermal domains advance one or two cycles per pass");
     if (cycles_per_pass >= 2 && any_on_node_walls(c))
@@ -886,6 +898,16 @@ int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
         return fail(LBM_ENOTSUP, "a population buffer of 4 GiB or more advances one cycle per pass");
     if (cycles_per_pass == 2 && c->batch && c->grid2 <= 0)
         return fail(LBM_ENOTSUP, "this batch has no tuned two-cycle schedule");
+    if (cycles_per_pass == 3 && c->batch) {
+        if (c->grid3 <= 0) return fail(LBM_ENOTSUP, "this batch has no tuned three-cycle schedule");
+        if (c->tb_rows != 16) {
+            // the three-cycle kernel walks 64 x 16 tiles; the two-cycle kernel then
+            // uses the same table
+            c->tb_rows = 16;
+            hipError_t e = upload_tiles2(c, 16);
+            if (e != hipSuccess) return device_fail(c, e, "tile table upload");
+        }
+    }
     c->tblock = cycles_per_pass;
     reset_graphs(c);
     return LBM_OK;
@@ -1065,7 +1087,7 @@ uint64_t batch_signature(const lbm_ctx *c) {
 struct Tuned {
     Schedule s{128, 1, 2, 0};
     int grid = 0;
-    int tblock = 1, tb_threads = 512, tb_rows = 16, grid2 = 0;
+    int tblock = 1, tb_threads = 512, tb_rows = 16, grid2 = 0, grid3 = 0;
 };
 
 bool cache_lookup(const char *path, uint64_t sig, Tuned &out) {
@@ -1076,12 +1098,14 @@ bool cache_lookup(const char *path, uint64_t sig, Tuned &out) {
     bool found = false;
     while (fgets(line, sizeof(line), f)) {
         unsigned long long key;
-        int tw, v, r, g, tb, tt, tr, g2;
-        if (sscanf(line, "%llx %d %d %d %d %d %d %d %d", &key, &tw, &v, &r, &g, &tb, &tt, &tr, &g2) != 9) continue;
+        int tw, v, r, g, tb, tt, tr, g2, g3;
+        if (sscanf(line, "%llx %d %d %d %d %d %d %d %d %d", &key, &tw, &v, &r, &g, &tb, &tt, &tr, &g2, &g3) != 10)
+            continue;
         const Schedule cand{tw, v, r, 0};
-        if (key == sig && schedule_supported(cand) && g > 0 && (tb == 1 || tb == 2) &&
-            step2_shape_supported(tt, tr) && g2 > 0) {
+        if (key == sig && schedule_supported(cand) && g > 0 && tb >= 1 && tb <= 3 &&
+            step2_shape_supported(tt, tr) && g2 > 0 && g3 >= 0 && (tb < 3 || (g3 > 0 && tr == 16))) {
             out.s = cand; out.grid = g; out.tblock = tb; out.tb_threads = tt; out.tb_rows = tr; out.grid2 = g2;
+            out.grid3 = g3;
             found = true;
         }
     }
@@ -1093,8 +1117,8 @@ void cache_store(const char *path, uint64_t sig, const Tuned &t) {
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%016llx %d %d %d %d %d %d %d %d\n", (unsigned long long)sig, t.s.tile_w, t.s.vec, t.s.rows,
-            t.grid, t.tblock, t.tb_threads, t.tb_rows, t.grid2);
+    fprintf(f, "%016llx %d %d %d %d %d %d %d %d %d\n", (unsigned long long)sig, t.s.tile_w, t.s.vec, t.s.rows,
+            t.grid, t.tblock, t.tb_threads, t.tb_rows, t.grid2, t.grid3);
     fclose(f);
 }
 
@@ -1160,7 +1184,25 @@ hipError_t autotune(lbm_ctx *c, Tuned &best) {
             }
         }
     }
+    // three cycles per pass (isothermal batches): the 64 x 16 tiles of the
+    // two-cycle table
+    float best3 = 1e30f;
+    if (e == hipSuccess && two_cycle_ok && !c->batch_thermal && (e = upload_tiles2(c, 16)) == hipSuccess) {
+        const int grids[4] = {2 * ncu, 4 * ncu, 8 * ncu, c->ntiles2};
+        for (int g : grids) {
+            if (g > c->ntiles2) g = c->ntiles2;
+            float ms = 0.0f;
+            e = time_it([&] { return launch_step3_batch(c->d_doms, c->d_tiles2, c->ntiles2, 0, c->storage, g,
+                                                        c->stream); }, ms);
+            if (e != hipSuccess) break;
+            if (ms / 3.0f < best3) { best3 = ms / 3.0f; best.grid3 = g; }
+        }
+    }
     best.tblock = (best2 < best1) ? 2 : 1;
+    if (best3 < best1 && best3 < best2) {
+        best.tblock = 3;
+        best.tb_rows = 16;   // the three-cycle kernel walks the 64 x 16 table
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return e;
@@ -1240,6 +1282,7 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
         c->tb_rows = best.tb_rows;
         e = upload_tiles2(c, best.tb_rows);
         c->grid2 = best.grid2 > c->ntiles2 ? c->ntiles2 : best.grid2;
+        c->grid3 = best.grid3 > c->ntiles2 ? c->ntiles2 : best.grid3;
         c->tblock = best.tblock;
     }
     if (e != hipSuccess) {

@@ -631,15 +631,11 @@ __device__ __forceinline__ void lds_gather(const Dom &d, const float *flat, bool
 // stress moments of the tile nodes are recorded at t (d.urec), t + 1 (urec1)
 // and t + 2 (urec2).
 template <typename S, int TW, int TH, int NT, bool REC, int MK>
-__global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
+__device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *urec1, float *urec2, float *lds) {
     constexpr int AW = TW + 4, AH = TH + 4, AN = AW * AH;
     constexpr int BW = TW + 2, BH = TH + 2, BN = BW * BH;
     constexpr int ES = (int)sizeof(S);
     constexpr int NBB = (BN + NT - 1) / NT;
-    __shared__ float lds[8 * AH * AW];
-    int b = blockIdx.x;
-    if (swz) b = xcd_swizzle(b, gridDim.x);
-    const int x0 = (b % tiles_x) * TW, y0 = (b / tiles_x) * TH;
     const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
     const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
     const MediumSrc<MK> med(d);
@@ -750,6 +746,31 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
     }
 }
 
+template <typename S, int TW, int TH, int NT, bool REC, int MK>
+__global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
+    __shared__ float lds[8 * (TH + 4) * (TW + 4)];
+    int b = blockIdx.x;
+    if (swz) b = xcd_swizzle(b, gridDim.x);
+    step3_tile<S, TW, TH, NT, REC, MK>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec1, urec2, lds);
+}
+
+// Persistent batched three-cycle pass over a table of TW x TH tiles (isothermal
+// domains of any medium).
+template <typename S, int TW, int TH, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_step3_batch(const Dom *__restrict__ doms, const int4 *__restrict__ tiles,
+                                                    int ntiles, int parity) {
+    __shared__ float lds[8 * (TH + 4) * (TW + 4)];
+    const int64_t nb = gridDim.x;
+    const int t0 = (int)((int64_t)blockIdx.x * ntiles / nb);
+    const int t1 = (int)(((int64_t)blockIdx.x + 1) * ntiles / nb);
+    for (int t = t0; t < t1; ++t) {
+        const int4 tl = tiles[t];
+        const Dom d = doms[2 * tl.x + parity];
+        step3_tile<S, TW, TH, NT, false, MK_BRANCHED>(d, tl.y * TW, tl.z * TH, nullptr, nullptr, lds);
+        lds_barrier();   // the next tile's phase A rewrites the LDS
+    }
+}
+
 constexpr int STEP3_TW = 64, STEP3_TH = 16, STEP3_NT = 512;
 
 void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y) {
@@ -766,6 +787,21 @@ static const void *step3_fn_t(int storage, bool rec) {
 
 const void *step3_kernel_fn(const Dom &d, int storage, bool rec) {
     return medium_kind(d) == MK_ERGUN ? step3_fn_t<MK_ERGUN>(storage, rec) : step3_fn_t<MK_ANY>(storage, rec);
+}
+
+const void *step3_batch_kernel_fn(int storage) {
+    return storage == ST_F32 ? (const void *)&k_step3_batch<float, STEP3_TW, STEP3_TH, STEP3_NT>
+                             : (const void *)&k_step3_batch<_Float16, STEP3_TW, STEP3_TH, STEP3_NT>;
+}
+
+int step3_threads() { return STEP3_NT; }
+
+hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, int grid,
+                              hipStream_t st) {
+    if (grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
+    const void *fn = step3_batch_kernel_fn(storage);
+    void *args[4] = {&doms, &tiles, &ntiles, &parity};
+    return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(STEP3_NT), args, 0, st);
 }
 
 hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, float *urec2, hipStream_t st) {

@@ -48,6 +48,11 @@ const void *step2_kernel_fn(const Dom &d, int storage, int threads, int rows, bo
 hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, float *urec2, hipStream_t st);
 void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y);
 const void *step3_kernel_fn(const Dom &d, int storage, bool rec);
+// batched three-cycle pass over a table of 64 x 16 tiles (isothermal domains)
+const void *step3_batch_kernel_fn(int storage);
+int step3_threads();
+hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, int grid,
+                              hipStream_t st);
 // Batched two-cycle pass over a table of 64 x rows tiles (domain, tx, ty, 0);
 // entry arguments (const Dom*, const int4*, int ntiles, int parity).
 hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage,

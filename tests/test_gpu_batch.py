@@ -35,15 +35,15 @@ def single_run(case, steps, storage):
 
 
 @pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
-@pytest.mark.parametrize("tblock", [1, 2])
+@pytest.mark.parametrize("tblock", [1, 2, 3])
 def test_batch_is_bitwise_equal_to_single_domains(storage, tblock, tmp_path):
-    """One and two cycles per pass, graph replays of 4 cycles, leftovers."""
+    """One, two and three cycles per pass, graph replays of 6 cycles, leftovers."""
     cases = mixed_cases()
     b = lbm.batch_for_cases(cases, storage=storage, tune_cache=tmp_path / "tune.txt")
     b.set_time_blocking(tblock)
-    b.set_graph_steps(4)
+    b.set_graph_steps(6)
     done = 0
-    for chunk in (1, 9, 3, 8):          # t = 0 cycle, graph replays, leftovers
+    for chunk in (1, 9, 3, 8, 13):      # t = 0 cycle, graph replays, leftovers
         b.step(chunk)
         done += chunk
         for k in range(len(cases)):
@@ -70,7 +70,7 @@ def test_tune_cache_is_written_and_reused(tmp_path):
     path = tmp_path / "tune.txt"
     b1 = lbm.batch_for_cases(cases, tune_cache=path)
     text = path.read_text().strip().splitlines()
-    assert len(text) == 1 and len(text[0].split()) == 9
+    assert len(text) == 1 and len(text[0].split()) == 10
     b2 = lbm.batch_for_cases(cases, tune_cache=path)
     assert b1.schedule() == b2.schedule()
     assert len(path.read_text().strip().splitlines()) == 1    # found, not re-tuned
