@@ -3,6 +3,7 @@ counters), written as short text/JSON files.
 
     python -m paper_1311_7239_amd.profiling stats <kernel_stats.csv> <out.txt> <command...>
     python -m paper_1311_7239_amd.profiling counters <fetch.csv> <write.csv> <out.json> <command...>
+    python -m paper_1311_7239_amd.profiling sq <counters.csv> <out.txt> <command...>
 
 FETCH_SIZE and WRITE_SIZE are read per dispatch (KiB) and scaled by what the same
 counters read for a plain device copy of known size recorded in the same run
@@ -78,6 +79,28 @@ def counters_summary(fetch_csv, write_csv, out_json, command, kernel_prefix="voi
     pathlib.Path(out_json).write_text(json.dumps(out, indent=1) + "\n")
 
 
+def sq_summary(counters_csv, out_txt, command, kernel_prefix="void mrt::k_step"):
+    """Per-kernel sums of SQ counters (instruction mix, waves) over the dispatches."""
+    rows = _rows(counters_csv)
+    agg, disp = {}, {}
+    for r in rows:
+        name = r["Kernel_Name"]
+        if not name.startswith(kernel_prefix):
+            continue
+        agg.setdefault(name, {})
+        agg[name][r["Counter_Name"]] = agg[name].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        disp.setdefault(name, set()).add(r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+    lines = ["# rocprofv3 --pmc SQ counter summary (sums over the dispatches)", f"# command: {command}",
+             f"# kernel sources sha256[:16]: {kernel_source_hash()}"]
+    for name, c in agg.items():
+        waves = c.get("SQ_WAVES", 0.0)
+        lines.append(f"{_short(name)}")
+        lines.append(f"    dispatches {len(disp[name])}  " + "  ".join(f"{k} {v:.4g}" for k, v in sorted(c.items())))
+        if waves:
+            lines.append(f"    SQ_INSTS_VALU per wave {c.get('SQ_INSTS_VALU', 0.0) / waves:.1f}")
+    pathlib.Path(out_txt).write_text("\n".join(lines) + "\n")
+
+
 def traffic_bytes(summary_json, kernel_name=None):
     """HBM bytes per dispatch of the step kernel from a counters summary, or None if the
     kernel sources changed since the counters were taken. kernel_name: the full name or a
@@ -105,5 +128,7 @@ if __name__ == "__main__":
         stats_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     elif mode == "counters":
         counters_summary(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:]))
+    elif mode == "sq":
+        sq_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
     else:
-        raise SystemExit("usage: profiling.py stats|counters ...")
+        raise SystemExit("usage: profiling.py stats|counters|sq ...")
