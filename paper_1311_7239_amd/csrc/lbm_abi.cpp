@@ -1362,9 +1362,8 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
                     // three cycles in one pass, recording at t, t + 1 and t + 2
                     e = launch_step3(dr, ST_F32, c->sched.swizzle, dr.urec + rstride, dr.urec + 2 * rstride, st);
                     t += 3;
-                } else if (c->tblock >= 2 && !th && t > 0 && t + 1 < s1) {
-                    // two cycles in one pass, recording at t and t + 1 (a thermal
-                    // recomputation also records dT and stays one cycle per pass)
+                } else if (c->tblock >= 2 && t > 0 && t + 1 < s1) {
+                    // two cycles in one pass, recording at t and t + 1 (with dT when thermal)
                     e = launch_step2(dr, ST_F32, c->sched.swizzle, c->tb_threads, c->tb_rows, dr.urec + rstride, st);
                     t += 2;
                 } else {

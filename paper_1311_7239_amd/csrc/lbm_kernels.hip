@@ -367,14 +367,14 @@ struct Pending {
 template <typename S, int TW, int TH, int NT, bool REC, int MK, bool THERMAL>
 __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *urec_next,
                                            float (&lds)[8][TH + 2][TW + 2], float *ldsg) {
-    static_assert(!(REC && THERMAL), "the recomputation of thermal runs is one cycle per pass");
     constexpr int EW = TW + 2, EH = TH + 2, EN = EW * EH;
     constexpr int ES = (int)sizeof(S);
     // the state buffers are below 4 GiB (the host keeps larger domains on the
     // one-cycle kernel), so every byte offset fits the buffer instructions
     const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
     const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
-    const uint32_t rbytes = REC ? (uint32_t)((d.rec_stress ? 4 : 2) * d.plane * 4) : 0u;
+    // recorded planes: u (2), the stress moments (2, with rec_stress), dT (plane 4, thermal)
+    const uint32_t rbytes = REC ? (uint32_t)((THERMAL ? 5 : (d.rec_stress ? 4 : 2)) * d.plane * 4) : 0u;
     // D2Q5 buffers (FP32, five planes, also below 4 GiB)
     const uint32_t gbytes = THERMAL ? (uint32_t)(5 * d.plane * 4) : 0u;
     const BufRes rgin = buf_res(THERMAL ? d.gin : nullptr, gbytes), rgout = buf_res(THERMAL ? d.gout : nullptr, gbytes);
@@ -406,8 +406,11 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
             for (int j = 0; j < 5; ++j) ldsg[(j * EH + ey) * EW + ex] = g[j];
         }
         if (REC && ex >= 1 && ex <= TW && ey >= 1 && ey <= TH && x0 - 1 + ex < d.nx &&
-            y0 - 1 + ey < d.ny)
-            record_node(d, buf_res(d.urec, rbytes), (uint32_t)(o * 4), ux, uy, n7, n8);
+            y0 - 1 + ey < d.ny) {
+            const BufRes rr = buf_res(d.urec, rbytes);
+            record_node(d, rr, (uint32_t)(o * 4), ux, uy, n7, n8);
+            if (THERMAL) BufIO<float>::st_nt(rr, (uint32_t)(o * 4), (uint32_t)(4 * d.plane * 4), dT);
+        }
     };
     if (interior) {
         // link i pulls from (gx - e_ix, gy - e_iy): the lane's offset of (gx - 1, gy - 1)
@@ -540,7 +543,11 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
                 else BufIO<float>::st(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
             }
         }
-        if (REC) record_node(d, buf_res(urec_next, rbytes), (uint32_t)(o * 4), ux, uy, n7, n8);
+        if (REC) {
+            const BufRes rr = buf_res(urec_next, rbytes);
+            record_node(d, rr, (uint32_t)(o * 4), ux, uy, n7, n8);
+            if (THERMAL) BufIO<float>::st_nt(rr, (uint32_t)(o * 4), (uint32_t)(4 * d.plane * 4), dT);
+        }
     }
 }
 
@@ -852,7 +859,7 @@ hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, in
 template <int MK>
 static const void *step2_fn_mk(int storage, int threads, int rows, bool rec, bool thermal) {
     if (thermal) {
-        if (rec) return nullptr;
+        if (rec) return storage == ST_F32 ? step2_fn_t<float, true, MK, true>(threads, rows) : nullptr;
         return storage == ST_F32 ? step2_fn_t<float, false, MK, true>(threads, rows)
                                  : step2_fn_t<_Float16, false, MK, true>(threads, rows);
     }

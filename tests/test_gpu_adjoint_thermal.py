@@ -94,3 +94,26 @@ def test_thermal_adjoint_matches_oracle_differences():
               _oracle_loss(_case(), phi0, col, **{name: base - hh})) / (2 * hh)
         print(f"thermal dL/d{name}: adjoint {th[name]:.6e}  FD {fd:.6e}")
         assert abs(th[name] - fd) <= 1e-4 * abs(fd), name
+
+
+def test_thermal_gradients_equal_for_one_and_two_cycle_recomputation():
+    """The recomputation two cycles per pass (recording u and dT at both) gives the
+    gradients of the one-cycle path bit for bit."""
+    c = _case()
+    col = c.nx // 2
+    out = []
+    for cycles in (1, 2):
+        s = lbm.solver_for_case(c, ckpt_every=64, max_steps_recorded=STEPS)
+        s.set_time_blocking(cycles)
+        T = _conduction(c)
+        dg = np.broadcast_to(((T - c.T0) / 5.0)[None], (5, c.ny, c.nx)).astype(np.float32).copy()
+        s.set_populations(torch.zeros((8, c.ny, c.nx), device="cuda"), torch.from_numpy(dg).cuda())
+        s.step(STEPS)
+        _, u, _ = s.macroscopic()
+        dLdu = torch.zeros_like(u)
+        dLdu[:, :, col] = u[:, :, col]
+        g, _, th = s.backward_params(dLdu)
+        torch.cuda.synchronize()
+        out.append((g.cpu().numpy(), th))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
