@@ -284,7 +284,8 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * domains (whose D2Q5 field is kept in LDS beside the populations) and for
  * smaller domains (with 8-row tiles), 1 for the others; for batches, the
  * autotuner's choice among 1, 2 and 3 (a batch switched to 3 walks 64 x 16
- * tiles, which its two-cycle passes then use too). ENOTSUP for on-node walls,
+ * tiles, which its two-cycle passes then use too; switching uploads that tile
+ * table and synchronises the stream). ENOTSUP for on-node walls,
  * population or thermal buffers of 4 GiB or more, mode 3 on thermal domains, a
  * mode a batch has no tuned schedule for; EINVAL for another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
