@@ -278,8 +278,8 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * while recording for lbm_backward no pass steps over a checkpoint time.
  * Shorter passes fill in where fewer cycles remain. The recomputation inside
  * lbm_backward uses passes of the same length (recording u at every cycle)
- * and its adjoint sweep two or three steps per pass in modes 2 and 3; a
- * thermal run's sweep stays one step per pass. Default for single domains that allow it:
+ * and its adjoint sweep two or three steps per pass in modes 2 and 3 (two for
+ * thermal runs). Default for single domains that allow it:
  * 3 for isothermal FP32 domains of at least 2^20 nodes, 2 for FP16, for thermal
  * domains (whose D2Q5 field is kept in LDS beside the populations) and for
  * smaller domains (with 8-row tiles), 1 for the others; for batches, the

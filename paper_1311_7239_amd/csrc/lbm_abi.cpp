@@ -1376,7 +1376,11 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
             // backward through the segment (two or three steps per pass in the multi-cycle modes)
             for (int64_t t = s1 - 1; t >= s0;) {
                 const float *ut = urec + (size_t)(t - s0) * rstride;
-                if (th) {
+                if (th && c->tblock >= 2 && t - 1 >= s0) {
+                    e = launch_adjoint_step2_thermal(D.dom, lam[la], lam[la ^ 1], lamg[la], lamg[la ^ 1], ut,
+                                                     ut - rstride, gphi, gk, acc_step2, st);
+                    t -= 2;
+                } else if (th) {
                     e = launch_adjoint_step_thermal(D.dom, lam[la], lam[la ^ 1], lamg[la], lamg[la ^ 1], ut, gphi, gk,
                                                     acc_step, st);
                     t -= 1;

@@ -353,6 +353,57 @@ __device__ __forceinline__ void gather_transposed_buf(const Dom &d, BufRes rlam,
     }
 }
 
+// Reverse mode of the D2Q5 collision (Eq. B.2 with varpi = 0, deviations from
+// T0/5): given the adjoint bg of g+, the adjoint ag of the pre-collision g
+// (through n = N g, T = T0 + n_0 and n^eq of Eq. B.6) and the adjoint of the
+// flow velocity it uses, added to ubx, uby.
+__device__ __forceinline__ void thermal_collide_adjoint(const float bg[5], const Dom &d, float ux, float uy,
+                                                        float dT, float ag[5], float &ubx, float &uby) {
+    // adjoint of n+: diag(1/5, 1/2, 1/2, 1/20, 1/4) N bg (g+ = N^T diag(...) n+)
+    const float nb0 = 0.2f * ((bg[0] + bg[1]) + (bg[2] + bg[3]) + bg[4]);
+    const float nb1 = 0.5f * (bg[1] - bg[3]);
+    const float nb2 = 0.5f * (bg[2] - bg[4]);
+    const float nb3 = 0.05f * ((bg[1] + bg[2]) + (bg[3] + bg[4]) - 4.0f * bg[0]);
+    const float nb4 = 0.25f * ((bg[1] - bg[2]) + (bg[3] - bg[4]));
+    const float T = d.T0 + dT;
+    // n1+ = n1 - zT (n1 - ux T / sigma), T = T0 + n0; n0+ = n0; n3, n4 relax to 0
+    const float nbar0 = nb0 + d.zT * (ux * nb1 + uy * nb2) * d.inv_sigma;
+    const float nbar1 = (1.0f - d.zT) * nb1, nbar2 = (1.0f - d.zT) * nb2;
+    const float nbar3 = (1.0f - d.z3) * nb3, nbar4 = (1.0f - d.z4) * nb4;
+    ubx += d.zT * T * d.inv_sigma * nb1;
+    uby += d.zT * T * d.inv_sigma * nb2;
+    // ag = N^T nbar
+    ag[0] = nbar0 - 4.0f * nbar3;
+    ag[1] = (nbar0 + nbar1) + (nbar3 + nbar4);
+    ag[2] = (nbar0 + nbar2) + (nbar3 - nbar4);
+    ag[3] = (nbar0 - nbar1) + (nbar3 + nbar4);
+    ag[4] = (nbar0 - nbar2) + (nbar3 - nbar4);
+}
+
+// gather_thermal_transposed's edge form through a buffer resource over the
+// five planes of a_g (below 4 GiB).
+__device__ __forceinline__ void gather_thermal_transposed_buf(const Dom &d, BufRes rg, int x, int y, float b[5]) {
+    const uint32_t o = (uint32_t)(y * d.pitch + x);
+    b[0] = BufIO<float>::ld(rg, o * 4u, 0u);
+#pragma unroll
+    for (int j = 1; j < 5; ++j) {
+        int sx = x + TXv[j], sy = y + TYv[j];
+        int kind = 0;  // 0 stream, 1 bounce-back, 2 anti-bounce-back
+        if (TXv[j] != 0 && (sx < 0 || sx >= d.nx)) {
+            if (d.bc_x == BC_PERIODIC) sx = (sx < 0) ? d.nx - 1 : 0;
+            else kind = 2;
+        }
+        if (TYv[j] != 0 && (sy < 0 || sy >= d.ny)) {
+            if (d.bc_y == BC_PERIODIC) sy = (sy < 0) ? d.ny - 1 : 0;
+            else kind = 1;
+        }
+        const uint32_t idx = kind == 0 ? (uint32_t)(j * d.plane + sy * d.pitch + sx)
+                                       : (uint32_t)(TOPP[j] * d.plane) + o;
+        const float v = BufIO<float>::ld(rg, idx * 4u, 0u);
+        b[j] = (kind == 2) ? -v : v;
+    }
+}
+
 // Two backward steps per pass: a(t) on a 64 x 16 tile plus a one-node ring
 // from a(t+1) in HBM into LDS (phase A), then a(t-1) on the tile from LDS
 // (phase B); the medium gradient of both steps is added in one
@@ -360,9 +411,12 @@ __device__ __forceinline__ void gather_transposed_buf(const Dom &d, BufRes rlam,
 // bitwise that of two k_adjoint_step launches.
 constexpr int ATW = 64, ATH = 16, ANT = 512;
 
-template <bool THETA, int MK>
-__global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k_adjoint_step2(Dom d, const float *__restrict__ lam_in,
+template <bool THETA, int MK, bool THERMAL>
+__global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(THERMAL ? 4 : 6))) void k_adjoint_step2(
+                                                       Dom d, const float *__restrict__ lam_in,
                                                        float *__restrict__ lam_out,
+                                                       const float *__restrict__ lamg_in,
+                                                       float *__restrict__ lamg_out,
                                                        const float *__restrict__ u_t,
                                                        const float *__restrict__ u_tm1,
                                                        float *__restrict__ gphi,
@@ -371,6 +425,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
     constexpr int EW = ATW + 2, EH = ATH + 2, EN = EW * EH;
     constexpr int NB = (ATW * ATH + ANT - 1) / ANT;
     __shared__ float lds[8][EH][EW];
+    __shared__ float ldsg[THERMAL ? 5 * EH * EW : 1];   // a_g(t) of the D2Q5 links
     __shared__ float gA[ATH][ATW];
     __shared__ float gkA[ATH][ATW];
     int b = blockIdx.x;
@@ -383,22 +438,35 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
     const BufRes rlin = buf_res(lam_in, 8 * pb4), rlout = buf_res(lam_out, 8 * pb4);
     const BufRes rut = buf_res(u_t, 5 * pb4), rutm = buf_res(u_tm1, 5 * pb4);
     const BufRes rg = buf_res(gphi, pb4), rgk = buf_res(gkappa, gkappa ? pb4 : 0u);
+    const BufRes rgin = buf_res(THERMAL ? lamg_in : nullptr, THERMAL ? 5 * pb4 : 0u);
+    const BufRes rgout = buf_res(THERMAL ? lamg_out : nullptr, THERMAL ? 5 * pb4 : 0u);
     const MediumSrc<MK> med(d);
     ThetaSum ts{0.0f, 0.0f, 0.0f, 0.0f};
 
     // phase A: a(t) on the tile plus a one-node ring, from a(t+1) in HBM
-    auto finish_a = [&](float (&bb)[8], const CellRaw &r, const float (&uu)[4], int ex, int ey, int gx,
-                        int gy) {
+    auto finish_a = [&](float (&bb)[8], const float (&bg)[5], const CellRaw &r, const float (&uu)[4], float dT,
+                        int ex, int ey, int gx, int gy) {
         const int64_t o = (int64_t)gy * d.pitch + gx;
         const Cell c = med.cell(d, r);
         float a[8];
         ParamBar pb;
-        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, uu[0], uu[1], uu[2], uu[3], a, pb);
+        // thermal: the D2Q5 reverse mode first (it adds to the adjoint of u), then
+        // the flow collision with the node's buoyancy, then the buoyancy's adjoint
+        // returned to every thermal link
+        float ag[5], ubx = 0.0f, uby = 0.0f;
+        if (THERMAL) thermal_collide_adjoint(bg, d, uu[0], uu[1], dT, ag, ubx, uby);
+        const float ay = THERMAL ? d.ay + d.gbeta * dT : d.ay;
+        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * ay, uu[0], uu[1], uu[2], uu[3], a, pb, ubx, uby);
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[i][ey][ex] = a[i];
+        if (THERMAL) {
+            const float Tb = c.phi * d.gbeta * pb.pay;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) ldsg[(j * EH + ey) * EW + ex] = ag[j] + Tb;
+        }
         if (ex >= 1 && ex <= ATW && ey >= 1 && ey <= ATH && x0 - 1 + ex < d.nx && y0 - 1 + ey < d.ny) {
             float gp, gk;
-            medium_gradient<MK>(d, c, r.kappa, pb, d.ax, d.ay, gp, gk);
+            medium_gradient<MK>(d, c, r.kappa, pb, d.ax, ay, gp, gk);
             gA[ey - 1][ex - 1] = gp;
             gkA[ey - 1][ex - 1] = gk;
             if (THETA) {
@@ -414,32 +482,41 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
         // b_i(x) = a_i(x + e_i): the lane's offset of (gx - 1, gy - 1) plus a uniform,
         // non-negative per-link offset; the next node's loads are issued before this
         // node's reverse-mode collision (software pipeline)
-        auto fetch = [&](int e, float (&bb)[8], CellRaw &r, float (&uu)[4]) {
+        auto fetch = [&](int e, float (&bb)[8], float (&bg)[5], CellRaw &r, float (&uu)[4], float &dT) {
             const int gx = x0 - 1 + e % EW, gy = y0 - 1 + e / EW;
             const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * 4);
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 bb[i] = BufIO<float>::ld(rlin, vo, (uint32_t)((i * d.plane + (1 + EY[i]) * d.pitch + (1 + EX[i])) * 4));
+            if (THERMAL) {
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                    bg[j] = BufIO<float>::ld(rgin, vo, (uint32_t)((j * d.plane + (1 + TYv[j]) * d.pitch + (1 + TXv[j])) * 4));
+            }
             const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
             r = med.load(o4);
             uu[0] = BufIO<float>::ld(rut, o4, 0u);
             uu[1] = BufIO<float>::ld(rut, o4, pb4);
             uu[2] = THETA ? BufIO<float>::ld(rut, o4, 2 * pb4) : 0.0f;
             uu[3] = THETA ? BufIO<float>::ld(rut, o4, 3 * pb4) : 0.0f;
+            dT = THERMAL ? BufIO<float>::ld(rut, o4, 4 * pb4) : 0.0f;
         };
-        float bn[8], un[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        float bn[8], gn[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f}, un[4] = {0.0f, 0.0f, 0.0f, 0.0f}, dn = 0.0f;
         CellRaw rn{0.0f, 0.0f, 0.0f};
-        if ((int)threadIdx.x < EN) fetch(threadIdx.x, bn, rn, un);
+        if ((int)threadIdx.x < EN) fetch(threadIdx.x, bn, gn, rn, un, dn);
         for (int e = threadIdx.x; e < EN; e += ANT) {
-            float bb[8], uu[4];
+            float bb[8], bg[5], uu[4];
 #pragma unroll
             for (int i = 0; i < 8; ++i) bb[i] = bn[i];
 #pragma unroll
+            for (int j = 0; j < 5; ++j) bg[j] = gn[j];
+#pragma unroll
             for (int k = 0; k < 4; ++k) uu[k] = un[k];
             const CellRaw r = rn;
-            if (e + ANT < EN) fetch(e + ANT, bn, rn, un);
+            const float dT = dn;
+            if (e + ANT < EN) fetch(e + ANT, bn, gn, rn, un, dn);
             const int ex = e % EW, ey = e / EW;
-            finish_a(bb, r, uu, ex, ey, x0 - 1 + ex, y0 - 1 + ey);
+            finish_a(bb, bg, r, uu, dT, ex, ey, x0 - 1 + ex, y0 - 1 + ey);
         }
     } else {
         for (int e = threadIdx.x; e < EN; e += ANT) {
@@ -453,15 +530,17 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
                 if (d.bc_y != BC_PERIODIC) continue;
                 gy = ((gy % d.ny) + d.ny) % d.ny;
             }
-            float bb[8];
+            float bb[8], bg[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             gather_transposed_buf(d, rlin, gx, gy, bb);
+            if (THERMAL) gather_thermal_transposed_buf(d, rgin, gx, gy, bg);
             const uint32_t o4 = (uint32_t)(((int64_t)gy * d.pitch + gx) * 4);
             float uu[4] = {BufIO<float>::ld(rut, o4, 0u), BufIO<float>::ld(rut, o4, pb4), 0.0f, 0.0f};
             if (THETA) {
                 uu[2] = BufIO<float>::ld(rut, o4, 2 * pb4);
                 uu[3] = BufIO<float>::ld(rut, o4, 3 * pb4);
             }
-            finish_a(bb, med.load(o4), uu, ex, ey, gx, gy);
+            const float dT = THERMAL ? BufIO<float>::ld(rut, o4, 4 * pb4) : 0.0f;
+            finish_a(bb, bg, med.load(o4), uu, dT, ex, ey, gx, gy);
         }
     }
     __syncthreads();
@@ -471,7 +550,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
     // first node's stores.
     const float *flat = &lds[0][0][0];
     CellRaw rawB[NB];
-    float uB[NB][4], gB[NB], gkB[NB];
+    float uB[NB][4], dTB[NB], gB[NB], gkB[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
         const int q = threadIdx.x + k * ANT;
@@ -483,6 +562,7 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
         uB[k][1] = BufIO<float>::ld(rutm, o4, pb4);
         uB[k][2] = THETA ? BufIO<float>::ld(rutm, o4, 2 * pb4) : 0.0f;
         uB[k][3] = THETA ? BufIO<float>::ld(rutm, o4, 3 * pb4) : 0.0f;
+        dTB[k] = THERMAL ? BufIO<float>::ld(rutm, o4, 4 * pb4) : 0.0f;
         gB[k] = BufIO<float>::ld(rg, o4, 0u);
         gkB[k] = gkappa ? BufIO<float>::ld(rgk, o4, 0u) : 0.0f;
     }
@@ -511,14 +591,41 @@ __global__ __launch_bounds__(ANT) __attribute__((amdgpu_waves_per_eu(6))) void k
                 bb[i] = flat[src];
             }
         }
+        float bg[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (THERMAL) {
+            // b_j(x) = a_g,j(x + e_j); across a wall the node's own opposite link,
+            // with the sign flipped at the isothermal (anti-bounce-back) walls
+            bg[0] = ldsg[(ly + 1) * EW + lx + 1];
+#pragma unroll
+            for (int j = 1; j < 5; ++j) {
+                int kind = 0;
+                if (!interior) {
+                    const int sx = gx + TXv[j], sy = gy + TYv[j];
+                    if (TXv[j] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) kind = 2;
+                    if (TYv[j] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) kind = 1;
+                }
+                const int src = kind == 0 ? (j * EH + ly + 1 + TYv[j]) * EW + lx + 1 + TXv[j]
+                                          : (TOPP[j] * EH + ly + 1) * EW + lx + 1;
+                const float v = ldsg[src];
+                bg[j] = kind == 2 ? -v : v;
+            }
+        }
         const Cell c = med.cell(d, rawB[k]);
         float a[8];
         ParamBar pb;
-        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * d.ay, uB[k][0], uB[k][1], uB[k][2], uB[k][3], a, pb);
+        float ag[5], ubx = 0.0f, uby = 0.0f;
+        if (THERMAL) thermal_collide_adjoint(bg, d, uB[k][0], uB[k][1], dTB[k], ag, ubx, uby);
+        const float ay = THERMAL ? d.ay + d.gbeta * dTB[k] : d.ay;
+        collide_adjoint(bb, d, c, c.phi * d.ax, c.phi * ay, uB[k][0], uB[k][1], uB[k][2], uB[k][3], a, pb, ubx, uby);
 #pragma unroll
         for (int i = 0; i < 8; ++i) BufIO<float>::st(rlout, o4, (uint32_t)i * pb4, a[i]);
+        if (THERMAL) {
+            const float Tb = c.phi * d.gbeta * pb.pay;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) BufIO<float>::st(rgout, o4, (uint32_t)j * pb4, ag[j] + Tb);
+        }
         float gp, gk;
-        medium_gradient<MK>(d, c, rawB[k].kappa, pb, d.ax, d.ay, gp, gk);
+        medium_gradient<MK>(d, c, rawB[k].kappa, pb, d.ax, ay, gp, gk);
         BufIO<float>::st(rg, o4, 0u, (gB[k] + gA[ly][lx]) + gp);
         if (gkappa) BufIO<float>::st(rgk, o4, 0u, (gkB[k] + gkA[ly][lx]) + gk);
         if (THETA) {
@@ -800,14 +907,33 @@ hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_ou
     const int tiles_x = (d.nx + ATW - 1) / ATW, tiles_y = (d.ny + ATH - 1) / ATH;
     const dim3 grid((unsigned)(tiles_x * tiles_y));
     const bool ergun = medium_kind(d) == MK_ERGUN;
+    const float *no_g = nullptr;
+    float *no_gout = nullptr;
 #define MRT_ADJ2(TH, MK) \
-    hipLaunchKernelGGL((k_adjoint_step2<TH, MK>), grid, dim3(ANT), 0, st, d, lam_in, lam_out, u_t, u_tm1, gphi, \
-                       gkappa, tiles_x, 1, acc)
+    hipLaunchKernelGGL((k_adjoint_step2<TH, MK, false>), grid, dim3(ANT), 0, st, d, lam_in, lam_out, no_g, no_gout, \
+                       u_t, u_tm1, gphi, gkappa, tiles_x, 1, acc)
     if (acc && ergun) MRT_ADJ2(true, MK_ERGUN);
     else if (acc) MRT_ADJ2(true, MK_ANY);
     else if (ergun) MRT_ADJ2(false, MK_ERGUN);
     else MRT_ADJ2(false, MK_ANY);
 #undef MRT_ADJ2
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step2_thermal(const Dom &d, const float *lam_in, float *lam_out, const float *lamg_in,
+                                        float *lamg_out, const float *u_t, const float *u_tm1, float *gphi,
+                                        float *gkappa, double *acc, hipStream_t st) {
+    const int tiles_x = (d.nx + ATW - 1) / ATW, tiles_y = (d.ny + ATH - 1) / ATH;
+    const dim3 grid((unsigned)(tiles_x * tiles_y));
+    const bool ergun = medium_kind(d) == MK_ERGUN;
+#define MRT_ADJ2T(TH, MK) \
+    hipLaunchKernelGGL((k_adjoint_step2<TH, MK, true>), grid, dim3(ANT), 0, st, d, lam_in, lam_out, lamg_in, \
+                       lamg_out, u_t, u_tm1, gphi, gkappa, tiles_x, 1, acc)
+    if (acc && ergun) MRT_ADJ2T(true, MK_ERGUN);
+    else if (acc) MRT_ADJ2T(true, MK_ANY);
+    else if (ergun) MRT_ADJ2T(false, MK_ERGUN);
+    else MRT_ADJ2T(false, MK_ANY);
+#undef MRT_ADJ2T
     return hipGetLastError();
 }
 
@@ -839,32 +965,6 @@ hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out
 
 // ------------------------------------------------------ thermal coupling
 
-// Reverse mode of the D2Q5 collision (Eq. B.2 with varpi = 0, deviations from
-// T0/5): given the adjoint bg of g+, the adjoint ag of the pre-collision g
-// (through n = N g, T = T0 + n_0 and n^eq of Eq. B.6) and the adjoint of the
-// flow velocity it uses, added to ubx, uby.
-__device__ __forceinline__ void thermal_collide_adjoint(const float bg[5], const Dom &d, float ux, float uy,
-                                                        float dT, float ag[5], float &ubx, float &uby) {
-    // adjoint of n+: diag(1/5, 1/2, 1/2, 1/20, 1/4) N bg (g+ = N^T diag(...) n+)
-    const float nb0 = 0.2f * ((bg[0] + bg[1]) + (bg[2] + bg[3]) + bg[4]);
-    const float nb1 = 0.5f * (bg[1] - bg[3]);
-    const float nb2 = 0.5f * (bg[2] - bg[4]);
-    const float nb3 = 0.05f * ((bg[1] + bg[2]) + (bg[3] + bg[4]) - 4.0f * bg[0]);
-    const float nb4 = 0.25f * ((bg[1] - bg[2]) + (bg[3] - bg[4]));
-    const float T = d.T0 + dT;
-    // n1+ = n1 - zT (n1 - ux T / sigma), T = T0 + n0; n0+ = n0; n3, n4 relax to 0
-    const float nbar0 = nb0 + d.zT * (ux * nb1 + uy * nb2) * d.inv_sigma;
-    const float nbar1 = (1.0f - d.zT) * nb1, nbar2 = (1.0f - d.zT) * nb2;
-    const float nbar3 = (1.0f - d.z3) * nb3, nbar4 = (1.0f - d.z4) * nb4;
-    ubx += d.zT * T * d.inv_sigma * nb1;
-    uby += d.zT * T * d.inv_sigma * nb2;
-    // ag = N^T nbar
-    ag[0] = nbar0 - 4.0f * nbar3;
-    ag[1] = (nbar0 + nbar1) + (nbar3 + nbar4);
-    ag[2] = (nbar0 + nbar2) + (nbar3 - nbar4);
-    ag[3] = (nbar0 - nbar1) + (nbar3 + nbar4);
-    ag[4] = (nbar0 - nbar2) + (nbar3 - nbar4);
-}
 
 // Transpose of the D2Q5 gather: b_j(x) = a_j(x + e_j), or across a wall the
 // node's own a of the opposite link, negated on the Dirichlet walls

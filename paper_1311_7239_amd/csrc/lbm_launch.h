@@ -100,6 +100,9 @@ hipError_t launch_adjoint_step(const Dom &d, const float *lam_in, float *lam_out
 // u(t) and u(t-1).
 hipError_t launch_adjoint_step2(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
                                 const float *u_tm1, float *gphi, float *gkappa, double *acc, hipStream_t st);
+hipError_t launch_adjoint_step2_thermal(const Dom &d, const float *lam_in, float *lam_out, const float *lamg_in,
+                                        float *lamg_out, const float *u_t, const float *u_tm1, float *gphi,
+                                        float *gkappa, double *acc, hipStream_t st);
 hipError_t launch_adjoint_step3(const Dom &d, const float *lam_in, float *lam_out, const float *u_t,
                                 const float *u_tm1, const float *u_tm2, float *gphi, float *gkappa, double *acc,
                                 hipStream_t st);

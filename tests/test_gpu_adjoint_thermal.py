@@ -96,9 +96,11 @@ def test_thermal_adjoint_matches_oracle_differences():
         assert abs(th[name] - fd) <= 1e-4 * abs(fd), name
 
 
-def test_thermal_gradients_equal_for_one_and_two_cycle_recomputation():
-    """The recomputation two cycles per pass (recording u and dT at both) gives the
-    gradients of the one-cycle path bit for bit."""
+def test_thermal_gradients_equal_for_one_and_two_cycle_passes():
+    """Two cycles per pass (the recomputation recording u and dT at both, the sweep two
+    adjoint steps per pass) give the porosity gradient of the one-cycle path bit for
+    bit; the parameter gradients, whose per-thread FP32 partial sums are grouped by the
+    pass's tiles, agree to that rounding (1e-9 relative measured, held at 1e-6)."""
     c = _case()
     col = c.nx // 2
     out = []
@@ -116,4 +118,6 @@ def test_thermal_gradients_equal_for_one_and_two_cycle_recomputation():
         torch.cuda.synchronize()
         out.append((g.cpu().numpy(), th))
     assert np.array_equal(out[0][0], out[1][0])
-    assert out[0][1] == out[1][1]
+    for name in ("nu", "ax", "ay", "lid_ux"):
+        a, b = out[0][1][name], out[1][1][name]
+        assert abs(a - b) <= 1e-6 * max(abs(a), 1e-300), (name, a, b)
