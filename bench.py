@@ -158,9 +158,8 @@ def extras(args):
     for storage, name, bpn in ((lbm.FP32_DEV, "batch256_f32", 64), (lbm.FP16_DEV, "batch256_f16", 32)):
         log(f"bench: ragged batch of 256 lid cavities ({name})")
         cases = I.cavity_batch()
-        b = lbm.batch_for_cases(cases, storage=storage,
-                                tune_cache=os.path.join(ROOT, "gpurun_out", "tune_cache.txt")
-                                if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+        # MRTLBM_TUNE_CACHE: optional autotuner cache file (tuned afresh without it)
+        b = lbm.batch_for_cases(cases, storage=storage, tune_cache=os.environ.get("MRTLBM_TUNE_CACHE"))
         ms = timed(b, args.steps, args.warmup)
         tb = b.time_blocking()
         per_launch = ms * tb["cycles_per_pass"]
