@@ -223,7 +223,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design note, not part of this build)", file=sys.stderr)
+              "(the library runs one domain or batch per GPU; the multi-GPU decomposition is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
