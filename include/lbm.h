@@ -280,9 +280,9 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * lbm_backward uses passes of the same length (recording u at every cycle)
  * and its adjoint sweep two or three steps per pass in modes 2 and 3 (two for
  * thermal runs). Default for single domains that allow it:
- * 3 for isothermal FP32 domains of at least 2^20 nodes, 2 for FP16, for thermal
- * domains (whose D2Q5 field is kept in LDS beside the populations) and for
- * smaller domains (with 8-row tiles), 1 for the others; for batches, the
+ * 3 for isothermal domains of at least 2^20 nodes, 2 for thermal domains
+ * (whose D2Q5 field is kept in LDS beside the populations) and for smaller
+ * domains (with 8-row tiles), 1 for the others; for batches, the
  * autotuner's choice among 1, 2 and 3 (a batch switched to 3 walks 64 x 16
  * tiles, which its two-cycle passes then use too; switching uploads that tile
  * table and synchronises the stream). ENOTSUP for on-node walls,

@@ -533,14 +533,14 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     D.L = L;
     c->rec_cap = cap;
     // several cycles per pass (the multi-cycle kernels implement bounce-back walls
-    // only): from 2^20 nodes isothermal FP32 takes three, FP16 and thermal domains
-    // two; smaller domains take two with 64 x 8 tiles, which keep more workgroups
-    // in flight (512^2 cavity: 81 GLUPS against 52 for one cycle per pass and 71
-    // for three)
+    // only): from 2^20 nodes isothermal domains take three (8192^2: FP32 177 against
+    // 146 GLUPS for two, FP16 190 against 188) and thermal domains two; smaller
+    // domains take two with 64 x 8 tiles, which keep more workgroups in flight
+    // (512^2 cavity: 81 GLUPS against 52 for one cycle per pass and 71 for three)
     if (!two_cycle_possible(c)) {
         c->tblock = 1;
     } else if ((int64_t)d->nx * d->ny >= ((int64_t)1 << 20)) {
-        c->tblock = (d->storage == LBM_FP16_DEV || !three_cycle_possible(c)) ? 2 : 3;
+        c->tblock = three_cycle_possible(c) ? 3 : 2;
     } else {
         c->tblock = 2;
         c->tb_rows = 8;
