@@ -272,21 +272,22 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * 2 (temporal blocking: one launch gathers, collides on its tile plus a
  * one-node ring kept in LDS, then collides again, so each population crosses
  * HBM about once per two cycles) or 3 (a two-node ring, three collisions per
- * launch; isothermal domains). Results are bitwise identical in every mode.
+ * launch). Results are bitwise identical in every mode.
  * Multi-cycle passes are skipped for t = 0 and for the last cycle of each
  * lbm_step call (so lbm_reduce's residual always compares u(t) with u(t-1));
  * while recording for lbm_backward no pass steps over a checkpoint time.
  * Shorter passes fill in where fewer cycles remain. The recomputation inside
  * lbm_backward uses passes of the same length (recording u at every cycle)
  * and its adjoint sweep two or three steps per pass in modes 2 and 3 (two for
- * thermal runs). Default for single domains that allow it:
- * 3 for isothermal domains of at least 2^20 nodes, 2 for thermal domains
- * (whose D2Q5 field is kept in LDS beside the populations) and for smaller
- * domains (with 8-row tiles), 1 for the others; for batches, the
+ * thermal runs). The D2Q5 field of a thermal domain rides in LDS beside the
+ * populations. Default for single domains that allow it: 3 for isothermal
+ * domains of at least 2^20 nodes and thermal domains of at least 2^22, 2 for
+ * smaller ones (with 8-row tiles below 2^20 nodes and for thermal domains), 1
+ * for the others; for batches, the
  * autotuner's choice among 1, 2 and 3 (a batch switched to 3 walks 64 x 16
  * tiles, which its two-cycle passes then use too; switching uploads that tile
  * table and synchronises the stream). ENOTSUP for on-node walls,
- * population or thermal buffers of 4 GiB or more, mode 3 on thermal domains, a
+ * population or thermal buffers of 4 GiB or more, mode 3 on thermal batches, a
  * mode a batch has no tuned schedule for; EINVAL for another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
 

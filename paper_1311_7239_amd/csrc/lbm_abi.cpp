@@ -273,9 +273,10 @@ bool two_cycle_possible(const lbm_ctx *c) {
     return true;
 }
 
-// Three cycles per pass: single isothermal domains only.
+// Three cycles per pass: single domains (with or without the D2Q5 field) and
+// isothermal batches.
 bool three_cycle_possible(const lbm_ctx *c) {
-    return !c->batch && two_cycle_possible(c) && !c->dom[0].desc.thermal.enabled;
+    return two_cycle_possible(c) && !(c->batch && c->batch_thermal);
 }
 
 int device_fail(lbm_ctx *c, hipError_t e, const char *what) {
@@ -534,13 +535,18 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     c->rec_cap = cap;
     // several cycles per pass (the multi-cycle kernels implement bounce-back walls
     // only): from 2^20 nodes isothermal domains take three (8192^2: FP32 177 against
-    // 146 GLUPS for two, FP16 190 against 188) and thermal domains two; smaller
-    // domains take two with 64 x 8 tiles, which keep more workgroups in flight
-    // (512^2 cavity: 81 GLUPS against 52 for one cycle per pass and 71 for three)
+    // 146 GLUPS for two, FP16 190 against 188), thermal domains three from 2^22
+    // nodes (their 13 LDS planes leave two workgroups per CU: convection 2048^2 92
+    // against 84 GLUPS, 4096^2 105 against 88, but 1024^2 80 against 87) and two
+    // below; smaller domains take two with 64 x 8 tiles, which keep more workgroups
+    // in flight (512^2 cavity: 81 GLUPS against 52 for one cycle per pass and 71
+    // for three)
+    const int64_t nodes = (int64_t)d->nx * d->ny;
     if (!two_cycle_possible(c)) {
         c->tblock = 1;
-    } else if ((int64_t)d->nx * d->ny >= ((int64_t)1 << 20)) {
-        c->tblock = three_cycle_possible(c) ? 3 : 2;
+    } else if (nodes >= ((int64_t)1 << 20)) {
+        const bool three = three_cycle_possible(c) && (!d->thermal.enabled || nodes >= ((int64_t)1 << 22));
+        c->tblock = three ? 3 : 2;
     } else {
         c->tblock = 2;
         c->tb_rows = 8;
@@ -890,8 +896,8 @@ int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (cycles_per_pass < 1 || cycles_per_pass > 3) return fail(LBM_EINVAL, "cycles per pass must be 1, 2 or 3");
-    if (cycles_per_pass == 3 && c->dom[0].desc.thermal.enabled)
-        return fail(LBM_ENOTSUP, "thermal domains advance one or two cycles per pass");
+    if (cycles_per_pass == 3 && c->batch && c->batch_thermal)
+        return fail(LBM_ENOTSUP, "thermal batches advance one or two cycles per pass");
     if (cycles_per_pass >= 2 && any_on_node_walls(c))
         return fail(LBM_ENOTSUP, "on-node (extrapolated) walls advance one cycle per pass");
     if (cycles_per_pass >= 2 && !two_cycle_possible(c))

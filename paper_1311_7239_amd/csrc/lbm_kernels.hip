@@ -336,16 +336,21 @@ __device__ __forceinline__ void record_node(const Dom &d, BufRes rec, uint32_t o
     }
 }
 
-// One node's record held back until the next node's loads have been issued.
+// One node's record held back until the next node's loads have been issued
+// (with THERMAL also dT, plane 4).
+template <bool THERMAL>
 struct Pending {
     uint32_t o4 = 0u;
-    float ux = 0.0f, uy = 0.0f, n7 = 0.0f, n8 = 0.0f;
+    float ux = 0.0f, uy = 0.0f, n7 = 0.0f, n8 = 0.0f, dT = 0.0f;
     bool on = false;
-    __device__ __forceinline__ void hold(uint32_t o, float a, float b, float c, float e) {
-        o4 = o; ux = a; uy = b; n7 = c; n8 = e; on = true;
+    __device__ __forceinline__ void hold(uint32_t o, float a, float b, float c, float e, float t) {
+        o4 = o; ux = a; uy = b; n7 = c; n8 = e; dT = t; on = true;
     }
     __device__ __forceinline__ void flush(const Dom &d, BufRes rec) {
-        if (on) record_node(d, rec, o4, ux, uy, n7, n8);
+        if (on) {
+            record_node(d, rec, o4, ux, uy, n7, n8);
+            if (THERMAL) BufIO<float>::st_nt(rec, o4, (uint32_t)(4 * d.plane * 4), dT);
+        }
         on = false;
     }
 };
@@ -626,6 +631,28 @@ __device__ __forceinline__ void lds_gather(const Dom &d, const float *flat, bool
     }
 }
 
+// The D2Q5 links of node (gx, gy) from an LDS layout [5][H][W] at position
+// (cx, cy): the neighbour's value, or across a wall the node's own opposite
+// link (bounce-back on y walls, anti-bounce-back on x walls), as one read at a
+// selected index.
+template <int W, int H>
+__device__ __forceinline__ void lds_gather_thermal(const Dom &d, const float *flat, bool interior, int gx, int gy,
+                                                   int cx, int cy, float g[5]) {
+    g[0] = flat[cy * W + cx];
+#pragma unroll
+    for (int j = 1; j < 5; ++j) {
+        int kind = 0;
+        if (!interior) {
+            const int sx = gx - TXv[j], sy = gy - TYv[j];
+            if (TXv[j] != 0 && (sx < 0 || sx >= d.nx) && d.bc_x != BC_PERIODIC) kind = (sx < 0) ? 2 : 3;
+            if (TYv[j] != 0 && (sy < 0 || sy >= d.ny) && d.bc_y != BC_PERIODIC) kind = 1;
+        }
+        const int src = kind == 0 ? (j * H + cy - TYv[j]) * W + cx - TXv[j] : (TOPP[j] * H + cy) * W + cx;
+        const float v = flat[src];
+        g[j] = (kind <= 1) ? v : ((kind == 2) ? d.abbh - v : d.abbc - v);
+    }
+}
+
 
 // Temporal blocking over three cycles: a workgroup owns a TW x TH tile. Phase A
 // gathers f(t) from HBM on the tile plus a two-node ring and collides into LDS;
@@ -637,8 +664,9 @@ __device__ __forceinline__ void lds_gather(const Dom &d, const float *flat, bool
 // With REC (FP32 recomputation for the adjoint) u and, with rec_stress, the
 // stress moments of the tile nodes are recorded at t (d.urec), t + 1 (urec1)
 // and t + 2 (urec2).
-template <typename S, int TW, int TH, int NT, bool REC, int MK>
-__device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *urec1, float *urec2, float *lds) {
+template <typename S, int TW, int TH, int NT, bool REC, int MK, bool THERMAL>
+__device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *urec1, float *urec2, float *lds,
+                                           float *ldsg) {
     constexpr int AW = TW + 4, AH = TH + 4, AN = AW * AH;
     constexpr int BW = TW + 2, BH = TH + 2, BN = BW * BH;
     constexpr int ES = (int)sizeof(S);
@@ -648,47 +676,61 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
     const MediumSrc<MK> med(d);
     const bool interior = x0 >= 3 && x0 + TW + 3 <= d.nx && y0 >= 3 && y0 + TH + 3 <= d.ny;
     // resources of the three recorded steps, each built where its phase starts
-    const uint32_t rbytes = REC ? (uint32_t)((d.rec_stress ? 4 : 2) * d.plane * 4) : 0u;
+    const uint32_t rbytes = REC ? (uint32_t)((THERMAL ? 5 : (d.rec_stress ? 4 : 2)) * d.plane * 4) : 0u;
+    // D2Q5 buffers (FP32, five planes, below 4 GiB)
+    const uint32_t gbytes = THERMAL ? (uint32_t)(5 * d.plane * 4) : 0u;
+    const BufRes rgin = buf_res(THERMAL ? d.gin : nullptr, gbytes), rgout = buf_res(THERMAL ? d.gout : nullptr, gbytes);
 
     // CDNA's vector-memory counter retires loads and stores in order, so a wait
     // for a load also waits for every store issued before it. Each phase
     // therefore issues its global loads before the stores that belong to the
     // previous node: records are held one node (Pending) and phase C fetches
     // its medium values before its first store.
-    Pending pend;
+    Pending<THERMAL> pend;
 
     // phase A: s_{t+1} on the tile + 2 ring
     const BufRes rr0 = buf_res(REC ? d.urec : nullptr, rbytes);
     for (int e = threadIdx.x; e < AN; e += NT) {
         const int ex = e % AW, ey = e / AW;
         int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
-        float f[8];
+        float f[8], g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (interior) {
             const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * ES);
 #pragma unroll
             for (int i = 0; i < 8; ++i)
                 f[i] = BufIO<S>::ld(rin, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
+            if (THERMAL) {
+                const uint32_t vg = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * 4);
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                    g[j] = BufIO<float>::ld(rgin, vg, (uint32_t)((j * d.plane + (1 - TYv[j]) * d.pitch + (1 - TXv[j])) * 4));
+            }
         } else {
             if (!wrap_node(d, gx, gy)) continue;
             gather_general_buf<S>(d, rin, gx, gy, f);
+            if (THERMAL) gather_thermal_buf(d, rgin, gx, gy, g);
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
         const CellRaw raw = med.load((uint32_t)(o * 4));
         if (REC) pend.flush(d, rr0);
         const Cell c = med.cell(d, raw);
-        float ux, uy, n7, n8;
-        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
+        float ux, uy, n7, n8, dT;
+        node_update<THERMAL>(d, c, f, g, ux, uy, n7, n8, dT);
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[(i * AH + ey) * AW + ex] = (float)(S)f[i];
+        if (THERMAL) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) ldsg[(j * AH + ey) * AW + ex] = g[j];
+        }
         if (REC && ex >= 2 && ex < TW + 2 && ey >= 2 && ey < TH + 2 && x0 - 2 + ex < d.nx && y0 - 2 + ey < d.ny)
-            pend.hold((uint32_t)(o * 4), ux, uy, n7, n8);
+            pend.hold((uint32_t)(o * 4), ux, uy, n7, n8, dT);
     }
     if (REC) pend.flush(d, rr0);
     lds_barrier();
 
     // phase B: s_{t+2} on the tile + 1 ring, kept in registers
     const BufRes rr1 = buf_res(urec1, rbytes);
-    float fb[NBB][8];
+    float fb[NBB][8], gb[NBB][THERMAL ? 5 : 1];
     int slot[NBB];
 #pragma unroll
     for (int k = 0; k < NBB; ++k) {
@@ -702,11 +744,17 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
         const CellRaw raw = med.load((uint32_t)(o * 4));
         if (REC) pend.flush(d, rr1);
         lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fb[k]);
+        float g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (THERMAL) lds_gather_thermal<AW, AH>(d, ldsg, interior, gx, gy, bx + 1, by + 1, g);
         const Cell c = med.cell(d, raw);
-        float ux, uy, n7, n8;
-        collide(fb[k], d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
+        float ux, uy, n7, n8, dT;
+        node_update<THERMAL>(d, c, fb[k], g, ux, uy, n7, n8, dT);
+        if (THERMAL) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) gb[k][THERMAL ? j : 0] = g[j];
+        }
         if (REC && bx >= 1 && bx <= TW && by >= 1 && by <= TH && x0 - 1 + bx < d.nx && y0 - 1 + by < d.ny)
-            pend.hold((uint32_t)(o * 4), ux, uy, n7, n8);
+            pend.hold((uint32_t)(o * 4), ux, uy, n7, n8, dT);
         slot[k] = e;
     }
     if (REC) pend.flush(d, rr1);
@@ -717,6 +765,10 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
         const int bx = slot[k] % BW, by = slot[k] / BW;
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[(i * BH + by) * BW + bx] = (float)(S)fb[k][i];
+        if (THERMAL) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) ldsg[(j * BH + by) * BW + bx] = gb[k][THERMAL ? j : 0];
+        }
     }
     lds_barrier();
 
@@ -737,28 +789,40 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
         const int lx = q % TW, ly = q / TW;
         const int gx = x0 + lx, gy = y0 + ly;
         if (q >= TW * TH || gx >= d.nx || gy >= d.ny) continue;
-        float f[8];
+        float f[8], g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         lds_gather<BW, BH>(d, lds, interior, gx, gy, lx + 1, ly + 1, f);
+        if (THERMAL) lds_gather_thermal<BW, BH>(d, ldsg, interior, gx, gy, lx + 1, ly + 1, g);
         const int64_t o = (int64_t)gy * d.pitch + gx;
         const Cell c = med.cell(d, rawC[k]);
-        float ux, uy, n7, n8;
-        collide(f, d, c, c.phi * d.ax, c.phi * d.ay, ux, uy, n7, n8);
+        float ux, uy, n7, n8, dT;
+        node_update<THERMAL>(d, c, f, g, ux, uy, n7, n8, dT);
         const uint32_t vo = (uint32_t)(o * ES);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             if (d.nt_store) BufIO<S>::st_nt(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
             else BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
         }
-        if (REC) record_node(d, rr2, (uint32_t)(o * 4), ux, uy, n7, n8);
+        if (THERMAL) {
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                if (d.nt_store) BufIO<float>::st_nt(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
+                else BufIO<float>::st(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
+            }
+        }
+        if (REC) {
+            record_node(d, rr2, (uint32_t)(o * 4), ux, uy, n7, n8);
+            if (THERMAL) BufIO<float>::st_nt(rr2, (uint32_t)(o * 4), (uint32_t)(4 * d.plane * 4), dT);
+        }
     }
 }
 
-template <typename S, int TW, int TH, int NT, bool REC, int MK>
+template <typename S, int TW, int TH, int NT, bool REC, int MK, bool THERMAL>
 __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
     __shared__ float lds[8 * (TH + 4) * (TW + 4)];
+    __shared__ float ldsg[THERMAL ? 5 * (TH + 4) * (TW + 4) : 1];
     int b = blockIdx.x;
     if (swz) b = xcd_swizzle(b, gridDim.x);
-    step3_tile<S, TW, TH, NT, REC, MK>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec1, urec2, lds);
+    step3_tile<S, TW, TH, NT, REC, MK, THERMAL>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec1, urec2, lds, ldsg);
 }
 
 // Persistent batched three-cycle pass over a table of TW x TH tiles (isothermal
@@ -773,7 +837,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
     for (int t = t0; t < t1; ++t) {
         const int4 tl = tiles[t];
         const Dom d = doms[2 * tl.x + parity];
-        step3_tile<S, TW, TH, NT, false, MK_BRANCHED>(d, tl.y * TW, tl.z * TH, nullptr, nullptr, lds);
+        step3_tile<S, TW, TH, NT, false, MK_BRANCHED, false>(d, tl.y * TW, tl.z * TH, nullptr, nullptr, lds, nullptr);
         lds_barrier();   // the next tile's phase A rewrites the LDS
     }
 }
@@ -785,15 +849,25 @@ void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y) {
     *tiles_y = (ny + STEP3_TH - 1) / STEP3_TH;
 }
 
-template <int MK>
+template <int MK, bool TH>
 static const void *step3_fn_t(int storage, bool rec) {
-    if (rec) return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, true, MK> : nullptr;
-    return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, false, MK>
-                             : (const void *)&k_step3<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, false, MK>;
+    if (rec)
+        return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, true, MK, TH> : nullptr;
+    return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, false, MK, TH>
+                             : (const void *)&k_step3<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, false, MK, TH>;
+}
+
+template <bool TH>
+static const void *step3_fn_th(const Dom &d, int storage, bool rec) {
+    switch (medium_kind(d)) {
+    case MK_ERGUN: return step3_fn_t<MK_ERGUN, TH>(storage, rec);
+    case MK_UNIFORM: return step3_fn_t<MK_UNIFORM, TH>(storage, rec);
+    default: return step3_fn_t<MK_ANY, TH>(storage, rec);
+    }
 }
 
 const void *step3_kernel_fn(const Dom &d, int storage, bool rec) {
-    return medium_kind(d) == MK_ERGUN ? step3_fn_t<MK_ERGUN>(storage, rec) : step3_fn_t<MK_ANY>(storage, rec);
+    return d.thermal ? step3_fn_th<true>(d, storage, rec) : step3_fn_th<false>(d, storage, rec);
 }
 
 const void *step3_batch_kernel_fn(int storage) {
@@ -812,7 +886,6 @@ hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, in
 }
 
 hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, float *urec2, hipStream_t st) {
-    if (d.thermal) return hipErrorInvalidValue;
     const bool rec = urec1 != nullptr;
     const void *fn = step3_kernel_fn(d, storage, rec);
     if (!fn || (rec && (!d.urec || !urec2))) return hipErrorInvalidValue;

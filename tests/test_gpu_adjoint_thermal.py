@@ -96,15 +96,15 @@ def test_thermal_adjoint_matches_oracle_differences():
         assert abs(th[name] - fd) <= 1e-4 * abs(fd), name
 
 
-def test_thermal_gradients_equal_for_one_and_two_cycle_passes():
-    """Two cycles per pass (the recomputation recording u and dT at both, the sweep two
-    adjoint steps per pass) give the porosity gradient of the one-cycle path bit for
-    bit; the parameter gradients, whose per-thread FP32 partial sums are grouped by the
-    pass's tiles, agree to that rounding (1e-9 relative measured, held at 1e-6)."""
+def test_thermal_gradients_equal_for_one_two_and_three_cycle_passes():
+    """Two or three cycles per pass (the recomputation recording u and dT at each, the
+    sweep two adjoint steps per pass) give the porosity gradient of the one-cycle path
+    bit for bit; the parameter gradients, whose per-thread FP32 partial sums are grouped
+    by the pass's tiles, agree to that rounding (1e-9 relative measured, held at 1e-6)."""
     c = _case()
     col = c.nx // 2
     out = []
-    for cycles in (1, 2):
+    for cycles in (1, 2, 3):
         s = lbm.solver_for_case(c, ckpt_every=64, max_steps_recorded=STEPS)
         s.set_time_blocking(cycles)
         T = _conduction(c)
@@ -117,7 +117,8 @@ def test_thermal_gradients_equal_for_one_and_two_cycle_passes():
         g, _, th = s.backward_params(dLdu)
         torch.cuda.synchronize()
         out.append((g.cpu().numpy(), th))
-    assert np.array_equal(out[0][0], out[1][0])
-    for name in ("nu", "ax", "ay", "lid_ux"):
-        a, b = out[0][1][name], out[1][1][name]
-        assert abs(a - b) <= 1e-6 * max(abs(a), 1e-300), (name, a, b)
+    for k in (1, 2):
+        assert np.array_equal(out[0][0], out[k][0]), k
+        for name in ("nu", "ax", "ay", "lid_ux"):
+            a, b = out[0][1][name], out[k][1][name]
+            assert abs(a - b) <= 1e-6 * max(abs(a), 1e-300), (k, name, a, b)

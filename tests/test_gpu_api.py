@@ -84,8 +84,10 @@ def test_argument_checks_on_a_live_context():
     assert e.value.status == lbm.EINVAL
     t = lbm.solver_for_case(I.natural_convection(n=32))
     t.set_time_blocking(2)
+    t.set_time_blocking(3)
+    w = lbm.solver_for_case(I.natural_convection(n=32, nee=True))
     with pytest.raises(lbm.LBMError) as e:
-        t.set_time_blocking(3)
+        w.set_time_blocking(2)       # on-node walls: one cycle per pass
     assert e.value.status == lbm.ENOTSUP
     with pytest.raises(lbm.LBMError) as e:
         lbm.lib().lbm_step and s.step(-1)

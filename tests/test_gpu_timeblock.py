@@ -176,9 +176,30 @@ def test_thermal_two_cycles_per_pass_is_bitwise_equal(name, case, storage, graph
         torch.cuda.synchronize()
         assert torch.equal(fa, fb), (name, chunk)
         assert torch.equal(ga, gb), (name, chunk)
-    with pytest.raises(lbm.LBMError) as e:
-        tb.set_time_blocking(3)
-    assert e.value.status == lbm.ENOTSUP
+
+
+@pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
+@pytest.mark.parametrize("name,case", thermal_cases(), ids=[n for n, _ in thermal_cases()])
+@pytest.mark.parametrize("graph", [0, 9])
+def test_thermal_three_cycles_per_pass_is_bitwise_equal(name, case, storage, graph):
+    """Three cycles per pass with the D2Q5 field (two-node ring of both fields in LDS)
+    equal one cycle per pass bit for bit, for flow and temperature."""
+    ref = lbm.solver_for_case(case, storage=storage)
+    ref.set_time_blocking(1)
+    tb = lbm.solver_for_case(case, storage=storage)
+    tb.set_time_blocking(3)
+    tb.set_graph_steps(graph)
+    df0, dg0 = _thermal_state(case, 7)
+    for s in (ref, tb):
+        s.set_populations(torch.from_numpy(df0).cuda(), torch.from_numpy(dg0).cuda())
+    for chunk in (1, 7, 10, 2, 5, 19, 4):
+        ref.step(chunk)
+        tb.step(chunk)
+        fa, ga = ref.populations(thermal=True)
+        fb, gb = tb.populations(thermal=True)
+        torch.cuda.synchronize()
+        assert torch.equal(fa, fb), (name, chunk)
+        assert torch.equal(ga, gb), (name, chunk)
 
 
 @pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
@@ -188,6 +209,9 @@ def test_thermal_batch_two_cycles_per_pass_is_bitwise_equal(storage):
     a.set_time_blocking(1)
     b = lbm.batch_for_cases(cases, storage=storage)
     b.set_time_blocking(2)
+    with pytest.raises(lbm.LBMError) as e:
+        b.set_time_blocking(3)       # thermal batches: one or two cycles per pass
+    assert e.value.status == lbm.ENOTSUP
     for k, c in enumerate(cases):
         df0, dg0 = _thermal_state(c, 10 + k)
         for s in (a, b):
