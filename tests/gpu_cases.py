@@ -1,4 +1,6 @@
 """Helpers for GPU-vs-oracle parity tests: build both sides from one seeded Case."""
+import copy
+
 import numpy as np
 import torch
 
@@ -69,3 +71,26 @@ def max_rel_velocity_error(u_gpu, ux_ref, uy_ref):
     ref = np.stack([ux_ref, uy_ref])
     scale = np.abs(ref).max()
     return float(np.abs(u_gpu - ref).max() / scale)
+
+
+def oracle_window(case, df0, x, y, R):
+    """Oracle inputs on the (2R+1)^2 window centred on node (x, y) of a domain with x
+    periodic and walls in y: after T < R steps the node depends only on the initial state
+    within T nodes, so the window (its own edges closed by any boundary) reproduces it
+    exactly. Rows start at a real wall when the node is within R of it. Returns the
+    window case, its FP64 deviations [8, w, w] and the node's position in the window."""
+    w = 2 * R + 1
+    ny, nx = case.ny, case.nx
+    if y < R:
+        y0 = 0
+    elif y > ny - 1 - R:
+        y0 = ny - w
+    else:
+        y0 = y - R
+    cols = np.arange(x - R, x + R + 1) % nx
+    rows = np.arange(y0, y0 + w)
+    sub = copy.copy(case)
+    sub.nx, sub.ny = w, w
+    sub.phi = np.ascontiguousarray(case.phi[np.ix_(rows, cols)])
+    dfw = df0[:, rows][:, :, cols].astype(np.float64)
+    return sub, dfw, R, y - y0

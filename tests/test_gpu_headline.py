@@ -5,8 +5,6 @@ size). Every population is bitwise that of one cycle per pass, and sampled
 nodes agree with the FP64 oracle run on windows around them: after T steps a
 node depends only on the initial state within T nodes, so a window of radius
 T + 1 (its own edges closed by any boundary) reproduces the node exactly."""
-import copy
-
 import numpy as np
 import pytest
 import torch
@@ -14,7 +12,7 @@ import torch
 import oracle
 from paper_1311_7239_amd import inputs as I
 from paper_1311_7239_amd import lbm
-from tests.gpu_cases import f_ref
+from tests.gpu_cases import f_ref, oracle_window
 from tests.oracle_cases import oracle_setup
 
 pytestmark = pytest.mark.gpu
@@ -59,26 +57,6 @@ def test_headline_is_bitwise_one_cycle_per_pass(headline):
     assert torch.equal(df, dr)
 
 
-def _window(case, df0, x, y):
-    """Oracle inputs on the (2R+1)^2 window centred on (x, y), R = T + 1; rows start
-    at a real wall when the node is within R of it."""
-    R = T + 1
-    w = 2 * R + 1
-    if y < R:
-        y0 = 0
-    elif y > N - 1 - R:
-        y0 = N - w
-    else:
-        y0 = y - R
-    cols = np.arange(x - R, x + R + 1) % N
-    rows = np.arange(y0, y0 + w)
-    sub = copy.copy(case)
-    sub.nx, sub.ny = w, w
-    sub.phi = np.ascontiguousarray(case.phi[np.ix_(rows, cols)])
-    dfw = df0[:, rows][:, :, cols].astype(np.float64)
-    return sub, dfw, R, y - y0
-
-
 def test_headline_sampled_nodes_match_oracle(headline):
     case, df0, _, df, u = headline
     rng = np.random.default_rng(41)
@@ -87,7 +65,7 @@ def test_headline_sampled_nodes_match_oracle(headline):
     worst_f = worst_u = 0.0
     for x, y in zip(xs, ys):
         x, y = int(x), int(y)
-        sub, dfw, cx, cy = _window(case, df0, x, y)
+        sub, dfw, cx, cy = oracle_window(case, df0, x, y, T + 1)
         p, phi, K, F = oracle_setup(sub, nthreads=8)
         f = np.ascontiguousarray(np.transpose(dfw, (1, 2, 0)) + f_ref(case.Pi0))
         oracle.run(p, phi, K, F, f, nsteps=T)
