@@ -111,6 +111,27 @@ def extras(args):
     out["two_cycles_per_pass_f32"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4),
                                       "bytes_per_node_per_launch": 68, "kernel": "k_step2<float, 64, 16>",
                                       "roofline": roofline(case.nodes, 68, 2 * ms)}
+    # the FP64 reductions (mass and steady residual: both states gathered, 2 x 36 B/node)
+    # and the macroscopic output (36 B/node read, p and u written: 48 B/node) on that state
+    s.reduce()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        s.reduce()
+    red_ms = (time.perf_counter() - t0) * 1e3 / 10
+    s.macroscopic()
+    m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    m0.record()
+    for _ in range(10):
+        s.macroscopic()
+    m1.record()
+    torch.cuda.synchronize()
+    mac_ms = m0.elapsed_time(m1) / 10
+    out["reduce_f32"] = {"ms": round(red_ms, 4), "bytes_per_node": 72,
+                         "roofline": roofline(case.nodes, 72, red_ms),
+                         "note": "lbm_reduce call incl. the copy of three doubles to the host"}
+    out["macroscopic_f32"] = {"ms": round(mac_ms, 4), "bytes_per_node": 48,
+                              "roofline": roofline(case.nodes, 48, mac_ms)}
     del s
     torch.cuda.empty_cache()
     # FP16-deviation storage on the headline workload (two cycles per pass by default)
