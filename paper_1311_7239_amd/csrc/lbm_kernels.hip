@@ -1174,18 +1174,18 @@ __device__ __forceinline__ void block_sum3(double v[3], double *out) {
 int reduce_blocks(int nx, int ny) {
     const int64_t n = (int64_t)nx * ny;
     int64_t b = (n + BLOCK - 1) / BLOCK;
-    if (b > 1024) b = 1024;
+    if (b > 4096) b = 4096;
     return (int)b;
 }
 
 template <typename S, bool THERMAL>
 __global__ __launch_bounds__(BLOCK) void k_reduce(Dom cur, int src_cur, Dom prev, int src_prev,
                                                   double *partials) {
-    const int64_t n = (int64_t)cur.nx * cur.ny;
+    // at most 2^31 nodes, so node numbers and the stride stay below 2^32
+    const uint32_t n = (uint32_t)cur.nx * (uint32_t)cur.ny, nx = (uint32_t)cur.nx;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t k = (int64_t)blockIdx.x * BLOCK + threadIdx.x; k < n;
-         k += (int64_t)gridDim.x * BLOCK) {
-        const int x = (int)(k % cur.nx), y = (int)(k / cur.nx);
+    for (uint32_t k = blockIdx.x * BLOCK + threadIdx.x; k < n; k += gridDim.x * BLOCK) {
+        const int x = (int)(k % nx), y = (int)(k / nx);
         const int64_t o = (int64_t)y * cur.pitch + x;
         float f[8], g[5];
         read_state<S, THERMAL>(cur, src_cur, x, y, f, g);
