@@ -65,3 +65,11 @@ def flow_velocity(phi: Optional[torch.Tensor], desc: lbm.Desc, steps: int, ckpt_
     MEDIUM_PHI_KAPPA) and theta = (nu, a_x, a_y, lid_ux) (overrides desc's values).
     Checkpoints every ``ckpt_every`` cycles bound the recording's memory."""
     return _FlowVelocity.apply(phi, kappa, theta, desc, int(steps), int(ckpt_every))
+
+
+def outlet_flow(phi: Optional[torch.Tensor], desc: lbm.Desc, steps: int, ckpt_every: int = 200,
+                kappa: Optional[torch.Tensor] = None, theta: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The outlet profile u(T)[:, :, nx - 1] as a [2, ny] tensor (the sensor column of the
+    inverse problem), differentiable like ``flow_velocity``: its gradient reaches the adjoint
+    as dL/du that is zero off the outlet column."""
+    return flow_velocity(phi, desc, steps, ckpt_every, kappa=kappa, theta=theta)[:, :, -1]

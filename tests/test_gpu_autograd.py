@@ -8,7 +8,7 @@ import torch
 import oracle
 from paper_1311_7239_amd import inputs as I
 from paper_1311_7239_amd import lbm
-from paper_1311_7239_amd.autograd import flow_velocity
+from paper_1311_7239_amd.autograd import flow_velocity, outlet_flow
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +49,22 @@ def test_autograd_matches_the_library_adjoint():
     phi2 = torch.from_numpy(c.phi).cuda().requires_grad_(True)
     _loss(flow_velocity(phi2, desc, c.steps, ckpt_every=64), target).backward()
     assert torch.equal(phi2.grad, g)
+
+
+def test_outlet_flow_gradient_equals_full_field_gradient():
+    c = _case()
+    desc = lbm.desc_from_case(c)
+    target = torch.zeros((2, c.ny), device="cuda")
+    target[0] = 1e-4
+    phi = torch.from_numpy(c.phi).cuda().requires_grad_(True)
+    out = outlet_flow(phi, desc, c.steps, ckpt_every=64)
+    assert out.shape == (2, c.ny)
+    (0.5 * ((out - target) ** 2).sum()).backward()
+    phi2 = torch.from_numpy(c.phi).cuda().requires_grad_(True)
+    u = flow_velocity(phi2, desc, c.steps, ckpt_every=64)
+    assert torch.equal(out.detach(), u.detach()[:, :, -1])
+    _loss(u, target).backward()
+    assert torch.equal(phi.grad, phi2.grad)
 
 
 def test_autograd_directional_derivative_against_oracle():
