@@ -221,6 +221,7 @@ struct lbm_ctx {
     bool poisoned = false;
     bool batch = false;
     bool batch_thermal = false;  // every batch domain carries the D2Q5 field
+    bool batch_uniform = false;  // every batch domain has a uniform medium and one s_nu
     Schedule sched{128, 1, 2, 1};
     // recording (single domain)
     bool rec_valid = false;
@@ -417,12 +418,13 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         void *args_s3[5] = {&d, &tx, &swz, &no_rec, &no_rec};
         void *args_b2[4] = {&c->d_doms, &c->d_tiles2, &c->ntiles2, &p};
         if (c->batch && c->tblock == 3) {
-            kp.func = (void *)step3_batch_kernel_fn(c->storage);
+            kp.func = (void *)step3_batch_kernel_fn(c->storage, c->batch_uniform);
             kp.gridDim = dim3((unsigned)c->grid3);
             kp.blockDim = dim3((unsigned)step3_threads());
             kp.kernelParams = args_b2;
         } else if (c->batch && c->tblock == 2) {
-            kp.func = (void *)step2_batch_kernel_fn(c->storage, c->batch_thermal, c->tb_threads, c->tb_rows);
+            kp.func = (void *)step2_batch_kernel_fn(c->storage, c->batch_thermal, c->batch_uniform, c->tb_threads,
+                                                    c->tb_rows);
             kp.gridDim = dim3((unsigned)c->grid2);
             kp.blockDim = dim3((unsigned)c->tb_threads);
             kp.kernelParams = args_b2;
@@ -615,7 +617,8 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         if (fused && c->tblock == 3 && n >= 4 && c->t + 3 <= next_ck) {
             Domain &D = c->dom[0];
             if (c->batch)
-                e = launch_step3_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->grid3, c->stream);
+                e = launch_step3_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_uniform,
+                                       c->grid3, c->stream);
             else
                 e = launch_step3(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
                                  c->sched.swizzle, nullptr, nullptr, c->stream);
@@ -629,8 +632,8 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         if (fused && n >= 3 && c->t + 2 <= next_ck) {
             Domain &D = c->dom[0];
             if (c->batch)
-                e = launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_thermal, c->tb_threads,
-                                       c->tb_rows, c->grid2, c->stream);
+                e = launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_thermal,
+                                       c->batch_uniform, c->tb_threads, c->tb_rows, c->grid2, c->stream);
             else
                 e = launch_step2(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
                                  c->sched.swizzle, c->tb_threads, c->tb_rows, nullptr, c->stream);
@@ -1181,8 +1184,8 @@ hipError_t autotune(lbm_ctx *c, Tuned &best) {
         for (int g : grids) {
             if (g > c->ntiles2) g = c->ntiles2;
             float ms = 0.0f;
-            e = time_it([&] { return launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, 0, c->storage, c->batch_thermal, sh[0],
-                                                        sh[1], g, c->stream); }, ms);
+            e = time_it([&] { return launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, 0, c->storage, c->batch_thermal,
+                                                        c->batch_uniform, sh[0], sh[1], g, c->stream); }, ms);
             if (e != hipSuccess) break;
             if (0.5f * ms < best2) {
                 best2 = 0.5f * ms;
@@ -1198,8 +1201,8 @@ hipError_t autotune(lbm_ctx *c, Tuned &best) {
         for (int g : grids) {
             if (g > c->ntiles2) g = c->ntiles2;
             float ms = 0.0f;
-            e = time_it([&] { return launch_step3_batch(c->d_doms, c->d_tiles2, c->ntiles2, 0, c->storage, g,
-                                                        c->stream); }, ms);
+            e = time_it([&] { return launch_step3_batch(c->d_doms, c->d_tiles2, c->ntiles2, 0, c->storage,
+                                                        c->batch_uniform, g, c->stream); }, ms);
             if (e != hipSuccess) break;
             if (ms / 3.0f < best3) { best3 = ms / 3.0f; best.grid3 = g; }
         }
@@ -1257,6 +1260,9 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
         if (rc) { delete c; return rc; }
         e = init_domain(D, 0, phi, kap, c->stream);
     }
+    c->batch_uniform = true;
+    for (const Domain &D : c->dom)
+        if (medium_kind(D.dom) != MK_UNIFORM) c->batch_uniform = false;
     c->d_doms = (Dom *)(base + B.off_doms);
     c->d_tiles = (int4 *)(base + B.off_tiles);
     size_t state_bytes = 0;

@@ -567,7 +567,7 @@ __global__ __launch_bounds__(NT) void k_step2(Dom d, int tiles_x, int swz, float
 }
 
 // Persistent batched two-cycle pass over a table of 64 x TH tiles.
-template <typename S, int TW, int TH, int NT, bool THERMAL>
+template <typename S, int TW, int TH, int NT, int MK, bool THERMAL>
 __global__ __launch_bounds__(NT) void k_step2_batch(const Dom *__restrict__ doms,
                                                     const int4 *__restrict__ tiles, int ntiles,
                                                     int parity) {
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(NT) void k_step2_batch(const Dom *__restrict__ doms
     for (int t = t0; t < t1; ++t) {
         const int4 tl = tiles[t];
         const Dom d = doms[2 * tl.x + parity];
-        step2_tile<S, TW, TH, NT, false, MK_BRANCHED, THERMAL>(d, tl.y * TW, tl.z * TH, nullptr, lds, ldsg);
+        step2_tile<S, TW, TH, NT, false, MK, THERMAL>(d, tl.y * TW, tl.z * TH, nullptr, lds, ldsg);
         lds_barrier();   // the next tile's phase A rewrites the LDS
     }
 }
@@ -826,8 +826,8 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
 }
 
 // Persistent batched three-cycle pass over a table of TW x TH tiles (isothermal
-// domains of any medium).
-template <typename S, int TW, int TH, int NT>
+// domains; MK_BRANCHED for any medium, MK_UNIFORM when every domain is uniform).
+template <typename S, int TW, int TH, int NT, int MK>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_step3_batch(const Dom *__restrict__ doms, const int4 *__restrict__ tiles,
                                                     int ntiles, int parity) {
     __shared__ float lds[8 * (TH + 4) * (TW + 4)];
@@ -837,7 +837,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
     for (int t = t0; t < t1; ++t) {
         const int4 tl = tiles[t];
         const Dom d = doms[2 * tl.x + parity];
-        step3_tile<S, TW, TH, NT, false, MK_BRANCHED, false>(d, tl.y * TW, tl.z * TH, nullptr, nullptr, lds, nullptr);
+        step3_tile<S, TW, TH, NT, false, MK, false>(d, tl.y * TW, tl.z * TH, nullptr, nullptr, lds, nullptr);
         lds_barrier();   // the next tile's phase A rewrites the LDS
     }
 }
@@ -870,17 +870,22 @@ const void *step3_kernel_fn(const Dom &d, int storage, bool rec) {
     return d.thermal ? step3_fn_th<true>(d, storage, rec) : step3_fn_th<false>(d, storage, rec);
 }
 
-const void *step3_batch_kernel_fn(int storage) {
-    return storage == ST_F32 ? (const void *)&k_step3_batch<float, STEP3_TW, STEP3_TH, STEP3_NT>
-                             : (const void *)&k_step3_batch<_Float16, STEP3_TW, STEP3_TH, STEP3_NT>;
+template <int MK>
+static const void *step3_batch_fn_mk(int storage) {
+    return storage == ST_F32 ? (const void *)&k_step3_batch<float, STEP3_TW, STEP3_TH, STEP3_NT, MK>
+                             : (const void *)&k_step3_batch<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, MK>;
+}
+
+const void *step3_batch_kernel_fn(int storage, bool uniform) {
+    return uniform ? step3_batch_fn_mk<MK_UNIFORM>(storage) : step3_batch_fn_mk<MK_BRANCHED>(storage);
 }
 
 int step3_threads() { return STEP3_NT; }
 
-hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, int grid,
-                              hipStream_t st) {
+hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, bool uniform,
+                              int grid, hipStream_t st) {
     if (grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
-    const void *fn = step3_batch_kernel_fn(storage);
+    const void *fn = step3_batch_kernel_fn(storage, uniform);
     void *args[4] = {&doms, &tiles, &ntiles, &parity};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(STEP3_NT), args, 0, st);
 }
@@ -905,25 +910,31 @@ static const void *step2_fn_t(int threads, int rows) {
     return nullptr;
 }
 
-template <typename S, bool THERMAL>
+template <typename S, int MK, bool THERMAL>
 static const void *step2_batch_fn_t(int threads, int rows) {
-#define MRT_S2BFN(N, H) if (threads == N && rows == H) return (const void *)&k_step2_batch<S, STEP2_TW, H, N, THERMAL>;
+#define MRT_S2BFN(N, H) if (threads == N && rows == H) return (const void *)&k_step2_batch<S, STEP2_TW, H, N, MK, THERMAL>;
     MRT_STEP2_SHAPES(MRT_S2BFN)
 #undef MRT_S2BFN
     return nullptr;
 }
 
-const void *step2_batch_kernel_fn(int storage, bool thermal, int threads, int rows) {
+template <int MK>
+static const void *step2_batch_fn_mk(int storage, bool thermal, int threads, int rows) {
     if (thermal)
-        return storage == ST_F32 ? step2_batch_fn_t<float, true>(threads, rows)
-                                 : step2_batch_fn_t<_Float16, true>(threads, rows);
-    return storage == ST_F32 ? step2_batch_fn_t<float, false>(threads, rows)
-                             : step2_batch_fn_t<_Float16, false>(threads, rows);
+        return storage == ST_F32 ? step2_batch_fn_t<float, MK, true>(threads, rows)
+                                 : step2_batch_fn_t<_Float16, MK, true>(threads, rows);
+    return storage == ST_F32 ? step2_batch_fn_t<float, MK, false>(threads, rows)
+                             : step2_batch_fn_t<_Float16, MK, false>(threads, rows);
+}
+
+const void *step2_batch_kernel_fn(int storage, bool thermal, bool uniform, int threads, int rows) {
+    return uniform ? step2_batch_fn_mk<MK_UNIFORM>(storage, thermal, threads, rows)
+                   : step2_batch_fn_mk<MK_BRANCHED>(storage, thermal, threads, rows);
 }
 
 hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage,
-                              bool thermal, int threads, int rows, int grid, hipStream_t st) {
-    const void *fn = step2_batch_kernel_fn(storage, thermal, threads, rows);
+                              bool thermal, bool uniform, int threads, int rows, int grid, hipStream_t st) {
+    const void *fn = step2_batch_kernel_fn(storage, thermal, uniform, threads, rows);
     if (!fn || grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
     void *args[4] = {&doms, &tiles, &ntiles, &parity};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)threads), args, 0, st);

@@ -48,16 +48,18 @@ const void *step2_kernel_fn(const Dom &d, int storage, int threads, int rows, bo
 hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, float *urec2, hipStream_t st);
 void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y);
 const void *step3_kernel_fn(const Dom &d, int storage, bool rec);
-// batched three-cycle pass over a table of 64 x 16 tiles (isothermal domains)
-const void *step3_batch_kernel_fn(int storage);
+// batched three-cycle pass over a table of 64 x 16 tiles (isothermal domains);
+// uniform: every domain has a uniform medium and one s_nu (medium_kind MK_UNIFORM),
+// so the kernel loads no medium planes
+const void *step3_batch_kernel_fn(int storage, bool uniform);
 int step3_threads();
-hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, int grid,
-                              hipStream_t st);
+hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, bool uniform,
+                              int grid, hipStream_t st);
 // Batched two-cycle pass over a table of 64 x rows tiles (domain, tx, ty, 0);
-// entry arguments (const Dom*, const int4*, int ntiles, int parity).
+// entry arguments (const Dom*, const int4*, int ntiles, int parity); uniform as above.
 hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage,
-                              bool thermal, int threads, int rows, int grid, hipStream_t st);
-const void *step2_batch_kernel_fn(int storage, bool thermal, int threads, int rows);
+                              bool thermal, bool uniform, int threads, int rows, int grid, hipStream_t st);
+const void *step2_batch_kernel_fn(int storage, bool thermal, bool uniform, int threads, int rows);
 
 // Persistent batched step over a tile table: doms[2*k + parity] describes
 // domain k with its buffers for this parity; tiles[j] = (domain, tx, ty, 0).

@@ -12,11 +12,14 @@ from tests.gpu_cases import Pair
 pytestmark = pytest.mark.gpu
 
 
-def mixed_cases():
+def mixed_cases(uniform=False):
+    """Ragged lid cavities; every other one has a porosity field unless uniform (then the
+    batch takes the kernels specialised for uniform media)."""
     sizes = [(70, 70), (130, 90), (64, 64), (300, 33), (257, 129)]
     cases = []
     for k, (nx, ny) in enumerate(sizes):
-        c = I.lid_cavity(n=max(nx, ny), Re=20.0 + 30 * k, heterogeneous=(k % 2 == 1), ell=6.0, seed=10 + k)
+        c = I.lid_cavity(n=max(nx, ny), Re=20.0 + 30 * k, heterogeneous=(k % 2 == 1 and not uniform), ell=6.0,
+                         seed=10 + k)
         c.nx, c.ny = nx, ny
         if c.phi is not None:
             c.phi = np.ascontiguousarray(c.phi[:ny, :nx])
@@ -34,11 +37,13 @@ def single_run(case, steps, storage):
     return df.cpu().numpy()
 
 
+@pytest.mark.parametrize("uniform", [False, True])
 @pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
 @pytest.mark.parametrize("tblock", [1, 2, 3])
-def test_batch_is_bitwise_equal_to_single_domains(storage, tblock, tmp_path):
-    """One, two and three cycles per pass, graph replays of 6 cycles, leftovers."""
-    cases = mixed_cases()
+def test_batch_is_bitwise_equal_to_single_domains(storage, tblock, uniform, tmp_path):
+    """One, two and three cycles per pass, graph replays of 6 cycles, leftovers; mixed
+    media and all-uniform media."""
+    cases = mixed_cases(uniform)
     b = lbm.batch_for_cases(cases, storage=storage, tune_cache=tmp_path / "tune.txt")
     b.set_time_blocking(tblock)
     b.set_graph_steps(6)

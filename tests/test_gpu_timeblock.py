@@ -202,9 +202,15 @@ def test_thermal_three_cycles_per_pass_is_bitwise_equal(name, case, storage, gra
         assert torch.equal(ga, gb), (name, chunk)
 
 
+@pytest.mark.parametrize("uniform", [False, True])
 @pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
-def test_thermal_batch_two_cycles_per_pass_is_bitwise_equal(storage):
+def test_thermal_batch_two_cycles_per_pass_is_bitwise_equal(storage, uniform):
+    """All thermal cases (one with an Ergun porosity field), or only the uniform ones (the
+    batch then takes the kernels specialised for uniform media)."""
     cases = [c for _, c in thermal_cases()]
+    if uniform:
+        cases = [c for c in cases if c.phi is None]
+        assert len(cases) == 2
     a = lbm.batch_for_cases(cases, storage=storage)
     a.set_time_blocking(1)
     b = lbm.batch_for_cases(cases, storage=storage)
