@@ -130,5 +130,7 @@ if __name__ == "__main__":
         counters_summary(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:]))
     elif mode == "sq":
         sq_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+    elif mode == "sq-all":   # every library kernel (the adjoint's as well as the step's)
+        sq_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]), kernel_prefix="void mrt::k_")
     else:
-        raise SystemExit("usage: profiling.py stats|counters|sq ...")
+        raise SystemExit("usage: profiling.py stats|counters|sq|sq-all ...")
