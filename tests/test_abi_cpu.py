@@ -79,6 +79,13 @@ def test_invalid_descriptor_is_rejected(field, value):
     assert lbm.lib().lbm_last_error().decode() != ""
 
 
+def test_node_count_limit():
+    """At most 2^31 nodes: the largest domain is sized, one row more is rejected."""
+    st, nbytes = _ws(_desc(nx=65536, ny=32768))
+    assert st == lbm.OK and nbytes > 2 * 8 * 4 * 2 ** 31
+    assert _ws(_desc(nx=65536, ny=32769))[0] == lbm.EINVAL
+
+
 def test_walled_axis_needs_two_nodes_and_lid_needs_walls():
     assert _ws(_desc(bc_y=lbm.WALLS, ny=1))[0] == lbm.EINVAL
     assert _ws(_desc(bc_y=lbm.PERIODIC, lid_ux=0.1))[0] == lbm.EINVAL
