@@ -418,14 +418,16 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         void *args_s3[5] = {&d, &tx, &swz, &no_rec, &no_rec};
         void *args_b2[4] = {&c->d_doms, &c->d_tiles2, &c->ntiles2, &p};
         if (c->batch && c->tblock == 3) {
-            kp.func = (void *)step3_batch_kernel_fn(c->storage, c->batch_uniform);
-            kp.gridDim = dim3((unsigned)c->grid3);
+            const int g = c->grid3 < c->ntiles2 ? c->grid3 : c->ntiles2;
+            kp.func = (void *)step3_batch_kernel_fn(c->storage, c->batch_uniform, g == c->ntiles2);
+            kp.gridDim = dim3((unsigned)g);
             kp.blockDim = dim3((unsigned)step3_threads());
             kp.kernelParams = args_b2;
         } else if (c->batch && c->tblock == 2) {
-            kp.func = (void *)step2_batch_kernel_fn(c->storage, c->batch_thermal, c->batch_uniform, c->tb_threads,
-                                                    c->tb_rows);
-            kp.gridDim = dim3((unsigned)c->grid2);
+            const int g = c->grid2 < c->ntiles2 ? c->grid2 : c->ntiles2;
+            kp.func = (void *)step2_batch_kernel_fn(c->storage, c->batch_thermal, c->batch_uniform, g == c->ntiles2,
+                                                    c->tb_threads, c->tb_rows);
+            kp.gridDim = dim3((unsigned)g);
             kp.blockDim = dim3((unsigned)c->tb_threads);
             kp.kernelParams = args_b2;
         } else if (c->batch) {

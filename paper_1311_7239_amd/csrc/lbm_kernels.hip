@@ -567,12 +567,19 @@ __global__ __launch_bounds__(NT) void k_step2(Dom d, int tiles_x, int swz, float
 }
 
 // Persistent batched two-cycle pass over a table of 64 x TH tiles.
-template <typename S, int TW, int TH, int NT, int MK, bool THERMAL>
+template <typename S, int TW, int TH, int NT, int MK, bool THERMAL, bool ONE>
 __global__ __launch_bounds__(NT) void k_step2_batch(const Dom *__restrict__ doms,
                                                     const int4 *__restrict__ tiles, int ntiles,
                                                     int parity) {
     __shared__ float lds[8][TH + 2][TW + 2];
     __shared__ float ldsg[THERMAL ? 5 * (TH + 2) * (TW + 2) : 1];
+    if (ONE) {
+        // one workgroup per tile (grid == ntiles): no loop state stays live
+        const int4 tl = tiles[blockIdx.x];
+        const Dom d = doms[2 * tl.x + parity];
+        step2_tile<S, TW, TH, NT, false, MK, THERMAL>(d, tl.y * TW, tl.z * TH, nullptr, lds, ldsg);
+        return;
+    }
     const int64_t nb = gridDim.x;
     const int t0 = (int)((int64_t)blockIdx.x * ntiles / nb);
     const int t1 = (int)(((int64_t)blockIdx.x + 1) * ntiles / nb);
@@ -827,10 +834,18 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
 
 // Persistent batched three-cycle pass over a table of TW x TH tiles (isothermal
 // domains; MK_BRANCHED for any medium, MK_UNIFORM when every domain is uniform).
-template <typename S, int TW, int TH, int NT, int MK>
+template <typename S, int TW, int TH, int NT, int MK, bool ONE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_step3_batch(const Dom *__restrict__ doms, const int4 *__restrict__ tiles,
                                                     int ntiles, int parity) {
     __shared__ float lds[8 * (TH + 4) * (TW + 4)];
+    if (ONE) {
+        // one workgroup per tile (grid == ntiles): without the loop's state the
+        // kernel stays within its registers (the loop variant spills)
+        const int4 tl = tiles[blockIdx.x];
+        const Dom d = doms[2 * tl.x + parity];
+        step3_tile<S, TW, TH, NT, false, MK, false>(d, tl.y * TW, tl.z * TH, nullptr, nullptr, lds, nullptr);
+        return;
+    }
     const int64_t nb = gridDim.x;
     const int t0 = (int)((int64_t)blockIdx.x * ntiles / nb);
     const int t1 = (int)(((int64_t)blockIdx.x + 1) * ntiles / nb);
@@ -870,14 +885,15 @@ const void *step3_kernel_fn(const Dom &d, int storage, bool rec) {
     return d.thermal ? step3_fn_th<true>(d, storage, rec) : step3_fn_th<false>(d, storage, rec);
 }
 
-template <int MK>
+template <int MK, bool ONE>
 static const void *step3_batch_fn_mk(int storage) {
-    return storage == ST_F32 ? (const void *)&k_step3_batch<float, STEP3_TW, STEP3_TH, STEP3_NT, MK>
-                             : (const void *)&k_step3_batch<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, MK>;
+    return storage == ST_F32 ? (const void *)&k_step3_batch<float, STEP3_TW, STEP3_TH, STEP3_NT, MK, ONE>
+                             : (const void *)&k_step3_batch<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, MK, ONE>;
 }
 
-const void *step3_batch_kernel_fn(int storage, bool uniform) {
-    return uniform ? step3_batch_fn_mk<MK_UNIFORM>(storage) : step3_batch_fn_mk<MK_BRANCHED>(storage);
+const void *step3_batch_kernel_fn(int storage, bool uniform, bool one) {
+    if (one) return uniform ? step3_batch_fn_mk<MK_UNIFORM, true>(storage) : step3_batch_fn_mk<MK_BRANCHED, true>(storage);
+    return uniform ? step3_batch_fn_mk<MK_UNIFORM, false>(storage) : step3_batch_fn_mk<MK_BRANCHED, false>(storage);
 }
 
 int step3_threads() { return STEP3_NT; }
@@ -885,7 +901,8 @@ int step3_threads() { return STEP3_NT; }
 hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, bool uniform,
                               int grid, hipStream_t st) {
     if (grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
-    const void *fn = step3_batch_kernel_fn(storage, uniform);
+    if (grid > ntiles) grid = ntiles;   // workgroups beyond the last tile would idle
+    const void *fn = step3_batch_kernel_fn(storage, uniform, grid == ntiles);
     void *args[4] = {&doms, &tiles, &ntiles, &parity};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3(STEP3_NT), args, 0, st);
 }
@@ -910,32 +927,37 @@ static const void *step2_fn_t(int threads, int rows) {
     return nullptr;
 }
 
-template <typename S, int MK, bool THERMAL>
+template <typename S, int MK, bool THERMAL, bool ONE>
 static const void *step2_batch_fn_t(int threads, int rows) {
-#define MRT_S2BFN(N, H) if (threads == N && rows == H) return (const void *)&k_step2_batch<S, STEP2_TW, H, N, MK, THERMAL>;
+#define MRT_S2BFN(N, H) if (threads == N && rows == H) return (const void *)&k_step2_batch<S, STEP2_TW, H, N, MK, THERMAL, ONE>;
     MRT_STEP2_SHAPES(MRT_S2BFN)
 #undef MRT_S2BFN
     return nullptr;
 }
 
-template <int MK>
+template <int MK, bool ONE>
 static const void *step2_batch_fn_mk(int storage, bool thermal, int threads, int rows) {
     if (thermal)
-        return storage == ST_F32 ? step2_batch_fn_t<float, MK, true>(threads, rows)
-                                 : step2_batch_fn_t<_Float16, MK, true>(threads, rows);
-    return storage == ST_F32 ? step2_batch_fn_t<float, MK, false>(threads, rows)
-                             : step2_batch_fn_t<_Float16, MK, false>(threads, rows);
+        return storage == ST_F32 ? step2_batch_fn_t<float, MK, true, ONE>(threads, rows)
+                                 : step2_batch_fn_t<_Float16, MK, true, ONE>(threads, rows);
+    return storage == ST_F32 ? step2_batch_fn_t<float, MK, false, ONE>(threads, rows)
+                             : step2_batch_fn_t<_Float16, MK, false, ONE>(threads, rows);
 }
 
-const void *step2_batch_kernel_fn(int storage, bool thermal, bool uniform, int threads, int rows) {
-    return uniform ? step2_batch_fn_mk<MK_UNIFORM>(storage, thermal, threads, rows)
-                   : step2_batch_fn_mk<MK_BRANCHED>(storage, thermal, threads, rows);
+const void *step2_batch_kernel_fn(int storage, bool thermal, bool uniform, bool one, int threads, int rows) {
+    if (one)
+        return uniform ? step2_batch_fn_mk<MK_UNIFORM, true>(storage, thermal, threads, rows)
+                       : step2_batch_fn_mk<MK_BRANCHED, true>(storage, thermal, threads, rows);
+    return uniform ? step2_batch_fn_mk<MK_UNIFORM, false>(storage, thermal, threads, rows)
+                   : step2_batch_fn_mk<MK_BRANCHED, false>(storage, thermal, threads, rows);
 }
 
 hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage,
                               bool thermal, bool uniform, int threads, int rows, int grid, hipStream_t st) {
-    const void *fn = step2_batch_kernel_fn(storage, thermal, uniform, threads, rows);
-    if (!fn || grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
+    if (grid <= 0 || ntiles <= 0) return hipErrorInvalidValue;
+    if (grid > ntiles) grid = ntiles;   // workgroups beyond the last tile would idle
+    const void *fn = step2_batch_kernel_fn(storage, thermal, uniform, grid == ntiles, threads, rows);
+    if (!fn) return hipErrorInvalidValue;
     void *args[4] = {&doms, &tiles, &ntiles, &parity};
     return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)threads), args, 0, st);
 }

@@ -50,8 +50,10 @@ void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y);
 const void *step3_kernel_fn(const Dom &d, int storage, bool rec);
 // batched three-cycle pass over a table of 64 x 16 tiles (isothermal domains);
 // uniform: every domain has a uniform medium and one s_nu (medium_kind MK_UNIFORM),
-// so the kernel loads no medium planes
-const void *step3_batch_kernel_fn(int storage, bool uniform);
+// so the kernel loads no medium planes; one: one workgroup per tile (a grid of
+// exactly ntiles), else workgroups walk runs of tiles. The launchers clamp the
+// grid to ntiles and pick one = (grid == ntiles).
+const void *step3_batch_kernel_fn(int storage, bool uniform, bool one);
 int step3_threads();
 hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, bool uniform,
                               int grid, hipStream_t st);
@@ -59,7 +61,7 @@ hipError_t launch_step3_batch(const Dom *doms, const int4 *tiles, int ntiles, in
 // entry arguments (const Dom*, const int4*, int ntiles, int parity); uniform as above.
 hipError_t launch_step2_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage,
                               bool thermal, bool uniform, int threads, int rows, int grid, hipStream_t st);
-const void *step2_batch_kernel_fn(int storage, bool thermal, bool uniform, int threads, int rows);
+const void *step2_batch_kernel_fn(int storage, bool thermal, bool uniform, bool one, int threads, int rows);
 
 // Persistent batched step over a tile table: doms[2*k + parity] describes
 // domain k with its buffers for this parity; tiles[j] = (domain, tx, ty, 0).

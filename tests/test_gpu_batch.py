@@ -58,6 +58,33 @@ def test_batch_is_bitwise_equal_to_single_domains(storage, tblock, uniform, tmp_
             assert np.array_equal(got, single_run(cases[k], done, storage)), (k, done)
 
 
+@pytest.mark.parametrize("tblock", [2, 3])
+def test_batch_workgroups_walking_runs_of_tiles(tblock, tmp_path):
+    """Small batches are tuned to one workgroup per tile. A tuning-cache entry with grids
+    of 3 and 5 workgroups makes each walk a run of tiles instead; the results stay
+    bitwise those of single domains."""
+    cases = mixed_cases()
+    path = tmp_path / "tune.txt"
+    lbm.batch_for_cases(cases, tune_cache=path)
+    fields = path.read_text().split()
+    assert len(fields) == 10        # key, one-cycle shape and grid, mode, two-cycle shape, grid2, grid3
+    fields[8], fields[9] = "3", "5"
+    path2 = tmp_path / "tune_small_grids.txt"
+    path2.write_text(" ".join(fields) + "\n")
+    b = lbm.batch_for_cases(cases, tune_cache=path2)
+    b.set_time_blocking(tblock)
+    assert b.time_blocking()["grid"] == (3 if tblock == 2 else 5)
+    b.set_graph_steps(6)
+    done = 0
+    for chunk in (1, 9, 8):
+        b.step(chunk)
+        done += chunk
+    torch.cuda.synchronize()
+    for k in range(len(cases)):
+        got = b.populations(k).cpu().numpy()
+        assert np.array_equal(got, single_run(cases[k], done, lbm.FP32_DEV)), k
+
+
 def test_batch_matches_oracle():
     cases = mixed_cases()[:3]
     b = lbm.batch_for_cases(cases)
