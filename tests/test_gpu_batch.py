@@ -58,20 +58,24 @@ def test_batch_is_bitwise_equal_to_single_domains(storage, tblock, uniform, tmp_
             assert np.array_equal(got, single_run(cases[k], done, storage)), (k, done)
 
 
-@pytest.mark.parametrize("tblock", [2, 3])
-def test_batch_workgroups_walking_runs_of_tiles(tblock, tmp_path):
+@pytest.mark.parametrize("kind,storage,tblock", [("mixed", lbm.FP32_DEV, 2), ("mixed", lbm.FP32_DEV, 3),
+                                                  ("mixed", lbm.FP16_DEV, 3), ("uniform", lbm.FP32_DEV, 3),
+                                                  ("thermal", lbm.FP32_DEV, 2)])
+def test_batch_workgroups_walking_runs_of_tiles(kind, storage, tblock, tmp_path):
     """Small batches are tuned to one workgroup per tile. A tuning-cache entry with grids
     of 3 and 5 workgroups makes each walk a run of tiles instead; the results stay
-    bitwise those of single domains."""
-    cases = mixed_cases()
+    bitwise those of single domains (flow and temperature)."""
+    from tests.test_gpu_timeblock import thermal_cases
+    thermal = kind == "thermal"
+    cases = [c for _, c in thermal_cases()] if thermal else mixed_cases(kind == "uniform")
     path = tmp_path / "tune.txt"
-    lbm.batch_for_cases(cases, tune_cache=path)
+    lbm.batch_for_cases(cases, storage=storage, tune_cache=path)
     fields = path.read_text().split()
     assert len(fields) == 10        # key, one-cycle shape and grid, mode, two-cycle shape, grid2, grid3
-    fields[8], fields[9] = "3", "5"
+    fields[8], fields[9] = "3", ("0" if thermal else "5")
     path2 = tmp_path / "tune_small_grids.txt"
     path2.write_text(" ".join(fields) + "\n")
-    b = lbm.batch_for_cases(cases, tune_cache=path2)
+    b = lbm.batch_for_cases(cases, storage=storage, tune_cache=path2)
     b.set_time_blocking(tblock)
     assert b.time_blocking()["grid"] == (3 if tblock == 2 else 5)
     b.set_graph_steps(6)
@@ -80,9 +84,16 @@ def test_batch_workgroups_walking_runs_of_tiles(tblock, tmp_path):
         b.step(chunk)
         done += chunk
     torch.cuda.synchronize()
-    for k in range(len(cases)):
-        got = b.populations(k).cpu().numpy()
-        assert np.array_equal(got, single_run(cases[k], done, lbm.FP32_DEV)), k
+    for k, c in enumerate(cases):
+        s = lbm.solver_for_case(c, storage=storage)
+        s.step(done)
+        df, dg = s.populations(thermal=thermal)
+        got = b.populations(k, thermal=thermal)
+        torch.cuda.synchronize()
+        if thermal:
+            assert torch.equal(got[0], df) and torch.equal(got[1], dg), k
+        else:
+            assert torch.equal(got, df), k
 
 
 def test_batch_matches_oracle():
