@@ -135,8 +135,9 @@ int lbm_workspace_size(const lbm_desc *d, int64_t max_steps_recorded, size_t *by
 int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *workspace,
                size_t ws_bytes, void *stream, lbm_ctx **out);
 
-/* Ragged batch: n independent domains stepped together by one persistent
- * launch per step (a tile table maps workgroups to (domain, tile)), replayed
+/* Ragged batch: n independent domains stepped together by one launch per
+ * pass (a tile table maps workgroups to (domain, tile); a workgroup takes one
+ * tile or walks a run of tiles, by the tuned grid size), replayed
  * from a HIP graph of graph_steps launches (default 32). descs, phis,
  * kappas: host arrays of n entries (phis[k]/kappas[k] device planes or
  * NULL). All domains must share the storage and be all thermal or all
