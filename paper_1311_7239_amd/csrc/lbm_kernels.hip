@@ -566,7 +566,8 @@ __global__ __launch_bounds__(NT) void k_step2(Dom d, int tiles_x, int swz, float
     step2_tile<S, TW, TH, NT, REC, MK, THERMAL>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec_next, lds, ldsg);
 }
 
-// Persistent batched two-cycle pass over a table of 64 x TH tiles.
+// Batched two-cycle pass over a table of 64 x TH tiles: with ONE each workgroup
+// takes one tile (grid == ntiles), else workgroup b walks a contiguous run.
 template <typename S, int TW, int TH, int NT, int MK, bool THERMAL, bool ONE>
 __global__ __launch_bounds__(NT) void k_step2_batch(const Dom *__restrict__ doms,
                                                     const int4 *__restrict__ tiles, int ntiles,
@@ -832,8 +833,9 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
     step3_tile<S, TW, TH, NT, REC, MK, THERMAL>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec1, urec2, lds, ldsg);
 }
 
-// Persistent batched three-cycle pass over a table of TW x TH tiles (isothermal
-// domains; MK_BRANCHED for any medium, MK_UNIFORM when every domain is uniform).
+// Batched three-cycle pass over a table of TW x TH tiles (isothermal domains;
+// MK_BRANCHED for any medium, MK_UNIFORM when every domain is uniform); ONE as
+// for the two-cycle pass.
 template <typename S, int TW, int TH, int NT, int MK, bool ONE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_step3_batch(const Dom *__restrict__ doms, const int4 *__restrict__ tiles,
                                                     int ntiles, int parity) {
