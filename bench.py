@@ -47,32 +47,83 @@ def timed(stepper, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def per_launch_ms(stepper, cycles, launches=20, reps=3):
+    """Average duration of one plain multi-cycle launch, from HIP events on the launch
+    stream: a call of (launches + 1) passes minus a call of one pass. Every lbm_step call
+    ends with one pass that also writes u(t - 1) for the residual; the difference cancels
+    it, leaving `launches` back-to-back plain launches of the dominant kernel."""
+    import torch
+    stream = torch.cuda.current_stream()
+
+    def call(n):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        stepper.step(n)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    call(cycles)
+    long = min(call(cycles * (launches + 1)) for _ in range(reps))
+    short = min(call(cycles) for _ in range(reps))
+    return (long - short) / launches
+
+
 def roofline(nodes, bytes_per_node, ms):
     achieved = nodes * bytes_per_node / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4)}
 
 
-def cpu_baseline(n=1024, steps=1500):
-    """FP64 oracle on the same workload recipe at n x n (a bounded sample)."""
+def host_cpu():
+    """(logical CPUs this process may run on, os.cpu_count(), CPU model name)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return usable, os.cpu_count() or 1, model
+
+
+def cpu_baseline(n=1024, steps=1000, n1=512, steps1=100):
+    """FP64 oracle on the same workload recipe (bounded samples): with every thread this
+    process is given (OMP_NUM_THREADS when set, the GPU's share of the host, else every
+    usable CPU) on n x n for `steps` steps, and with one thread on n1 x n1."""
     import numpy as np
     import oracle
     from paper_1311_7239_amd import inputs as I
 
-    case = I.lognormal_channel(n=n, seed=5, K_ref=1e-6 * 2048.0 ** 2)
-    threads = min(os.cpu_count() or 1, 16)
-    p = oracle.make_params(case.nx, case.ny, bc_x=case.bc_x, bc_y=case.bc_y, nu=case.nu,
-                           ax=case.ax, nthreads=threads)
-    phi = case.phi.astype(np.float64)
-    K, F = oracle.ergun(phi, case.dp)
-    f = oracle.rest_state(p, case.Pi0)
-    oracle.run(p, phi, K, F, f, nsteps=2)
-    t0 = time.perf_counter()
-    oracle.run(p, phi, K, F, f, nsteps=steps)
-    dt = time.perf_counter() - t0
-    return {"value": round(case.nodes * steps / dt / 1e6, 2), "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n}x{n} log-normal porous channel (same recipe), {steps} FP64 steps, {dt:.1f} s"}
+    usable, count, model = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS") or usable)
+
+    def rate(size, nsteps, nthreads):
+        case = I.lognormal_channel(n=size, seed=5, K_ref=1e-6 * 2048.0 ** 2)
+        p = oracle.make_params(case.nx, case.ny, bc_x=case.bc_x, bc_y=case.bc_y, nu=case.nu,
+                               ax=case.ax, nthreads=nthreads)
+        phi = case.phi.astype(np.float64)
+        K, F = oracle.ergun(phi, case.dp)
+        f = oracle.rest_state(p, case.Pi0)
+        oracle.run(p, phi, K, F, f, nsteps=2)
+        t0 = time.perf_counter()
+        oracle.run(p, phi, K, F, f, nsteps=nsteps)
+        dt = time.perf_counter() - t0
+        return case.nodes * nsteps / dt / 1e6, dt
+
+    v, dt = rate(n, steps, threads)
+    v1, dt1 = rate(n1, steps1, 1)
+    return {"value": round(v, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n}x{n} log-normal porous channel (same recipe), {steps} FP64 steps on {threads} "
+                      f"threads, {dt:.1f} s; {n1}x{n1}, {steps1} steps on 1 thread, {dt1:.1f} s",
+            "value_1_thread": round(v1, 2), "usable_cpus": usable, "os_cpu_count": count, "cpu_model": model}
 
 
 def extras(args):
@@ -111,8 +162,9 @@ def extras(args):
     out["two_cycles_per_pass_f32"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4),
                                       "bytes_per_node_per_launch": 68, "kernel": "k_step2<float, 64, 16>",
                                       "roofline": roofline(case.nodes, 68, 2 * ms)}
-    # the FP64 reductions (mass and steady residual: both states gathered, 2 x 36 B/node)
-    # and the macroscopic output (36 B/node read, p and u written: 48 B/node) on that state
+    # the FP64 reductions (mass and steady residual: the state gathered, 36 B/node, and the
+    # recorded u(t - 1), 8 B/node) and the macroscopic output (36 B/node read, p and u
+    # written: 48 B/node) on that state
     s.reduce()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -127,8 +179,8 @@ def extras(args):
     m1.record()
     torch.cuda.synchronize()
     mac_ms = m0.elapsed_time(m1) / 10
-    out["reduce_f32"] = {"ms": round(red_ms, 4), "bytes_per_node": 72,
-                         "roofline": roofline(case.nodes, 72, red_ms),
+    out["reduce_f32"] = {"ms": round(red_ms, 4), "bytes_per_node": 44,
+                         "roofline": roofline(case.nodes, 44, red_ms),
                          "note": "lbm_reduce call incl. the copy of three doubles to the host"}
     out["macroscopic_f32"] = {"ms": round(mac_ms, 4), "bytes_per_node": 48,
                               "roofline": roofline(case.nodes, 48, mac_ms)}
@@ -272,7 +324,8 @@ def main():
     ms = timed(solver, args.steps, args.warmup)
     mlups = case.nodes / (ms * 1e-3) / 1e6
     bytes_per_node = 68  # per pass: 8 FP32 loads + 8 FP32 stores + the FP32 porosity load
-    launch_ms = cycles * ms  # one launch advances `cycles` cycles
+    # the dominant kernel's own launch duration (HIP events around back-to-back launches)
+    launch_ms = per_launch_ms(solver, cycles)
     rl = roofline(case.nodes, bytes_per_node, launch_ms)
     kname = {3: ("void mrt::k_step3<float", "k_step3<float, 64, 16>: three collide-stream cycles per launch"),
              2: ("void mrt::k_step2<float", "k_step2<float, 64, 16>: two collide-stream cycles per launch"),
@@ -282,6 +335,11 @@ def main():
     rl["traffic_unit"] = "GB per launch"
     rl["kernel"] = kname[1]
     rl["algorithmic_bytes_per_launch"] = case.nodes * bytes_per_node
+    rl["launch_ms"] = round(launch_ms, 4)
+    rl["launch_timing"] = ("HIP events on the launch stream: 21-pass call minus 1-pass call, 20 back-to-back "
+                           "launches, best of 3")
+    # the whole timed call (every pass, the last one writing u(t - 1), and launch gaps)
+    rl["effective_gbs"] = round(case.nodes * bytes_per_node / (cycles * ms * 1e-3) / 1e9, 1)
     rl["one_cycle_equivalent_gbs"] = round(case.nodes * bytes_per_node / (ms * 1e-3) / 1e9, 1)
     mass, res, _ = solver.reduce()
     out = {

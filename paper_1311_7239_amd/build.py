@@ -29,18 +29,22 @@ def build(verbose: bool = False) -> pathlib.Path:
     objs = []
     build_dir = PKG / "_build"
     build_dir.mkdir(exist_ok=True)
+    procs = []
+    # the translation units compile concurrently (one hipcc process each)
     for src in SOURCES:
         path = CSRC / src
         if not path.exists():
             continue
         obj = build_dir / (src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-        cmd = [hipcc, *FLAGS, *lang, "-I", str(ROOT / "include"), "-I", str(CSRC), "-c", str(path),
+        cmd = [hipcc, *FLAGS, "-x", "hip", "-I", str(ROOT / "include"), "-I", str(CSRC), "-c", str(path),
                "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(str(obj))
+    failed = [cmd for cmd, proc in procs if proc.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB.with_suffix(".so.tmp")
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", str(tmp), *objs]
     if verbose:

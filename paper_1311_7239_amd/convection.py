@@ -76,7 +76,8 @@ def run_sweep(keyed_cases: List[Tuple[tuple, I.Case]], chunk: int = 4000, tol: f
               device="cuda") -> Dict[tuple, dict]:
     """Steps all cases as one thermal batch from the conduction profile until every
     Nusselt number changes by less than tol over a chunk (or max_steps / the time
-    limit is reached). Returns {key: {"nu", "steps", "converged"}}."""
+    limit is reached). Returns {key: {"nu", "steps", "converged", "diverged"}}: a case whose
+    Nusselt number stops being finite is stopped and reported as diverged, not converged."""
     cases = [c for _, c in keyed_cases]
     b = lbm.batch_for_cases(cases, storage=storage, device=device)
     for k, c in enumerate(cases):
@@ -84,6 +85,7 @@ def run_sweep(keyed_cases: List[Tuple[tuple, I.Case]], chunk: int = 4000, tol: f
                           torch.from_numpy(conduction_state(c)).to(device))
     prev = [None] * len(cases)
     done = [False] * len(cases)
+    diverged = [False] * len(cases)
     nu = [float("nan")] * len(cases)
     when = [0] * len(cases)
     t0 = time.time()
@@ -97,7 +99,7 @@ def run_sweep(keyed_cases: List[Tuple[tuple, I.Case]], chunk: int = 4000, tol: f
             _, _, T = b.macroscopic(k, want_T=True)
             nu[k] = nusselt_hot_wall(T.cpu().numpy().astype(np.float64), c)
             if not np.isfinite(nu[k]):
-                done[k] = True
+                done[k] = diverged[k] = True
                 when[k] = steps
             elif prev[k] is not None and abs(nu[k] - prev[k]) < tol:
                 done[k] = True
@@ -107,7 +109,8 @@ def run_sweep(keyed_cases: List[Tuple[tuple, I.Case]], chunk: int = 4000, tol: f
             log(f"t={steps} converged {sum(done)}/{len(cases)} elapsed {time.time() - t0:.1f}s")
         if all(done) or (time_limit is not None and time.time() - t0 > time_limit):
             break
-    return {key: {"nu": nu[k], "steps": when[k] if done[k] else steps, "converged": bool(done[k])}
+    return {key: {"nu": nu[k], "steps": when[k] if done[k] else steps,
+                  "converged": bool(done[k] and not diverged[k]), "diverged": diverged[k]}
             for k, (key, _) in enumerate(keyed_cases)}
 
 
@@ -124,9 +127,9 @@ def _main(argv=None):
     keyed = table1_cases(nee=a.walls == "on-node")
     res = run_sweep(keyed, chunk=a.chunk, tol=a.tol, max_steps=a.max_steps, time_limit=a.time_limit,
                     log=lambda m: print(m, flush=True))
-    print("Da Ra phi Nu steps converged")
+    print("Da Ra phi Nu steps converged diverged")
     for (Da, Ra, phi), r in res.items():
-        print(f"{Da:g} {Ra:g} {phi} {r['nu']:.4f} {r['steps']} {int(r['converged'])}")
+        print(f"{Da:g} {Ra:g} {phi} {r['nu']:.4f} {r['steps']} {int(r['converged'])} {int(r['diverged'])}")
 
 
 if __name__ == "__main__":

@@ -47,6 +47,7 @@ struct Layout {
     size_t p_bytes = 0;  // one FP32 plane
     size_t off_f[2] = {0, 0}, off_g[2] = {0, 0};
     size_t off_phi = 0, off_kappa = 0, off_snu = 0, off_part = 0, off_res = 0;
+    size_t off_uprev = 0;  // u(t - 1): two FP32 planes written by the last pass of lbm_step
     int red_blocks = 0;
     // recording for the adjoint
     int64_t nck = 0, ring = 0;
@@ -84,6 +85,7 @@ Layout make_layout(const lbm_desc &d, int64_t max_rec) {
     L.red_blocks = reduce_blocks(d.nx, d.ny);
     L.off_part = carve(sizeof(double) * 3 * (size_t)L.red_blocks);
     L.off_res = carve(sizeof(double) * 4);
+    L.off_uprev = carve(L.p_bytes * 2);
     if (d.ckpt_every > 0) {
         L.nck = max_rec / d.ckpt_every + 1;
         L.ring = d.ckpt_every;
@@ -228,6 +230,7 @@ struct lbm_ctx {
     int64_t rec_cap = 0;
     // batched stepping
     Dom *d_doms = nullptr;
+    Dom *d_doms_rec = nullptr;  // the same descriptors with u(t - 1) recording (last pass of a call)
     int4 *d_tiles = nullptr;
     int ntiles = 0;
     int grid = 0;
@@ -296,8 +299,15 @@ Dom dom_for(const Domain &D, int cur) {
     return d;
 }
 
+// The descriptor of the last pass of an lbm_step call: its last collision
+// writes u into the domain's two u(t - 1) planes for the steady residual.
+Dom dom_rec(const Domain &D, int cur) {
+    Dom d = dom_for(D, cur);
+    d.uprev = (float *)(D.base + D.L.off_uprev);
+    return d;
+}
+
 Source src_now(int64_t t) { return t == 0 ? SRC_DIRECT : SRC_GATHER; }
-Source src_prev(int64_t t) { return t == 0 ? SRC_NONE : (t == 1 ? SRC_DIRECT : SRC_GATHER); }
 
 int check_ctx(lbm_ctx *c) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
@@ -580,13 +590,17 @@ int lbm_step(lbm_ctx *c, int64_t n) {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    // The last pass of every call (the one that brings n to 0) records the
+    // velocity of its last collision, u(t - 1) of the final time t, for
+    // lbm_reduce's residual; graph replays never end a call.
     while (n > 0) {
         hipError_t e;
         if (c->t == 0) {
             // collide-only first cycle of every domain
             for (Domain &D : c->dom) {
-                e = launch_step(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
-                                SRC_DIRECT, false, c->sched, c->stream);
+                const Dom d = n == 1 ? dom_rec(D, c->cur) : dom_for(D, c->cur);
+                e = launch_step(d, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, SRC_DIRECT, false, c->sched,
+                                c->stream);
                 if (e != hipSuccess) return device_fail(c, e, "step launch");
             }
             c->cur ^= 1;
@@ -596,15 +610,13 @@ int lbm_step(lbm_ctx *c, int64_t n) {
             continue;
         }
         const bool recording = c->rec_valid && c->dom[0].desc.ckpt_every > 0;
-        // several cycles per pass while at least one single cycle remains for the end of
-        // this call (so the previous buffer always holds f+(t-2) -> u(t-1) for the residual);
-        // when recording, a pass never steps over a checkpoint time (the checkpoint
-        // needs the state there)
+        // several cycles per pass where they fit; when recording, a pass never
+        // steps over a checkpoint time (the checkpoint needs the state there)
         const bool fused = c->tblock >= 2;
         const int64_t next_ck = recording ? (c->t / c->dom[0].desc.ckpt_every + 1) * c->dom[0].desc.ckpt_every
                                           : INT64_MAX;
         const int64_t gcyc = graph_cycles(c);
-        if (gcyc > 0 && !recording && n - (fused ? 1 : 0) >= gcyc) {
+        if (gcyc > 0 && !recording && n - 1 >= gcyc) {
             if (!c->gexec[c->cur]) {
                 if ((e = build_graph(c, c->cur)) != hipSuccess) return device_fail(c, e, "graph build");
             }
@@ -616,48 +628,37 @@ int lbm_step(lbm_ctx *c, int64_t n) {
             n -= gcyc;
             continue;
         }
-        if (fused && c->tblock == 3 && n >= 4 && c->t + 3 <= next_ck) {
-            Domain &D = c->dom[0];
+        Domain &D = c->dom[0];
+        const int st = D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32;
+        int cycles = 1;
+        if (fused && c->tblock == 3 && n >= 3 && c->t + 3 <= next_ck) cycles = 3;
+        else if (fused && n >= 2 && c->t + 2 <= next_ck) cycles = 2;
+        const bool last = (n == cycles);
+        const Dom d = last ? dom_rec(D, c->cur) : dom_for(D, c->cur);
+        Dom *doms = last ? c->d_doms_rec : c->d_doms;
+        if (cycles == 3) {
             if (c->batch)
-                e = launch_step3_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_uniform,
-                                       c->grid3, c->stream);
+                e = launch_step3_batch(doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_uniform, c->grid3,
+                                       c->stream);
             else
-                e = launch_step3(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
-                                 c->sched.swizzle, nullptr, nullptr, c->stream);
-            if (e != hipSuccess) return device_fail(c, e, "step launch");
-            c->cur ^= 1;
-            c->t += 3;
-            n -= 3;
-            if ((e = checkpoint(c)) != hipSuccess) return device_fail(c, e, "checkpoint copy");
-            continue;
-        }
-        if (fused && n >= 3 && c->t + 2 <= next_ck) {
-            Domain &D = c->dom[0];
+                e = launch_step3(d, st, c->sched.swizzle, nullptr, nullptr, c->stream);
+        } else if (cycles == 2) {
             if (c->batch)
-                e = launch_step2_batch(c->d_doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_thermal,
+                e = launch_step2_batch(doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_thermal,
                                        c->batch_uniform, c->tb_threads, c->tb_rows, c->grid2, c->stream);
             else
-                e = launch_step2(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
-                                 c->sched.swizzle, c->tb_threads, c->tb_rows, nullptr, c->stream);
-            if (e != hipSuccess) return device_fail(c, e, "step launch");
-            c->cur ^= 1;
-            c->t += 2;
-            n -= 2;
-            if ((e = checkpoint(c)) != hipSuccess) return device_fail(c, e, "checkpoint copy");
-            continue;
-        }
-        if (c->batch) {
-            e = launch_step_batch(c->d_doms, c->d_tiles, c->ntiles, c->cur, c->storage, c->batch_thermal, c->sched, c->grid,
-                                  c->stream);
+                e = launch_step2(d, st, c->sched.swizzle, c->tb_threads, c->tb_rows, nullptr, c->stream);
         } else {
-            Domain &D = c->dom[0];
-            e = launch_step(dom_for(D, c->cur), D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, SRC_GATHER,
-                            false, c->sched, c->stream);
+            if (c->batch)
+                e = launch_step_batch(doms, c->d_tiles, c->ntiles, c->cur, c->storage, c->batch_thermal, c->sched,
+                                      c->grid, c->stream);
+            else
+                e = launch_step(d, st, SRC_GATHER, false, c->sched, c->stream);
         }
         if (e != hipSuccess) return device_fail(c, e, "step launch");
         c->cur ^= 1;
-        c->t += 1;
-        n -= 1;
+        c->t += cycles;
+        n -= cycles;
         if ((e = checkpoint(c)) != hipSuccess) return device_fail(c, e, "checkpoint copy");
     }
     return LBM_OK;
@@ -724,11 +725,12 @@ int lbm_reduce(lbm_ctx *c, int32_t k, double *mass, double *residual) {
     if ((rc = check_domain(c, k))) return rc;
     Domain &D = c->dom[k];
     const Dom cur = dom_for(D, c->cur);
-    const Dom prev = dom_for(D, c->cur ^ 1);
+    // u(t - 1) was recorded by the last pass of the last lbm_step call
+    const float *uprev = c->t >= 1 ? (const float *)(D.base + D.L.off_uprev) : nullptr;
     double *partials = (double *)(D.base + D.L.off_part);
     double *result = (double *)(D.base + D.L.off_res);
-    hipError_t e = launch_reduce(cur, src_now(c->t), prev, src_prev(c->t),
-                                 D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, partials, result, c->stream);
+    hipError_t e = launch_reduce(cur, src_now(c->t), uprev, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
+                                 partials, result, c->stream);
     if (e != hipSuccess) return device_fail(c, e, "reduce launch");
     double h[3];
     e = hipMemcpyAsync(h, result, sizeof(h), hipMemcpyDeviceToHost, c->stream);
@@ -748,18 +750,45 @@ int lbm_state_bytes(const lbm_ctx *c, size_t *bytes) {
     if (!c || !bytes) return fail(LBM_EINVAL, "NULL argument");
     if (c->batch) return fail(LBM_ENOTSUP, "save/load is per single-domain context");
     const Domain &D = c->dom[0];
-    *bytes = 64 + 2 * (D.L.f_bytes + (D.desc.thermal.enabled ? D.L.g_bytes : 0));
+    *bytes = 64 + D.L.f_bytes + (D.desc.thermal.enabled ? D.L.g_bytes : 0) + 2 * D.L.p_bytes;
     return LBM_OK;
 }
 
 namespace {
-uint64_t desc_hash(const lbm_desc &d) {
-    // FNV-1a over the descriptor bytes that define the state's meaning
-    const unsigned char *p = (const unsigned char *)&d;
+// FNV-1a over every descriptor field that gives a saved state its meaning,
+// field by field (struct padding never enters): grid, boundaries, lid,
+// viscosity, J and its plane, relaxation rates, medium, forcing, Pi0, storage
+// and, with the thermal model on, every thermal parameter. ckpt_every only
+// decides recording and is left out.
+struct Fnv {
     uint64_t h = 1469598103934665603ull;
-    for (size_t i = 0; i < offsetof(lbm_desc, ckpt_every); ++i) { h ^= p[i]; h *= 1099511628211ull; }
-    return h;
+    void add(const void *v, size_t n) {
+        const unsigned char *p = (const unsigned char *)v;
+        for (size_t i = 0; i < n; ++i) { h ^= p[i]; h *= 1099511628211ull; }
+    }
+    void i32(int32_t v) { add(&v, sizeof(v)); }
+    void f64(double v) { add(&v, sizeof(v)); }
+};
+
+uint64_t desc_hash(const lbm_desc &d) {
+    Fnv f;
+    f.i32(d.nx); f.i32(d.ny); f.i32(d.bc_x); f.i32(d.bc_y); f.f64(d.lid_ux);
+    f.f64(d.nu); f.f64(d.J); f.f64(d.s_e); f.f64(d.s_q);
+    f.i32(d.medium); f.f64(d.phi0); f.f64(d.kappa0); f.f64(d.dp); f.f64(d.F_eps);
+    f.f64(d.ax); f.f64(d.ay); f.f64(d.Pi0); f.i32(d.storage); f.i32(d.j_plane);
+    const lbm_thermal &t = d.thermal;
+    f.i32(t.enabled);
+    if (t.enabled) {
+        f.f64(t.tau_T); f.f64(t.sigma); f.f64(t.zeta3); f.f64(t.zeta4);
+        f.f64(t.Th); f.f64(t.Tc); f.f64(t.T0); f.f64(t.g_beta);
+    }
+    return f.h;
 }
+
+// Snapshot header (64 bytes): magic, descriptor hash, t, payload bytes; then
+// the populations f (and g) in the current buffer's layout and the two u(t - 1)
+// planes.
+constexpr uint64_t kSnapMagic = 0x4d52544c424d3032ull;  // "MRTLBM02"
 }  // namespace
 
 int lbm_save(lbm_ctx *c, void *host_buf, size_t bytes) {
@@ -771,22 +800,20 @@ int lbm_save(lbm_ctx *c, void *host_buf, size_t bytes) {
     Domain &D = c->dom[0];
     char *h = (char *)host_buf;
     std::memset(h, 0, 64);
-    const uint64_t magic = 0x4d52544c424d3031ull, hash = desc_hash(D.desc);
-    std::memcpy(h, &magic, 8);
+    const uint64_t hash = desc_hash(D.desc), payload = need - 64;
+    std::memcpy(h, &kSnapMagic, 8);
     std::memcpy(h + 8, &hash, 8);
     std::memcpy(h + 16, &c->t, 8);
+    std::memcpy(h + 24, &payload, 8);
     size_t o = 64;
-    const int order[2] = {c->cur, c->cur ^ 1};
-    hipError_t e = hipSuccess;
-    for (int b : order) {
-        e = hipMemcpyAsync(h + o, D.base + D.L.off_f[b], D.L.f_bytes, hipMemcpyDeviceToHost, c->stream);
-        o += D.L.f_bytes;
-        if (e == hipSuccess && D.desc.thermal.enabled) {
-            e = hipMemcpyAsync(h + o, D.base + D.L.off_g[b], D.L.g_bytes, hipMemcpyDeviceToHost, c->stream);
-            o += D.L.g_bytes;
-        }
-        if (e != hipSuccess) break;
+    hipError_t e = hipMemcpyAsync(h + o, D.base + D.L.off_f[c->cur], D.L.f_bytes, hipMemcpyDeviceToHost, c->stream);
+    o += D.L.f_bytes;
+    if (e == hipSuccess && D.desc.thermal.enabled) {
+        e = hipMemcpyAsync(h + o, D.base + D.L.off_g[c->cur], D.L.g_bytes, hipMemcpyDeviceToHost, c->stream);
+        o += D.L.g_bytes;
     }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h + o, D.base + D.L.off_uprev, 2 * D.L.p_bytes, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_fail(c, e, "save");
     return LBM_OK;
@@ -797,29 +824,31 @@ int lbm_load(lbm_ctx *c, const void *host_buf, size_t bytes) {
     if (rc) return rc;
     size_t need;
     if ((rc = lbm_state_bytes(c, &need))) return rc;
-    if (!host_buf || bytes < need) return fail(LBM_EINVAL, "snapshot too small (%zu < %zu)", bytes, need);
+    if (!host_buf || bytes < 64) return fail(LBM_EINVAL, "snapshot too small (%zu bytes)", bytes);
     Domain &D = c->dom[0];
     const char *h = (const char *)host_buf;
-    uint64_t magic, hash;
+    uint64_t magic, hash, payload;
     int64_t t;
     std::memcpy(&magic, h, 8);
     std::memcpy(&hash, h + 8, 8);
     std::memcpy(&t, h + 16, 8);
-    if (magic != 0x4d52544c424d3031ull) return fail(LBM_EINVAL, "not a snapshot of this library");
+    std::memcpy(&payload, h + 24, 8);
+    if (magic != kSnapMagic) return fail(LBM_EINVAL, "not a snapshot of this library");
     if (hash != desc_hash(D.desc)) return fail(LBM_EINVAL, "snapshot was taken with a different descriptor");
+    if (payload != need - 64)
+        return fail(LBM_EINVAL, "snapshot holds %llu bytes of state, this context %zu", (unsigned long long)payload,
+                    need - 64);
+    if (bytes < need) return fail(LBM_EINVAL, "snapshot too small (%zu < %zu)", bytes, need);
     if (t < 0) return fail(LBM_EINVAL, "corrupt snapshot time");
     size_t o = 64;
-    const int order[2] = {c->cur, c->cur ^ 1};
-    hipError_t e = hipSuccess;
-    for (int b : order) {
-        e = hipMemcpyAsync(D.base + D.L.off_f[b], h + o, D.L.f_bytes, hipMemcpyHostToDevice, c->stream);
-        o += D.L.f_bytes;
-        if (e == hipSuccess && D.desc.thermal.enabled) {
-            e = hipMemcpyAsync(D.base + D.L.off_g[b], h + o, D.L.g_bytes, hipMemcpyHostToDevice, c->stream);
-            o += D.L.g_bytes;
-        }
-        if (e != hipSuccess) break;
+    hipError_t e = hipMemcpyAsync(D.base + D.L.off_f[c->cur], h + o, D.L.f_bytes, hipMemcpyHostToDevice, c->stream);
+    o += D.L.f_bytes;
+    if (e == hipSuccess && D.desc.thermal.enabled) {
+        e = hipMemcpyAsync(D.base + D.L.off_g[c->cur], h + o, D.L.g_bytes, hipMemcpyHostToDevice, c->stream);
+        o += D.L.g_bytes;
     }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(D.base + D.L.off_uprev, h + o, 2 * D.L.p_bytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return device_fail(c, e, "load");
     c->t = t;
@@ -1035,7 +1064,7 @@ BatchLayout batch_layout(int32_t n, const lbm_desc *descs) {
         if (t > B.max_tiles) B.max_tiles = t;
     }
     B.off_doms = o;
-    o = align_up(o + sizeof(Dom) * 2 * (size_t)n, ALIGN);
+    o = align_up(o + sizeof(Dom) * 4 * (size_t)n, ALIGN);  // two per parity: plain and recording
     B.off_tiles = o;
     o = align_up(o + sizeof(int4) * (size_t)B.max_tiles, ALIGN);
     for (const auto &sh : kTwoCycleShapes) {
@@ -1269,11 +1298,14 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
     c->d_tiles = (int4 *)(base + B.off_tiles);
     size_t state_bytes = 0;
     for (const Domain &D : c->dom) state_bytes += D.L.f_bytes + D.L.g_bytes;
-    c->h_doms.resize(2 * (size_t)n);
+    c->h_doms.resize(4 * (size_t)n);
+    c->d_doms_rec = c->d_doms + 2 * (size_t)n;
     for (int32_t k = 0; k < n; ++k) {
         c->dom[(size_t)k].dom.nt_store = state_bytes >= kCacheBytes ? 1 : 0;
         c->h_doms[2 * (size_t)k] = dom_for(c->dom[(size_t)k], 0);
         c->h_doms[2 * (size_t)k + 1] = dom_for(c->dom[(size_t)k], 1);
+        c->h_doms[2 * (size_t)n + 2 * (size_t)k] = dom_rec(c->dom[(size_t)k], 0);
+        c->h_doms[2 * (size_t)n + 2 * (size_t)k + 1] = dom_rec(c->dom[(size_t)k], 1);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(c->d_doms, c->h_doms.data(), sizeof(Dom) * c->h_doms.size(), hipMemcpyHostToDevice,

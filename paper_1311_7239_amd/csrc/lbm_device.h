@@ -69,6 +69,9 @@ struct Dom {
     int32_t nt_store;                // store the state non-temporally (state buffers
                                      // larger than the Infinity Cache)
     float inv_nu;                    // 1 / nu (parameter gradients)
+    float *uprev;                    // optional: u_x, u_y planes ([ny][pitch] each) of the
+                                     // last collision of the pass, i.e. u(t - 1) once the
+                                     // pass has advanced the state to t (steady residual)
 };
 
 // Square root and reciprocal by the hardware instructions (v_sqrt_f32,

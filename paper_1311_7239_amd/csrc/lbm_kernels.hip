@@ -109,6 +109,15 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
                     else store_row<float, NX>(d.gout + j * d.plane + o, g[THERMAL ? r : 0][j]);
                 }
             }
+            if (d.uprev) {
+                if (d.nt_store) {
+                    store_row_nt<float, NX>(d.uprev + o, ux);
+                    store_row_nt<float, NX>(d.uprev + d.plane + o, uy);
+                } else {
+                    store_row<float, NX>(d.uprev + o, ux);
+                    store_row<float, NX>(d.uprev + d.plane + o, uy);
+                }
+            }
             if (REC) {
                 store_row<float, NX>(d.urec + o, ux);
                 store_row<float, NX>(d.urec + d.plane + o, uy);
@@ -149,6 +158,10 @@ __device__ __forceinline__ void step_tile(const Dom &d, int tx, int ty) {
             if (THERMAL) {
 #pragma unroll
                 for (int j = 0; j < 5; ++j) d.gout[j * d.plane + o] = gn[j];
+            }
+            if (d.uprev) {
+                d.uprev[o] = ux;
+                d.uprev[d.plane + o] = uy;
             }
             if (REC) {
                 d.urec[o] = ux;
@@ -355,6 +368,21 @@ struct Pending {
     }
 };
 
+// u of a pass's last collision (the velocity one cycle before the state the
+// pass leaves) into the two planes d.uprev, for the steady residual. Only the
+// last pass of an lbm_step call records it; the planes are below 4 GiB
+// whenever multi-cycle passes run.
+__device__ __forceinline__ void store_uprev(const Dom &d, uint32_t o4, float ux, float uy) {
+    const BufRes r = buf_res(d.uprev, (uint32_t)(2 * d.plane * 4));
+    if (d.nt_store) {
+        BufIO<float>::st_nt(r, o4, 0u, ux);
+        BufIO<float>::st_nt(r, o4, (uint32_t)(d.plane * 4), uy);
+    } else {
+        BufIO<float>::st(r, o4, 0u, ux);
+        BufIO<float>::st(r, o4, (uint32_t)(d.plane * 4), uy);
+    }
+}
+
 // ------------------------------------------------- two steps per pass
 
 // Temporal blocking: one launch advances t -> t + 2 with a single HBM pass.
@@ -548,6 +576,7 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
                 else BufIO<float>::st(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
             }
         }
+        if (d.uprev) store_uprev(d, (uint32_t)(o * 4), ux, uy);
         if (REC) {
             const BufRes rr = buf_res(urec_next, rbytes);
             record_node(d, rr, (uint32_t)(o * 4), ux, uy, n7, n8);
@@ -817,6 +846,7 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
                 else BufIO<float>::st(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
             }
         }
+        if (d.uprev) store_uprev(d, (uint32_t)(o * 4), ux, uy);
         if (REC) {
             record_node(d, rr2, (uint32_t)(o * 4), ux, uy, n7, n8);
             if (THERMAL) BufIO<float>::st_nt(rr2, (uint32_t)(o * 4), (uint32_t)(4 * d.plane * 4), dT);
@@ -1214,7 +1244,7 @@ int reduce_blocks(int nx, int ny) {
 }
 
 template <typename S, bool THERMAL>
-__global__ __launch_bounds__(BLOCK) void k_reduce(Dom cur, int src_cur, Dom prev, int src_prev,
+__global__ __launch_bounds__(BLOCK) void k_reduce(Dom cur, int src_cur, const float *uprev,
                                                   double *partials) {
     // at most 2^31 nodes, so node numbers and the stride stay below 2^32
     const uint32_t n = (uint32_t)cur.nx * (uint32_t)cur.ny, nx = (uint32_t)cur.nx;
@@ -1228,10 +1258,9 @@ __global__ __launch_bounds__(BLOCK) void k_reduce(Dom cur, int src_cur, Dom prev
         state_velocity<THERMAL>(cur, o, f, g, ux, uy, m1, dT);
         acc[0] += (double)m1;
         acc[2] += (double)ux * ux + (double)uy * uy;
-        if (src_prev != SRC_NONE) {
-            read_state<S, THERMAL>(prev, src_prev, x, y, f, g);
-            float px, py, pm1, pdT;
-            state_velocity<THERMAL>(prev, o, f, g, px, py, pm1, pdT);
+        if (uprev) {
+            // u(t - 1) as the last collision of the previous pass computed it
+            const float px = uprev[o], py = uprev[cur.plane + o];
             const double dx = (double)ux - px, dy = (double)uy - py;
             acc[1] += dx * dx + dy * dy;
         }
@@ -1250,16 +1279,16 @@ __global__ __launch_bounds__(BLOCK) void k_reduce_final(const double *partials, 
     block_sum3(acc, result);
 }
 
-hipError_t launch_reduce(const Dom &cur, Source src_cur, const Dom &prev, Source src_prev,
-                         int storage, double *partials, double *result, hipStream_t st) {
+hipError_t launch_reduce(const Dom &cur, Source src_cur, const float *uprev, int storage, double *partials,
+                         double *result, hipStream_t st) {
     const int nb = reduce_blocks(cur.nx, cur.ny);
     const bool th = cur.thermal != 0;
     if (storage == ST_F32) {
-        if (th) hipLaunchKernelGGL((k_reduce<float, true>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, prev, (int)src_prev, partials);
-        else hipLaunchKernelGGL((k_reduce<float, false>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, prev, (int)src_prev, partials);
+        if (th) hipLaunchKernelGGL((k_reduce<float, true>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, uprev, partials);
+        else hipLaunchKernelGGL((k_reduce<float, false>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, uprev, partials);
     } else {
-        if (th) hipLaunchKernelGGL((k_reduce<_Float16, true>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, prev, (int)src_prev, partials);
-        else hipLaunchKernelGGL((k_reduce<_Float16, false>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, prev, (int)src_prev, partials);
+        if (th) hipLaunchKernelGGL((k_reduce<_Float16, true>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, uprev, partials);
+        else hipLaunchKernelGGL((k_reduce<_Float16, false>), dim3(nb), dim3(BLOCK), 0, st, cur, (int)src_cur, uprev, partials);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

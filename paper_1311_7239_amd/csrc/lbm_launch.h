@@ -84,10 +84,12 @@ hipError_t launch_set_populations(const Dom &d, int storage, const float *df,
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 
 // FP64 reductions: partial sums (sum dm1, sum |u - u_prev|^2, sum |u|^2) per
-// block, then one fixed-order pass into result[3].
+// block, then one fixed-order pass into result[3]. u_prev comes from the two
+// planes uprev ([ny][pitch] u_x then u_y, recorded by the last pass); with
+// uprev NULL the second sum is 0.
 int reduce_blocks(int nx, int ny);
-hipError_t launch_reduce(const Dom &cur, Source src_cur, const Dom &prev, Source src_prev,
-                         int storage, double *partials, double *result, hipStream_t st);
+hipError_t launch_reduce(const Dom &cur, Source src_cur, const float *uprev, int storage, double *partials,
+                         double *result, hipStream_t st);
 
 // Discrete adjoint pieces (FP32 storage, isothermal). acc (may be NULL):
 // per-workgroup FP64 slots of 4 (nu, a_x, a_y, U_lid) to which each launch

@@ -41,7 +41,8 @@ class Case:
     K0: float = math.inf         # uniform permeability (used when phi is None)
     phi: Optional[np.ndarray] = None   # float32 [ny, nx] porosity field
     dp: Optional[float] = None   # particle diameter for Eq. (4) when phi varies
-    Fphi: Optional[float] = None  # constant F_phi, or None for Eq. (4) per cell
+    Fphi: Optional[float] = None  # constant F_phi, or None: F_phi from Eq. (4) at the
+                                  # cell's porosity, evaluated by each side itself
     kappa: Optional[np.ndarray] = None  # float32 [ny, nx] 1/K plane (0 = free fluid); with phi
     Jfield: Optional[np.ndarray] = None  # float32 [ny, nx] per-node viscosity ratio
     Pi0: float = 1.0             # rest value of phi*p (initial state)
@@ -65,14 +66,11 @@ class Case:
         return np.full((self.ny, self.nx), self.phi0, dtype=np.float32)
 
 
-def ergun_F(phi: float) -> float:
-    """F_phi of Ergun's relation (Eq. 4), for uniform-medium inputs."""
-    return 1.75 / math.sqrt(150.0 * phi ** 3)
-
-
 def ergun_dp(K_ref: float, phi_ref: float) -> float:
-    """Particle diameter d_p that gives permeability K_ref at porosity phi_ref in
-    Ergun's relation (Eq. 4); used to build heterogeneous fields with a fixed d_p."""
+    """Particle diameter d_p at which Ergun's permeability (Eq. 4) equals K_ref at
+    porosity phi_ref: the input parameter of heterogeneous fields, which keep d_p
+    fixed. Neither side uses this to compute K or F_phi: the GPU library and the
+    oracle each evaluate Eq. (4) from (phi, d_p) themselves."""
     return math.sqrt(150.0 * K_ref * (1.0 - phi_ref) ** 2 / phi_ref ** 3)
 
 
@@ -108,7 +106,7 @@ def poiseuille_channel(ny: int = 64, nx: int = 8, phi: float = 0.1, Da: float = 
     th = math.sqrt(phi * nu / (K * J * nu))
     ax = u0 * nu / (K * (1.0 - 1.0 / math.cosh(0.5 * th * L)))
     return Case(name=f"poiseuille_{nx}x{ny}" + ("_nee" if nee else ""), nx=nx, ny=ny,
-                bc_x=PERIODIC, bc_y=NEE if nee else WALLS, nu=nu, J=J, ax=ax, phi0=phi, K0=K, Fphi=ergun_F(phi) if forchheimer else 0.0,
+                bc_x=PERIODIC, bc_y=NEE if nee else WALLS, nu=nu, J=J, ax=ax, phi0=phi, K0=K, Fphi=None if forchheimer else 0.0,
                 Pi0=phi, meta=dict(L=L, u0=u0, Da=Da, Re=Re))
 
 
@@ -154,7 +152,7 @@ def lid_cavity(n: int = 512, phi: float = 0.4, Da: float = 1e-2, Re: float = 100
     K = Da * L * L
     bc = NEE if nee else WALLS
     case = Case(name=f"cavity_{n}" + ("_nee" if nee else ""), nx=n, ny=n, bc_x=bc, bc_y=bc, nu=nu, lid_ux=U,
-                phi0=phi, K0=K, Fphi=ergun_F(phi), Pi0=phi, steps=steps,
+                phi0=phi, K0=K, Fphi=None, Pi0=phi, steps=steps,
                 meta=dict(L=L, Da=Da, Re=Re, U=U))
     if heterogeneous:
         G = grf(n, n, ell, seed)
@@ -187,7 +185,7 @@ def natural_convection(n: int = 1024, phi: float = 0.6, Da: float = 1e-4, Ra: fl
     bc = NEE if nee else WALLS
     return Case(name=f"convection_{n}" + ("_nee" if nee else ""), nx=n, ny=n, bc_x=bc, bc_y=bc,
                 nu=nu, J=J,
-                phi0=phi, K0=Da * L * L, Fphi=ergun_F(phi), Pi0=phi, steps=steps,
+                phi0=phi, K0=Da * L * L, Fphi=None, Pi0=phi, steps=steps,
                 thermal=True, sigma=sigma, tau_T=tau_T, Th=Th, Tc=Tc, T0=0.5 * (Th + Tc),
                 gbeta=gbeta, meta=dict(L=L, Da=Da, Ra=Ra, Pr=Pr, Ma=Ma, tau_v=tau_v))
 
@@ -207,7 +205,7 @@ def cavity_batch(count: int = 256, seed: int = 4, nmin: int = 64, nmax: int = 76
         nu = U * L / float(Re[k])
         K = 10.0 ** float(lDa[k]) * L * L
         cases.append(Case(name=f"batch{k}_{n}", nx=n, ny=n, bc_x=WALLS, bc_y=WALLS, nu=nu,
-                          lid_ux=U, phi0=float(phis[k]), K0=K, Fphi=ergun_F(float(phis[k])),
+                          lid_ux=U, phi0=float(phis[k]), K0=K, Fphi=None,
                           Pi0=float(phis[k]),
                           meta=dict(L=L, Da=10.0 ** float(lDa[k]), Re=float(Re[k]))))
     return cases

@@ -18,13 +18,19 @@ import pathlib
 import sys
 
 PKG = pathlib.Path(__file__).resolve().parent
-KERNEL_SOURCES = ["csrc/lbm_device.h", "csrc/lbm_kernels.hip"]
+
+
+def kernel_sources():
+    """Every source of the library (kernels, device header, launch interface, C ABI):
+    a change to any of them, launch choices included, marks older summaries stale."""
+    return sorted(p for p in (PKG / "csrc").iterdir() if p.suffix in (".hip", ".h", ".cpp"))
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        h.update((PKG / rel).read_bytes())
+    for path in kernel_sources():
+        h.update(path.name.encode() + b"\0")
+        h.update(path.read_bytes())
     return h.hexdigest()[:16]
 
 

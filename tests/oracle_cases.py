@@ -35,6 +35,15 @@ def oracle_setup(case, nthreads=0):
     return p, phi, K, F
 
 
+def uniform_F(case):
+    """F_phi of a uniform-medium case: the constant it fixes, or else the oracle's own
+    Eq. (4) at its porosity (the closed forms of Sec. 3 take it as a parameter)."""
+    if case.Fphi is not None:
+        return float(case.Fphi)
+    _, F = oracle.ergun(np.array([case.phi0], dtype=np.float64), 1.0)
+    return float(F[0])
+
+
 def run_to_steady(p, phi, K, F, f, tol=1e-10, every=100, max_steps=5_000_000):
     """Run until r(t) = ||u(t) - u(t-1)|| / ||u(t)|| < tol, checked every `every` steps."""
     t = 0

@@ -56,9 +56,13 @@ def gpu_gradient(case, target, kappa=None, ckpt=64):
     return g.cpu().numpy().astype(np.float64), (None if gk is None else gk.cpu().numpy().astype(np.float64))
 
 
-def test_adjoint_matches_oracle_finite_differences():
-    case = twin()
-    target = oracle_outlet(case, twin(seed=55).phi)
+@pytest.mark.parametrize("size", [(96, 64, 300), (256, 256, 400)], ids=["96x64_300", "256x256_400"])
+def test_adjoint_matches_oracle_finite_differences(size):
+    """16 cells against central differences of the FP64 oracle, on the small twin and on
+    the 256^2 / 400-step twin of the 2048^2 inverse problem (checkpoints every 64)."""
+    nx, ny, steps = size
+    case = twin(nx=nx, ny=ny, steps=steps)
+    target = oracle_outlet(case, twin(nx=nx, ny=ny, steps=steps, seed=55).phi)
     g, _ = gpu_gradient(case, target)
     phi0 = case.phi.astype(np.float64)
     # 16 cells: the 8 largest |g| and 8 seeded random cells with |g| above 1% of the max
@@ -75,6 +79,7 @@ def test_adjoint_matches_oracle_finite_differences():
         pm = phi0.copy(); pm[j, i] -= h
         fd = (loss(oracle_outlet(case, pp), target) - loss(oracle_outlet(case, pm), target)) / (2 * h)
         worst = max(worst, abs(g[j, i] - fd) / abs(fd))
+    print(f"adjoint {nx}x{ny}, {steps} steps: worst relative error over 16 cells {worst:.2e}")
     assert worst < 2e-3, worst
 
 

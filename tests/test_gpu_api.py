@@ -41,6 +41,52 @@ def test_load_rejects_a_snapshot_of_another_descriptor():
         a.load(blob[:100])
 
 
+def test_load_rejects_snapshots_of_other_thermal_setups():
+    """The descriptor hash covers the thermal block: a thermal snapshot does not load into
+    an isothermal context with otherwise equal fields, nor into one with another hot-wall
+    temperature or g beta."""
+    case = I.natural_convection(n=48)
+    a = lbm.solver_for_case(case)
+    a.step(7)
+    blob = a.save()
+    iso = I.natural_convection(n=48)
+    iso.thermal = False
+    variants = [iso]
+    for field, value in (("Th", case.Th + 1.0), ("gbeta", 2.0 * case.gbeta)):
+        v = I.natural_convection(n=48)
+        setattr(v, field, value)
+        variants.append(v)
+    for v in variants:
+        b = lbm.solver_for_case(v)
+        with pytest.raises(lbm.LBMError) as e:
+            b.load(blob)
+        assert e.value.status == lbm.EINVAL
+        assert b.time == 0
+    same = lbm.solver_for_case(I.natural_convection(n=48))
+    same.load(blob)
+    assert same.time == 7
+
+
+@pytest.mark.parametrize("tblock", [2, 3])
+def test_snapshot_after_a_multi_cycle_pass_keeps_the_residual(tblock):
+    """A snapshot carries the u(t - 1) planes of the last pass, so the residual of the
+    restored context equals the original's bit for bit."""
+    case = I.lognormal_channel(n=128, seed=3, ell=8.0, K_ref=30.0, drive=0.05)
+    a = lbm.solver_for_case(case)
+    a.set_time_blocking(tblock)
+    a.step(31)
+    blob = a.save()
+    b = lbm.solver_for_case(case)
+    b.load(blob)
+    assert b.reduce() == a.reduce()
+    a.step(8)
+    b.step(8)
+    assert b.reduce() == a.reduce()
+    with pytest.raises(lbm.LBMError) as e:
+        b.load(blob[:-4])
+    assert e.value.status == lbm.EINVAL
+
+
 def test_non_finite_state_is_reported_unstable():
     case = I.lid_cavity(n=64)
     s = lbm.solver_for_case(case)

@@ -14,7 +14,7 @@ from oracle import analytic as A
 from paper_1311_7239_amd import inputs as I
 from paper_1311_7239_amd import lbm
 from tests.gpu_cases import Pair, max_rel_velocity_error
-from tests.oracle_cases import oracle_setup, run_to_steady
+from tests.oracle_cases import oracle_setup, run_to_steady, uniform_F
 
 pytestmark = pytest.mark.gpu
 GOLDEN = pathlib.Path(__file__).parent / "golden"
@@ -49,7 +49,7 @@ def test_poiseuille_channel_fp32_error_is_reported():
     u = gpu_u(s)
     e_orc = np.sqrt(np.sum((u[0] - ux_o) ** 2) / np.sum(ux_o ** 2))
     y = np.arange(64) + 0.5
-    ref = A.bf_poiseuille(y, 64, case.ax, case.phi0, case.K0, case.nu, case.Fphi)
+    ref = A.bf_poiseuille(y, 64, case.ax, case.phi0, case.K0, case.nu, uniform_F(case))
     e_bvp = np.sqrt(np.sum((u[0, :, 0] - ref) ** 2) / np.sum(ref ** 2))
     print(f"Poiseuille 8x64 FP32 after {t} steps: rel L2 vs FP64 oracle {e_orc:.2e}, vs Eq. (23) {e_bvp:.2e}")
     assert e_orc < 2e-3 and e_bvp < 2e-3
@@ -127,14 +127,15 @@ def test_cavity_batch_against_oracle_subset(storage, tol):
 def test_inverse_problem_2048_gradient_by_finite_differences():
     """2048^2 log-normal channel, 4000 steps, checkpoints every 200: the adjoint gradient of
     the outlet misfit (target: the same model on field seed 55) against central finite
-    differences of GPU forward runs, the loss summed in FP64.
+    differences of GPU forward runs, the loss summed in FP64, and against the tangent-linear
+    model of the same recorded pass (the dot-product identity, exact up to rounding).
 
     Along a seeded random direction with every cell perturbed the signal is large and the
     agreement tight. For single cells (16 from the top decile of |g|, seed 505) the FP32
     forward runs resolve the loss change only to a few per cent at h = 5e-2 phi (rounding
     of the two perturbed runs decorrelates), so those errors are printed and held to a
-    loose bound; the per-cell check at tight tolerance is the FP64-oracle one on the
-    small twin (test_gpu_adjoint)."""
+    loose bound; the same cells are held tightly against the tangent model of the
+    recorded pass, and against FP64-oracle differences on the 256^2 twin (test_gpu_adjoint)."""
     steps = 4000
     case = I.lognormal_channel(n=2048, seed=5)
     tgt_case = I.lognormal_channel(n=2048, seed=55)
@@ -156,19 +157,43 @@ def test_inverse_problem_2048_gradient_by_finite_differences():
     dLdu[:, :, -1] = u[:, :, -1] - torch.from_numpy(target.astype(np.float32)).cuda()
     g, _ = s.backward(dLdu)
     g = g.cpu().numpy().astype(np.float64)
-    del s
 
     phi0 = case.phi.astype(np.float64)
     r = np.random.default_rng(506).uniform(-1.0, 1.0, size=phi0.shape) * phi0
+    # dot-product identity on the real problem, free of finite-difference noise: the
+    # tangent-linear rerun of the recorded pass along r against the adjoint gradient
+    du = s.tangent(dphi=torch.from_numpy(r.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    lhs = float(np.sum(dLdu.cpu().numpy().astype(np.float64) * du.cpu().numpy().astype(np.float64)))
+    rhs = float(np.sum(g * r.astype(np.float32).astype(np.float64)))
+    dot_err = abs(lhs / rhs - 1.0)
+    print(f"2048^2 dot-product identity: <dL/du, J r> {lhs:.9e}, <dL/dphi, r> {rhs:.9e}, rel {dot_err:.2e}")
+    assert dot_err < 1e-4
+
+    # 16 cells from the top decile of |g| (seed 505): each against the tangent model along
+    # that cell alone (no finite-difference noise) and, loosely, against GPU differences
+    flat = np.abs(g).ravel()
+    top = np.flatnonzero(flat >= np.quantile(flat, 0.9))
+    cells = np.random.default_rng(505).choice(top, size=16, replace=False)
+    dLdu_np = dLdu.cpu().numpy().astype(np.float64)
+    tan_errs = []
+    for idx in cells:
+        j, i = divmod(int(idx), 2048)
+        e = torch.zeros((2048, 2048), dtype=torch.float32, device="cuda")
+        e[j, i] = 1.0
+        du = s.tangent(dphi=e)
+        torch.cuda.synchronize()
+        tl = float(np.sum(dLdu_np * du.cpu().numpy().astype(np.float64)))
+        tan_errs.append(abs(g[j, i] - tl) / abs(tl))
+    print("2048^2 adjoint vs tangent model per cell, relative errors:", [f"{v:.1e}" for v in tan_errs])
+    assert max(tan_errs) < 1e-3
+    del s
     eps = 1e-3
     fd_dir = (loss_of(phi0 + eps * r) - loss_of(phi0 - eps * r)) / (2 * eps)
     dir_err = abs(np.sum(g * r) / fd_dir - 1.0)
     print(f"2048^2 directional derivative: adjoint {np.sum(g * r):.6e}, FD {fd_dir:.6e}, rel err {dir_err:.2e}")
     assert dir_err < 1e-2
 
-    flat = np.abs(g).ravel()
-    top = np.flatnonzero(flat >= np.quantile(flat, 0.9))
-    cells = np.random.default_rng(505).choice(top, size=16, replace=False)
     errs = []
     for idx in cells:
         j, i = divmod(int(idx), 2048)
@@ -178,4 +203,7 @@ def test_inverse_problem_2048_gradient_by_finite_differences():
         errs.append(abs(g[j, i] - fd) / abs(fd))
     print("2048^2 adjoint vs single-cell GPU finite differences, relative errors:",
           np.round(errs, 4).tolist())
-    assert np.median(errs) < 0.1
+    # each FP32 forward run rounds differently once phi changes, so the single-cell
+    # differences carry noise of a few per cent (26% measured on one cell); the tight
+    # per-cell check is the tangent model's above
+    assert np.median(errs) < 0.05 and max(errs) < 0.5

@@ -14,7 +14,7 @@ import pytest
 import oracle
 from oracle import analytic as A
 from paper_1311_7239_amd import inputs as I
-from tests.oracle_cases import oracle_setup, run_to_steady
+from tests.oracle_cases import oracle_setup, run_to_steady, uniform_F
 
 GOLDEN = pathlib.Path(__file__).parent / "golden"
 
@@ -181,6 +181,68 @@ def test_rest_state_is_a_fixed_point():
     np.testing.assert_allclose(pres, 1.0, rtol=1e-15)
 
 
+# --------------------------------------------------------- Eq. (4), Sec. 2.1
+
+def _ergun_pressure_drop(phi, dp, nu, U):
+    """Ergun's packed-bed correlation per unit density: -dp/dx / rho =
+    150 nu (1 - phi)^2 U / (phi^3 dp^2) + 1.75 (1 - phi) U^2 / (phi^3 dp), U the
+    volume-averaged (superficial) velocity; Eq. (4) is derived from it (Sec. 2.1)."""
+    return (150.0 * nu * (1.0 - phi) ** 2 * U / (phi ** 3 * dp ** 2)
+            + 1.75 * (1.0 - phi) * U * U / (phi ** 3 * dp))
+
+
+def test_ergun_drag_reproduces_ergun_pressure_drop():
+    """Eq. (4) pinned to Ergun's relation: in steady uniform flow Eq. (2) leaves
+    grad(phi p)/rho0 = F of Eq. (3) with a = 0, so the drag per unit porosity,
+    nu u / K + F_phi u^2 / sqrt(K), must equal Ergun's pressure drop for every
+    porosity, particle diameter, viscosity and velocity. Separating two speeds
+    checks the Darcy part (K) and the Forchheimer part (F_phi) each on its own."""
+    rng = np.random.default_rng(404)
+    phi = rng.uniform(0.05, 0.95, 200)
+    dp = 10.0 ** rng.uniform(-1.0, 2.0, 200)
+    nu = 10.0 ** rng.uniform(-3.0, 0.0, 200)
+    K = np.empty(200)
+    F = np.empty(200)
+    for k in range(200):
+        Kk, Fk = oracle.ergun(np.array([phi[k]]), dp[k])
+        K[k], F[k] = Kk[0], Fk[0]
+    for U in (1e-4, 3e-2):
+        drag = nu * U / K + F * U * U / np.sqrt(K)
+        np.testing.assert_allclose(drag, _ergun_pressure_drop(phi, dp, nu, U), rtol=1e-13)
+    # the linear and quadratic coefficients on their own
+    lin = nu / K
+    quad = F / np.sqrt(K)
+    np.testing.assert_allclose(lin, 150.0 * nu * (1.0 - phi) ** 2 / (phi ** 3 * dp ** 2), rtol=1e-13)
+    np.testing.assert_allclose(quad, 1.75 * (1.0 - phi) / (phi ** 3 * dp), rtol=1e-13)
+
+
+def test_ergun_round_trip_through_particle_diameter():
+    """The input recipe picks d_p so that K(phi_ref) = K_ref (heterogeneous fields keep
+    d_p fixed); the oracle's Eq. (4) evaluated at that d_p gives K_ref back."""
+    for K_ref, phi_ref in ((2621.44, 0.4), (4.194304, 0.4), (30.0, 0.4), (104.8576, 0.6), (6.4, 0.1)):
+        dp = I.ergun_dp(K_ref, phi_ref)
+        K, _ = oracle.ergun(np.array([phi_ref]), dp)
+        assert abs(K[0] / K_ref - 1.0) < 1e-14
+
+
+def test_ergun_scalings():
+    """Eq. (4): K grows with d_p^2 and F_phi does not depend on d_p; F_phi phi^(3/2) is the
+    same for every porosity; a cell without solid matrix (phi = 1) has K = infinity
+    (free fluid, no Darcy drag) and a finite F_phi."""
+    phi = np.linspace(0.05, 0.95, 19)
+    K1, F1 = oracle.ergun(phi, 1.0)
+    K3, F3 = oracle.ergun(phi, 3.0)
+    np.testing.assert_allclose(K3 / K1, 9.0, rtol=1e-15)
+    np.testing.assert_array_equal(F1, F3)
+    c = F1 * phi ** 1.5
+    np.testing.assert_allclose(c, c[0], rtol=1e-14)
+    # K rises monotonically with porosity at fixed d_p
+    assert np.all(np.diff(K1) > 0)
+    Kf, Ff = oracle.ergun(np.array([1.0]), 2.0)
+    assert math.isinf(Kf[0]) and Kf[0] > 0
+    assert np.isfinite(Ff[0]) and Ff[0] > 0
+
+
 # ------------------------------------------------------------ flows, Sec. 3
 
 @pytest.mark.parametrize("forchheimer", [False, True])
@@ -195,7 +257,7 @@ def test_poiseuille_matches_closed_form_at_second_order(forchheimer):
         _, ux, uy = run_to_steady(p, phi, K, F, f)
         y = np.arange(ny) + 0.5
         if forchheimer:
-            ref = A.bf_poiseuille(y, ny, case.ax, case.phi0, case.K0, case.nu, case.Fphi)
+            ref = A.bf_poiseuille(y, ny, case.ax, case.phi0, case.K0, case.nu, uniform_F(case))
         else:
             ref = A.brinkman_poiseuille(y, ny, case.ax, case.phi0, case.K0, case.nu)
         errs.append(np.sqrt(np.sum((ux[:, 0] - ref) ** 2) / np.sum(ref ** 2)))
@@ -209,7 +271,7 @@ def test_forchheimer_lowers_the_centreline():
     """Eq. (23): the quadratic drag slows the flow below the Brinkman value of Eq. (24)."""
     c = I.poiseuille_channel(ny=64)
     y = np.arange(64) + 0.5
-    bf = A.bf_poiseuille(y, 64, c.ax, c.phi0, c.K0, c.nu, c.Fphi)
+    bf = A.bf_poiseuille(y, 64, c.ax, c.phi0, c.K0, c.nu, uniform_F(c))
     br = A.brinkman_poiseuille(y, 64, c.ax, c.phi0, c.K0, c.nu)
     assert np.all(bf < br)
     assert abs(A.poiseuille_u0(64, c.ax, c.phi0, c.K0, c.nu) - c.meta["u0"]) < 1e-18
@@ -223,7 +285,7 @@ def test_poiseuille_config_nx8_fp64_until_residual_1e10():
     f = oracle.rest_state(p, case.Pi0)
     t, ux, uy = run_to_steady(p, phi, K, F, f)
     y = np.arange(64) + 0.5
-    ref = A.bf_poiseuille(y, 64, case.ax, case.phi0, case.K0, case.nu, case.Fphi)
+    ref = A.bf_poiseuille(y, 64, case.ax, case.phi0, case.K0, case.nu, uniform_F(case))
     for col in range(8):
         e = np.sqrt(np.sum((ux[:, col] - ref) ** 2) / np.sum(ref ** 2))
         assert e <= 5e-4
