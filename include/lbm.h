@@ -196,7 +196,9 @@ int lbm_set_populations(lbm_ctx *c, int32_t domain, const float *df, const float
 /* FP64 reductions of one domain at the current time, computed on the GPU
  * with a fixed-order two-pass tree (bitwise reproducible): total mass
  * sum_x sum_i f_i(t), and the steady residual
- * ||u(t) - u(t-1)||_2 / ||u(t)||_2 (NaN at t = 0). Synchronises the stream.
+ * ||u(t) - u(t-1)||_2 / ||u(t)||_2 (NaN at t = 0), with u(t-1) as the last
+ * pass of the last lbm_step call computed it (any pass length gives the same
+ * bits). Synchronises the stream.
  * mass, residual: host, either may be NULL. EUNSTABLE if either is not
  * finite (values are still written). */
 int lbm_reduce(lbm_ctx *c, int32_t domain, double *mass, double *residual);
@@ -241,7 +243,13 @@ int lbm_backward_params(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *d
  * lbm_backward_params up to rounding. */
 int lbm_tangent(lbm_ctx *c, const float *dphi, const double *dtheta, float *du);
 
-/* Snapshot of one context's state (host memory, synchronous). */
+/* Snapshot of one context's state (host memory, synchronous): a 64-byte
+ * header (format tag, a hash of every descriptor field that gives the state
+ * its meaning, the thermal block included, t, and the payload size), then
+ * f(t) (and g(t)) in the storage type and the two u(t-1) planes of the
+ * residual. lbm_state_bytes gives the size; lbm_load takes a snapshot of a
+ * context with the same descriptor (else EINVAL, nothing changed) and clears
+ * any recording. */
 int lbm_state_bytes(const lbm_ctx *c, size_t *bytes);
 int lbm_save(lbm_ctx *c, void *host_buf, size_t bytes);
 int lbm_load(lbm_ctx *c, const void *host_buf, size_t bytes);
@@ -274,10 +282,12 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * one-node ring kept in LDS, then collides again, so each population crosses
  * HBM about once per two cycles) or 3 (a two-node ring, three collisions per
  * launch). Results are bitwise identical in every mode.
- * Multi-cycle passes are skipped for t = 0 and for the last cycle of each
- * lbm_step call (so lbm_reduce's residual always compares u(t) with u(t-1));
- * while recording for lbm_backward no pass steps over a checkpoint time.
- * Shorter passes fill in where fewer cycles remain. The recomputation inside
+ * Multi-cycle passes are skipped for t = 0; while recording for lbm_backward
+ * no pass steps over a checkpoint time. Shorter passes fill in where fewer
+ * cycles remain. The last pass of each lbm_step call also writes the
+ * velocity of its last collision, u(t-1) of the final time t, into two FP32
+ * planes of the workspace (8 bytes per node), which lbm_reduce's residual
+ * reads. The recomputation inside
  * lbm_backward uses passes of the same length (recording u at every cycle)
  * and its adjoint sweep two or three steps per pass in modes 2 and 3 (two for
  * thermal runs). The D2Q5 field of a thermal domain rides in LDS beside the
