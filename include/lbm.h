@@ -203,6 +203,20 @@ int lbm_set_populations(lbm_ctx *c, int32_t domain, const float *df, const float
  * finite (values are still written). */
 int lbm_reduce(lbm_ctx *c, int32_t domain, double *mass, double *residual);
 
+/* lbm_reduce for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and results, bit for bit, with the partial sums in a static
+ * device array of the library (3 x 4096 + 4 doubles, 96 KiB, one copy per
+ * GPU, held until the process ends) instead of the context's workspace. Calls
+ * no allocating routine; the array's address is looked up once per device on
+ * the first call there, with the context's device (the one current at
+ * creation) made current for that lookup. Every call on one GPU shares that
+ * array: calls that overlap on one GPU (from several host threads or streams)
+ * race; calls from one thread do not overlap, since each synchronises its
+ * stream. EINVAL if the domain needed more than 4096 workgroups of partial
+ * sums (never for nx*ny <= 2^31); EDEVICE if the lookup fails. */
+int lbm_reduce_static(lbm_ctx *c, int32_t domain, double *mass, double *residual);
+
 /* Discrete adjoint of the recorded forward pass (hand-written, checkpointed
  * recomputation every ckpt_every steps). The loss L must depend on the state
  * only through u(T) at the current time T: dL_du is device [2][ny][nx]

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,6 +19,14 @@
 #include "lbm_launch.h"
 
 using namespace mrt;
+
+// Device scratch of lbm_reduce_static: the FP64 partial sums of the reduction
+// (three per workgroup, at most kReduceMaxBlocks workgroups) followed by the
+// three final sums. One copy per GPU, held until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress gives per device.
+constexpr int kReduceMaxBlocks = 4096;
+constexpr int kScratchDoubles = 3 * kReduceMaxBlocks + 4;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -251,6 +260,7 @@ struct lbm_ctx {
     int tblock = 1;
     int tb_threads = 512;
     int tb_rows = 16;
+    int device = 0;  // the device current at creation (the static scratch's copy)
 };
 
 namespace {
@@ -541,6 +551,7 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(LBM_EINVAL, "host allocation failed");
     c->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&c->device);
     c->dom.resize(1);
     Domain &D = c->dom[0];
     rc = setup_domain(D, d, phi, kappa, (char *)workspace);
@@ -719,16 +730,17 @@ int lbm_set_populations(lbm_ctx *c, int32_t k, const float *df, const float *dg)
     return LBM_OK;
 }
 
-int lbm_reduce(lbm_ctx *c, int32_t k, double *mass, double *residual) {
-    int rc = check_ctx(c);
-    if (rc) return rc;
-    if ((rc = check_domain(c, k))) return rc;
+}  // extern "C"
+
+namespace {
+
+// The reductions of lbm_reduce with the partial sums (3 doubles per workgroup)
+// and the three final sums in the given device memory.
+int reduce_into(lbm_ctx *c, int32_t k, double *mass, double *residual, double *partials, double *result) {
     Domain &D = c->dom[k];
     const Dom cur = dom_for(D, c->cur);
     // u(t - 1) was recorded by the last pass of the last lbm_step call
     const float *uprev = c->t >= 1 ? (const float *)(D.base + D.L.off_uprev) : nullptr;
-    double *partials = (double *)(D.base + D.L.off_part);
-    double *result = (double *)(D.base + D.L.off_res);
     hipError_t e = launch_reduce(cur, src_now(c->t), uprev, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32,
                                  partials, result, c->stream);
     if (e != hipSuccess) return device_fail(c, e, "reduce launch");
@@ -744,6 +756,60 @@ int lbm_reduce(lbm_ctx *c, int32_t k, double *mass, double *residual) {
     if (!std::isfinite(m) || !std::isfinite(h[1]) || !std::isfinite(h[2]))
         return fail(LBM_EUNSTABLE, "non-finite mass or residual (t = %lld)", (long long)c->t);
     return LBM_OK;
+}
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (each GPU holds its own copy at its own address).
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_on(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e == hipSuccess && prev != dev) e = hipSetDevice(dev);
+        void *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != dev) {
+            const hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_reduce(lbm_ctx *c, int32_t k, double *mass, double *residual) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if ((rc = check_domain(c, k))) return rc;
+    Domain &D = c->dom[k];
+    return reduce_into(c, k, mass, residual, (double *)(D.base + D.L.off_part), (double *)(D.base + D.L.off_res));
+}
+
+int lbm_reduce_static(lbm_ctx *c, int32_t k, double *mass, double *residual) {
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if ((rc = check_domain(c, k))) return rc;
+    const Domain &D = c->dom[k];
+    const int nb = reduce_blocks(D.desc.nx, D.desc.ny);
+    if (nb > kReduceMaxBlocks)
+        return fail(LBM_EINVAL, "the reduction needs %d workgroups of partial sums; the static scratch holds %d",
+                    nb, kReduceMaxBlocks);
+    double *ptr = nullptr;
+    hipError_t e = scratch_on(c->device, &ptr);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "static scratch address: %s", hipGetErrorString(e));
+    // every partial and final sum is written before it is read: nothing to clear
+    return reduce_into(c, k, mass, residual, ptr, ptr + 3 * kReduceMaxBlocks);
 }
 
 int lbm_state_bytes(const lbm_ctx *c, size_t *bytes) {
@@ -1277,6 +1343,7 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
     lbm_ctx *c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(LBM_EINVAL, "host allocation failed");
     c->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&c->device);
     c->batch = true;
     c->storage = descs[0].storage == LBM_FP16_DEV ? ST_F16 : ST_F32;
     c->batch_thermal = descs[0].thermal.enabled != 0;

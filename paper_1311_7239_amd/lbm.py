@@ -75,6 +75,8 @@ def lib():
         L.lbm_set_populations.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
         L.lbm_reduce.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)]
+        L.lbm_reduce_static.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]
         L.lbm_backward.argtypes = [_vp, _vp, _vp, _vp]
         L.lbm_backward_params.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
         L.lbm_tangent.argtypes = [_vp, _vp, ctypes.POINTER(ctypes.c_double), _vp]
@@ -223,6 +225,15 @@ class Solver:
     def reduce(self):
         m = ctypes.c_double(); r = ctypes.c_double()
         st = lib().lbm_reduce(self._ctx, 0, ctypes.byref(m), ctypes.byref(r))
+        if st not in (OK, EUNSTABLE):
+            check(st)
+        return m.value, r.value, st
+
+    def reduce_static(self):
+        """reduce() through lbm_reduce_static (partial sums in the library's static device
+        scratch instead of the workspace)."""
+        m = ctypes.c_double(); r = ctypes.c_double()
+        st = lib().lbm_reduce_static(self._ctx, 0, ctypes.byref(m), ctypes.byref(r))
         if st not in (OK, EUNSTABLE):
             check(st)
         return m.value, r.value, st
