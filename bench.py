@@ -320,12 +320,15 @@ def main():
     case = I.lognormal_channel(n=n, seed=5, K_ref=1e-6 * 2048.0 ** 2)
     solver = lbm.solver_for_case(case, storage=lbm.FP32_DEV)   # the default cycles per HBM pass
     cycles = solver.time_blocking()["cycles_per_pass"]
+    # The dominant kernel's own launch duration (HIP events around back-to-back launches),
+    # measured first: its ~130 launches also bring the GPU out of the clock state it idles
+    # in while the host builds the porosity field (right after that, launches run up to
+    # 25% slower for the first ~20 ms, longer than a short timed region)
+    launch_ms = per_launch_ms(solver, cycles)
     log(f"bench: stepping ({args.warmup} warmup + {args.steps} timed, {cycles} cycles per pass)")
     ms = timed(solver, args.steps, args.warmup)
     mlups = case.nodes / (ms * 1e-3) / 1e6
     bytes_per_node = 68  # per pass: 8 FP32 loads + 8 FP32 stores + the FP32 porosity load
-    # the dominant kernel's own launch duration (HIP events around back-to-back launches)
-    launch_ms = per_launch_ms(solver, cycles)
     rl = roofline(case.nodes, bytes_per_node, launch_ms)
     kname = {3: ("void mrt::k_step3<float", "k_step3<float, 64, 16>: three collide-stream cycles per launch"),
              2: ("void mrt::k_step2<float", "k_step2<float, 64, 16>: two collide-stream cycles per launch"),

@@ -182,6 +182,10 @@ Dom make_dom(const lbm_desc &d, const Layout &L) {
     o.h_e = (float)(1.0 - 0.5 * d.s_e); o.h_q = (float)(1.0 - 0.5 * d.s_q);
     // from the rounded rate, as the kernels form 1 - s/2 for a per-node rate
     o.h_nu = (float)(1.0 - 0.5 * (double)o.s_nu);
+    o.h_e16 = (float)(1.6 * (1.0 - 0.5 * d.s_e));
+    o.h_q2 = 2.0f * o.h_q;
+    o.h_nu2 = 2.0f * o.h_nu;
+    o.h_nu4 = 4.0f * o.h_nu;
     o.medium = d.medium;
     o.nu = (float)d.nu;
     o.inv_nu = (float)(1.0 / d.nu);
@@ -192,13 +196,18 @@ Dom make_dom(const lbm_desc &d, const Layout &L) {
         o.inv_phi0 = (float)(1.0 / d.phi0);
         o.cd0 = (float)(d.phi0 * d.nu * d.kappa0);
         o.cf0 = (float)(d.phi0 * F * std::sqrt(d.kappa0));
+        o.cd0h = 0.5f * o.cd0;
+        o.cf0h = 0.5f * o.cf0;
     }
     if (d.medium == LBM_MEDIUM_PHI_ERGUN) {
         o.kcoef = (float)(150.0 / (d.dp * d.dp));
         o.cdk = (float)(150.0 * d.nu / (d.dp * d.dp));
         o.cfk = (float)(1.75 / d.dp);
+        o.cdkh = 0.5f * o.cdk;
+        o.cfkh = 0.5f * o.cfk;
     }
     o.ax = (float)d.ax; o.ay = (float)d.ay;
+    o.axh = 0.5f * o.ax; o.ayh = 0.5f * o.ay;
     if (d.thermal.enabled) {
         const lbm_thermal &t = d.thermal;
         o.thermal = 1;
@@ -207,6 +216,7 @@ Dom make_dom(const lbm_desc &d, const Layout &L) {
         o.inv_sigma = (float)(1.0 / t.sigma);
         o.T0 = (float)t.T0;
         o.gbeta = (float)t.g_beta;
+        o.gbetah = 0.5f * o.gbeta;
         o.abbh = (float)(0.4 * (t.Th - t.T0));  // 2 w_T (T_w - T0), w_T = 1/5
         o.abbc = (float)(0.4 * (t.Tc - t.T0));
         o.dTh = (float)(t.Th - t.T0);

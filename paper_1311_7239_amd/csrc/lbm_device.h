@@ -44,18 +44,24 @@ struct Dom {
     // medium
     int32_t medium;
     float phi0, inv_phi0, cd0, cf0;  // uniform: phi, 1/phi, phi nu kappa, phi F sqrt(kappa)
+    float cd0h, cf0h;                // cd0 / 2, cf0 / 2 (exact halves)
     float nu;                        // fluid viscosity (per-cell drag)
     float kcoef;                     // 150 / dp^2 (Eq. 4): kappa = kcoef (1-phi)^2 / phi^3
     float cdk, cfk;                  // 150 nu / dp^2 and 1.75 / dp (Eq. 4 drag in closed form)
+    float cdkh, cfkh;                // their exact halves
     float Fconst;                    // >= 0: constant F_phi; < 0: Eq. (4)
     float ax, ay;                    // uniform external acceleration
+    float axh, ayh;                  // a / 2 (exact halves: the step works on half forces)
+    // rates of the half-force forcing: 1.6 (1 - s_e/2), 2 (1 - s_q/2), and
+    // 2 (1 - s_nu/2), 4 (1 - s_nu/2) (exact multiples of the float h_q, h_nu)
+    float h_e16, h_q2, h_nu2, h_nu4;
     const float *phi;                // [ny][pitch] (MED_PHI_*)
     const float *kappa;              // [ny][pitch] (MED_PHI_KAPPA)
     const float *snu;                // [ny][pitch] per-node s_nu (NULL: s_nu everywhere)
     // thermal (App. B); deviations from wT*T0
     int32_t thermal;
     float zT, z3, z4;                // 1/tau_T, zeta3, zeta4
-    float inv_sigma, T0, gbeta;
+    float inv_sigma, T0, gbeta, gbetah;  // ..., g beta, g beta / 2
     float abbh, abbc;                // 2 wT (Th - T0), 2 wT (Tc - T0)
     float dTh, dTc;                  // Th - T0, Tc - T0 (on-node Dirichlet walls)
     // state buffers (storage type erased)
@@ -119,7 +125,9 @@ struct Cell {
     float phi, inv_phi;
     float cd;   // phi nu / K             (linear drag coefficient, Eq. 3)
     float cf;   // phi F_phi / sqrt(K)    (Forchheimer coefficient, Eq. 3)
+    float cdh, cfh;    // cd / 2 and cf / 2 (exact halves; the step uses these)
     float s_nu, h_nu;  // s_7 = s_8 = 1/tau of the node's own J (Eq. 21) and 1 - s_nu/2
+    float h_nu2, h_nu4;  // 2 h_nu = 2 - s_nu and 4 h_nu = 4 - 2 s_nu (exact)
 };
 
 // Ergun's F_phi (Eq. 4): 1.75 / sqrt(150 phi^3) = (1.75/sqrt(150)) phi^{-3/2}.
@@ -134,17 +142,20 @@ __device__ __forceinline__ void ergun_closed(const Dom &d, float phi, Cell &c) {
     c.phi = phi; c.inv_phi = ip;
     const float om = 1.0f - phi;
     const float t = om * (ip * ip);
-    c.cd = (d.cdk * om) * t;
-    c.cf = d.cfk * t;
+    c.cdh = (d.cdkh * om) * t;
+    c.cfh = d.cfkh * t;
+    c.cd = c.cdh + c.cdh;   // the same bits as (cdk om) t and cfk t
+    c.cf = c.cfh + c.cfh;
 }
 
 // Per-cell drag coefficients from the porosity (and 1/K when it has its own
 // plane); kappa is ignored unless the medium is MED_PHI_KAPPA.
 __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_plane) {
     Cell c;
-    c.s_nu = d.s_nu; c.h_nu = d.h_nu;
+    c.s_nu = d.s_nu; c.h_nu = d.h_nu; c.h_nu2 = d.h_nu2; c.h_nu4 = d.h_nu4;
     if (d.medium == MED_UNIFORM) {
         c.phi = d.phi0; c.inv_phi = d.inv_phi0; c.cd = d.cd0; c.cf = d.cf0;
+        c.cdh = d.cd0h; c.cfh = d.cf0h;
         return c;
     }
     if (d.medium == MED_PHI_ERGUN && d.Fconst < 0.0f) {
@@ -163,6 +174,8 @@ __device__ __forceinline__ Cell cell_from(const Dom &d, float phi, float kappa_p
     const float F = (d.Fconst >= 0.0f) ? d.Fconst : ergun_F(ip);
     c.cd = phi * d.nu * kappa;
     c.cf = phi * F * hw_sqrt(kappa);
+    c.cdh = 0.5f * c.cd;
+    c.cfh = 0.5f * c.cf;
     return c;
 }
 
@@ -174,6 +187,8 @@ __device__ __forceinline__ void cell_viscosity(const Dom &d, Cell &c, int64_t id
         const float s = d.snu[idx];
         c.s_nu = s;
         c.h_nu = 1.0f - 0.5f * s;
+        c.h_nu2 = 2.0f - s;
+        c.h_nu4 = fmaf(-2.0f, s, 4.0f);
     }
 }
 
@@ -185,23 +200,28 @@ __device__ __forceinline__ Cell load_cell(const Dom &d, int64_t idx) {
     return c;
 }
 
-// Eqs. (18)-(19) in cancellation-free form. With d = cd/2 and
-// l1 = cf/2, the denominator l0 + sqrt(l0^2 + l1|v|) equals 1 + d + delta with
-// delta = l1|v| / (l0 + sqrt(l0^2 + l1|v|)), so u = v - v q with
-// q = (d + delta)/(1 + d + delta): the small drag terms keep full relative
-// precision instead of being rounded against 1.
-__device__ __forceinline__ void velocity(const Cell &c, float vx, float vy, float &ux,
-                                         float &uy) {
-    const float dd = 0.5f * c.cd;
-    const float l1 = 0.5f * c.cf;
-    const float l0 = fmaf(0.5f, dd, 0.5f);
+// Eqs. (18)-(19) in cancellation-free form. With d = cd/2, l0 = (1 + d)/2,
+// l1 = cf/2, s = sqrt(l0^2 + l1|v|) and w = l0 + s, the denominator of Eq. (18)
+// is w, and w^2 = (1 + d) w + l1|v|, so u = v / w = v - v q with
+// q = 1 - 1/w = (d w + l1|v|) / w^2 = r (d + l1|v| r), r = 1/w: a sum of
+// non-negative terms, so the small drag terms keep full relative precision
+// instead of being rounded against 1 (one reciprocal). |u| = |v| (1 - q)
+// comes with it.
+__device__ __forceinline__ void velocity(const Cell &c, float vx, float vy, float &ux, float &uy,
+                                         float &umag) {
+    const float l0 = fmaf(0.5f, c.cdh, 0.5f);
     const float vmag = hw_sqrt(fmaf(vx, vx, vy * vy));
-    const float t = l1 * vmag;
-    const float delta = t * hw_rcp(l0 + hw_sqrt(fmaf(l0, l0, t)));
-    const float qn = dd + delta;
-    const float q = qn * hw_rcp(1.0f + qn);
+    const float t = c.cfh * vmag;
+    const float r = hw_rcp(l0 + hw_sqrt(fmaf(l0, l0, t)));
+    const float q = r * fmaf(t, r, c.cdh);
     ux = fmaf(-vx, q, vx);
     uy = fmaf(-vy, q, vy);
+    umag = fmaf(-vmag, q, vmag);
+}
+
+__device__ __forceinline__ void velocity(const Cell &c, float vx, float vy, float &ux, float &uy) {
+    float umag;
+    velocity(c, vx, vy, ux, uy, umag);
 }
 
 // Moments m_1, m_3, m_5 of the deviations (rows 1, 3, 5 of Eq. 10).
@@ -215,20 +235,29 @@ __device__ __forceinline__ void conserved_moments(const float f[8], float &m1, f
 }
 
 // Velocity of a node from its pre-collision deviations (Eqs. 17-19);
-// pax/pay = phi * a.
-__device__ __forceinline__ void node_velocity(const float f[8], const Cell &c, float pax,
-                                              float pay, float &ux, float &uy, float &m1) {
+// paxh/payh = phi * a / 2 (half the external force per unit mass).
+__device__ __forceinline__ void node_velocity_h(const float f[8], const Cell &c, float paxh,
+                                                float payh, float &ux, float &uy, float &m1) {
     float m3, m5;
     conserved_moments(f, m1, m3, m5);
-    velocity(c, fmaf(0.5f, pax, m3), fmaf(0.5f, pay, m5), ux, uy);
+    velocity(c, m3 + paxh, m5 + payh, ux, uy);
+}
+
+// The same with the full force pax/pay = phi * a (halving is exact).
+__device__ __forceinline__ void node_velocity(const float f[8], const Cell &c, float pax,
+                                              float pay, float &ux, float &uy, float &m1) {
+    node_velocity_h(f, c, 0.5f * pax, 0.5f * pay, ux, uy, m1);
 }
 
 // One node's collision (Eq. 14) followed by f+ = M^-1 m+, in place on the
-// deviations. Returns u. pax/pay = phi * a (a may include buoyancy).
+// deviations. Returns u. paxh/payh = phi * a / 2 (a may include buoyancy).
 // Also returns the non-equilibrium stress moments n7 = m7 - m7^eq and
 // n8 = m8 - m8^eq before relaxation (dropped by the compiler when unused).
-__device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c, float pax,
-                                        float pay, float &ux, float &uy, float &n7, float &n8) {
+// The step works on half forces Fh = F/2 (Eq. 3 scaled by 1/2: every drag and
+// force term is an exact power-of-two multiple of the full one), which the
+// forcing of Eq. (16) takes with doubled rates.
+__device__ __forceinline__ void collide_h(float f[8], const Dom &d, const Cell &c, float paxh,
+                                          float payh, float &ux, float &uy, float &n7, float &n8) {
     // m = M f (Eq. 8, rows of Eq. 10), shared sums first
     const float a = f[0] + f[2], b = f[1] + f[3], cc = f[4] + f[6], dg = f[5] + f[7];
     const float x13 = f[0] - f[2], y24 = f[1] - f[3], p57 = f[4] - f[6], q68 = f[5] - f[7];
@@ -243,41 +272,47 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
     const float m7 = a - b;
     const float m8 = cc - dg;
 
-    // velocity (Eqs. 18-19) and total force (Eq. 3)
-    velocity(c, fmaf(0.5f, pax, m3), fmaf(0.5f, pay, m5), ux, uy);
-    const float umag = hw_sqrt(fmaf(ux, ux, uy * uy));
-    const float drag = fmaf(c.cf, umag, c.cd);
-    const float Fx = fmaf(-drag, ux, pax);
-    const float Fy = fmaf(-drag, uy, pay);
+    // velocity (Eqs. 18-19) and half the total force (Eq. 3)
+    float umag;
+    velocity(c, m3 + paxh, m5 + payh, ux, uy, umag);
+    const float dragh = fmaf(c.cfh, umag, c.cdh);
+    const float Fx = fmaf(-dragh, ux, paxh);   // F_x / 2
+    const float Fy = fmaf(-dragh, uy, payh);   // F_y / 2
 
     // relaxation toward m^eq (Eqs. 11-12) with forcing (Eq. 16)
     const float ip = c.inv_phi;
-    const float u2 = fmaf(ux, ux, uy * uy);
-    const float uF = fmaf(ux, Fx, uy * Fy);
+    const float uyy = uy * uy;
+    const float u2 = fmaf(ux, ux, uyy);
+    const float uF = fmaf(ux, Fx, uy * Fy);    // u . F / 2
     // e - e^eq = dm2 + (3/5) dm1 - (2/5)|u|^2/phi  (Pi from Eq. 20, alpha2 = -1, gamma2 = 0);
     // e enters neither m1 nor j of f+, so single-rounded constants suffice here
-    const float ne = fmaf(0.6f, m1, m2) - 0.4f * (u2 * ip);
-    const float m2p = fmaf(d.h_e, 0.8f * (uF * ip), fmaf(-d.s_e, ne, m2));
+    const float ne = fmaf(-0.4f, u2 * ip, fmaf(0.6f, m1, m2));
+    // S_2 = (4/5) u . F / phi: (1 - s_e/2) 4/5 S_2 = h_e16 (u . F/2) / phi
+    const float m2p = fmaf(d.h_e16, uF * ip, fmaf(-d.s_e, ne, m2));
     // s1 = s3 = s5 = 1: m1+ = m1, j+ = rho0 u + F/2
-    const float m3p = fmaf(0.5f, Fx, ux);
-    const float m5p = fmaf(0.5f, Fy, uy);
-    // q^eq = -u (c1 = c2 = -2)
-    const float m4p = fmaf(-d.h_q, Fx, fmaf(-d.s_q, m4 + ux, m4));
-    const float m6p = fmaf(-d.h_q, Fy, fmaf(-d.s_q, m6 + uy, m6));
-    // p_xx^eq = (ux^2 - uy^2)/phi, p_xy^eq = ux uy / phi (gamma1 = gamma3 = 2/3)
-    const float pxx = fmaf(ux, ux, -(uy * uy)) * ip;
+    const float m3p = ux + Fx;
+    const float m5p = uy + Fy;
+    // q^eq = -u (c1 = c2 = -2), S_4 = -F_x (and S_6 = -F_y)
+    const float m4p = fmaf(-d.h_q2, Fx, fmaf(-d.s_q, m4 + ux, m4));
+    const float m6p = fmaf(-d.h_q2, Fy, fmaf(-d.s_q, m6 + uy, m6));
+    // p_xx^eq = (ux^2 - uy^2)/phi, p_xy^eq = ux uy / phi (gamma1 = gamma3 = 2/3);
+    // S_7 = 2 (ux Fx - uy Fy)/phi and S_8 = (ux Fy + uy Fx)/phi, in half forces
+    const float pxx = fmaf(ux, ux, -uyy) * ip;
     const float pxy = (ux * uy) * ip;
-    const float Sxx = 2.0f * fmaf(ux, Fx, -(uy * Fy)) * ip;
-    const float Sxy = fmaf(ux, Fy, uy * Fx) * ip;
+    const float Sxx4 = fmaf(ux, Fx, -(uy * Fy)) * ip;   // S_7 / 4
+    const float Sxy2 = fmaf(ux, Fy, uy * Fx) * ip;      // S_8 / 2
     n7 = m7 - pxx;
     n8 = m8 - pxy;
-    const float m7p = fmaf(c.h_nu, Sxx, fmaf(-c.s_nu, n7, m7));
-    const float m8p = fmaf(c.h_nu, Sxy, fmaf(-c.s_nu, n8, m8));
+    const float m7p = fmaf(c.h_nu4, Sxx4, fmaf(-c.s_nu, n7, m7));
+    const float m8p = fmaf(c.h_nu2, Sxy2, fmaf(-c.s_nu, n8, m8));
 
-    // f+ = M^T diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m+
+    // f+ = M^T diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m+; the 1/6 of the
+    // momentum rows goes through the split constant (their rounding would bias
+    // the momentum every step); the 1/12 of the energy-flux rows cancels from
+    // mass and momentum and is a plain multiply
     const float A = 0.125f * m1, B = 0.125f * m2p;
-    const float X = mulc(m3p, MRT_C1_6), Qx = mulc(m4p, MRT_C1_12);
-    const float Y = mulc(m5p, MRT_C1_6), Qy = mulc(m6p, MRT_C1_12);
+    const float X = mulc(m3p, MRT_C1_6), Qx = m4p * 0x1.555556p-4f;
+    const float Y = mulc(m5p, MRT_C1_6), Qy = m6p * 0x1.555556p-4f;
     const float P = 0.25f * m7p, R = 0.25f * m8p;
     const float amb = A - B, apb = A + B;
     const float xa = fmaf(-2.0f, Qx, X), ya = fmaf(-2.0f, Qy, Y);
@@ -290,6 +325,12 @@ __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c,
     f[5] = (apb - xd) + (yd - R);
     f[6] = (apb - xd) - (yd - R);
     f[7] = (apb + xd) - (yd + R);
+}
+
+// The same with the full force pax/pay = phi * a.
+__device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c, float pax,
+                                        float pay, float &ux, float &uy, float &n7, float &n8) {
+    collide_h(f, d, c, 0.5f * pax, 0.5f * pay, ux, uy, n7, n8);
 }
 
 __device__ __forceinline__ void collide(float f[8], const Dom &d, const Cell &c, float pax,
@@ -462,6 +503,8 @@ __device__ __forceinline__ Cell cell_of(const Dom &d, const CellRaw &r) {
     if (d.snu) {
         c.s_nu = r.snu;
         c.h_nu = 1.0f - 0.5f * r.snu;
+        c.h_nu2 = 2.0f - r.snu;
+        c.h_nu4 = fmaf(-2.0f, r.snu, 4.0f);
     }
     return c;
 }
@@ -521,6 +564,8 @@ template <> struct MediumSrc<MK_ERGUN> {
         Cell c;
         c.s_nu = d.s_nu;
         c.h_nu = d.h_nu;
+        c.h_nu2 = d.h_nu2;
+        c.h_nu4 = d.h_nu4;
         ergun_closed(d, r.phi, c);
         return c;
     }

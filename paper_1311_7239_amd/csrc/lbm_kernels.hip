@@ -26,13 +26,14 @@ constexpr int BLOCK = 256;
 template <bool THERMAL>
 __device__ __forceinline__ void node_update(const Dom &d, const Cell &c, float f[8], float g[5],
                                             float &ux, float &uy, float &n7, float &n8, float &dT) {
-    float ay = d.ay;
+    // half of a (the step works on half forces; every product is halved exactly)
+    float ayh = d.ayh;
     dT = 0.0f;
     if (THERMAL) {
         dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
-        ay = d.ay + d.gbeta * dT;
+        ayh = d.ayh + d.gbetah * dT;
     }
-    collide(f, d, c, c.phi * d.ax, c.phi * ay, ux, uy, n7, n8);
+    collide_h(f, d, c, c.phi * d.axh, c.phi * ayh, ux, uy, n7, n8);
     if (THERMAL) thermal_collide(g, d, ux, uy);
 }
 
@@ -1050,13 +1051,13 @@ __device__ __forceinline__ void state_velocity(const Dom &d, int64_t o, const fl
                                                const float g[5], float &ux, float &uy,
                                                float &m1, float &dT) {
     const Cell c = load_cell(d, o);
-    float ay = d.ay;
+    float ayh = d.ayh;
     dT = 0.0f;
     if (THERMAL) {
         dT = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
-        ay = d.ay + d.gbeta * dT;
+        ayh = d.ayh + d.gbetah * dT;
     }
-    node_velocity(f, c, c.phi * d.ax, c.phi * ay, ux, uy, m1);
+    node_velocity_h(f, c, c.phi * d.axh, c.phi * ayh, ux, uy, m1);
 }
 
 template <typename S, bool THERMAL>
