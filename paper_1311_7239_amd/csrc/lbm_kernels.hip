@@ -726,30 +726,13 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
     // its medium values before its first store.
     Pending<THERMAL> pend;
 
-    // phase A: s_{t+1} on the tile + 2 ring
+    // phase A: s_{t+1} on the tile + 2 ring. Items follow tile_item: each wave
+    // takes one whole 64-node row of the tile (aligned, coalesced loads and
+    // stride-1 LDS stores), the 4 x AH ring columns come last (whole waves,
+    // since 64 AH items fill whole waves).
     const BufRes rr0 = buf_res(REC ? d.urec : nullptr, rbytes);
-    for (int e = threadIdx.x; e < AN; e += NT) {
-        const int ex = e % AW, ey = e / AW;
-        int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
-        float f[8], g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        if (interior) {
-            const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * ES);
-#pragma unroll
-            for (int i = 0; i < 8; ++i)
-                f[i] = BufIO<S>::ld(rin, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
-            if (THERMAL) {
-                const uint32_t vg = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * 4);
-#pragma unroll
-                for (int j = 0; j < 5; ++j)
-                    g[j] = BufIO<float>::ld(rgin, vg, (uint32_t)((j * d.plane + (1 - TYv[j]) * d.pitch + (1 - TXv[j])) * 4));
-            }
-        } else {
-            if (!wrap_node(d, gx, gy)) continue;
-            gather_general_buf<S>(d, rin, gx, gy, f);
-            if (THERMAL) gather_thermal_buf(d, rgin, gx, gy, g);
-        }
-        const int64_t o = (int64_t)gy * d.pitch + gx;
-        const CellRaw raw = med.load((uint32_t)(o * 4));
+    auto finish_a = [&](float (&f)[8], float (&g)[5], const CellRaw &raw, int ex, int ey, int gx, int gy,
+                        int64_t o) {
         if (REC) pend.flush(d, rr0);
         const Cell c = med.cell(d, raw);
         float ux, uy, n7, n8, dT;
@@ -760,13 +743,62 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
 #pragma unroll
             for (int j = 0; j < 5; ++j) ldsg[(j * AH + ey) * AW + ex] = g[j];
         }
-        if (REC && ex >= 2 && ex < TW + 2 && ey >= 2 && ey < TH + 2 && x0 - 2 + ex < d.nx && y0 - 2 + ey < d.ny)
+        if (REC && ex >= 2 && ex < TW + 2 && ey >= 2 && ey < TH + 2 && gx < d.nx && gy < d.ny)
             pend.hold((uint32_t)(o * 4), ux, uy, n7, n8, dT);
+    };
+    if (interior) {
+        // software pipelined: the next item's loads are issued before this one collides
+        auto fetch = [&](int e, float (&f)[8], float (&g)[5], CellRaw &r) {
+            int ex, ey;
+            tile_item<TW, AH, 2>(e, ex, ey);
+            const int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
+            const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * ES);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                f[i] = BufIO<S>::ld(rin, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
+            if (THERMAL) {
+                const uint32_t vg = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * 4);
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                    g[j] = BufIO<float>::ld(rgin, vg, (uint32_t)((j * d.plane + (1 - TYv[j]) * d.pitch + (1 - TXv[j])) * 4));
+            }
+            r = med.load((uint32_t)((gy * d.pitch + gx) * 4));
+        };
+        float fn[8], gn[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        CellRaw rn{0.0f, 0.0f, 0.0f};
+        if ((int)threadIdx.x < AN) fetch(threadIdx.x, fn, gn, rn);
+        for (int e = threadIdx.x; e < AN; e += NT) {
+            float f[8], g[5];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) f[i] = fn[i];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) g[j] = gn[j];
+            const CellRaw r = rn;
+            if (e + NT < AN) fetch(e + NT, fn, gn, rn);
+            int ex, ey;
+            tile_item<TW, AH, 2>(e, ex, ey);
+            const int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
+            finish_a(f, g, r, ex, ey, gx, gy, (int64_t)gy * d.pitch + gx);
+        }
+    } else {
+        for (int e = threadIdx.x; e < AN; e += NT) {
+            int ex, ey;
+            tile_item<TW, AH, 2>(e, ex, ey);
+            int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
+            if (!wrap_node(d, gx, gy)) continue;
+            float f[8], g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            gather_general_buf<S>(d, rin, gx, gy, f);
+            if (THERMAL) gather_thermal_buf(d, rgin, gx, gy, g);
+            const int64_t o = (int64_t)gy * d.pitch + gx;
+            // a wrapped ring node is recorded by the tile that owns it
+            finish_a(f, g, med.load((uint32_t)(o * 4)), ex, ey, x0 - 2 + ex, y0 - 2 + ey, o);
+        }
     }
     if (REC) pend.flush(d, rr0);
     lds_barrier();
 
-    // phase B: s_{t+2} on the tile + 1 ring, kept in registers
+    // phase B: s_{t+2} on the tile + 1 ring, kept in registers (items as in phase A:
+    // whole rows per wave, then the two ring columns)
     const BufRes rr1 = buf_res(urec1, rbytes);
     float fb[NBB][8], gb[NBB][THERMAL ? 5 : 1];
     int slot[NBB];
@@ -775,7 +807,8 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
         slot[k] = -1;
         const int e = threadIdx.x + k * NT;
         if (e >= BN) continue;
-        const int bx = e % BW, by = e / BW;
+        int bx, by;
+        tile_item<TW, BH, 1>(e, bx, by);
         int gx = x0 - 1 + bx, gy = y0 - 1 + by;
         if (!interior && !wrap_node(d, gx, gy)) continue;
         const int64_t o = (int64_t)gy * d.pitch + gx;
@@ -793,19 +826,18 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
         }
         if (REC && bx >= 1 && bx <= TW && by >= 1 && by <= TH && x0 - 1 + bx < d.nx && y0 - 1 + by < d.ny)
             pend.hold((uint32_t)(o * 4), ux, uy, n7, n8, dT);
-        slot[k] = e;
+        slot[k] = by * BW + bx;
     }
     if (REC) pend.flush(d, rr1);
     lds_barrier();
 #pragma unroll
     for (int k = 0; k < NBB; ++k) {
         if (slot[k] < 0) continue;
-        const int bx = slot[k] % BW, by = slot[k] / BW;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) lds[(i * BH + by) * BW + bx] = (float)(S)fb[k][i];
+        for (int i = 0; i < 8; ++i) lds[i * BN + slot[k]] = (float)(S)fb[k][i];
         if (THERMAL) {
 #pragma unroll
-            for (int j = 0; j < 5; ++j) ldsg[(j * BH + by) * BW + bx] = gb[k][THERMAL ? j : 0];
+            for (int j = 0; j < 5; ++j) ldsg[j * BN + slot[k]] = gb[k][THERMAL ? j : 0];
         }
     }
     lds_barrier();
