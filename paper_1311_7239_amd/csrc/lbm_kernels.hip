@@ -699,16 +699,32 @@ __device__ __forceinline__ void lds_gather_thermal(const Dom &d, const float *fl
 // in the same LDS (a smaller layout), and phase C gathers f(t+2), collides and
 // stores f+(t+2). Same per-node function and FP16 rounding of every
 // intermediate as three one-cycle passes, so the result is bitwise theirs.
+//
+// Work items: thread (wave w, lane l) owns row r = w + NW k of the
+// (TW + 4) x (TH + 4) frame of phase A, column 2 + l, for k = 0 .. NK - 1, in
+// every phase: phase A visits all frame rows, phase B rows 1 .. TH + 2 and
+// phase C rows 2 .. TH + 1, so a thread meets the same node in each phase. The
+// node's porosity is loaded and its drag coefficients computed once, in phase
+// A, and kept in registers for B and C. Each wave covers one whole TW = 64
+// row (aligned, coalesced loads, stride-1 LDS access); the ring columns (4 of
+// phase A, 2 of phase B) go to the waves without a row at the last iteration.
 // With REC (FP32 recomputation for the adjoint) u and, with rec_stress, the
 // stress moments of the tile nodes are recorded at t (d.urec), t + 1 (urec1)
 // and t + 2 (urec2).
 template <typename S, int TW, int TH, int NT, bool REC, int MK, bool THERMAL>
 __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *urec1, float *urec2, float *lds,
                                            float *ldsg) {
-    constexpr int AW = TW + 4, AH = TH + 4, AN = AW * AH;
+    constexpr int AW = TW + 4, AH = TH + 4;
     constexpr int BW = TW + 2, BH = TH + 2, BN = BW * BH;
     constexpr int ES = (int)sizeof(S);
-    constexpr int NBB = (BN + NT - 1) / NT;
+    constexpr int NW = NT / 64;                 // waves per workgroup
+    constexpr int NK = (AH + NW - 1) / NW;      // frame rows per thread
+    constexpr int WR = AH - NW * (NK - 1);      // first wave without a row at k = NK - 1
+    constexpr int RA = 4 * AH, RB = 2 * BH;     // ring items of phases A and B
+    static_assert(TW == 64 && NT % 64 == 0, "one tile row per wave");
+    static_assert((NW - WR) * 64 >= RA && (NW - WR) * 64 >= RB, "ring items fit the free waves");
+    static_assert(WR >= BH + 1 - NW * (NK - 1) && WR >= TH + 2 - NW * (NK - 1), "free waves have no B or C row");
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
     const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
     const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
     const MediumSrc<MK> med(d);
@@ -722,36 +738,45 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
     // CDNA's vector-memory counter retires loads and stores in order, so a wait
     // for a load also waits for every store issued before it. Each phase
     // therefore issues its global loads before the stores that belong to the
-    // previous node: records are held one node (Pending) and phase C fetches
-    // its medium values before its first store.
+    // previous node: records are held one node (Pending).
     Pending<THERMAL> pend;
+    Cell ck[NK];   // the cell of this thread's frame node k (rows only, not ring items)
 
-    // phase A: s_{t+1} on the tile + 2 ring. Items follow tile_item: each wave
-    // takes one whole 64-node row of the tile (aligned, coalesced loads and
-    // stride-1 LDS stores), the 4 x AH ring columns come last (whole waves,
-    // since 64 AH items fill whole waves).
+    // item k of phase A: the thread's frame row, or at k = NK - 1 a ring item
+    auto a_item = [&](int k, int &ca, int &ra) -> bool {
+        ra = w + NW * k;
+        ca = 2 + lane;
+        if (k < NK - 1 || ra < AH) return true;
+        const int ri = (w - WR) * 64 + lane;
+        if (ri >= RA) return false;
+        ra = ri >> 2;
+        const int c = ri & 3;
+        ca = c < 2 ? c : TW + c;
+        return true;
+    };
+
+    // phase A: s_{t+1} on the tile + 2 ring
     const BufRes rr0 = buf_res(REC ? d.urec : nullptr, rbytes);
-    auto finish_a = [&](float (&f)[8], float (&g)[5], const CellRaw &raw, int ex, int ey, int gx, int gy,
-                        int64_t o) {
+    auto finish_a = [&](int k, float (&f)[8], float (&g)[5], const CellRaw &raw, int ca, int ra, int64_t o) {
         if (REC) pend.flush(d, rr0);
         const Cell c = med.cell(d, raw);
+        ck[k] = c;
         float ux, uy, n7, n8, dT;
         node_update<THERMAL>(d, c, f, g, ux, uy, n7, n8, dT);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) lds[(i * AH + ey) * AW + ex] = (float)(S)f[i];
+        for (int i = 0; i < 8; ++i) lds[(i * AH + ra) * AW + ca] = (float)(S)f[i];
         if (THERMAL) {
 #pragma unroll
-            for (int j = 0; j < 5; ++j) ldsg[(j * AH + ey) * AW + ex] = g[j];
+            for (int j = 0; j < 5; ++j) ldsg[(j * AH + ra) * AW + ca] = g[j];
         }
-        if (REC && ex >= 2 && ex < TW + 2 && ey >= 2 && ey < TH + 2 && gx < d.nx && gy < d.ny)
+        if (REC && ca >= 2 && ca < TW + 2 && ra >= 2 && ra < TH + 2 && x0 - 2 + ca < d.nx && y0 - 2 + ra < d.ny)
             pend.hold((uint32_t)(o * 4), ux, uy, n7, n8, dT);
     };
     if (interior) {
         // software pipelined: the next item's loads are issued before this one collides
-        auto fetch = [&](int e, float (&f)[8], float (&g)[5], CellRaw &r) {
-            int ex, ey;
-            tile_item<TW, AH, 2>(e, ex, ey);
-            const int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
+        auto fetch = [&](int k, float (&f)[8], float (&g)[5], CellRaw &r, int &ca, int &ra) -> bool {
+            if (!a_item(k, ca, ra)) return false;
+            const int gx = x0 - 2 + ca, gy = y0 - 2 + ra;
             const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * ES);
 #pragma unroll
             for (int i = 0; i < 8; ++i)
@@ -763,61 +788,72 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
                     g[j] = BufIO<float>::ld(rgin, vg, (uint32_t)((j * d.plane + (1 - TYv[j]) * d.pitch + (1 - TXv[j])) * 4));
             }
             r = med.load((uint32_t)((gy * d.pitch + gx) * 4));
+            return true;
         };
         float fn[8], gn[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         CellRaw rn{0.0f, 0.0f, 0.0f};
-        if ((int)threadIdx.x < AN) fetch(threadIdx.x, fn, gn, rn);
-        for (int e = threadIdx.x; e < AN; e += NT) {
+        int can = 0, ran = 0;
+        bool vn = fetch(0, fn, gn, rn, can, ran);
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
             float f[8], g[5];
 #pragma unroll
             for (int i = 0; i < 8; ++i) f[i] = fn[i];
 #pragma unroll
             for (int j = 0; j < 5; ++j) g[j] = gn[j];
             const CellRaw r = rn;
-            if (e + NT < AN) fetch(e + NT, fn, gn, rn);
-            int ex, ey;
-            tile_item<TW, AH, 2>(e, ex, ey);
-            const int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
-            finish_a(f, g, r, ex, ey, gx, gy, (int64_t)gy * d.pitch + gx);
+            const int ca = can, ra = ran;
+            const bool v = vn;
+            if (k + 1 < NK) vn = fetch(k + 1, fn, gn, rn, can, ran);
+            if (v) finish_a(k, f, g, r, ca, ra, (int64_t)(y0 - 2 + ra) * d.pitch + (x0 - 2 + ca));
         }
     } else {
-        for (int e = threadIdx.x; e < AN; e += NT) {
-            int ex, ey;
-            tile_item<TW, AH, 2>(e, ex, ey);
-            int gx = x0 - 2 + ex, gy = y0 - 2 + ey;
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            int ca, ra;
+            if (!a_item(k, ca, ra)) continue;
+            int gx = x0 - 2 + ca, gy = y0 - 2 + ra;
             if (!wrap_node(d, gx, gy)) continue;
             float f[8], g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
             gather_general_buf<S>(d, rin, gx, gy, f);
             if (THERMAL) gather_thermal_buf(d, rgin, gx, gy, g);
             const int64_t o = (int64_t)gy * d.pitch + gx;
             // a wrapped ring node is recorded by the tile that owns it
-            finish_a(f, g, med.load((uint32_t)(o * 4)), ex, ey, x0 - 2 + ex, y0 - 2 + ey, o);
+            finish_a(k, f, g, med.load((uint32_t)(o * 4)), ca, ra, o);
         }
     }
     if (REC) pend.flush(d, rr0);
     lds_barrier();
 
-    // phase B: s_{t+2} on the tile + 1 ring, kept in registers (items as in phase A:
-    // whole rows per wave, then the two ring columns)
+    // phase B: s_{t+2} on the tile + 1 ring, kept in registers
     const BufRes rr1 = buf_res(urec1, rbytes);
-    float fb[NBB][8], gb[NBB][THERMAL ? 5 : 1];
-    int slot[NBB];
+    float fb[NK][8], gb[NK][THERMAL ? 5 : 1];
+    int slot[NK];
 #pragma unroll
-    for (int k = 0; k < NBB; ++k) {
+    for (int k = 0; k < NK; ++k) {
         slot[k] = -1;
-        const int e = threadIdx.x + k * NT;
-        if (e >= BN) continue;
-        int bx, by;
-        tile_item<TW, BH, 1>(e, bx, by);
+        const int rb = w + NW * k - 1;
+        int bx = 1 + lane, by = rb;
+        const bool row = rb >= 0 && rb < BH;
+        if (!row) {
+            const int ri = (w - WR) * 64 + lane;
+            if (k != NK - 1 || w < WR || ri >= RB) continue;
+            by = ri >> 1;
+            bx = (ri & 1) ? BW - 1 : 0;
+        }
         int gx = x0 - 1 + bx, gy = y0 - 1 + by;
         if (!interior && !wrap_node(d, gx, gy)) continue;
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const CellRaw raw = med.load((uint32_t)(o * 4));
+        Cell c;
+        if (row) {
+            c = ck[k];
+        } else {
+            c = med.cell(d, med.load((uint32_t)(o * 4)));
+        }
         if (REC) pend.flush(d, rr1);
         lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fb[k]);
         float g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (THERMAL) lds_gather_thermal<AW, AH>(d, ldsg, interior, gx, gy, bx + 1, by + 1, g);
-        const Cell c = med.cell(d, raw);
         float ux, uy, n7, n8, dT;
         node_update<THERMAL>(d, c, fb[k], g, ux, uy, n7, n8, dT);
         if (THERMAL) {
@@ -831,7 +867,7 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
     if (REC) pend.flush(d, rr1);
     lds_barrier();
 #pragma unroll
-    for (int k = 0; k < NBB; ++k) {
+    for (int k = 0; k < NK; ++k) {
         if (slot[k] < 0) continue;
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[i * BN + slot[k]] = (float)(S)fb[k][i];
@@ -844,28 +880,17 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
 
     // phase C: s_{t+3} on the tile, to HBM
     const BufRes rr2 = buf_res(urec2, rbytes);
-    constexpr int NC = (TW * TH + NT - 1) / NT;
-    CellRaw rawC[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        const int q = threadIdx.x + k * NT;
-        const int gx = x0 + q % TW, gy = y0 + q / TW;
-        if (q < TW * TH && gx < d.nx && gy < d.ny)
-            rawC[k] = med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
-    }
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-        const int q = threadIdx.x + k * NT;
-        const int lx = q % TW, ly = q / TW;
-        const int gx = x0 + lx, gy = y0 + ly;
-        if (q >= TW * TH || gx >= d.nx || gy >= d.ny) continue;
+    for (int k = 0; k < NK; ++k) {
+        const int rc = w + NW * k - 2;
+        const int gx = x0 + lane, gy = y0 + rc;
+        if (rc < 0 || rc >= TH || gx >= d.nx || gy >= d.ny) continue;
         float f[8], g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        lds_gather<BW, BH>(d, lds, interior, gx, gy, lx + 1, ly + 1, f);
-        if (THERMAL) lds_gather_thermal<BW, BH>(d, ldsg, interior, gx, gy, lx + 1, ly + 1, g);
+        lds_gather<BW, BH>(d, lds, interior, gx, gy, lane + 1, rc + 1, f);
+        if (THERMAL) lds_gather_thermal<BW, BH>(d, ldsg, interior, gx, gy, lane + 1, rc + 1, g);
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = med.cell(d, rawC[k]);
         float ux, uy, n7, n8, dT;
-        node_update<THERMAL>(d, c, f, g, ux, uy, n7, n8, dT);
+        node_update<THERMAL>(d, ck[k], f, g, ux, uy, n7, n8, dT);
         const uint32_t vo = (uint32_t)(o * ES);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
