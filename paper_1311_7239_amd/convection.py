@@ -27,15 +27,32 @@ TABLE1_PHIS = (0.4, 0.6, 0.9)
 
 def table1_cases(pairs: Iterable[Tuple[float, float]] = TABLE1_PAIRS,
                  phis: Iterable[float] = TABLE1_PHIS, nee: bool = False,
-                 grid: Optional[Dict[float, int]] = None) -> List[Tuple[tuple, I.Case]]:
-    """((Da, Ra, phi), Case) for every combination, Pr = 1, Ma = 0.1, J = sigma =
-    gamma = 1, Th = 21, Tc = 1 (Sec. 3.4), on the paper's grid per Da."""
+                 grid: Optional[Dict[float, int]] = None, Ma: float = 0.1) -> List[Tuple[tuple, I.Case]]:
+    """((Da, Ra, phi), Case) for every combination, Pr = 1, Ma = 0.1 (unless given),
+    J = sigma = gamma = 1, Th = 21, Tc = 1 (Sec. 3.4), on the paper's grid per Da."""
     grid = TABLE1_GRID if grid is None else grid
     out = []
     for Da, Ra in pairs:
         for phi in phis:
-            c = I.natural_convection(n=grid[Da], phi=phi, Da=Da, Ra=Ra, nee=nee)
+            c = I.natural_convection(n=grid[Da], phi=phi, Da=Da, Ra=Ra, nee=nee, Ma=Ma)
             out.append(((Da, Ra, phi), c))
+    return out
+
+
+# Resolution and Mach-number variants of the Da = 1e-6 row at Ra = 1e8 and 1e9:
+# (label, grid, Ma); the first is the paper's grid at the Ma this build reads.
+DA6_VARIANTS = [("250 Ma0.1", 250, 0.1), ("500 Ma0.1", 500, 0.1), ("250 Ma0.05", 250, 0.05),
+                ("250 Ma0.2", 250, 0.2)]
+
+
+def da6_study_cases(variants=DA6_VARIANTS, ras=(1e8, 1e9), phis=TABLE1_PHIS,
+                    nee: bool = False) -> List[Tuple[tuple, I.Case]]:
+    """((label, Ra, phi), Case) of the Da = 1e-6 cases under each (grid, Ma) variant."""
+    out = []
+    for label, n, Ma in variants:
+        for Ra in ras:
+            for phi in phis:
+                out.append(((label, Ra, phi), I.natural_convection(n=n, phi=phi, Da=1e-6, Ra=Ra, Ma=Ma, nee=nee)))
     return out
 
 
@@ -73,7 +90,7 @@ def nusselt_hot_wall(T: np.ndarray, case: I.Case) -> float:
 def run_sweep(keyed_cases: List[Tuple[tuple, I.Case]], chunk: int = 4000, tol: float = 1e-6,
               max_steps: int = 2_000_000, time_limit: Optional[float] = None,
               storage: int = lbm.FP32_DEV, log: Optional[Callable[[str], None]] = None,
-              device="cuda") -> Dict[tuple, dict]:
+              device="cuda", history: Optional[Dict[tuple, list]] = None) -> Dict[tuple, dict]:
     """Steps all cases as one thermal batch from the conduction profile until every
     Nusselt number changes by less than tol over a chunk (or max_steps / the time
     limit is reached). Returns {key: {"nu", "steps", "converged", "diverged"}}: a case whose
@@ -98,6 +115,8 @@ def run_sweep(keyed_cases: List[Tuple[tuple, I.Case]], chunk: int = 4000, tol: f
                 continue
             _, _, T = b.macroscopic(k, want_T=True)
             nu[k] = nusselt_hot_wall(T.cpu().numpy().astype(np.float64), c)
+            if history is not None:
+                history.setdefault(keyed_cases[k][0], []).append((steps, nu[k]))
             if not np.isfinite(nu[k]):
                 done[k] = diverged[k] = True
                 when[k] = steps
@@ -114,6 +133,44 @@ def run_sweep(keyed_cases: List[Tuple[tuple, I.Case]], chunk: int = 4000, tol: f
             for k, (key, _) in enumerate(keyed_cases)}
 
 
+def steady_nusselt(case: I.Case, chunk: int = 20_000, tol: float = 1e-6, max_steps: int = 4_000_000,
+                   max_seconds: Optional[float] = None, storage: int = lbm.FP32_DEV, device="cuda") -> dict:
+    """One cavity stepped alone (its default cycles per pass) from the conduction profile
+    until the hot-wall Nusselt number changes by less than tol over a chunk (or max_steps
+    / max_seconds). Returns {"nu", "steps", "converged", "diverged", "seconds",
+    "last_change", "nu_aitken"}: the last change per chunk, and Aitken's delta-squared
+    estimate of the limit from the last three values (the slowest thermal mode decays
+    geometrically once the faster ones have gone)."""
+    s = lbm.solver_for_case(case, storage=storage, device=device)
+    s.set_populations(torch.zeros((8, case.ny, case.nx), device=device),
+                      torch.from_numpy(conduction_state(case)).to(device))
+    vals, steps = [], 0
+    t0 = time.time()
+    converged = diverged = False
+    while steps < max_steps:
+        s.step(chunk)
+        steps += chunk
+        _, _, T = s.macroscopic(want_T=True)
+        vals.append(nusselt_hot_wall(T.cpu().numpy().astype(np.float64), case))
+        if not np.isfinite(vals[-1]):
+            diverged = True
+            break
+        if len(vals) > 1 and abs(vals[-1] - vals[-2]) < tol:
+            converged = True
+            break
+        if max_seconds is not None and time.time() - t0 > max_seconds:
+            break
+    nu = vals[-1] if vals else float("nan")
+    last = abs(vals[-1] - vals[-2]) if len(vals) > 1 else float("nan")
+    aitken = nu
+    if len(vals) > 2:
+        d1, d2 = vals[-2] - vals[-3], vals[-1] - vals[-2]
+        if d2 != d1 and abs(d2) < abs(d1):
+            aitken = vals[-1] - d2 * d2 / (d2 - d1)
+    return {"nu": nu, "steps": steps, "converged": converged, "diverged": diverged,
+            "seconds": time.time() - t0, "last_change": last, "nu_aitken": aitken}
+
+
 def _main(argv=None):
     """Runs the Table 1 sweep and prints the hot-wall Nusselt number of every case."""
     import argparse
@@ -123,7 +180,31 @@ def _main(argv=None):
     ap.add_argument("--chunk", type=int, default=5000)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--time-limit", type=float, default=None)
+    ap.add_argument("--steady", type=int, default=0, metavar="N",
+                    help="only the Sec. 3.4 cavity (phi 0.6, Da 1e-4, Ra 1e5) on an N^2 grid to a steady Nu")
+    ap.add_argument("--da6-study", action="store_true",
+                    help="the Da = 1e-6, Ra = 1e8 / 1e9 cases on 250^2 and 500^2 grids and at Ma 0.05, 0.1, 0.2")
     a = ap.parse_args(argv)
+    if a.steady:
+        r = steady_nusselt(I.natural_convection(n=a.steady), chunk=a.chunk, tol=a.tol, max_steps=a.max_steps,
+                           max_seconds=a.time_limit)
+        print(f"{a.steady}^2: Nu {r['nu']:.6f} after {r['steps']} steps ({r['seconds']:.1f} s), last change "
+              f"{r['last_change']:.2e} per {a.chunk} steps, converged {int(r['converged'])}, "
+              f"Aitken limit {r['nu_aitken']:.6f}", flush=True)
+        return
+    if a.da6_study:
+        keyed = da6_study_cases(nee=a.walls == "on-node")
+        hist: Dict[tuple, list] = {}
+        res = run_sweep(keyed, chunk=a.chunk, tol=a.tol, max_steps=a.max_steps, time_limit=a.time_limit,
+                        log=lambda m: print(m, flush=True), history=hist)
+        print("variant Ra phi Nu steps converged diverged | Nu at 1/4, 1/2, 3/4 of its steps")
+        for key, r in res.items():
+            h = hist.get(key, [])
+            marks = [h[max(0, int(len(h) * q) - 1)][1] for q in (0.25, 0.5, 0.75)] if h else []
+            label, Ra, phi = key
+            print(f"{label} {Ra:g} {phi} {r['nu']:.4f} {r['steps']} {int(r['converged'])} {int(r['diverged'])} | "
+                  + " ".join(f"{m:.4f}" for m in marks))
+        return
     keyed = table1_cases(nee=a.walls == "on-node")
     res = run_sweep(keyed, chunk=a.chunk, tol=a.tol, max_steps=a.max_steps, time_limit=a.time_limit,
                     log=lambda m: print(m, flush=True))

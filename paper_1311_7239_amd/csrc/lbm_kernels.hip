@@ -316,23 +316,6 @@ hipError_t launch_step_batch(const Dom *doms, const int4 *tiles, int ntiles, int
                    : launch_batch_t<_Float16, false>(doms, tiles, ntiles, parity, s, grid, st);
 }
 
-// Item -> node of a (TW + 2R) x H tile that has R ring columns on each side:
-// the TW-wide interior of every row first, row-major (with TW = 64 each wave
-// covers one whole row: aligned, coalesced accesses and no division by the
-// padded width), then the 2R ring columns of every row.
-template <int TW, int H, int R>
-__device__ __forceinline__ void tile_item(int item, int &cx, int &cy) {
-    if (item < TW * H) {
-        cy = item / TW;
-        cx = R + item % TW;
-    } else {
-        const int r = item - TW * H;
-        cy = r / (2 * R);
-        const int c = r % (2 * R);
-        cx = c < R ? c : TW + c;
-    }
-}
-
 // Recorded u (and stress moments) of the multi-cycle passes.
 // The records go through buffer stores: a recorded step spans at most five
 // planes, below 4 GiB whenever multi-cycle passes run. They are read back only
@@ -398,11 +381,24 @@ __device__ __forceinline__ void store_uprev(const Dom &d, uint32_t o4, float ux,
 // bitwise that of two one-step launches. With THERMAL the D2Q5 field takes the
 // same path: phase A keeps g beside f in LDS (ldsg, five planes), phase B
 // gathers it with bounce-back and anti-bounce-back across the walls.
+//
+// Work items: thread (wave w, lane l) owns row r = w + NW k of the
+// (TW + 2) x (TH + 2) frame, column 1 + l, in both phases (phase B visits
+// rows 1 .. TH), so its node's porosity is loaded and its drag coefficients
+// computed once, in phase A. Each wave covers one whole TW = 64 row; the two
+// ring columns go to the waves without a row at the last iteration.
 template <typename S, int TW, int TH, int NT, bool REC, int MK, bool THERMAL>
 __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *urec_next,
                                            float (&lds)[8][TH + 2][TW + 2], float *ldsg) {
-    constexpr int EW = TW + 2, EH = TH + 2, EN = EW * EH;
+    constexpr int EW = TW + 2, EH = TH + 2;
     constexpr int ES = (int)sizeof(S);
+    constexpr int NW = NT / 64;                 // waves per workgroup
+    constexpr int NK = (EH + NW - 1) / NW;      // frame rows per thread
+    constexpr int WR = EH - NW * (NK - 1);      // first wave without a row at k = NK - 1
+    constexpr int RA = 2 * EH;                  // ring items of phase A
+    static_assert(TW == 64 && NT % 64 == 0, "one tile row per wave");
+    static_assert((NW - WR) * 64 >= RA, "ring items fit the free waves");
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
     // the state buffers are below 4 GiB (the host keeps larger domains on the
     // one-cycle kernel), so every byte offset fits the buffer instructions
     const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
@@ -415,22 +411,24 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
     const MediumSrc<MK> med(d);
     // every source of phase A inside the domain, no wrap needed
     const bool interior = x0 >= 2 && x0 + TW + 2 <= d.nx && y0 >= 2 && y0 + TH + 2 <= d.ny;
+    Cell ck[NK];   // the cell of this thread's frame node k (rows only, not ring items)
 
-    // medium values of this thread's phase-B nodes, fetched now so that they
-    // arrive during phase A
-    constexpr int NB = (TW * TH + NT - 1) / NT;
-    CellRaw rawB[NB];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        const int q = threadIdx.x + k * NT;
-        const int gx = x0 + q % TW, gy = y0 + q / TW;
-        rawB[k] = CellRaw{0.0f, 0.0f, 0.0f};
-        if (q < TW * TH && gx < d.nx && gy < d.ny)
-            rawB[k] = med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
-    }
+    // item k of phase A: the thread's frame row, or at k = NK - 1 a ring item
+    auto a_item = [&](int k, int &ex, int &ey) -> bool {
+        ey = w + NW * k;
+        ex = 1 + lane;
+        if (k < NK - 1 || ey < EH) return true;
+        const int ri = (w - WR) * 64 + lane;
+        if (ri >= RA) return false;
+        ey = ri >> 1;
+        ex = (ri & 1) ? EW - 1 : 0;
+        return true;
+    };
 
     // phase A: s_{t+1} on the extended tile (and u(t) on the tile when recording)
-    auto finish_a = [&](float (&f)[8], float (&g)[5], const Cell &c, int ex, int ey, int64_t o) {
+    auto finish_a = [&](int k, float (&f)[8], float (&g)[5], const CellRaw &raw, int ex, int ey, int64_t o) {
+        const Cell c = med.cell(d, raw);
+        ck[k] = c;
         float ux, uy, n7, n8, dT;
         node_update<THERMAL>(d, c, f, g, ux, uy, n7, n8, dT);
 #pragma unroll
@@ -449,10 +447,9 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
     if (interior) {
         // link i pulls from (gx - e_ix, gy - e_iy): the lane's offset of (gx - 1, gy - 1)
         // plus a uniform, non-negative per-link offset. Software pipelined: the next
-        // node's loads are issued before this node collides.
-        auto fetch = [&](int e, float (&f)[8], float (&g)[5], CellRaw &r) {
-            int ex, ey;
-            tile_item<TW, EH, 1>(e, ex, ey);
+        // item's loads are issued before this one collides.
+        auto fetch = [&](int k, float (&f)[8], float (&g)[5], CellRaw &r, int &ex, int &ey) -> bool {
+            if (!a_item(k, ex, ey)) return false;
             const int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
             const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * ES);
 #pragma unroll
@@ -464,28 +461,31 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
                 for (int j = 0; j < 5; ++j)
                     g[j] = BufIO<float>::ld(rgin, vg, (uint32_t)((j * d.plane + (1 - TYv[j]) * d.pitch + (1 - TXv[j])) * 4));
             }
-            r = med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4));
+            r = med.load((uint32_t)((gy * d.pitch + gx) * 4));
+            return true;
         };
         float fn[8], gn[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         CellRaw rn{0.0f, 0.0f, 0.0f};
-        if ((int)threadIdx.x < EN) fetch(threadIdx.x, fn, gn, rn);
-        for (int e = threadIdx.x; e < EN; e += NT) {
+        int exn = 0, eyn = 0;
+        bool vn = fetch(0, fn, gn, rn, exn, eyn);
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
             float f[8], g[5];
 #pragma unroll
             for (int i = 0; i < 8; ++i) f[i] = fn[i];
 #pragma unroll
             for (int j = 0; j < 5; ++j) g[j] = gn[j];
             const CellRaw r = rn;
-            if (e + NT < EN) fetch(e + NT, fn, gn, rn);
-            int ex, ey;
-            tile_item<TW, EH, 1>(e, ex, ey);
-            const int64_t o = (int64_t)(y0 - 1 + ey) * d.pitch + (x0 - 1 + ex);
-            finish_a(f, g, med.cell(d, r), ex, ey, o);
+            const int ex = exn, ey = eyn;
+            const bool v = vn;
+            if (k + 1 < NK) vn = fetch(k + 1, fn, gn, rn, exn, eyn);
+            if (v) finish_a(k, f, g, r, ex, ey, (int64_t)(y0 - 1 + ey) * d.pitch + (x0 - 1 + ex));
         }
     } else {
-        for (int e = threadIdx.x; e < EN; e += NT) {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
             int ex, ey;
-            tile_item<TW, EH, 1>(e, ex, ey);
+            if (!a_item(k, ex, ey)) continue;
             int gx = x0 - 1 + ex, gy = y0 - 1 + ey;
             if (gx < 0 || gx >= d.nx) {
                 if (d.bc_x != BC_PERIODIC) continue;
@@ -499,19 +499,17 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
             gather_general_buf<S>(d, rin, gx, gy, f);
             if (THERMAL) gather_thermal_buf(d, rgin, gx, gy, g);
             const int64_t o = (int64_t)gy * d.pitch + gx;
-            finish_a(f, g, med.cell(d, med.load((uint32_t)(o * 4))), ex, ey, o);
+            finish_a(k, f, g, med.load((uint32_t)(o * 4)), ex, ey, o);
         }
     }
     lds_barrier();
 
     // phase B: s_{t+2} on the tile (and u(t+1) when recording)
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        const int q = threadIdx.x + k * NT;
-        if (q >= TW * TH) continue;
-        const int lx = q % TW, ly = q / TW;
+    for (int k = 0; k < NK; ++k) {
+        const int ly = w + NW * k - 1, lx = lane;
         const int gx = x0 + lx, gy = y0 + ly;
-        if (gx >= d.nx || gy >= d.ny) continue;
+        if (ly < 0 || ly >= TH || gx >= d.nx || gy >= d.ny) continue;
         float f[8];
         const float *flat = &lds[0][0][0];
         if (interior) {
@@ -559,9 +557,8 @@ __device__ __forceinline__ void step2_tile(const Dom &d, int x0, int y0, float *
             }
         }
         const int64_t o = (int64_t)gy * d.pitch + gx;
-        const Cell c = med.cell(d, rawB[k]);
         float ux, uy, n7, n8, dT;
-        node_update<THERMAL>(d, c, f, g, ux, uy, n7, n8, dT);
+        node_update<THERMAL>(d, ck[k], f, g, ux, uy, n7, n8, dT);
         const uint32_t vo = (uint32_t)(o * ES);
         if (d.nt_store) {
 #pragma unroll
