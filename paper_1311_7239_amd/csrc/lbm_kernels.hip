@@ -889,16 +889,20 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
         float ux, uy, n7, n8, dT;
         node_update<THERMAL>(d, ck[k], f, g, ux, uy, n7, n8, dT);
         const uint32_t vo = (uint32_t)(o * ES);
+        // one branch for the whole store sequence (per-store branches split the stream)
+        if (d.nt_store) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            if (d.nt_store) BufIO<S>::st_nt(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
-            else BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
-        }
-        if (THERMAL) {
+            for (int i = 0; i < 8; ++i) BufIO<S>::st_nt(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+            if (THERMAL) {
 #pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                if (d.nt_store) BufIO<float>::st_nt(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
-                else BufIO<float>::st(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
+                for (int j = 0; j < 5; ++j) BufIO<float>::st_nt(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+            if (THERMAL) {
+#pragma unroll
+                for (int j = 0; j < 5; ++j) BufIO<float>::st(rgout, (uint32_t)(o * 4), (uint32_t)(j * d.plane * 4), g[j]);
             }
         }
         if (d.uprev) store_uprev(d, (uint32_t)(o * 4), ux, uy);
