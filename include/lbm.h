@@ -33,7 +33,8 @@
  *   - Every function returns LBM_OK (0) or a negative status; a failed call
  *     has no side effect unless it returns LBM_EDEVICE, after which the
  *     context is poisoned. No function prints, aborts or throws.
- *   - A context is not thread-safe.
+ *   - A context is not thread-safe. Handles are checked against the set of
+ *     live contexts (see lbm_destroy).
  */
 #ifndef MRTLBM_LBM_H
 #define MRTLBM_LBM_H
@@ -268,7 +269,12 @@ int lbm_state_bytes(const lbm_ctx *c, size_t *bytes);
 int lbm_save(lbm_ctx *c, void *host_buf, size_t bytes);
 int lbm_load(lbm_ctx *c, const void *host_buf, size_t bytes);
 
-/* Destroys the context (NULL is accepted). The workspace is not touched. */
+/* Destroys the context (NULL is accepted). The workspace is not touched.
+ * The library keeps the set of live contexts: a handle that was already
+ * destroyed, or never returned by lbm_create / lbm_create_batch, gets
+ * LBM_EINVAL here and from every other entry point, without its memory
+ * being read, so a second lbm_destroy is harmless. (Once the allocator has
+ * reused the address for a newer context, a stale handle names that one.) */
 int lbm_destroy(lbm_ctx *c);
 
 /* Static text for a status code, and the thread-local message of the last

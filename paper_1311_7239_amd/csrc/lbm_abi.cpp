@@ -14,6 +14,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "lbm_launch.h"
@@ -303,8 +304,12 @@ bool three_cycle_possible(const lbm_ctx *c) {
     return two_cycle_possible(c) && !(c->batch && c->batch_thermal);
 }
 
+// A failed HIP call: poisons the context (if any) and reads the thread's
+// stored HIP error, which HIP keeps from any failed call until it is read, so
+// that the next launch check of another context does not report it again.
 int device_fail(lbm_ctx *c, hipError_t e, const char *what) {
     if (c) c->poisoned = true;
+    (void)hipGetLastError();
     return fail(LBM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -329,8 +334,26 @@ Dom dom_rec(const Domain &D, int cur) {
 
 Source src_now(int64_t t) { return t == 0 ? SRC_DIRECT : SRC_GATHER; }
 
-int check_ctx(lbm_ctx *c) {
+// Contexts returned by lbm_create / lbm_create_batch and not yet destroyed.
+// Every entry point looks a handle up here before touching it, so a destroyed
+// (or never created) handle is refused and a second lbm_destroy is harmless.
+std::mutex g_live_mu;
+std::unordered_set<const lbm_ctx *> g_live;
+
+void register_live(const lbm_ctx *c) {
+    std::lock_guard<std::mutex> lock(g_live_mu);
+    g_live.insert(c);
+}
+
+int check_handle(const lbm_ctx *c) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
+    std::lock_guard<std::mutex> lock(g_live_mu);
+    if (!g_live.count(c)) return fail(LBM_EINVAL, "not a live context (destroyed, or never created)");
+    return LBM_OK;
+}
+
+int check_ctx(lbm_ctx *c) {
+    if (int rc = check_handle(c)) return rc;
     if (c->poisoned) return fail(LBM_EDEVICE, "context is poisoned by an earlier device error");
     return LBM_OK;
 }
@@ -592,17 +615,18 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     if (d->storage == LBM_FP16_DEV) c->sched = Schedule{64, 2, 2, 1};
     hipError_t e = init_domain(D, 0, phi, kappa, c->stream);
     if (e != hipSuccess) {
-        rc = fail(LBM_EDEVICE, "initialisation: %s", hipGetErrorString(e));
+        rc = device_fail(nullptr, e, "initialisation");
         delete c;
         return rc;
     }
     c->rec_valid = d->ckpt_every > 0;
     e = checkpoint(c);
     if (e != hipSuccess) {
-        rc = fail(LBM_EDEVICE, "checkpoint: %s", hipGetErrorString(e));
+        rc = device_fail(nullptr, e, "checkpoint");
         delete c;
         return rc;
     }
+    register_live(c);
     *out = c;
     return LBM_OK;
 }
@@ -686,7 +710,8 @@ int lbm_step(lbm_ctx *c, int64_t n) {
 }
 
 int lbm_time(const lbm_ctx *c, int64_t *t) {
-    if (!c || !t) return fail(LBM_EINVAL, "NULL argument");
+    if (int rc = check_handle(c)) return rc;
+    if (!t) return fail(LBM_EINVAL, "NULL argument");
     *t = c->t;
     return LBM_OK;
 }
@@ -817,13 +842,14 @@ int lbm_reduce_static(lbm_ctx *c, int32_t k, double *mass, double *residual) {
                     nb, kReduceMaxBlocks);
     double *ptr = nullptr;
     hipError_t e = scratch_on(c->device, &ptr);
-    if (e != hipSuccess) return fail(LBM_EDEVICE, "static scratch address: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return device_fail(c, e, "static scratch address");
     // every partial and final sum is written before it is read: nothing to clear
     return reduce_into(c, k, mass, residual, ptr, ptr + 3 * kReduceMaxBlocks);
 }
 
 int lbm_state_bytes(const lbm_ctx *c, size_t *bytes) {
-    if (!c || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    if (int rc = check_handle(c)) return rc;
+    if (!bytes) return fail(LBM_EINVAL, "NULL argument");
     if (c->batch) return fail(LBM_ENOTSUP, "save/load is per single-domain context");
     const Domain &D = c->dom[0];
     *bytes = 64 + D.L.f_bytes + (D.desc.thermal.enabled ? D.L.g_bytes : 0) + 2 * D.L.p_bytes;
@@ -934,6 +960,10 @@ int lbm_load(lbm_ctx *c, const void *host_buf, size_t bytes) {
 
 int lbm_destroy(lbm_ctx *c) {
     if (!c) return LBM_OK;
+    {
+        std::lock_guard<std::mutex> lock(g_live_mu);
+        if (!g_live.erase(c)) return fail(LBM_EINVAL, "not a live context (destroyed, or never created)");
+    }
     reset_graphs(c);
     delete c;
     return LBM_OK;
@@ -954,7 +984,7 @@ const char *lbm_strerror(int s) {
 const char *lbm_last_error(void) { return g_last_error.c_str(); }
 
 int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows, int32_t *grid) {
-    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (int rc = check_handle(c)) return rc;
     if (tile_w) *tile_w = c->sched.tile_w;
     if (vec) *vec = c->sched.vec;
     if (rows) *rows = c->sched.rows;
@@ -971,7 +1001,7 @@ int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows,
 
 int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threads, int32_t *rows,
                       int32_t *grid) {
-    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (int rc = check_handle(c)) return rc;
     if (cycles_per_pass) *cycles_per_pass = c->tblock;
     if (threads) *threads = c->tb_threads;
     if (rows) *rows = c->tb_rows;
@@ -1409,11 +1439,12 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
         c->tblock = best.tblock;
     }
     if (e != hipSuccess) {
-        rc = fail(LBM_EDEVICE, "batch creation: %s", hipGetErrorString(e));
+        rc = device_fail(nullptr, e, "batch creation");
         delete c;
         return rc;
     }
     c->graph_steps = 32;
+    register_live(c);
     *out = c;
     return LBM_OK;
 }

@@ -7,7 +7,13 @@
   the kernel objects of the normal build) takes valid and invalid descriptors, workspace
   sizing, the refusal paths of lbm_create and lbm_create_batch, and calls on NULL
   contexts (tests/sanitize/abi_driver.cpp).
-Leak detection is on in both. Each driver exits 0 only when every call returned what
+* Fault injection through a null device (tests/sanitize/null_device.cpp, test code only):
+  the same host code and the kernel objects' launch stubs run on a fake HIP runtime in host
+  memory, where launches are recorded and not executed. A NaN injected into a population
+  gives LBM_EUNSTABLE, an injected HIP failure poisons the context, calls out of order get
+  the status the header names, and a second lbm_destroy is refused
+  (tests/sanitize/null_driver.cpp).
+Leak detection is on in all three. Each driver exits 0 only when every call returned what
 the header promises; a sanitizer report aborts it."""
 import os
 import pathlib
@@ -17,7 +23,7 @@ import subprocess
 import pytest
 
 ROOT = pathlib.Path(__file__).resolve().parent.parent
-SAN = ROOT / "tests" / "sanitize"
+SAN_DIR = ROOT / "tests" / "sanitize"
 CSRC = ROOT / "paper_1311_7239_amd" / "csrc"
 BUILD = ROOT / "paper_1311_7239_amd" / "_build"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -33,7 +39,7 @@ def test_oracle_under_address_and_ub_sanitizers(tmp_path):
     exe = tmp_path / "oracle_asan"
     r = _run(["gcc", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
               "-fno-omit-frame-pointer", "-fopenmp", "-I", str(ROOT / "oracle"),
-              str(ROOT / "oracle" / "mrt_oracle.c"), str(SAN / "oracle_driver.c"), "-lm", "-o", str(exe)])
+              str(ROOT / "oracle" / "mrt_oracle.c"), str(SAN_DIR / "oracle_driver.c"), "-lm", "-o", str(exe)])
     assert r.returncode == 0, r.stderr
     r = _run([str(exe)], env=ENV, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
@@ -41,23 +47,56 @@ def test_oracle_under_address_and_ub_sanitizers(tmp_path):
     assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
 
 
-@pytest.mark.skipif(not shutil.which(HIPCC) and not os.path.exists(HIPCC), reason="hipcc not available")
-def test_abi_host_code_under_address_and_ub_sanitizers(tmp_path):
-    kernels = [BUILD / "lbm_kernels.hip.o", BUILD / "lbm_adjoint.hip.o"]
-    if not all(k.exists() for k in kernels):
+HAVE_HIPCC = bool(shutil.which(HIPCC)) or os.path.exists(HIPCC)
+KERNELS = [BUILD / "lbm_kernels.hip.o", BUILD / "lbm_adjoint.hip.o"]
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+COMMON = ["-O1", "-g", "-std=c++17", "-fno-omit-frame-pointer", "-I", str(ROOT / "include")]
+CLANG = pathlib.Path(HIPCC).resolve().parent.parent / "llvm" / "bin" / "clang++"
+
+
+@pytest.fixture(scope="module")
+def abi_asan_object(tmp_path_factory):
+    """lbm_abi.cpp with its host code built under the sanitizers (device code as usual)."""
+    if not HAVE_HIPCC:
+        pytest.skip("hipcc not available")
+    if not all(k.exists() for k in KERNELS):
         pytest.skip("kernel objects not built (run paper_1311_7239_amd.build first)")
-    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
-    common = ["-O1", "-g", "-std=c++17", "-fno-omit-frame-pointer", "-I", str(ROOT / "include")]
-    abi_o, drv_o, exe = tmp_path / "abi.o", tmp_path / "drv.o", tmp_path / "abi_asan"
-    r = _run([HIPCC, "--offload-arch=gfx950", *common, "-fPIC", "-ffp-contract=off", "-Xclang", "-target-feature",
-              "-Xclang", "-packed-fp32-ops", *san, "-x", "hip", "-I", str(CSRC), "-c",
-              str(CSRC / "lbm_abi.cpp"), "-o", str(abi_o)])
+    obj = tmp_path_factory.mktemp("abi") / "abi.o"
+    r = _run([HIPCC, "--offload-arch=gfx950", *COMMON, "-fPIC", "-ffp-contract=off", "-Xclang", "-target-feature",
+              "-Xclang", "-packed-fp32-ops", *SAN, "-x", "hip", "-I", str(CSRC), "-c",
+              str(CSRC / "lbm_abi.cpp"), "-o", str(obj)])
     assert r.returncode == 0, r.stderr
-    r = _run([HIPCC, *common, *san, "-c", str(SAN / "abi_driver.cpp"), "-o", str(drv_o)])
+    return obj
+
+
+def test_abi_host_code_under_address_and_ub_sanitizers(tmp_path, abi_asan_object):
+    drv_o, exe = tmp_path / "drv.o", tmp_path / "abi_asan"
+    r = _run([HIPCC, *COMMON, *SAN, "-c", str(SAN_DIR / "abi_driver.cpp"), "-o", str(drv_o)])
     assert r.returncode == 0, r.stderr
-    r = _run([HIPCC, "--offload-arch=gfx950", *san, str(drv_o), str(abi_o), *map(str, kernels), "-o", str(exe)])
+    r = _run([HIPCC, "--offload-arch=gfx950", *SAN, str(drv_o), str(abi_asan_object), *map(str, KERNELS),
+              "-o", str(exe)])
     assert r.returncode == 0, r.stderr
     r = _run([str(exe)], env=ENV, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "0 failures" in r.stdout
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
+
+
+def test_fault_injection_through_the_null_device(tmp_path, abi_asan_object):
+    if not CLANG.exists():
+        pytest.skip("ROCm clang++ not found")
+    dev_o, drv_o, exe = tmp_path / "null_device.o", tmp_path / "null_driver.o", tmp_path / "null_asan"
+    r = _run([HIPCC, "-x", "hip", "--cuda-host-only", "--offload-arch=gfx950", *COMMON, "-fPIC", *SAN,
+              "-I", str(CSRC), "-c", str(SAN_DIR / "null_device.cpp"), "-o", str(dev_o)])
+    assert r.returncode == 0, r.stderr
+    r = _run([str(CLANG), *COMMON, "-fsanitize=address,undefined", "-c", str(SAN_DIR / "null_driver.cpp"),
+              "-o", str(drv_o)])
+    assert r.returncode == 0, r.stderr
+    # linked without the HIP runtime: every HIP symbol resolves to the null device
+    r = _run([str(CLANG), "-fsanitize=address,undefined", str(drv_o), str(abi_asan_object), str(dev_o),
+              *map(str, KERNELS), "-o", str(exe)])
+    assert r.returncode == 0, r.stderr
+    r = _run([str(exe)], env=ENV, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "null-device driver: 0 failures" in r.stdout
     assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr
