@@ -339,8 +339,10 @@ def main():
     mlups = case.nodes / (ms * 1e-3) / 1e6
     bytes_per_node = 68  # per pass: 8 FP32 loads + 8 FP32 stores + the FP32 porosity load
     rl = roofline(case.nodes, bytes_per_node, launch_ms)
-    kname = {3: ("void mrt::k_step3<float", "k_step3<float, 64, 16>: three collide-stream cycles per launch"),
-             2: ("void mrt::k_step2<float", "k_step2<float, 64, 16>: two collide-stream cycles per launch"),
+    tb = solver.time_blocking()
+    shape = f"64 x {tb['rows']} tiles, {tb['threads']} threads"
+    kname = {3: ("void mrt::k_step3<float", f"k_step3<float> ({shape}): three collide-stream cycles per launch"),
+             2: ("void mrt::k_step2<float", f"k_step2<float> ({shape}): two collide-stream cycles per launch"),
              1: ("void mrt::k_step<float, false, 0", "k_step<float>: one collide-stream cycle per launch")}[cycles]
     traffic = profiling.traffic_bytes(COUNTERS, kname[0]) if n == 8192 else None
     rl["traffic"] = None if traffic is None else round(traffic / 1e9, 4)

@@ -322,8 +322,12 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * mode a batch has no tuned schedule for; EINVAL for another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
 
-/* Current cycles per pass and the two-cycle kernel's workgroup size, tile
- * rows and grid size (host outputs, each may be NULL). */
+/* Current cycles per pass, and the workgroup size, tile rows (tiles are 64
+ * nodes wide) and grid size of the multi-cycle pass it runs: the three-cycle
+ * kernel in mode 3 (single isothermal domains of 2^23 nodes or more: 768
+ * threads, 28 rows; other domains and batches: 512 threads, 16 rows), else
+ * the two-cycle kernel's
+ * (host outputs, each may be NULL). */
 int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threads, int32_t *rows,
                       int32_t *grid);
 

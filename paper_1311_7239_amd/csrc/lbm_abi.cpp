@@ -490,10 +490,10 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         } else if (c->tblock == 3) {
             Domain &D = c->dom[0];
             d = dom_for(D, p);
-            step3_tiles(D.desc.nx, D.desc.ny, &tx, &ty);
+            step3_tiles(D.dom, false, &tx, &ty);
             kp.func = (void *)step3_kernel_fn(D.dom, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32, false);
             kp.gridDim = dim3((unsigned)(tx * ty));
-            kp.blockDim = dim3((unsigned)step3_threads());
+            kp.blockDim = dim3((unsigned)step3_single_threads(D.dom, false));
             kp.kernelParams = args_s3;
         } else if (c->tblock == 2) {
             Domain &D = c->dom[0];
@@ -1002,17 +1002,26 @@ int lbm_schedule(const lbm_ctx *c, int32_t *tile_w, int32_t *vec, int32_t *rows,
 int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threads, int32_t *rows,
                       int32_t *grid) {
     if (int rc = check_handle(c)) return rc;
-    if (cycles_per_pass) *cycles_per_pass = c->tblock;
-    if (threads) *threads = c->tb_threads;
-    if (rows) *rows = c->tb_rows;
-    if (grid) {
-        if (c->batch) *grid = c->tblock == 3 ? c->grid3 : c->grid2;
-        else {
-            int tx, ty;
-            step2_tiles(c->dom[0].desc.nx, c->dom[0].desc.ny, c->tb_rows, &tx, &ty);
-            *grid = tx * ty;
-        }
+    int32_t nt = c->tb_threads, nr = c->tb_rows, ng = 0;
+    if (c->batch) {
+        if (c->tblock == 3) nt = step3_threads();
+        ng = c->tblock == 3 ? c->grid3 : c->grid2;
+    } else if (c->tblock == 3) {
+        const Dom &d = c->dom[0].dom;
+        int tx, ty;
+        step3_tiles(d, false, &tx, &ty);
+        nt = step3_single_threads(d, false);
+        nr = step3_single_rows(d, false);
+        ng = tx * ty;
+    } else {
+        int tx, ty;
+        step2_tiles(c->dom[0].desc.nx, c->dom[0].desc.ny, c->tb_rows, &tx, &ty);
+        ng = tx * ty;
     }
+    if (cycles_per_pass) *cycles_per_pass = c->tblock;
+    if (threads) *threads = nt;
+    if (rows) *rows = nr;
+    if (grid) *grid = ng;
     return LBM_OK;
 }
 

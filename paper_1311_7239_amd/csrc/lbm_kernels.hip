@@ -948,27 +948,56 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_
     }
 }
 
+// Batched passes and single domains below 2^23 nodes: 64 x 16 tiles, 512 threads.
 constexpr int STEP3_TW = 64, STEP3_TH = 16, STEP3_NT = 512;
+// Single isothermal domains of 2^23 nodes or more: 64 x 28 tiles with 768
+// threads (12 waves: 8 with three frame rows, 4 with two plus the ring
+// columns), two workgroups and 24 waves per CU. The ring recomputation falls
+// from 3572 collisions per 3072 updates (1.163) to 5948 per 5376 (1.106).
+// Measured (log-normal channel, FP32, ms per step): 8192^2 0.326 against
+// 0.342, 4096^2 0.0830 against 0.0873, but 2048^2 0.0246 against 0.0236 and
+// 1024^2 0.0080 against 0.0077, where fewer, larger workgroups lose more to
+// the tail of the grid than they save. At 8192^2, 64 x 18 tiles with 512
+// threads took 1.01 ms per launch and 64 x 24 with 640 threads 1.41 ms
+// (ten waves leave room for one workgroup per CU), against 0.967 here.
+// Thermal domains (13 LDS planes) and the recording pass (86 VGPRs) keep
+// 64 x 16: at 768 threads either would leave one workgroup per CU.
+constexpr int STEP3_TH_TALL = 28, STEP3_NT_TALL = 768;
 
-void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y) {
-    *tiles_x = (nx + STEP3_TW - 1) / STEP3_TW;
-    *tiles_y = (ny + STEP3_TH - 1) / STEP3_TH;
+static bool step3_tall(const Dom &d, bool rec) {
+    return !d.thermal && !rec && (int64_t)d.nx * d.ny >= ((int64_t)1 << 23);
 }
 
+void step3_tiles(const Dom &d, bool rec, int *tiles_x, int *tiles_y) {
+    const int th = step3_tall(d, rec) ? STEP3_TH_TALL : STEP3_TH;
+    *tiles_x = (d.nx + STEP3_TW - 1) / STEP3_TW;
+    *tiles_y = (d.ny + th - 1) / th;
+}
+
+int step3_single_threads(const Dom &d, bool rec) { return step3_tall(d, rec) ? STEP3_NT_TALL : STEP3_NT; }
+
+int step3_single_rows(const Dom &d, bool rec) { return step3_tall(d, rec) ? STEP3_TH_TALL : STEP3_TH; }
+
 template <int MK, bool TH>
-static const void *step3_fn_t(int storage, bool rec) {
-    if (rec)
-        return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, true, MK, TH> : nullptr;
+static const void *step3_fn_t(int storage, bool rec, bool tall) {
+    if (rec) return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, true, MK, TH> : nullptr;
+    if constexpr (!TH) {
+        if (tall)
+            return storage == ST_F32
+                       ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH_TALL, STEP3_NT_TALL, false, MK, false>
+                       : (const void *)&k_step3<_Float16, STEP3_TW, STEP3_TH_TALL, STEP3_NT_TALL, false, MK, false>;
+    }
     return storage == ST_F32 ? (const void *)&k_step3<float, STEP3_TW, STEP3_TH, STEP3_NT, false, MK, TH>
                              : (const void *)&k_step3<_Float16, STEP3_TW, STEP3_TH, STEP3_NT, false, MK, TH>;
 }
 
 template <bool TH>
 static const void *step3_fn_th(const Dom &d, int storage, bool rec) {
+    const bool tall = step3_tall(d, rec);
     switch (medium_kind(d)) {
-    case MK_ERGUN: return step3_fn_t<MK_ERGUN, TH>(storage, rec);
-    case MK_UNIFORM: return step3_fn_t<MK_UNIFORM, TH>(storage, rec);
-    default: return step3_fn_t<MK_ANY, TH>(storage, rec);
+    case MK_ERGUN: return step3_fn_t<MK_ERGUN, TH>(storage, rec, tall);
+    case MK_UNIFORM: return step3_fn_t<MK_UNIFORM, TH>(storage, rec, tall);
+    default: return step3_fn_t<MK_ANY, TH>(storage, rec, tall);
     }
 }
 
@@ -1003,11 +1032,11 @@ hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, fl
     const void *fn = step3_kernel_fn(d, storage, rec);
     if (!fn || (rec && (!d.urec || !urec2))) return hipErrorInvalidValue;
     int tx, ty;
-    step3_tiles(d.nx, d.ny, &tx, &ty);
+    step3_tiles(d, rec, &tx, &ty);
     Dom dd = d;
     int swz = swizzle;
     void *args[5] = {&dd, &tx, &swz, &urec1, &urec2};
-    return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3(STEP3_NT), args, 0, st);
+    return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3((unsigned)step3_single_threads(d, rec)), args, 0, st);
 }
 
 template <typename S, bool REC, int MK, bool THERMAL>

@@ -42,11 +42,15 @@ hipError_t launch_step2(const Dom &d, int storage, int swizzle, int threads, int
 bool step2_shape_supported(int threads, int rows);
 void step2_tiles(int nx, int ny, int rows, int *tiles_x, int *tiles_y);
 const void *step2_kernel_fn(const Dom &d, int storage, int threads, int rows, bool rec);
-// Three collide-stream cycles in one HBM pass (64 x 16 tiles, 512 threads;
-// kernel arguments (Dom, int tiles_x, int swizzle, float *urec1, float *urec2)).
+// Three collide-stream cycles in one HBM pass (64-wide tiles; step3_tiles and
+// step3_single_threads give the grid and the workgroup size; kernel arguments
+// (Dom, int tiles_x, int swizzle, float *urec1, float *urec2)).
 // With urec1/urec2 (FP32 only) the pass records at t (d.urec), t + 1, t + 2.
 hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, float *urec2, hipStream_t st);
-void step3_tiles(int nx, int ny, int *tiles_x, int *tiles_y);
+// grid and workgroup size of launch_step3 for a domain, with or without recording
+void step3_tiles(const Dom &d, bool rec, int *tiles_x, int *tiles_y);
+int step3_single_threads(const Dom &d, bool rec);
+int step3_single_rows(const Dom &d, bool rec);
 const void *step3_kernel_fn(const Dom &d, int storage, bool rec);
 // batched three-cycle pass over a table of 64 x 16 tiles (isothermal domains);
 // uniform: every domain has a uniform medium and one s_nu (medium_kind MK_UNIFORM),

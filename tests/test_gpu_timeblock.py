@@ -61,6 +61,47 @@ def test_three_cycles_per_pass_is_bitwise_equal(name, case, storage, graph):
         assert torch.equal(a, b), (name, chunk)
 
 
+def tall_cases():
+    # 2900 x 2935 = 8.5e6 nodes (at least 2^23: 64 x 28 tiles of 768 threads), ragged
+    # in x (45 tiles + 20 columns) and in y (104 tiles + 23 rows)
+    c = I.lognormal_channel(n=2935, seed=9, ell=40.0, K_ref=400.0)
+    c.nx = 2900
+    c.phi = np.ascontiguousarray(c.phi[:, :2900])
+    out = [("lognormal_2900x2935", c)]
+    c = I.lid_cavity(n=2935, heterogeneous=True, ell=30.0, seed=6)
+    c.nx = 2900
+    c.phi = np.ascontiguousarray(c.phi[:, :2900])
+    out.append(("cavity_2900x2935_grf", c))
+    return out
+
+
+@pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
+@pytest.mark.parametrize("name,case", tall_cases(), ids=[n for n, _ in tall_cases()])
+@pytest.mark.parametrize("graph", [0, 9])
+def test_tall_three_cycle_tiles_are_bitwise_equal(name, case, storage, graph):
+    """The 64 x 28 three-cycle tiles of large single domains equal one cycle per pass
+    bit for bit, ragged edges included."""
+    ref = lbm.solver_for_case(case, storage=storage)
+    ref.set_time_blocking(1)
+    tb = lbm.solver_for_case(case, storage=storage)
+    shape = tb.time_blocking()
+    assert (shape["cycles_per_pass"], shape["rows"], shape["threads"]) == (3, 28, 768)
+    assert shape["grid"] == 46 * 105
+    tb.set_graph_steps(graph)
+    df0 = I.random_deviation_state(case.ny, case.nx, 1e-3, seed=6)
+    for s in (ref, tb):
+        s.set_populations(torch.from_numpy(df0).cuda())
+    del df0
+    for chunk in (1, 7, 5):
+        ref.step(chunk)
+        tb.step(chunk)
+        a, _ = ref.populations()
+        b, _ = tb.populations()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), (name, chunk)
+        del a, b
+
+
 @pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
 @pytest.mark.parametrize("name,case", cases(), ids=[n for n, _ in cases()])
 @pytest.mark.parametrize("graph,shape", [(0, (512, 16)), (8, (256, 16)), (0, (256, 8)), (8, (512, 8))])
