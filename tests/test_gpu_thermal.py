@@ -56,8 +56,11 @@ def test_convection_1024_matches_oracle_samples():
     umax = float([l for l in path.read_text().splitlines() if l.startswith("# max_abs_u")][0].split()[-1])
     x, y = rows[:, 0].astype(int), rows[:, 1].astype(int)
     err = max(np.abs(u[0, y, x] - rows[:, 2]).max(), np.abs(u[1, y, x] - rows[:, 3]).max()) / umax
+    errT = np.abs(T[y, x] - rows[:, 5]).max()
+    print(f"convection 1024^2 FP32, 2000 steps, {len(x)} sampled nodes: max rel velocity error {err:.2e}, "
+          f"max temperature error {errT:.2e}")
     assert err <= 1e-5, err
-    assert np.abs(T[y, x] - rows[:, 5]).max() < 1e-4
+    assert errT < 1e-4
 
 
 def test_nusselt_on_200_grid_matches_table1():
