@@ -1132,12 +1132,30 @@ __device__ __forceinline__ void read_state(const Dom &d, int src, int x, int y, 
     }
 }
 
+// f(t) of a node one link or more from every edge of a gather-layout state
+// below 4 GiB: pulled at constant per-link offsets through a buffer resource
+// (no wrap, wall or extrapolation can reach it).
+template <typename S>
+__device__ __forceinline__ void gather_inner(const Dom &d, const BufRes &r, int x, int y, float f[8]) {
+    constexpr int ES = (int)sizeof(S);
+    const uint32_t vo = (uint32_t)(((y - 1) * d.pitch + (x - 1)) * ES);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        f[i] = BufIO<S>::ld(r, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
+}
+
+// whether an output kernel may take gather_inner for a state: the pull layout of
+// an isothermal domain whose population buffer is below 4 GiB
+template <typename S, bool THERMAL>
+__device__ __forceinline__ bool inner_gather_ok(const Dom &d, int src) {
+    return !THERMAL && src == SRC_GATHER && (uint64_t)8 * (uint64_t)d.plane * sizeof(S) < ((uint64_t)1 << 32);
+}
+
 // velocity of node (x, y) at the state's time, as the step computes it
 template <bool THERMAL>
-__device__ __forceinline__ void state_velocity(const Dom &d, int64_t o, const float f[8],
-                                               const float g[5], float &ux, float &uy,
-                                               float &m1, float &dT) {
-    const Cell c = load_cell(d, o);
+__device__ __forceinline__ void state_velocity_c(const Dom &d, const Cell &c, const float f[8],
+                                                 const float g[5], float &ux, float &uy,
+                                                 float &m1, float &dT) {
     float ayh = d.ayh;
     dT = 0.0f;
     if (THERMAL) {
@@ -1147,22 +1165,37 @@ __device__ __forceinline__ void state_velocity(const Dom &d, int64_t o, const fl
     node_velocity_h(f, c, c.phi * d.axh, c.phi * ayh, ux, uy, m1);
 }
 
+template <bool THERMAL>
+__device__ __forceinline__ void state_velocity(const Dom &d, int64_t o, const float f[8],
+                                               const float g[5], float &ux, float &uy,
+                                               float &m1, float &dT) {
+    state_velocity_c<THERMAL>(d, load_cell(d, o), f, g, ux, uy, m1, dT);
+}
+
+// A workgroup covers BLOCK consecutive nodes of row y; blocks one node or more
+// from every edge gather through gather_inner.
 template <typename S, bool THERMAL>
 __global__ __launch_bounds__(BLOCK) void k_macro(Dom d, int src, float Pi0, float *p, float *ux,
                                                  float *uy, float *T) {
-    const int x = blockIdx.x * BLOCK + threadIdx.x, y = blockIdx.y;
-    if (x >= d.nx) return;
+    const int xb = blockIdx.x * BLOCK, x = xb + threadIdx.x, y = blockIdx.y;
+    const bool ok = inner_gather_ok<S, THERMAL>(d, src);
+    const BufRes rin = buf_res(d.fin, ok ? (uint32_t)(8 * d.plane * (int64_t)sizeof(S)) : 0u);
     float f[8], g[5];
-    read_state<S, THERMAL>(d, src, x, y, f, g);
+    if (ok && y >= 1 && y <= d.ny - 2 && xb >= 1 && xb + BLOCK <= d.nx - 1) {
+        gather_inner<S>(d, rin, x, y, f);
+    } else {
+        if (x >= d.nx) return;
+        read_state<S, THERMAL>(d, src, x, y, f, g);
+    }
     const int64_t o = (int64_t)y * d.pitch + x;
+    const Cell c = load_cell(d, o);
     float u, v, m1, dT;
-    state_velocity<THERMAL>(d, o, f, g, u, v, m1, dT);
+    state_velocity_c<THERMAL>(d, c, f, g, u, v, m1, dT);
     const int64_t q = (int64_t)y * d.nx + x;
     if (ux) ux[q] = u;
     if (uy) uy[q] = v;
     if (p) {
         // Eq. (20): phi p = (3/5)(m1 - (2/3)|u|^2/phi), m1 = (5/3) Pi0 + dm1
-        const Cell c = load_cell(d, o);
         const float Pi = Pi0 + (mulc(m1, MRT_C3_5) - mulc((u * u + v * v) * c.inv_phi, MRT_C2_5));
         p[q] = Pi * c.inv_phi;
     }
