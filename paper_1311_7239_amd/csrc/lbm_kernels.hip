@@ -926,7 +926,7 @@ __global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float
 // MK_BRANCHED for any medium, MK_UNIFORM when every domain is uniform); ONE as
 // for the two-cycle pass.
 template <typename S, int TW, int TH, int NT, int MK, bool ONE>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_step3_batch(const Dom *__restrict__ doms, const int4 *__restrict__ tiles,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(ONE ? 6 : 4))) void k_step3_batch(const Dom *__restrict__ doms, const int4 *__restrict__ tiles,
                                                     int ntiles, int parity) {
     __shared__ float lds[8 * (TH + 4) * (TW + 4)];
     if (ONE) {
