@@ -478,3 +478,43 @@ def test_uniform_flow_decays_at_darcy_rate():
     ux, _, _, _ = oracle.macroscopic(p, phi, K, F, f)
     d = 0.5 * 0.1 / 20.0
     np.testing.assert_allclose(ux, ux0 * ((1 - d / 2) / (1 + d / 2)) ** 40, rtol=1e-12)
+
+
+def test_periodic_domain_is_translation_equivariant():
+    """On a domain periodic in x and y the scheme has no preferred origin: stepping a
+    state and its medium shifted by (dx, dy) gives the shifted result, exactly (every node
+    runs the same arithmetic on the same numbers)."""
+    nx, ny, dx, dy = 9, 7, 4, 3
+    p = oracle.make_params(nx, ny, bc_x=oracle.PERIODIC, bc_y=oracle.PERIODIC, nu=0.07, ax=2e-4,
+                           ay=-1e-4, nthreads=1)
+    rng = np.random.default_rng(11)
+    phi = rng.uniform(0.3, 0.9, (ny, nx)); K = rng.uniform(5.0, 50.0, (ny, nx))
+    F = rng.uniform(0.1, 0.5, (ny, nx))
+    f = oracle.rest_state(p, 0.6) + rng.normal(0.0, 1e-3, (ny, nx, 8))
+    roll = lambda a: np.roll(np.roll(a, dy, axis=0), dx, axis=1)
+    a, b = f.copy(), roll(f)
+    oracle.run(p, phi, K, F, a, nsteps=6)
+    oracle.run(p, roll(phi), roll(K), roll(F), b, nsteps=6)
+    np.testing.assert_array_equal(roll(a), b)
+
+
+def test_homogeneous_modes_relax_at_their_rates():
+    """Periodic, spatially uniform state at rest without drag or force, with the energy,
+    energy-flux and stress moments off equilibrium: streaming is the identity and u = 0,
+    so Eq. (14) multiplies each deviation from m^eq by (1 - s) per step with the rates of
+    Sec. 3: s_2 = 1.1 for e, s_4 = s_6 = 1.2 for q_x, q_y, and s_7 = s_8 = 1/tau for the
+    stresses (tau = 1/2 + 3 nu, Eq. 21); mass and momentum stay where they are."""
+    nu = 0.1
+    p = oracle.make_params(3, 3, bc_x=oracle.PERIODIC, bc_y=oracle.PERIODIC, nu=nu, nthreads=1)
+    phi = np.full((3, 3), 0.5); K = np.full((3, 3), np.inf); F = np.zeros((3, 3))
+    M, _ = oracle.flow_matrices()
+    dm = np.array([0.0, 0.01, 0.0, 0.02, 0.0, -0.015, 0.005, -0.008])
+    f0 = oracle.rest_state(p, 0.5)
+    m_rest = M @ f0[0, 0]
+    f = f0 + np.linalg.solve(M, dm)
+    s = np.array([1.0, 1.1, 1.0, 1.2, 1.0, 1.2, 1.0 / (0.5 + 3 * nu), 1.0 / (0.5 + 3 * nu)])
+    for n in (1, 4):
+        oracle.run(p, phi, K, F, f, nsteps=n if n == 1 else n - 1)
+        got = np.einsum("ai,yxi->yxa", M, f) - m_rest
+        want = np.where(s == 1.0, dm, dm * (1.0 - s) ** n)
+        np.testing.assert_allclose(got, np.broadcast_to(want, got.shape), rtol=1e-11, atol=1e-15)
