@@ -40,7 +40,8 @@ def table1_cases(pairs: Iterable[Tuple[float, float]] = TABLE1_PAIRS,
 
 
 # Resolution and Mach-number variants of the Da = 1e-6 row at Ra = 1e8 and 1e9:
-# (label, grid, Ma); the first is the paper's grid at the Ma this build reads.
+# (label, grid, Ma); the first is the paper's grid at Ma = 0.1, the value taken where Sec. 3.4
+# leaves the Mach number open.
 DA6_VARIANTS = [("250 Ma0.1", 250, 0.1), ("500 Ma0.1", 500, 0.1), ("250 Ma0.05", 250, 0.05),
                 ("250 Ma0.2", 250, 0.2)]
 

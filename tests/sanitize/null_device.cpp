@@ -13,7 +13,7 @@
 // real reduction over such a state returns. Nothing else of the method is
 // computed here.
 //
-// Test hooks (extern "C", declared by the driver):
+// Test hooks (extern "C", declared by tests/sanitize/null_driver.cpp):
 //   null_device_launches(sub)      launches (direct and graph replays) of
 //                                  kernels whose name contains sub
 //   null_device_fail_after(n)      the n-th next fallible call (launch, copy,
