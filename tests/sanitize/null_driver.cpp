@@ -13,7 +13,8 @@
 //   * a failed call leaves the time unchanged;
 //   * a second lbm_destroy, calls on a destroyed handle and on a handle that
 //     was never created are refused without touching memory;
-//   * the step is launched (directly and from a replayed graph).
+//   * the step is launched (directly and from a replayed graph);
+//   * the three-cycle tile shape switches at 2^23 nodes (isothermal only).
 // Built and run by tests/test_sanitize_cpu.py; exits 0 when every call
 // returns what the header promises.
 #include <cmath>
@@ -219,7 +220,55 @@ static void batch() {
     expect(lbm_destroy(c) == LBM_EINVAL, "second destroy of a batch");
 }
 
+// The three-cycle tile shape: 64 x 28 tiles of 768 threads from 2^23 nodes on
+// isothermal single domains, 64 x 16 tiles of 512 threads below and for thermal ones.
+static void tile_shapes() {
+    struct Shape { int nx, ny, thermal, cycles, threads, rows, grid; };
+    const Shape shapes[] = {
+        {2896, 2896, 0, 3, 512, 16, 46 * 181},    // 8,386,816 nodes: below 2^23
+        {2896, 2897, 0, 3, 768, 28, 46 * 104},    // 8,389,712 nodes: tall tiles
+        {2896, 2897, 1, 3, 512, 16, 46 * 182},    // thermal: 64 x 16
+    };
+    for (const Shape &sh : shapes) {
+        lbm_desc d = channel(sh.nx, sh.ny);
+        d.phi0 = 1.0; d.kappa0 = 0.0;
+        if (sh.thermal) {
+            d.bc_x = LBM_WALLS;
+            d.thermal.enabled = 1; d.thermal.tau_T = 0.8; d.thermal.Th = 2.0; d.thermal.Tc = 1.0;
+            d.thermal.T0 = 1.5; d.thermal.g_beta = 1e-6;
+        }
+        size_t bytes = 0;
+        expect(lbm_workspace_size(&d, 0, &bytes) == LBM_OK, "workspace size (tile shapes)");
+        Workspace ws(bytes);
+        lbm_ctx *c = nullptr;
+        expect(lbm_create(&d, nullptr, nullptr, ws.p, ws.bytes, nullptr, &c) == LBM_OK, "create (tile shapes)");
+        if (!c) continue;
+        int32_t cyc = 0, thr = 0, rows = 0, grid = 0;
+        expect(lbm_time_blocking(c, &cyc, &thr, &rows, &grid) == LBM_OK, "time blocking query");
+        expect(cyc == sh.cycles && thr == sh.threads && rows == sh.rows && grid == sh.grid,
+               "three-cycle tile shape at the 2^23-node switch");
+        const long before = null_device_launches("k_step3");
+        expect(lbm_step(c, 7) == LBM_OK, "step (tile shapes)");
+        expect(null_device_launches("k_step3") > before, "three-cycle kernel launched");
+        lbm_destroy(c);
+    }
+    // a small domain switched to three cycles keeps 64 x 16 tiles
+    lbm_desc d = channel(200, 130);
+    size_t bytes = 0;
+    lbm_workspace_size(&d, 0, &bytes);
+    Workspace ws(bytes);
+    lbm_ctx *c = nullptr;
+    expect(lbm_create(&d, nullptr, nullptr, ws.p, ws.bytes, nullptr, &c) == LBM_OK, "create (small)");
+    if (!c) return;
+    int32_t cyc = 0, thr = 0, rows = 0, grid = 0;
+    expect(lbm_set_time_blocking(c, 3) == LBM_OK, "three cycles on a small domain");
+    expect(lbm_time_blocking(c, &cyc, &thr, &rows, &grid) == LBM_OK && cyc == 3 && thr == 512 && rows == 16 &&
+               grid == 4 * 9, "small domain keeps 64 x 16 tiles");
+    lbm_destroy(c);
+}
+
 int main() {
+    tile_shapes();
     single_domain();
     recording();
     thermal_snapshot_into_isothermal();
