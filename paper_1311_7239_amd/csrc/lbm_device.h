@@ -308,23 +308,30 @@ __device__ __forceinline__ void collide_h(float f[8], const Dom &d, const Cell &
 
     // f+ = M^T diag(1/8, 1/8, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m+; the 1/6 of the
     // momentum rows goes through the split constant (their rounding would bias
-    // the momentum every step); the 1/12 of the energy-flux rows cancels from
-    // mass and momentum and is a plain multiply
+    // the momentum every step). The 1/12 of the energy-flux rows (which cancel
+    // from mass and momentum) and the 1/4 of the stress rows are folded into the
+    // fused multiply-adds that form the terms shared by two populations (with
+    // X = j+_x/6 and Q_x = q+_x/12: X - 2 Q_x, X + Q_x, (A - B) +- m+_7/4,
+    // (Y + Q_y) +- m+_8/4). Every population itself ends in an add, so no
+    // kernel variant can merge its last rounding with the conversion to a
+    // binary16 store (a mixed-precision multiply-add rounds once where the
+    // separate instructions round twice).
     const float A = 0.125f * m1, B = 0.125f * m2p;
-    const float X = mulc(m3p, MRT_C1_6), Qx = m4p * 0x1.555556p-4f;
-    const float Y = mulc(m5p, MRT_C1_6), Qy = m6p * 0x1.555556p-4f;
-    const float P = 0.25f * m7p, R = 0.25f * m8p;
+    const float X = mulc(m3p, MRT_C1_6);
+    const float Y = mulc(m5p, MRT_C1_6);
     const float amb = A - B, apb = A + B;
-    const float xa = fmaf(-2.0f, Qx, X), ya = fmaf(-2.0f, Qy, Y);
-    const float xd = X + Qx, yd = Y + Qy;
-    f[0] = (amb + xa) + P;
-    f[2] = (amb - xa) + P;
-    f[1] = (amb + ya) - P;
-    f[3] = (amb - ya) - P;
-    f[4] = (apb + xd) + (yd + R);
-    f[5] = (apb - xd) + (yd - R);
-    f[6] = (apb - xd) - (yd - R);
-    f[7] = (apb + xd) - (yd + R);
+    const float xa = fmaf(-0x1.555556p-3f, m4p, X), ya = fmaf(-0x1.555556p-3f, m6p, Y);   // X - 2 Q
+    const float xd = fmaf(0x1.555556p-4f, m4p, X), yd = fmaf(0x1.555556p-4f, m6p, Y);     // X + Q
+    const float pa = fmaf(0.25f, m7p, amb), pm = fmaf(-0.25f, m7p, amb);   // A - B +- m+_7/4
+    const float ypr = fmaf(0.25f, m8p, yd), ymr = fmaf(-0.25f, m8p, yd);   // Y + Q_y +- m+_8/4
+    f[0] = pa + xa;
+    f[2] = pa - xa;
+    f[1] = pm + ya;
+    f[3] = pm - ya;
+    f[4] = (apb + xd) + ypr;
+    f[5] = (apb - xd) + ymr;
+    f[6] = (apb - xd) - ymr;
+    f[7] = (apb + xd) - ypr;
 }
 
 // The same with the full force pax/pay = phi * a.
