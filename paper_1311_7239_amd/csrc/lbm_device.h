@@ -279,16 +279,19 @@ __device__ __forceinline__ void collide_h(float f[8], const Dom &d, const Cell &
     const float Fx = fmaf(-dragh, ux, paxh);   // F_x / 2
     const float Fy = fmaf(-dragh, uy, payh);   // F_y / 2
 
-    // relaxation toward m^eq (Eqs. 11-12) with forcing (Eq. 16)
+    // relaxation toward m^eq (Eqs. 11-12) with forcing (Eq. 16); every 1/phi term
+    // is formed from u/phi, so the products uy uy/phi, uy Fy/phi, uy Fx/phi serve
+    // two terms each
     const float ip = c.inv_phi;
-    const float uyy = uy * uy;
-    const float u2 = fmaf(ux, ux, uyy);
-    const float uF = fmaf(ux, Fx, uy * Fy);    // u . F / 2
+    const float uxi = ux * ip, uyi = uy * ip;  // u / phi
+    const float yyi = uy * uyi, yFyi = uyi * Fy, yFxi = uyi * Fx;
+    const float u2i = fmaf(ux, uxi, yyi);      // |u|^2 / phi
+    const float uFi = fmaf(uxi, Fx, yFyi);     // u . F / (2 phi)
     // e - e^eq = dm2 + (3/5) dm1 - (2/5)|u|^2/phi  (Pi from Eq. 20, alpha2 = -1, gamma2 = 0);
     // e enters neither m1 nor j of f+, so single-rounded constants suffice here
-    const float ne = fmaf(-0.4f, u2 * ip, fmaf(0.6f, m1, m2));
+    const float ne = fmaf(-0.4f, u2i, fmaf(0.6f, m1, m2));
     // S_2 = (4/5) u . F / phi: (1 - s_e/2) 4/5 S_2 = h_e16 (u . F/2) / phi
-    const float m2p = fmaf(d.h_e16, uF * ip, fmaf(-d.s_e, ne, m2));
+    const float m2p = fmaf(d.h_e16, uFi, fmaf(-d.s_e, ne, m2));
     // s1 = s3 = s5 = 1: m1+ = m1, j+ = rho0 u + F/2
     const float m3p = ux + Fx;
     const float m5p = uy + Fy;
@@ -297,10 +300,10 @@ __device__ __forceinline__ void collide_h(float f[8], const Dom &d, const Cell &
     const float m6p = fmaf(-d.h_q2, Fy, fmaf(-d.s_q, m6 + uy, m6));
     // p_xx^eq = (ux^2 - uy^2)/phi, p_xy^eq = ux uy / phi (gamma1 = gamma3 = 2/3);
     // S_7 = 2 (ux Fx - uy Fy)/phi and S_8 = (ux Fy + uy Fx)/phi, in half forces
-    const float pxx = fmaf(ux, ux, -uyy) * ip;
-    const float pxy = (ux * uy) * ip;
-    const float Sxx4 = fmaf(ux, Fx, -(uy * Fy)) * ip;   // S_7 / 4
-    const float Sxy2 = fmaf(ux, Fy, uy * Fx) * ip;      // S_8 / 2
+    const float pxx = fmaf(ux, uxi, -yyi);
+    const float pxy = ux * uyi;
+    const float Sxx4 = fmaf(uxi, Fx, -yFyi);   // S_7 / 4
+    const float Sxy2 = fmaf(uxi, Fy, yFxi);    // S_8 / 2
     n7 = m7 - pxx;
     n8 = m8 - pxy;
     const float m7p = fmaf(c.h_nu4, Sxx4, fmaf(-c.s_nu, n7, m7));
@@ -316,10 +319,10 @@ __device__ __forceinline__ void collide_h(float f[8], const Dom &d, const Cell &
     // kernel variant can merge its last rounding with the conversion to a
     // binary16 store (a mixed-precision multiply-add rounds once where the
     // separate instructions round twice).
-    const float A = 0.125f * m1, B = 0.125f * m2p;
+    const float B = 0.125f * m2p;
     const float X = mulc(m3p, MRT_C1_6);
     const float Y = mulc(m5p, MRT_C1_6);
-    const float amb = A - B, apb = A + B;
+    const float amb = fmaf(0.125f, m1, -B), apb = fmaf(0.125f, m1, B);   // m1/8 -+ m2+/8
     const float xa = fmaf(-0x1.555556p-3f, m4p, X), ya = fmaf(-0x1.555556p-3f, m6p, Y);   // X - 2 Q
     const float xd = fmaf(0x1.555556p-4f, m4p, X), yd = fmaf(0x1.555556p-4f, m6p, Y);     // X + Q
     const float pa = fmaf(0.25f, m7p, amb), pm = fmaf(-0.25f, m7p, amb);   // A - B +- m+_7/4
