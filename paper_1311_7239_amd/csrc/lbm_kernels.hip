@@ -847,7 +847,6 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
         } else {
             c = med.cell(d, med.load((uint32_t)(o * 4)));
         }
-        if (REC) pend.flush(d, rr1);
         lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fb[k]);
         float g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (THERMAL) lds_gather_thermal<AW, AH>(d, ldsg, interior, gx, gy, bx + 1, by + 1, g);
@@ -857,11 +856,14 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
 #pragma unroll
             for (int j = 0; j < 5; ++j) gb[k][THERMAL ? j : 0] = g[j];
         }
-        if (REC && bx >= 1 && bx <= TW && by >= 1 && by <= TH && x0 - 1 + bx < d.nx && y0 - 1 + by < d.ny)
-            pend.hold((uint32_t)(o * 4), ux, uy, n7, n8, dT);
+        // phase B loads nothing from HBM on tile rows, so its records are stored
+        // at once rather than held behind the next node's loads
+        if (REC && bx >= 1 && bx <= TW && by >= 1 && by <= TH && x0 - 1 + bx < d.nx && y0 - 1 + by < d.ny) {
+            record_node(d, rr1, (uint32_t)(o * 4), ux, uy, n7, n8);
+            if (THERMAL) BufIO<float>::st_nt(rr1, (uint32_t)(o * 4), (uint32_t)(4 * d.plane * 4), dT);
+        }
         slot[k] = by * BW + bx;
     }
-    if (REC) pend.flush(d, rr1);
     lds_barrier();
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
@@ -913,8 +915,11 @@ __device__ __forceinline__ void step3_tile(const Dom &d, int x0, int y0, float *
     }
 }
 
+// The isothermal recording pass is held to 80 VGPRs, six waves per SIMD: three
+// 512-thread workgroups per CU instead of two (a two-dword spill).
 template <typename S, int TW, int TH, int NT, bool REC, int MK, bool THERMAL>
-__global__ __launch_bounds__(NT) void k_step3(Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(REC && !THERMAL ? 6 : 1))) void k_step3(
+    Dom d, int tiles_x, int swz, float *urec1, float *urec2) {
     __shared__ float lds[8 * (TH + 4) * (TW + 4)];
     __shared__ float ldsg[THERMAL ? 5 * (TH + 4) * (TW + 4) : 1];
     int b = blockIdx.x;
