@@ -162,6 +162,13 @@ def extras(args):
     out["two_cycles_per_pass_f32"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4),
                                       "bytes_per_node_per_launch": 68, "kernel": "k_step2<float, 64, 16>",
                                       "roofline": roofline(case.nodes, 68, 2 * ms)}
+    s.set_time_blocking(3)
+    launch3 = per_launch_ms(s, 3)
+    ms = timed(s, args.steps, args.warmup)
+    out["three_cycles_per_pass_f32"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+                                        "bytes_per_node_per_launch": 68, "launch_ms": round(launch3, 4),
+                                        "kernel": "k_step3<float, 64, 28> (768 threads)",
+                                        "roofline": roofline(case.nodes, 68, launch3)}
     # the FP64 reductions (mass and steady residual: the state gathered, 36 B/node, and the
     # recorded u(t - 1), 8 B/node) and the macroscopic output (36 B/node read, p and u
     # written: 48 B/node) on that state
@@ -186,14 +193,17 @@ def extras(args):
                               "roofline": roofline(case.nodes, 48, mac_ms)}
     del s
     torch.cuda.empty_cache()
-    # FP16-deviation storage on the headline workload (two cycles per pass by default)
+    # FP16-deviation storage on the headline workload (its default cycles per pass)
     s = lbm.solver_for_case(case, storage=lbm.FP16_DEV)
     s.set_schedule(64, 2, 2, 1)
-    ms = timed(s, args.steps, args.warmup)
     tb = s.time_blocking()
+    # the launch timing first, as for the headline: it also brings the clocks up
+    launch16 = per_launch_ms(s, tb["cycles_per_pass"])
+    ms = timed(s, args.steps, args.warmup)
     out["fp16_lognormal_channel"] = {"mlups": round(case.nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4),
                                      "bytes_per_node_per_launch": 36, "time_blocking": tb,
-                                     "roofline": roofline(case.nodes, 36, ms * tb["cycles_per_pass"])}
+                                     "launch_ms": round(launch16, 4),
+                                     "roofline": roofline(case.nodes, 36, launch16)}
     del s
     torch.cuda.empty_cache()
     log("bench: 512^2 porous lid cavity")
@@ -267,10 +277,16 @@ def adjoint_ratio():
     f = lbm.solver_for_case(case)
     f.step(10)
     torch.cuda.synchronize()
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
     e[0].record()
     f.step(4000)
     e[1].record()
+    # the same forward in four cycles per pass, which the recomputation does not use
+    mode0 = f.time_blocking()["cycles_per_pass"]
+    f.set_time_blocking(4)
+    e[6].record()
+    f.step(4000)
+    e[7].record()
     e[4].record()
     s.step(4000)
     e[5].record()
@@ -284,10 +300,15 @@ def adjoint_ratio():
     torch.cuda.synchronize()
     fwd = e[0].elapsed_time(e[1])
     bwd = e[2].elapsed_time(e[3])
+    fwd4 = e[6].elapsed_time(e[7])
     return {"forward_ms": round(fwd, 2), "recorded_forward_ms": round(e[4].elapsed_time(e[5]), 2),
             "backward_ms": round(bwd, 2), "adjoint_forward_ratio": round(bwd / fwd, 3),
-            "note": "backward = recomputation from checkpoints + adjoint steps; the recorded forward "
-                    "also copies a checkpoint every 200 steps"}
+            "forward_cycles_per_pass": mode0,
+            "forward_four_cycles_ms": round(fwd4, 2), "adjoint_forward_ratio_four_cycles": round(bwd / fwd4, 3),
+            "note": "backward = recomputation from checkpoints (three cycles per pass, recording u) + "
+                    "adjoint steps (three per pass); forward_ms in the default mode at this size "
+                    f"({mode0} cycles per pass), forward_four_cycles_ms the same forward in four; the "
+                    "recorded forward also copies a checkpoint every 200 steps"}
 
 
 def main():
@@ -341,7 +362,8 @@ def main():
     rl = roofline(case.nodes, bytes_per_node, launch_ms)
     tb = solver.time_blocking()
     shape = f"64 x {tb['rows']} tiles, {tb['threads']} threads"
-    kname = {3: ("void mrt::k_step3<float", f"k_step3<float> ({shape}): three collide-stream cycles per launch"),
+    kname = {4: ("void mrt::k_step4<float", f"k_step4<float> ({shape}): four collide-stream cycles per launch"),
+             3: ("void mrt::k_step3<float", f"k_step3<float> ({shape}): three collide-stream cycles per launch"),
              2: ("void mrt::k_step2<float", f"k_step2<float> ({shape}): two collide-stream cycles per launch"),
              1: ("void mrt::k_step<float, false, 0", "k_step<float>: one collide-stream cycle per launch")}[cycles]
     traffic = profiling.traffic_bytes(COUNTERS, kname[0]) if n == 8192 else None

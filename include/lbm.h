@@ -300,33 +300,37 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
 /* Cycles per HBM pass of a context with bounce-back walls: 1,
  * 2 (temporal blocking: one launch gathers, collides on its tile plus a
  * one-node ring kept in LDS, then collides again, so each population crosses
- * HBM about once per two cycles) or 3 (a two-node ring, three collisions per
- * launch). Results are bitwise identical in every mode.
+ * HBM about once per two cycles), 3 (a two-node ring, three collisions per
+ * launch) or 4 (a three-node ring, four collisions per launch; single
+ * isothermal domains only). Results are bitwise identical in every mode.
  * Multi-cycle passes are skipped for t = 0; while recording for lbm_backward
  * no pass steps over a checkpoint time. Shorter passes fill in where fewer
  * cycles remain. The last pass of each lbm_step call also writes the
  * velocity of its last collision, u(t-1) of the final time t, into two FP32
  * planes of the workspace (8 bytes per node), which lbm_reduce's residual
  * reads. The recomputation inside
- * lbm_backward uses passes of the same length (recording u at every cycle)
- * and its adjoint sweep two or three steps per pass in modes 2 and 3 (two for
- * thermal runs). The D2Q5 field of a thermal domain rides in LDS beside the
- * populations. Default for single domains that allow it: 3 for isothermal
- * domains of at least 2^20 nodes and thermal domains of at least 2^22, 2 for
+ * lbm_backward uses passes of the same length (recording u at every cycle;
+ * three in mode 4) and its adjoint sweep two or three steps per pass in modes
+ * 2, 3 and 4 (two for thermal runs). The D2Q5 field of a thermal domain rides
+ * in LDS beside the populations. Default for single domains that allow it: 4
+ * for isothermal domains of at least 2^23 nodes, 3 for isothermal domains of
+ * at least 2^20 nodes and thermal domains of at least 2^22, 2 for
  * smaller ones (with 8-row tiles below 2^20 nodes and for thermal domains), 1
  * for the others; for batches, the
  * autotuner's choice among 1, 2 and 3 (a batch switched to 3 walks 64 x 16
  * tiles, which its two-cycle passes then use too; switching uploads that tile
  * table and synchronises the stream). ENOTSUP for on-node walls,
- * population or thermal buffers of 4 GiB or more, mode 3 on thermal batches, a
- * mode a batch has no tuned schedule for; EINVAL for another value. */
+ * population or thermal buffers of 4 GiB or more, mode 3 on thermal batches,
+ * mode 4 on batches and thermal domains, a mode a batch has no tuned schedule
+ * for; EINVAL for another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
 
 /* Current cycles per pass, and the workgroup size, tile rows (tiles are 64
- * nodes wide) and grid size of the multi-cycle pass it runs: the three-cycle
- * kernel in mode 3 (single isothermal domains of 2^23 nodes or more: 768
- * threads, 28 rows; other domains and batches: 512 threads, 16 rows), else
- * the two-cycle kernel's
+ * nodes wide) and grid size of the multi-cycle pass it runs: the four-cycle
+ * kernel in mode 4 (768 threads, 26 rows), the three-cycle kernel in mode 3
+ * (single isothermal domains of 2^23 nodes or more: 768 threads, 28 rows;
+ * other domains and batches: 512 threads, 16 rows), else the two-cycle
+ * kernel's
  * (host outputs, each may be NULL). */
 int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threads, int32_t *rows,
                       int32_t *grid);

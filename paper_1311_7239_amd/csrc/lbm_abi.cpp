@@ -487,6 +487,14 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
             kp.func = (void *)batch_kernel_fn(c->storage, c->batch_thermal, c->sched);
             kp.gridDim = dim3((unsigned)c->grid);
             kp.kernelParams = args_b;
+        } else if (c->tblock == 4) {
+            Domain &D = c->dom[0];
+            d = dom_for(D, p);
+            step4_tiles(D.dom, &tx, &ty);
+            kp.func = (void *)step4_kernel_fn(D.dom, D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32);
+            kp.gridDim = dim3((unsigned)(tx * ty));
+            kp.blockDim = dim3((unsigned)step4_threads());
+            kp.kernelParams = args_s;
         } else if (c->tblock == 3) {
             Domain &D = c->dom[0];
             d = dom_for(D, p);
@@ -593,7 +601,9 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     c->rec_cap = cap;
     // several cycles per pass (the multi-cycle kernels implement bounce-back walls
     // only): from 2^20 nodes isothermal domains take three (8192^2: FP32 177 against
-    // 146 GLUPS for two, FP16 190 against 188), thermal domains three from 2^22
+    // 146 GLUPS for two, FP16 190 against 188) and from 2^23 four (8192^2 in 20-step
+    // calls: FP32 232 against 201 GLUPS for three, FP16 258 against 251; 4096^2: 227
+    // against 196, 247 against 230-240), thermal domains three from 2^22
     // nodes (their 13 LDS planes leave two workgroups per CU: convection 2048^2 92
     // against 84 GLUPS, 4096^2 105 against 88, but 1024^2 80 against 87) and two
     // below; smaller domains take two with 64 x 8 tiles, which keep more workgroups
@@ -602,6 +612,8 @@ int lbm_create(const lbm_desc *d, const float *phi, const float *kappa, void *wo
     const int64_t nodes = (int64_t)d->nx * d->ny;
     if (!two_cycle_possible(c)) {
         c->tblock = 1;
+    } else if (!d->thermal.enabled && nodes >= ((int64_t)1 << 23)) {
+        c->tblock = 4;
     } else if (nodes >= ((int64_t)1 << 20)) {
         const bool three = three_cycle_possible(c) && (!d->thermal.enabled || nodes >= ((int64_t)1 << 22));
         c->tblock = three ? 3 : 2;
@@ -676,12 +688,15 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         Domain &D = c->dom[0];
         const int st = D.desc.storage == LBM_FP16_DEV ? ST_F16 : ST_F32;
         int cycles = 1;
-        if (fused && c->tblock == 3 && n >= 3 && c->t + 3 <= next_ck) cycles = 3;
+        if (fused && c->tblock == 4 && n >= 4 && c->t + 4 <= next_ck) cycles = 4;
+        else if (fused && c->tblock >= 3 && n >= 3 && c->t + 3 <= next_ck) cycles = 3;
         else if (fused && n >= 2 && c->t + 2 <= next_ck) cycles = 2;
         const bool last = (n == cycles);
         const Dom d = last ? dom_rec(D, c->cur) : dom_for(D, c->cur);
         Dom *doms = last ? c->d_doms_rec : c->d_doms;
-        if (cycles == 3) {
+        if (cycles == 4) {
+            e = launch_step4(d, st, c->sched.swizzle, c->stream);
+        } else if (cycles == 3) {
             if (c->batch)
                 e = launch_step3_batch(doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_uniform, c->grid3,
                                        c->stream);
@@ -1006,6 +1021,12 @@ int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threa
     if (c->batch) {
         if (c->tblock == 3) nt = step3_threads();
         ng = c->tblock == 3 ? c->grid3 : c->grid2;
+    } else if (c->tblock == 4) {
+        int tx, ty;
+        step4_tiles(c->dom[0].dom, &tx, &ty);
+        nt = step4_threads();
+        nr = step4_rows();
+        ng = tx * ty;
     } else if (c->tblock == 3) {
         const Dom &d = c->dom[0].dom;
         int tx, ty;
@@ -1044,7 +1065,9 @@ hipError_t upload_tiles2(lbm_ctx *c, int rows);
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
     int rc = check_ctx(c);
     if (rc) return rc;
-    if (cycles_per_pass < 1 || cycles_per_pass > 3) return fail(LBM_EINVAL, "cycles per pass must be 1, 2 or 3");
+    if (cycles_per_pass < 1 || cycles_per_pass > 4) return fail(LBM_EINVAL, "cycles per pass must be 1, 2, 3 or 4");
+    if (cycles_per_pass == 4 && (c->batch || c->dom[0].desc.thermal.enabled))
+        return fail(LBM_ENOTSUP, "four cycles per pass take single isothermal domains");
     if (cycles_per_pass == 3 && c->batch && c->batch_thermal)
         return fail(LBM_ENOTSUP, "thermal batches advance one or two cycles per pass");
     if (cycles_per_pass >= 2 && any_on_node_walls(c))
@@ -1521,7 +1544,7 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
                     dr.gin = (const float *)(D.base + L.off_rg[p]);
                     dr.gout = (float *)(D.base + L.off_rg[p ^ 1]);
                 }
-                if (c->tblock == 3 && t > 0 && t + 2 < s1) {
+                if (c->tblock >= 3 && t > 0 && t + 2 < s1) {
                     // three cycles in one pass, recording at t, t + 1 and t + 2
                     e = launch_step3(dr, ST_F32, c->sched.swizzle, dr.urec + rstride, dr.urec + 2 * rstride, st);
                     t += 3;
@@ -1547,7 +1570,7 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
                     e = launch_adjoint_step_thermal(D.dom, lam[la], lam[la ^ 1], lamg[la], lamg[la ^ 1], ut, gphi, gk,
                                                     acc_step, st);
                     t -= 1;
-                } else if (c->tblock == 3 && t - 2 >= s0) {
+                } else if (c->tblock >= 3 && t - 2 >= s0) {
                     e = launch_adjoint_step3(D.dom, lam[la], lam[la ^ 1], ut, ut - rstride, ut - 2 * rstride, gphi,
                                              gk, acc_step2, st);
                     t -= 3;

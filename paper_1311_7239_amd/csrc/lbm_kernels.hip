@@ -965,8 +965,10 @@ constexpr int STEP3_TW = 64, STEP3_TH = 16, STEP3_NT = 512;
 // the tail of the grid than they save. At 8192^2, 64 x 18 tiles with 512
 // threads took 1.01 ms per launch and 64 x 24 with 640 threads 1.41 ms
 // (ten waves leave room for one workgroup per CU), against 0.967 here.
-// Thermal domains (13 LDS planes) and the recording pass (86 VGPRs) keep
-// 64 x 16: at 768 threads either would leave one workgroup per CU.
+// Thermal domains (13 LDS planes) and the recording pass (80 VGPRs) keep
+// 64 x 16: at 768 threads either would leave one workgroup per CU. Single
+// isothermal domains of 2^23 nodes or more take four cycles per pass by
+// default (k_step4 below); these tiles serve them when switched to three.
 constexpr int STEP3_TH_TALL = 28, STEP3_NT_TALL = 768;
 
 static bool step3_tall(const Dom &d, bool rec) {
@@ -1042,6 +1044,243 @@ hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, fl
     int swz = swizzle;
     void *args[5] = {&dd, &tx, &swz, &urec1, &urec2};
     return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3((unsigned)step3_single_threads(d, rec)), args, 0, st);
+}
+
+// ------------------------------------------------- four cycles per pass
+
+// Temporal blocking over four cycles, for single isothermal domains that do
+// not record: the three-cycle pass with one more LDS phase. A workgroup owns a
+// TW x TH tile. Phase A gathers f(t) from HBM on the tile plus a three-node
+// ring and collides into LDS; phase B gathers f(t+1) from LDS on the tile plus
+// a two-node ring and phase C f(t+2) on the tile plus a one-node ring, each
+// keeping its results in registers until a barrier lets them replace the
+// previous layout in the same LDS (each layout smaller than the one before);
+// phase D gathers f(t+3), collides and stores f+(t+3). Same per-node function
+// and FP16 rounding of every intermediate as four one-cycle passes, so the
+// result is bitwise theirs.
+//
+// Thread (wave w, lane l) owns row r = w + NW k of the (TW + 6) x (TH + 6)
+// frame of phase A, column 3 + l, in every phase (phase B visits frame rows
+// 1 .. TH + 4, C rows 2 .. TH + 3, D rows 3 .. TH + 2), so its cell is
+// computed once; the ring columns (6 of phase A, 4 of B, 2 of C) go to the
+// waves without a row at the last iteration.
+template <typename S, int TW, int TH, int NT, int MK>
+__device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *lds) {
+    constexpr int AW = TW + 6, AH = TH + 6;
+    constexpr int BW = TW + 4, BH = TH + 4, BN = BW * BH;
+    constexpr int CW = TW + 2, CH = TH + 2, CN = CW * CH;
+    constexpr int ES = (int)sizeof(S);
+    constexpr int NW = NT / 64;                 // waves per workgroup
+    constexpr int NK = (AH + NW - 1) / NW;      // frame rows per thread
+    constexpr int WR = AH - NW * (NK - 1);      // first wave without a row at k = NK - 1
+    constexpr int RA = 6 * AH, RB = 4 * BH, RC = 2 * CH;   // ring items of phases A, B, C
+    static_assert(TW == 64 && NT % 64 == 0, "one tile row per wave");
+    static_assert((NW - WR) * 64 >= RA && RA >= RB && RB >= RC, "ring items fit the free waves");
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    const uint32_t fbytes = (uint32_t)(8 * d.plane * ES);
+    const BufRes rin = buf_res(d.fin, fbytes), rout = buf_res(d.fout, fbytes);
+    const MediumSrc<MK> med(d);
+    // every gather of every phase reads inside the domain, at constant offsets
+    const bool interior = x0 >= 4 && x0 + TW + 4 <= d.nx && y0 >= 4 && y0 + TH + 4 <= d.ny;
+    Cell ck[NK];   // the cell of this thread's frame node k (rows only, not ring items)
+    float g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // no D2Q5 field
+    float ux, uy, n7, n8, dT;
+
+    // item k of phase A: the thread's frame row, or at k = NK - 1 a ring item
+    auto a_item = [&](int k, int &ca, int &ra) -> bool {
+        ra = w + NW * k;
+        ca = 3 + lane;
+        if (k < NK - 1 || ra < AH) return true;
+        const int ri = (w - WR) * 64 + lane;
+        if (ri >= RA) return false;
+        ra = ri / 6;
+        const int c = ri - 6 * ra;
+        ca = c < 3 ? c : TW + c;
+        return true;
+    };
+
+    // phase A: s_{t+1} on the tile + 3 ring
+    auto finish_a = [&](int k, float (&f)[8], const CellRaw &raw, int ca, int ra) {
+        const Cell c = med.cell(d, raw);
+        ck[k] = c;
+        node_update<false>(d, c, f, g, ux, uy, n7, n8, dT);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[(i * AH + ra) * AW + ca] = (float)(S)f[i];
+    };
+    if (interior) {
+        // software pipelined: the next item's loads are issued before this one collides
+        auto fetch = [&](int k, float (&f)[8], CellRaw &r, int &ca, int &ra) -> bool {
+            if (!a_item(k, ca, ra)) return false;
+            const int gx = x0 - 3 + ca, gy = y0 - 3 + ra;
+            const uint32_t vo = (uint32_t)(((gy - 1) * d.pitch + (gx - 1)) * ES);
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                f[i] = BufIO<S>::ld(rin, vo, (uint32_t)((i * d.plane + (1 - EY[i]) * d.pitch + (1 - EX[i])) * ES));
+            r = med.load((uint32_t)((gy * d.pitch + gx) * 4));
+            return true;
+        };
+        float fn[8];
+        CellRaw rn{0.0f, 0.0f, 0.0f};
+        int can = 0, ran = 0;
+        bool vn = fetch(0, fn, rn, can, ran);
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            float f[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) f[i] = fn[i];
+            const CellRaw r = rn;
+            const int ca = can, ra = ran;
+            const bool v = vn;
+            if (k + 1 < NK) vn = fetch(k + 1, fn, rn, can, ran);
+            if (v) finish_a(k, f, r, ca, ra);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NK; ++k) {
+            int ca, ra;
+            if (!a_item(k, ca, ra)) continue;
+            int gx = x0 - 3 + ca, gy = y0 - 3 + ra;
+            if (!wrap_node(d, gx, gy)) continue;
+            float f[8];
+            gather_general_buf<S>(d, rin, gx, gy, f);
+            finish_a(k, f, med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4)), ca, ra);
+        }
+    }
+    lds_barrier();
+
+    float fr[NK][8];
+    int slot[NK];
+
+    // phase B: s_{t+2} on the tile + 2 ring, kept in registers
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        slot[k] = -1;
+        const int rb = w + NW * k - 1;
+        int bx = 2 + lane, by = rb;
+        const bool row = rb >= 0 && rb < BH;
+        if (!row) {
+            const int ri = (w - WR) * 64 + lane;
+            if (k != NK - 1 || w < WR || ri >= RB) continue;
+            by = ri >> 2;
+            const int c = ri & 3;
+            bx = c < 2 ? c : TW + c;
+        }
+        int gx = x0 - 2 + bx, gy = y0 - 2 + by;
+        if (!interior && !wrap_node(d, gx, gy)) continue;
+        const Cell c = row ? ck[k] : med.cell(d, med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4)));
+        lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fr[k]);
+        node_update<false>(d, c, fr[k], g, ux, uy, n7, n8, dT);
+        slot[k] = by * BW + bx;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        if (slot[k] < 0) continue;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[i * BN + slot[k]] = (float)(S)fr[k][i];
+    }
+    lds_barrier();
+
+    // phase C: s_{t+3} on the tile + 1 ring, kept in registers
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        slot[k] = -1;
+        const int rc = w + NW * k - 2;
+        int cx = 1 + lane, cy = rc;
+        const bool row = rc >= 0 && rc < CH;
+        if (!row) {
+            const int ri = (w - WR) * 64 + lane;
+            if (k != NK - 1 || w < WR || ri >= RC) continue;
+            cy = ri >> 1;
+            cx = (ri & 1) ? CW - 1 : 0;
+        }
+        int gx = x0 - 1 + cx, gy = y0 - 1 + cy;
+        if (!interior && !wrap_node(d, gx, gy)) continue;
+        const Cell c = row ? ck[k] : med.cell(d, med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4)));
+        lds_gather<BW, BH>(d, lds, interior, gx, gy, cx + 1, cy + 1, fr[k]);
+        node_update<false>(d, c, fr[k], g, ux, uy, n7, n8, dT);
+        slot[k] = cy * CW + cx;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        if (slot[k] < 0) continue;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[i * CN + slot[k]] = (float)(S)fr[k][i];
+    }
+    lds_barrier();
+
+    // phase D: s_{t+4} on the tile, to HBM
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+        const int rd = w + NW * k - 3;
+        const int gx = x0 + lane, gy = y0 + rd;
+        if (rd < 0 || rd >= TH || gx >= d.nx || gy >= d.ny) continue;
+        float f[8];
+        lds_gather<CW, CH>(d, lds, interior, gx, gy, lane + 1, rd + 1, f);
+        node_update<false>(d, ck[k], f, g, ux, uy, n7, n8, dT);
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const uint32_t vo = (uint32_t)(o * ES);
+        // one branch for the whole store sequence (per-store branches split the stream)
+        if (d.nt_store) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) BufIO<S>::st_nt(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
+        }
+        if (d.uprev) store_uprev(d, (uint32_t)(o * 4), ux, uy);
+    }
+}
+
+template <typename S, int TW, int TH, int NT, int MK>
+__global__ __launch_bounds__(NT) void k_step4(Dom d, int tiles_x, int swz) {
+    __shared__ float lds[8 * (TH + 6) * (TW + 6)];
+    int b = blockIdx.x;
+    if (swz) b = xcd_swizzle(b, gridDim.x);
+    step4_tile<S, TW, TH, NT, MK>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, lds);
+}
+
+// 64 x 26 tiles with 768 threads (12 waves: 8 with three frame rows, 4 with
+// two plus the ring columns): 72 KB of LDS, two workgroups per CU. Per
+// workgroup 2240 + 2040 + 1848 + 1664 collisions for 6656 updates (1.171, against
+// 1.106 for three cycles on 64 x 28), and phase A reads a 70 x 32 frame per
+// 64 x 26 tile for four cycles instead of a 68 x 32 frame per 64 x 28 for three.
+constexpr int STEP4_TW = 64, STEP4_TH = 26, STEP4_NT = 768;
+
+void step4_tiles(const Dom &d, int *tiles_x, int *tiles_y) {
+    *tiles_x = (d.nx + STEP4_TW - 1) / STEP4_TW;
+    *tiles_y = (d.ny + STEP4_TH - 1) / STEP4_TH;
+}
+
+int step4_threads() { return STEP4_NT; }
+
+int step4_rows() { return STEP4_TH; }
+
+template <int MK>
+static const void *step4_fn_t(int storage) {
+    return storage == ST_F32 ? (const void *)&k_step4<float, STEP4_TW, STEP4_TH, STEP4_NT, MK>
+                             : (const void *)&k_step4<_Float16, STEP4_TW, STEP4_TH, STEP4_NT, MK>;
+}
+
+const void *step4_kernel_fn(const Dom &d, int storage) {
+    if (d.thermal) return nullptr;
+    switch (medium_kind(d)) {
+    case MK_ERGUN: return step4_fn_t<MK_ERGUN>(storage);
+    case MK_UNIFORM: return step4_fn_t<MK_UNIFORM>(storage);
+    default: return step4_fn_t<MK_ANY>(storage);
+    }
+}
+
+hipError_t launch_step4(const Dom &d, int storage, int swizzle, hipStream_t st) {
+    const void *fn = step4_kernel_fn(d, storage);
+    if (!fn) return hipErrorInvalidValue;
+    int tx, ty;
+    step4_tiles(d, &tx, &ty);
+    Dom dd = d;
+    int swz = swizzle;
+    void *args[3] = {&dd, &tx, &swz};
+    return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3((unsigned)STEP4_NT), args, 0, st);
 }
 
 template <typename S, bool REC, int MK, bool THERMAL>

@@ -52,6 +52,14 @@ void step3_tiles(const Dom &d, bool rec, int *tiles_x, int *tiles_y);
 int step3_single_threads(const Dom &d, bool rec);
 int step3_single_rows(const Dom &d, bool rec);
 const void *step3_kernel_fn(const Dom &d, int storage, bool rec);
+// Four collide-stream cycles in one HBM pass (single isothermal domains, no
+// recording; 64 x 26 tiles, step4_threads() threads; kernel arguments
+// (Dom, tiles_x, swizzle)). step4_kernel_fn is null for a thermal domain.
+hipError_t launch_step4(const Dom &d, int storage, int swizzle, hipStream_t st);
+void step4_tiles(const Dom &d, int *tiles_x, int *tiles_y);
+int step4_threads();
+int step4_rows();
+const void *step4_kernel_fn(const Dom &d, int storage);
 // batched three-cycle pass over a table of 64 x 16 tiles (isothermal domains);
 // uniform: every domain has a uniform medium and one s_nu (medium_kind MK_UNIFORM),
 // so the kernel loads no medium planes; one: one workgroup per tile (a grid of

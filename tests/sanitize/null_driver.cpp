@@ -14,7 +14,8 @@
 //   * a second lbm_destroy, calls on a destroyed handle and on a handle that
 //     was never created are refused without touching memory;
 //   * the step is launched (directly and from a replayed graph);
-//   * the three-cycle tile shape switches at 2^23 nodes (isothermal only).
+//   * the pass shape switches at 2^23 nodes (isothermal only): four cycles on
+//     64 x 26 tiles by default, 64 x 28 tiles when switched to three.
 // Built and run by tests/test_sanitize_cpu.py; exits 0 when every call
 // returns what the header promises.
 #include <cmath>
@@ -164,6 +165,22 @@ static void recording() {
     expect(lbm_backward(c, du.data(), dphi.data(), nullptr) == LBM_ESTATE, "backward after a load");
     expect(lbm_tangent(c, nullptr, dth, du.data()) == LBM_ESTATE, "tangent after a load");
     expect(lbm_destroy(c) == LBM_OK, "destroy recording context");
+
+    // in mode 4 the recorded forward takes four-cycle passes (never over a
+    // checkpoint time) and the recomputation inside lbm_backward three-cycle ones
+    Workspace ws4(bytes);
+    lbm_ctx *c4 = nullptr;
+    expect(lbm_create(&d, phi.data(), kappa.data(), ws4.p, ws4.bytes, nullptr, &c4) == LBM_OK, "create (mode 4)");
+    if (!c4) return;
+    expect(lbm_set_time_blocking(c4, 4) == LBM_OK, "mode 4 on a recording context");
+    const long f4 = null_device_launches("k_step4");
+    expect(lbm_step(c4, 25) == LBM_OK && time_of(c4) == 25, "recorded steps in mode 4");
+    expect(null_device_launches("k_step4") == f4 + 5, "four-cycle passes 1-5, 5-9, 10-14, 14-18, 20-24 while recording");
+    const long b4 = null_device_launches("k_step4"), b3 = null_device_launches("k_step3");
+    expect(lbm_backward(c4, du.data(), dphi.data(), nullptr) == LBM_OK, "backward in mode 4");
+    expect(null_device_launches("k_step4") == b4 && null_device_launches("k_step3") > b3,
+           "the recomputation takes three-cycle passes");
+    expect(lbm_destroy(c4) == LBM_OK, "destroy (mode 4)");
 }
 
 static void thermal_snapshot_into_isothermal() {
@@ -220,14 +237,17 @@ static void batch() {
     expect(lbm_destroy(c) == LBM_EINVAL, "second destroy of a batch");
 }
 
-// The three-cycle tile shape: 64 x 28 tiles of 768 threads from 2^23 nodes on
-// isothermal single domains, 64 x 16 tiles of 512 threads below and for thermal ones.
+// The multi-cycle pass shape: from 2^23 nodes isothermal single domains take four
+// cycles on 64 x 26 tiles of 768 threads, or, switched to three, 64 x 28 tiles of
+// 768 threads; below 2^23 and for thermal domains three cycles on 64 x 16 tiles of
+// 512 threads.
 static void tile_shapes() {
-    struct Shape { int nx, ny, thermal, cycles, threads, rows, grid; };
+    struct Shape { int nx, ny, thermal, set3, cycles, threads, rows, grid; };
     const Shape shapes[] = {
-        {2896, 2896, 0, 3, 512, 16, 46 * 181},    // 8,386,816 nodes: below 2^23
-        {2896, 2897, 0, 3, 768, 28, 46 * 104},    // 8,389,712 nodes: tall tiles
-        {2896, 2897, 1, 3, 512, 16, 46 * 182},    // thermal: 64 x 16
+        {2896, 2896, 0, 0, 3, 512, 16, 46 * 181},    // 8,386,816 nodes: below 2^23
+        {2896, 2897, 0, 0, 4, 768, 26, 46 * 112},    // 8,389,712 nodes: four cycles
+        {2896, 2897, 0, 1, 3, 768, 28, 46 * 104},    // switched to three: tall tiles
+        {2896, 2897, 1, 0, 3, 512, 16, 46 * 182},    // thermal: 64 x 16
     };
     for (const Shape &sh : shapes) {
         lbm_desc d = channel(sh.nx, sh.ny);
@@ -243,13 +263,15 @@ static void tile_shapes() {
         lbm_ctx *c = nullptr;
         expect(lbm_create(&d, nullptr, nullptr, ws.p, ws.bytes, nullptr, &c) == LBM_OK, "create (tile shapes)");
         if (!c) continue;
+        if (sh.set3) expect(lbm_set_time_blocking(c, 3) == LBM_OK, "switch to three cycles");
         int32_t cyc = 0, thr = 0, rows = 0, grid = 0;
         expect(lbm_time_blocking(c, &cyc, &thr, &rows, &grid) == LBM_OK, "time blocking query");
         expect(cyc == sh.cycles && thr == sh.threads && rows == sh.rows && grid == sh.grid,
-               "three-cycle tile shape at the 2^23-node switch");
-        const long before = null_device_launches("k_step3");
-        expect(lbm_step(c, 7) == LBM_OK, "step (tile shapes)");
-        expect(null_device_launches("k_step3") > before, "three-cycle kernel launched");
+               "multi-cycle pass shape at the 2^23-node switch");
+        const char *kname = sh.cycles == 4 ? "k_step4" : "k_step3";
+        const long before = null_device_launches(kname);
+        expect(lbm_step(c, 9) == LBM_OK, "step (tile shapes)");
+        expect(null_device_launches(kname) > before, "multi-cycle kernel launched");
         lbm_destroy(c);
     }
     // a small domain switched to three cycles keeps 64 x 16 tiles
@@ -264,6 +286,13 @@ static void tile_shapes() {
     expect(lbm_set_time_blocking(c, 3) == LBM_OK, "three cycles on a small domain");
     expect(lbm_time_blocking(c, &cyc, &thr, &rows, &grid) == LBM_OK && cyc == 3 && thr == 512 && rows == 16 &&
                grid == 4 * 9, "small domain keeps 64 x 16 tiles");
+    // and switched to four cycles takes 64 x 26 tiles
+    expect(lbm_set_time_blocking(c, 4) == LBM_OK, "four cycles on a small domain");
+    expect(lbm_time_blocking(c, &cyc, &thr, &rows, &grid) == LBM_OK && cyc == 4 && thr == 768 && rows == 26 &&
+               grid == 4 * 5, "small domain in mode 4: 64 x 26 tiles");
+    const long before = null_device_launches("k_step4");
+    expect(lbm_step(c, 9) == LBM_OK, "step in mode 4");
+    expect(null_device_launches("k_step4") == before + 2, "two four-cycle passes after the collide-only cycle");
     lbm_destroy(c);
 }
 

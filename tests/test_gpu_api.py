@@ -122,15 +122,19 @@ def test_argument_checks_on_a_live_context():
     with pytest.raises(lbm.LBMError) as e:
         s.set_schedule(100, 1, 1)
     assert e.value.status == lbm.EINVAL
-    with pytest.raises(lbm.LBMError) as e:
-        s.set_time_blocking(4)
-    assert e.value.status == lbm.EINVAL
+    for bad in (0, 5):
+        with pytest.raises(lbm.LBMError) as e:
+            s.set_time_blocking(bad)
+        assert e.value.status == lbm.EINVAL
     with pytest.raises(lbm.LBMError) as e:
         s.macroscopic(want_T=True)          # no thermal model
     assert e.value.status == lbm.EINVAL
     t = lbm.solver_for_case(I.natural_convection(n=32))
     t.set_time_blocking(2)
     t.set_time_blocking(3)
+    with pytest.raises(lbm.LBMError) as e:
+        t.set_time_blocking(4)              # four cycles: isothermal single domains
+    assert e.value.status == lbm.ENOTSUP
     w = lbm.solver_for_case(I.natural_convection(n=32, nee=True))
     with pytest.raises(lbm.LBMError) as e:
         w.set_time_blocking(2)       # on-node walls: one cycle per pass

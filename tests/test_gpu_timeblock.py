@@ -84,6 +84,7 @@ def test_tall_three_cycle_tiles_are_bitwise_equal(name, case, storage, graph):
     ref = lbm.solver_for_case(case, storage=storage)
     ref.set_time_blocking(1)
     tb = lbm.solver_for_case(case, storage=storage)
+    tb.set_time_blocking(3)
     shape = tb.time_blocking()
     assert (shape["cycles_per_pass"], shape["rows"], shape["threads"]) == (3, 28, 768)
     assert shape["grid"] == 46 * 105
@@ -100,6 +101,76 @@ def test_tall_three_cycle_tiles_are_bitwise_equal(name, case, storage, graph):
         torch.cuda.synchronize()
         assert torch.equal(a, b), (name, chunk)
         del a, b
+
+
+@pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
+@pytest.mark.parametrize("name,case", cases(), ids=[n for n, _ in cases()])
+@pytest.mark.parametrize("graph", [0, 9, 8])
+def test_four_cycles_per_pass_is_bitwise_equal(name, case, storage, graph):
+    """Four cycles per pass (three-node LDS ring), alone and mixed with the three-, two-
+    and one-cycle passes that finish a call, equal one cycle per pass bit for bit, on
+    every boundary kind, ragged and tiny domain (8 x 64, 1 x 16, periodic 70 x 70)."""
+    ref = lbm.solver_for_case(case, storage=storage)
+    ref.set_time_blocking(1)
+    tb = lbm.solver_for_case(case, storage=storage)
+    tb.set_time_blocking(4)
+    shape = tb.time_blocking()
+    assert (shape["cycles_per_pass"], shape["rows"], shape["threads"]) == (4, 26, 768)
+    assert shape["grid"] == ((case.nx + 63) // 64) * ((case.ny + 25) // 26)
+    tb.set_graph_steps(graph)
+    df0 = I.random_deviation_state(case.ny, case.nx, 1e-3, seed=5)
+    for s in (ref, tb):
+        s.set_populations(torch.from_numpy(df0).cuda())
+    for chunk in (1, 7, 10, 2, 5, 19, 4, 3, 12):
+        ref.step(chunk)
+        tb.step(chunk)
+        a, _ = ref.populations()
+        b, _ = tb.populations()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), (name, chunk)
+
+
+@pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
+@pytest.mark.parametrize("name,case", tall_cases(), ids=[n for n, _ in tall_cases()])
+def test_tall_four_cycle_tiles_are_bitwise_equal(name, case, storage):
+    """Four cycles per pass on a domain of 8.5e6 nodes, ragged in x (45 tiles + 20
+    columns) and in y (112 tiles + 23 rows), equal one cycle per pass bit for bit."""
+    ref = lbm.solver_for_case(case, storage=storage)
+    ref.set_time_blocking(1)
+    tb = lbm.solver_for_case(case, storage=storage)
+    tb.set_time_blocking(4)
+    assert tb.time_blocking()["grid"] == 46 * 113
+    df0 = I.random_deviation_state(case.ny, case.nx, 1e-3, seed=6)
+    for s in (ref, tb):
+        s.set_populations(torch.from_numpy(df0).cuda())
+    del df0
+    for chunk in (1, 9, 6):
+        ref.step(chunk)
+        tb.step(chunk)
+        a, _ = ref.populations()
+        b, _ = tb.populations()
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), (name, chunk)
+        del a, b
+
+
+def test_four_cycles_take_single_isothermal_domains():
+    """Mode 4 is refused (ENOTSUP) for thermal domains and for batches, and leaves
+    the context's mode unchanged."""
+    _, thermal = thermal_cases()[0]
+    s = lbm.solver_for_case(thermal)
+    before = s.time_blocking()["cycles_per_pass"]
+    with pytest.raises(lbm.LBMError) as e:
+        s.set_time_blocking(4)
+    assert e.value.status == lbm.ENOTSUP
+    assert s.time_blocking()["cycles_per_pass"] == before
+    b = lbm.batch_for_cases([c for _, c in cases()[:2]])
+    with pytest.raises(lbm.LBMError) as e:
+        b.set_time_blocking(4)
+    assert e.value.status == lbm.ENOTSUP
+    with pytest.raises(lbm.LBMError) as e:
+        s.set_time_blocking(5)
+    assert e.value.status == lbm.EINVAL
 
 
 @pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
@@ -130,16 +201,17 @@ def test_two_cycles_per_pass_is_bitwise_equal(name, case, storage, graph, shape)
 @pytest.mark.parametrize("kappa_plane", [False, True])
 def test_backward_with_two_cycle_passes_is_bitwise_equal(kappa_plane):
     """In the multi-cycle modes the adjoint's recomputation runs two or three cycles per
-    pass (recording u at each) and the backward sweep two or three adjoint steps per pass;
-    gradients are bitwise those of the one-cycle path (odd step count: segments of every
-    length modulo 2 and 3)."""
+    pass (recording u at each) and the backward sweep two or three adjoint steps per pass
+    (mode 4 steps forward four cycles per pass and recomputes and sweeps three); gradients
+    are bitwise those of the one-cycle path (odd step count: segments of every length
+    modulo 2, 3 and 4)."""
     case = I.lognormal_channel(n=160, seed=9, ell=10.0, K_ref=40.0, drive=0.02)
     kap = None
     if kappa_plane:
         kap = torch.from_numpy((150.0 * (1 - case.phi) ** 2 / (case.phi ** 3 * case.dp ** 2))
                                .astype(np.float32)).cuda()
     grads = []
-    for tblock in (1, 2, 3):
+    for tblock in (1, 2, 3, 4):
         desc = lbm.desc_from_case(case, ckpt_every=50)
         if kappa_plane:
             desc.medium = lbm.MEDIUM_PHI_KAPPA
@@ -154,7 +226,7 @@ def test_backward_with_two_cycle_passes_is_bitwise_equal(kappa_plane):
         g, gk = s.backward(dLdu, want_kappa=kappa_plane)
         torch.cuda.synchronize()
         grads.append((g.cpu().numpy(), None if gk is None else gk.cpu().numpy()))
-    for k in (1, 2):
+    for k in (1, 2, 3):
         assert np.array_equal(grads[0][0], grads[k][0]), k
         if kappa_plane:
             assert np.array_equal(grads[0][1], grads[k][1]), k
