@@ -305,7 +305,7 @@ def adjoint_ratio():
             "backward_ms": round(bwd, 2), "adjoint_forward_ratio": round(bwd / fwd, 3),
             "forward_cycles_per_pass": mode0,
             "forward_four_cycles_ms": round(fwd4, 2), "adjoint_forward_ratio_four_cycles": round(bwd / fwd4, 3),
-            "note": "backward = recomputation from checkpoints (three cycles per pass, recording u) + "
+            "note": "backward = recomputation from checkpoints (four cycles per pass, recording u) + "
                     "adjoint steps (three per pass); forward_ms in the default mode at this size "
                     f"({mode0} cycles per pass), forward_four_cycles_ms the same forward in four; the "
                     "recorded forward also copies a checkpoint every 200 steps"}

@@ -310,8 +310,9 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * planes of the workspace (8 bytes per node), which lbm_reduce's residual
  * reads. The recomputation inside
  * lbm_backward uses passes of the same length (recording u at every cycle;
- * three in mode 4) and its adjoint sweep two or three steps per pass in modes
- * 2, 3 and 4 (two for thermal runs). The D2Q5 field of a thermal domain rides
+ * four-cycle passes also in mode 3 for isothermal domains of at least 2^22
+ * nodes, where they are faster) and its adjoint sweep two or three steps per
+ * pass in modes 2, 3 and 4 (two for thermal runs). The D2Q5 field of a thermal domain rides
  * in LDS beside the populations. Default for single domains that allow it: 4
  * for isothermal domains of at least 2^23 nodes, 3 for isothermal domains of
  * at least 2^20 nodes and thermal domains of at least 2^22, 2 for

@@ -1498,6 +1498,11 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
     if (d.storage != LBM_FP32_DEV) return fail(LBM_ENOTSUP, "adjoint needs FP32 storage");
     if (dL_dphi && d.medium == LBM_MEDIUM_UNIFORM) return fail(LBM_ENOTSUP, "dL/dphi needs a porosity plane");
     const bool th = d.thermal.enabled != 0;
+    // The recomputation's passes record u at every cycle and give the same bits
+    // whatever their length; from 2^22 nodes isothermal domains in mode 3 or 4 take
+    // four-cycle recording passes (2048^2: backward 256 ms against 274.5 with
+    // three-cycle ones).
+    const bool rec4 = !th && (c->tblock == 4 || (c->tblock == 3 && (int64_t)d.nx * d.ny >= ((int64_t)1 << 22)));
     if (dL_dkappa && d.medium != LBM_MEDIUM_PHI_KAPPA) return fail(LBM_EINVAL, "dL_dkappa needs LBM_MEDIUM_PHI_KAPPA");
     if (!c->rec_valid) return fail(LBM_ESTATE, "no recorded trajectory leads to the current state");
     const int64_t T = c->t, k = d.ckpt_every;
@@ -1544,7 +1549,12 @@ int backward_impl(lbm_ctx *c, const float *dL_du, float *dL_dphi, float *dL_dkap
                     dr.gin = (const float *)(D.base + L.off_rg[p]);
                     dr.gout = (float *)(D.base + L.off_rg[p ^ 1]);
                 }
-                if (c->tblock >= 3 && t > 0 && t + 2 < s1) {
+                if (rec4 && t > 0 && t + 3 < s1) {
+                    // four cycles in one pass, recording at t, t + 1, t + 2 and t + 3
+                    e = launch_step4_rec(dr, c->sched.swizzle, dr.urec + rstride, dr.urec + 2 * rstride,
+                                         dr.urec + 3 * rstride, st);
+                    t += 4;
+                } else if (c->tblock >= 3 && t > 0 && t + 2 < s1) {
                     // three cycles in one pass, recording at t, t + 1 and t + 2
                     e = launch_step3(dr, ST_F32, c->sched.swizzle, dr.urec + rstride, dr.urec + 2 * rstride, st);
                     t += 3;

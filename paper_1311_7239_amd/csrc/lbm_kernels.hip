@@ -1063,9 +1063,12 @@ hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, fl
 // frame of phase A, column 3 + l, in every phase (phase B visits frame rows
 // 1 .. TH + 4, C rows 2 .. TH + 3, D rows 3 .. TH + 2), so its cell is
 // computed once; the ring columns (6 of phase A, 4 of B, 2 of C) go to the
-// waves without a row at the last iteration.
-template <typename S, int TW, int TH, int NT, int MK>
-__device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *lds) {
+// waves without a row at the last iteration. With REC (FP32 recomputation for
+// the adjoint) u and, with rec_stress, the stress moments of the tile nodes are
+// recorded at t (d.urec), t + 1, t + 2 and t + 3 (urec1 .. urec3).
+template <typename S, int TW, int TH, int NT, bool REC, int MK>
+__device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *urec1, float *urec2, float *urec3,
+                                           float *lds) {
     constexpr int AW = TW + 6, AH = TH + 6;
     constexpr int BW = TW + 4, BH = TH + 4, BN = BW * BH;
     constexpr int CW = TW + 2, CH = TH + 2, CN = CW * CH;
@@ -1085,6 +1088,10 @@ __device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *
     Cell ck[NK];   // the cell of this thread's frame node k (rows only, not ring items)
     float g[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // no D2Q5 field
     float ux, uy, n7, n8, dT;
+    // the recorded planes of one step (u, and with rec_stress the stress moments)
+    const uint32_t rbytes = REC ? (uint32_t)((d.rec_stress ? 4 : 2) * d.plane * 4) : 0u;
+    // phase A's records are held one node, so that its loads go out before them
+    Pending<false> pend;
 
     // item k of phase A: the thread's frame row, or at k = NK - 1 a ring item
     auto a_item = [&](int k, int &ca, int &ra) -> bool {
@@ -1100,12 +1107,16 @@ __device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *
     };
 
     // phase A: s_{t+1} on the tile + 3 ring
-    auto finish_a = [&](int k, float (&f)[8], const CellRaw &raw, int ca, int ra) {
+    const BufRes rr0 = buf_res(REC ? d.urec : nullptr, rbytes);
+    auto finish_a = [&](int k, float (&f)[8], const CellRaw &raw, int ca, int ra, int64_t o) {
+        if (REC) pend.flush(d, rr0);
         const Cell c = med.cell(d, raw);
         ck[k] = c;
         node_update<false>(d, c, f, g, ux, uy, n7, n8, dT);
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[(i * AH + ra) * AW + ca] = (float)(S)f[i];
+        if (REC && ca >= 3 && ca < TW + 3 && ra >= 3 && ra < TH + 3 && x0 - 3 + ca < d.nx && y0 - 3 + ra < d.ny)
+            pend.hold((uint32_t)(o * 4), ux, uy, n7, n8, dT);
     };
     if (interior) {
         // software pipelined: the next item's loads are issued before this one collides
@@ -1132,7 +1143,7 @@ __device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *
             const int ca = can, ra = ran;
             const bool v = vn;
             if (k + 1 < NK) vn = fetch(k + 1, fn, rn, can, ran);
-            if (v) finish_a(k, f, r, ca, ra);
+            if (v) finish_a(k, f, r, ca, ra, (int64_t)(y0 - 3 + ra) * d.pitch + (x0 - 3 + ca));
         }
     } else {
 #pragma unroll
@@ -1143,15 +1154,20 @@ __device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *
             if (!wrap_node(d, gx, gy)) continue;
             float f[8];
             gather_general_buf<S>(d, rin, gx, gy, f);
-            finish_a(k, f, med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4)), ca, ra);
+            // a wrapped ring node is recorded by the tile that owns it
+            const int64_t o = (int64_t)gy * d.pitch + gx;
+            finish_a(k, f, med.load((uint32_t)(o * 4)), ca, ra, o);
         }
     }
+    if (REC) pend.flush(d, rr0);
     lds_barrier();
 
     float fr[NK][8];
     int slot[NK];
 
-    // phase B: s_{t+2} on the tile + 2 ring, kept in registers
+    // phase B: s_{t+2} on the tile + 2 ring, kept in registers (no HBM loads on tile
+    // rows, so the records are stored at once)
+    const BufRes rr1 = buf_res(urec1, rbytes);
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
         slot[k] = -1;
@@ -1167,9 +1183,12 @@ __device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *
         }
         int gx = x0 - 2 + bx, gy = y0 - 2 + by;
         if (!interior && !wrap_node(d, gx, gy)) continue;
-        const Cell c = row ? ck[k] : med.cell(d, med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4)));
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = row ? ck[k] : med.cell(d, med.load((uint32_t)(o * 4)));
         lds_gather<AW, AH>(d, lds, interior, gx, gy, bx + 1, by + 1, fr[k]);
         node_update<false>(d, c, fr[k], g, ux, uy, n7, n8, dT);
+        if (REC && bx >= 2 && bx < TW + 2 && by >= 2 && by < TH + 2 && x0 - 2 + bx < d.nx && y0 - 2 + by < d.ny)
+            record_node(d, rr1, (uint32_t)(o * 4), ux, uy, n7, n8);
         slot[k] = by * BW + bx;
     }
     lds_barrier();
@@ -1182,6 +1201,7 @@ __device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *
     lds_barrier();
 
     // phase C: s_{t+3} on the tile + 1 ring, kept in registers
+    const BufRes rr2 = buf_res(urec2, rbytes);
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
         slot[k] = -1;
@@ -1196,9 +1216,12 @@ __device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *
         }
         int gx = x0 - 1 + cx, gy = y0 - 1 + cy;
         if (!interior && !wrap_node(d, gx, gy)) continue;
-        const Cell c = row ? ck[k] : med.cell(d, med.load((uint32_t)(((int64_t)gy * d.pitch + gx) * 4)));
+        const int64_t o = (int64_t)gy * d.pitch + gx;
+        const Cell c = row ? ck[k] : med.cell(d, med.load((uint32_t)(o * 4)));
         lds_gather<BW, BH>(d, lds, interior, gx, gy, cx + 1, cy + 1, fr[k]);
         node_update<false>(d, c, fr[k], g, ux, uy, n7, n8, dT);
+        if (REC && cx >= 1 && cx < TW + 1 && cy >= 1 && cy < TH + 1 && x0 - 1 + cx < d.nx && y0 - 1 + cy < d.ny)
+            record_node(d, rr2, (uint32_t)(o * 4), ux, uy, n7, n8);
         slot[k] = cy * CW + cx;
     }
     lds_barrier();
@@ -1211,6 +1234,7 @@ __device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *
     lds_barrier();
 
     // phase D: s_{t+4} on the tile, to HBM
+    const BufRes rr3 = buf_res(urec3, rbytes);
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
         const int rd = w + NW * k - 3;
@@ -1230,6 +1254,7 @@ __device__ __forceinline__ void step4_tile(const Dom &d, int x0, int y0, float *
             for (int i = 0; i < 8; ++i) BufIO<S>::st(rout, vo, (uint32_t)(i * d.plane * ES), f[i]);
         }
         if (d.uprev) store_uprev(d, (uint32_t)(o * 4), ux, uy);
+        if (REC) record_node(d, rr3, (uint32_t)(o * 4), ux, uy, n7, n8);
     }
 }
 
@@ -1238,7 +1263,18 @@ __global__ __launch_bounds__(NT) void k_step4(Dom d, int tiles_x, int swz) {
     __shared__ float lds[8 * (TH + 6) * (TW + 6)];
     int b = blockIdx.x;
     if (swz) b = xcd_swizzle(b, gridDim.x);
-    step4_tile<S, TW, TH, NT, MK>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, lds);
+    step4_tile<S, TW, TH, NT, false, MK>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, nullptr, nullptr, nullptr, lds);
+}
+
+// The recording pass of the adjoint's recomputation (FP32), held to 80 VGPRs:
+// six waves per SIMD, two workgroups per CU.
+template <int TW, int TH, int NT, int MK>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6))) void k_step4_rec(
+    Dom d, int tiles_x, int swz, float *urec1, float *urec2, float *urec3) {
+    __shared__ float lds[8 * (TH + 6) * (TW + 6)];
+    int b = blockIdx.x;
+    if (swz) b = xcd_swizzle(b, gridDim.x);
+    step4_tile<float, TW, TH, NT, true, MK>(d, (b % tiles_x) * TW, (b / tiles_x) * TH, urec1, urec2, urec3, lds);
 }
 
 // 64 x 26 tiles with 768 threads (12 waves: 8 with three frame rows, 4 with
@@ -1280,6 +1316,22 @@ hipError_t launch_step4(const Dom &d, int storage, int swizzle, hipStream_t st) 
     Dom dd = d;
     int swz = swizzle;
     void *args[3] = {&dd, &tx, &swz};
+    return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3((unsigned)STEP4_NT), args, 0, st);
+}
+
+hipError_t launch_step4_rec(const Dom &d, int swizzle, float *urec1, float *urec2, float *urec3, hipStream_t st) {
+    if (d.thermal || !d.urec || !urec1 || !urec2 || !urec3) return hipErrorInvalidValue;
+    const void *fn;
+    switch (medium_kind(d)) {
+    case MK_ERGUN: fn = (const void *)&k_step4_rec<STEP4_TW, STEP4_TH, STEP4_NT, MK_ERGUN>; break;
+    case MK_UNIFORM: fn = (const void *)&k_step4_rec<STEP4_TW, STEP4_TH, STEP4_NT, MK_UNIFORM>; break;
+    default: fn = (const void *)&k_step4_rec<STEP4_TW, STEP4_TH, STEP4_NT, MK_ANY>; break;
+    }
+    int tx, ty;
+    step4_tiles(d, &tx, &ty);
+    Dom dd = d;
+    int swz = swizzle;
+    void *args[6] = {&dd, &tx, &swz, &urec1, &urec2, &urec3};
     return hipLaunchKernel(fn, dim3((unsigned)(tx * ty)), dim3((unsigned)STEP4_NT), args, 0, st);
 }
 

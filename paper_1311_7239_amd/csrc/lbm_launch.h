@@ -60,6 +60,9 @@ void step4_tiles(const Dom &d, int *tiles_x, int *tiles_y);
 int step4_threads();
 int step4_rows();
 const void *step4_kernel_fn(const Dom &d, int storage);
+// the four-cycle pass recording u (and with d.rec_stress the stress moments) at
+// t (d.urec), t + 1, t + 2, t + 3 (FP32 isothermal domains; same grid)
+hipError_t launch_step4_rec(const Dom &d, int swizzle, float *urec1, float *urec2, float *urec3, hipStream_t st);
 // batched three-cycle pass over a table of 64 x 16 tiles (isothermal domains);
 // uniform: every domain has a uniform medium and one s_nu (medium_kind MK_UNIFORM),
 // so the kernel loads no medium planes; one: one workgroup per tile (a grid of

@@ -58,7 +58,7 @@ def _gpu(case, target, col, cycles):
 
 
 @pytest.mark.parametrize("kind", ["channel", "cavity"])
-@pytest.mark.parametrize("cycles", [1, 2, 3])
+@pytest.mark.parametrize("cycles", [1, 2, 3, 4])
 def test_parameter_gradients_match_oracle_differences(kind, cycles):
     case = _channel() if kind == "channel" else _cavity()
     col = case.nx - 1 if kind == "channel" else case.nx // 2

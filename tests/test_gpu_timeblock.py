@@ -202,7 +202,7 @@ def test_two_cycles_per_pass_is_bitwise_equal(name, case, storage, graph, shape)
 def test_backward_with_two_cycle_passes_is_bitwise_equal(kappa_plane):
     """In the multi-cycle modes the adjoint's recomputation runs two or three cycles per
     pass (recording u at each) and the backward sweep two or three adjoint steps per pass
-    (mode 4 steps forward four cycles per pass and recomputes and sweeps three); gradients
+    (mode 4 recomputes four cycles per pass and sweeps three steps per pass); gradients
     are bitwise those of the one-cycle path (odd step count: segments of every length
     modulo 2, 3 and 4)."""
     case = I.lognormal_channel(n=160, seed=9, ell=10.0, K_ref=40.0, drive=0.02)
