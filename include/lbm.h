@@ -318,17 +318,19 @@ int lbm_set_schedule(lbm_ctx *c, int32_t tile_w, int32_t vec, int32_t rows, int3
  * at least 2^20 nodes and thermal domains of at least 2^22, 2 for
  * smaller ones (with 8-row tiles below 2^20 nodes and for thermal domains), 1
  * for the others; for batches, the
- * autotuner's choice among 1, 2 and 3 (a batch switched to 3 walks 64 x 16
- * tiles, which its two-cycle passes then use too; switching uploads that tile
- * table and synchronises the stream). ENOTSUP for on-node walls,
+ * autotuner's choice among 1, 2, 3 and 4 (isothermal batches; mode 4 runs one
+ * workgroup per 64 x 26 tile from a table of its own; a batch switched to 3 or
+ * 4 walks 64 x 16 tiles in its three- and two-cycle passes; switching uploads
+ * that tile table and synchronises the stream). ENOTSUP for on-node walls,
  * population or thermal buffers of 4 GiB or more, mode 3 on thermal batches,
- * mode 4 on batches and thermal domains, a mode a batch has no tuned schedule
+ * mode 4 on thermal domains and thermal batches, a mode a batch has no tuned schedule
  * for; EINVAL for another value. */
 int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass);
 
 /* Current cycles per pass, and the workgroup size, tile rows (tiles are 64
  * nodes wide) and grid size of the multi-cycle pass it runs: the four-cycle
- * kernel in mode 4 (768 threads, 26 rows), the three-cycle kernel in mode 3
+ * kernel in mode 4 (768 threads, 26 rows; for a batch the grid is its number
+ * of 64 x 26 tiles), the three-cycle kernel in mode 3
  * (single isothermal domains of 2^23 nodes or more: 768 threads, 28 rows;
  * other domains and batches: 512 threads, 16 rows), else the two-cycle
  * kernel's

@@ -261,6 +261,10 @@ struct lbm_ctx {
     int ntiles2 = 0;
     int grid2 = 0;
     int grid3 = 0;              // grid of the batched three-cycle kernel (64 x 16 tiles of d_tiles2)
+    int4 *d_tiles4 = nullptr;   // tiles of the batched four-cycle kernel (64 x 26, one workgroup each)
+    int ntiles4 = 0;
+    bool four_ok = false;       // an isothermal batch with bounce-back walls: four cycles available
+    std::vector<int4> h_tiles4;
     std::vector<int4> h_tiles2;
     // steps replayed from one hand-built HIP graph (0: launch each step);
     // one executable graph per starting buffer parity
@@ -470,7 +474,13 @@ hipError_t build_graph(lbm_ctx *c, int parity) {
         void *args_s2[4] = {&d, &tx, &swz, &no_rec};
         void *args_s3[5] = {&d, &tx, &swz, &no_rec, &no_rec};
         void *args_b2[4] = {&c->d_doms, &c->d_tiles2, &c->ntiles2, &p};
-        if (c->batch && c->tblock == 3) {
+        void *args_b4[3] = {&c->d_doms, &c->d_tiles4, &p};
+        if (c->batch && c->tblock == 4) {
+            kp.func = (void *)step4_batch_kernel_fn(c->storage, c->batch_uniform);
+            kp.gridDim = dim3((unsigned)c->ntiles4);
+            kp.blockDim = dim3((unsigned)step4_threads());
+            kp.kernelParams = args_b4;
+        } else if (c->batch && c->tblock == 3) {
             const int g = c->grid3 < c->ntiles2 ? c->grid3 : c->ntiles2;
             kp.func = (void *)step3_batch_kernel_fn(c->storage, c->batch_uniform, g == c->ntiles2);
             kp.gridDim = dim3((unsigned)g);
@@ -695,7 +705,10 @@ int lbm_step(lbm_ctx *c, int64_t n) {
         const Dom d = last ? dom_rec(D, c->cur) : dom_for(D, c->cur);
         Dom *doms = last ? c->d_doms_rec : c->d_doms;
         if (cycles == 4) {
-            e = launch_step4(d, st, c->sched.swizzle, c->stream);
+            if (c->batch)
+                e = launch_step4_batch(doms, c->d_tiles4, c->ntiles4, c->cur, c->storage, c->batch_uniform, c->stream);
+            else
+                e = launch_step4(d, st, c->sched.swizzle, c->stream);
         } else if (cycles == 3) {
             if (c->batch)
                 e = launch_step3_batch(doms, c->d_tiles2, c->ntiles2, c->cur, c->storage, c->batch_uniform, c->grid3,
@@ -1018,7 +1031,11 @@ int lbm_time_blocking(const lbm_ctx *c, int32_t *cycles_per_pass, int32_t *threa
                       int32_t *grid) {
     if (int rc = check_handle(c)) return rc;
     int32_t nt = c->tb_threads, nr = c->tb_rows, ng = 0;
-    if (c->batch) {
+    if (c->batch && c->tblock == 4) {
+        nt = step4_threads();
+        nr = step4_rows();
+        ng = c->ntiles4;
+    } else if (c->batch) {
         if (c->tblock == 3) nt = step3_threads();
         ng = c->tblock == 3 ? c->grid3 : c->grid2;
     } else if (c->tblock == 4) {
@@ -1066,8 +1083,8 @@ int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
     int rc = check_ctx(c);
     if (rc) return rc;
     if (cycles_per_pass < 1 || cycles_per_pass > 4) return fail(LBM_EINVAL, "cycles per pass must be 1, 2, 3 or 4");
-    if (cycles_per_pass == 4 && (c->batch || c->dom[0].desc.thermal.enabled))
-        return fail(LBM_ENOTSUP, "four cycles per pass take single isothermal domains");
+    if (cycles_per_pass == 4 && (c->batch ? c->batch_thermal : c->dom[0].desc.thermal.enabled != 0))
+        return fail(LBM_ENOTSUP, "four cycles per pass take isothermal domains");
     if (cycles_per_pass == 3 && c->batch && c->batch_thermal)
         return fail(LBM_ENOTSUP, "thermal batches advance one or two cycles per pass");
     if (cycles_per_pass >= 2 && any_on_node_walls(c))
@@ -1076,11 +1093,13 @@ int lbm_set_time_blocking(lbm_ctx *c, int32_t cycles_per_pass) {
         return fail(LBM_ENOTSUP, "a population buffer of 4 GiB or more advances one cycle per pass");
     if (cycles_per_pass == 2 && c->batch && c->grid2 <= 0)
         return fail(LBM_ENOTSUP, "this batch has no tuned two-cycle schedule");
-    if (cycles_per_pass == 3 && c->batch) {
+    if (cycles_per_pass == 4 && c->batch && !c->four_ok)
+        return fail(LBM_ENOTSUP, "this batch has no four-cycle tile table");
+    if (cycles_per_pass >= 3 && c->batch) {
         if (c->grid3 <= 0) return fail(LBM_ENOTSUP, "this batch has no tuned three-cycle schedule");
         if (c->tb_rows != 16) {
-            // the three-cycle kernel walks 64 x 16 tiles; the two-cycle kernel then
-            // uses the same table
+            // the three-cycle kernel walks 64 x 16 tiles (also for the three-cycle
+            // passes of mode 4); the two-cycle kernel then uses the same table
             c->tb_rows = 16;
             hipError_t e = upload_tiles2(c, 16);
             if (e != hipSuccess) return device_fail(c, e, "tile table upload");
@@ -1174,8 +1193,8 @@ int64_t batch_tiles(int32_t n, const lbm_desc *descs, const Schedule &s) {
 
 struct BatchLayout {
     std::vector<size_t> off;  // per-domain base offsets
-    size_t off_doms = 0, off_tiles = 0, off_tiles2 = 0, total = 0;
-    int64_t max_tiles = 0, max_tiles2 = 0;
+    size_t off_doms = 0, off_tiles = 0, off_tiles2 = 0, off_tiles4 = 0, total = 0;
+    int64_t max_tiles = 0, max_tiles2 = 0, tiles4 = 0;
 };
 
 const int kTwoCycleShapes[][2] = {{256, 16}, {512, 16}, {256, 8}, {512, 8}};
@@ -1211,6 +1230,9 @@ BatchLayout batch_layout(int32_t n, const lbm_desc *descs) {
     }
     B.off_tiles2 = o;
     o = align_up(o + sizeof(int4) * (size_t)B.max_tiles2, ALIGN);
+    B.tiles4 = batch_tiles2(n, descs, step4_rows());
+    B.off_tiles4 = o;
+    o = align_up(o + sizeof(int4) * (size_t)B.tiles4, ALIGN);
     B.total = o;
     return B;
 }
@@ -1240,6 +1262,22 @@ hipError_t upload_tiles2(lbm_ctx *c, int rows) {
     return e;
 }
 
+// the 64 x 26 tiles of the batched four-cycle kernel, in their own table
+hipError_t upload_tiles4(lbm_ctx *c) {
+    c->h_tiles4.clear();
+    for (size_t k = 0; k < c->dom.size(); ++k) {
+        int tx, ty;
+        step4_tiles(c->dom[k].dom, &tx, &ty);
+        for (int y = 0; y < ty; ++y)
+            for (int x = 0; x < tx; ++x) c->h_tiles4.push_back(make_int4((int)k, x, y, 0));
+    }
+    c->ntiles4 = (int)c->h_tiles4.size();
+    hipError_t e = hipMemcpyAsync(c->d_tiles4, c->h_tiles4.data(), sizeof(int4) * c->h_tiles4.size(),
+                                  hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+}
+
 uint64_t batch_signature(const lbm_ctx *c) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](int64_t v) {
@@ -1260,12 +1298,13 @@ uint64_t batch_signature(const lbm_ctx *c) {
     return h;
 }
 
-// One tuning result: the one-cycle schedule and grid, and the two-cycle
-// shape and grid, plus which of the two is faster.
+// One tuning result: the one-cycle schedule and grid, the two-cycle shape
+// and grid, the three-cycle grid, whether the four-cycle pass (one workgroup
+// per tile) was timed, and which mode is fastest.
 struct Tuned {
     Schedule s{128, 1, 2, 0};
     int grid = 0;
-    int tblock = 1, tb_threads = 512, tb_rows = 16, grid2 = 0, grid3 = 0;
+    int tblock = 1, tb_threads = 512, tb_rows = 16, grid2 = 0, grid3 = 0, four = 0;
 };
 
 bool cache_lookup(const char *path, uint64_t sig, Tuned &out) {
@@ -1276,14 +1315,17 @@ bool cache_lookup(const char *path, uint64_t sig, Tuned &out) {
     bool found = false;
     while (fgets(line, sizeof(line), f)) {
         unsigned long long key;
-        int tw, v, r, g, tb, tt, tr, g2, g3;
-        if (sscanf(line, "%llx %d %d %d %d %d %d %d %d %d", &key, &tw, &v, &r, &g, &tb, &tt, &tr, &g2, &g3) != 10)
+        int tw, v, r, g, tb, tt, tr, g2, g3, f4;
+        if (sscanf(line, "%llx %d %d %d %d %d %d %d %d %d %d", &key, &tw, &v, &r, &g, &tb, &tt, &tr, &g2, &g3,
+                   &f4) != 11)
             continue;
         const Schedule cand{tw, v, r, 0};
-        if (key == sig && schedule_supported(cand) && g > 0 && tb >= 1 && tb <= 3 &&
-            step2_shape_supported(tt, tr) && g2 > 0 && g3 >= 0 && (tb < 3 || (g3 > 0 && tr == 16))) {
+        if (key == sig && schedule_supported(cand) && g > 0 && tb >= 1 && tb <= 4 &&
+            step2_shape_supported(tt, tr) && g2 > 0 && g3 >= 0 && (f4 == 0 || f4 == 1) &&
+            (tb < 3 || (g3 > 0 && tr == 16)) && (tb < 4 || f4 == 1)) {
             out.s = cand; out.grid = g; out.tblock = tb; out.tb_threads = tt; out.tb_rows = tr; out.grid2 = g2;
             out.grid3 = g3;
+            out.four = f4;
             found = true;
         }
     }
@@ -1295,8 +1337,8 @@ void cache_store(const char *path, uint64_t sig, const Tuned &t) {
     if (!path) return;
     FILE *f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%016llx %d %d %d %d %d %d %d %d %d\n", (unsigned long long)sig, t.s.tile_w, t.s.vec, t.s.rows,
-            t.grid, t.tblock, t.tb_threads, t.tb_rows, t.grid2, t.grid3);
+    fprintf(f, "%016llx %d %d %d %d %d %d %d %d %d %d\n", (unsigned long long)sig, t.s.tile_w, t.s.vec, t.s.rows,
+            t.grid, t.tblock, t.tb_threads, t.tb_rows, t.grid2, t.grid3, t.four);
     fclose(f);
 }
 
@@ -1376,10 +1418,25 @@ hipError_t autotune(lbm_ctx *c, Tuned &best) {
             if (ms / 3.0f < best3) { best3 = ms / 3.0f; best.grid3 = g; }
         }
     }
+    // four cycles per pass (isothermal batches): one workgroup per 64 x 26 tile
+    float best4 = 1e30f;
+    if (e == hipSuccess && two_cycle_ok && !c->batch_thermal && (e = upload_tiles4(c)) == hipSuccess) {
+        float ms = 0.0f;
+        e = time_it([&] { return launch_step4_batch(c->d_doms, c->d_tiles4, c->ntiles4, 0, c->storage,
+                                                    c->batch_uniform, c->stream); }, ms);
+        if (e == hipSuccess) {
+            best4 = ms / 4.0f;
+            best.four = 1;
+        }
+    }
     best.tblock = (best2 < best1) ? 2 : 1;
     if (best3 < best1 && best3 < best2) {
         best.tblock = 3;
         best.tb_rows = 16;   // the three-cycle kernel walks the 64 x 16 table
+    }
+    if (best4 < best1 && best4 < best2 && best4 < best3) {
+        best.tblock = 4;
+        best.tb_rows = 16;   // its three-cycle passes walk the 64 x 16 table
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -1451,6 +1508,7 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
                            c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     c->d_tiles2 = (int4 *)(base + B.off_tiles2);
+    c->d_tiles4 = (int4 *)(base + B.off_tiles4);
     Tuned best;
     const uint64_t sig = batch_signature(c);
     if (e == hipSuccess && !cache_lookup(tune_cache, sig, best)) {
@@ -1469,6 +1527,10 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
         c->grid2 = best.grid2 > c->ntiles2 ? c->ntiles2 : best.grid2;
         c->grid3 = best.grid3 > c->ntiles2 ? c->ntiles2 : best.grid3;
         c->tblock = best.tblock;
+    }
+    if (e == hipSuccess && !c->batch_thermal && two_cycle_possible(c)) {
+        e = upload_tiles4(c);
+        c->four_ok = e == hipSuccess;
     }
     if (e != hipSuccess) {
         rc = device_fail(nullptr, e, "batch creation");

@@ -1293,6 +1293,37 @@ int step4_threads() { return STEP4_NT; }
 
 int step4_rows() { return STEP4_TH; }
 
+// Batched four-cycle pass over a table of 64 x 26 tiles (isothermal domains;
+// MK_BRANCHED for any medium, MK_UNIFORM when every domain is uniform), one
+// workgroup per tile. (Workgroups walking runs of tiles, as the three-cycle
+// batch offers, spill 42-44 VGPRs at two workgroups per CU and are not built.)
+template <typename S, int MK>
+__global__ __launch_bounds__(STEP4_NT) __attribute__((amdgpu_waves_per_eu(6))) void k_step4_batch(
+    const Dom *__restrict__ doms, const int4 *__restrict__ tiles, int parity) {
+    __shared__ float lds[8 * (STEP4_TH + 6) * (STEP4_TW + 6)];
+    const int4 tl = tiles[blockIdx.x];
+    const Dom d = doms[2 * tl.x + parity];
+    step4_tile<S, STEP4_TW, STEP4_TH, STEP4_NT, false, MK>(d, tl.y * STEP4_TW, tl.z * STEP4_TH, nullptr, nullptr,
+                                                          nullptr, lds);
+}
+
+template <int MK>
+static const void *step4_batch_fn_mk(int storage) {
+    return storage == ST_F32 ? (const void *)&k_step4_batch<float, MK> : (const void *)&k_step4_batch<_Float16, MK>;
+}
+
+const void *step4_batch_kernel_fn(int storage, bool uniform) {
+    return uniform ? step4_batch_fn_mk<MK_UNIFORM>(storage) : step4_batch_fn_mk<MK_BRANCHED>(storage);
+}
+
+hipError_t launch_step4_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, bool uniform,
+                              hipStream_t st) {
+    if (ntiles <= 0) return hipErrorInvalidValue;
+    const void *fn = step4_batch_kernel_fn(storage, uniform);
+    void *args[3] = {&doms, &tiles, &parity};
+    return hipLaunchKernel(fn, dim3((unsigned)ntiles), dim3(STEP4_NT), args, 0, st);
+}
+
 template <int MK>
 static const void *step4_fn_t(int storage) {
     return storage == ST_F32 ? (const void *)&k_step4<float, STEP4_TW, STEP4_TH, STEP4_NT, MK>

@@ -63,6 +63,12 @@ const void *step4_kernel_fn(const Dom &d, int storage);
 // the four-cycle pass recording u (and with d.rec_stress the stress moments) at
 // t (d.urec), t + 1, t + 2, t + 3 (FP32 isothermal domains; same grid)
 hipError_t launch_step4_rec(const Dom &d, int swizzle, float *urec1, float *urec2, float *urec3, hipStream_t st);
+// batched four-cycle pass over a table of 64 x 26 tiles (isothermal domains),
+// one workgroup per tile (a grid of ntiles; kernel arguments (doms, tiles,
+// parity)); uniform as for the three-cycle batch
+const void *step4_batch_kernel_fn(int storage, bool uniform);
+hipError_t launch_step4_batch(const Dom *doms, const int4 *tiles, int ntiles, int parity, int storage, bool uniform,
+                              hipStream_t st);
 // batched three-cycle pass over a table of 64 x 16 tiles (isothermal domains);
 // uniform: every domain has a uniform medium and one s_nu (medium_kind MK_UNIFORM),
 // so the kernel loads no medium planes; one: one workgroup per tile (a grid of

@@ -39,10 +39,10 @@ def single_run(case, steps, storage):
 
 @pytest.mark.parametrize("uniform", [False, True])
 @pytest.mark.parametrize("storage", [lbm.FP32_DEV, lbm.FP16_DEV])
-@pytest.mark.parametrize("tblock", [1, 2, 3])
+@pytest.mark.parametrize("tblock", [1, 2, 3, 4])
 def test_batch_is_bitwise_equal_to_single_domains(storage, tblock, uniform, tmp_path):
-    """One, two and three cycles per pass, graph replays of 6 cycles, leftovers; mixed
-    media and all-uniform media."""
+    """One to four cycles per pass, graph replays of 6 cycles (4 in mode 4), leftovers;
+    mixed media and all-uniform media."""
     cases = mixed_cases(uniform)
     b = lbm.batch_for_cases(cases, storage=storage, tune_cache=tmp_path / "tune.txt")
     b.set_time_blocking(tblock)
@@ -71,7 +71,7 @@ def test_batch_workgroups_walking_runs_of_tiles(kind, storage, tblock, tmp_path)
     path = tmp_path / "tune.txt"
     lbm.batch_for_cases(cases, storage=storage, tune_cache=path)
     fields = path.read_text().split()
-    assert len(fields) == 10        # key, one-cycle shape and grid, mode, two-cycle shape, grid2, grid3
+    assert len(fields) == 11        # key, one-cycle shape and grid, mode, two-cycle shape, grid2, grid3, four
     fields[8], fields[9] = "3", ("0" if thermal else "5")
     path2 = tmp_path / "tune_small_grids.txt"
     path2.write_text(" ".join(fields) + "\n")
@@ -113,7 +113,7 @@ def test_tune_cache_is_written_and_reused(tmp_path):
     path = tmp_path / "tune.txt"
     b1 = lbm.batch_for_cases(cases, tune_cache=path)
     text = path.read_text().strip().splitlines()
-    assert len(text) == 1 and len(text[0].split()) == 10
+    assert len(text) == 1 and len(text[0].split()) == 11
     b2 = lbm.batch_for_cases(cases, tune_cache=path)
     assert b1.schedule() == b2.schedule()
     assert len(path.read_text().strip().splitlines()) == 1    # found, not re-tuned

@@ -154,9 +154,10 @@ def test_tall_four_cycle_tiles_are_bitwise_equal(name, case, storage):
         del a, b
 
 
-def test_four_cycles_take_single_isothermal_domains():
-    """Mode 4 is refused (ENOTSUP) for thermal domains and for batches, and leaves
-    the context's mode unchanged."""
+def test_four_cycles_take_isothermal_domains():
+    """Mode 4 is refused (ENOTSUP) for thermal domains and thermal batches, and leaves
+    the context's mode unchanged; an isothermal batch takes it (64 x 26 tiles, one
+    workgroup each)."""
     _, thermal = thermal_cases()[0]
     s = lbm.solver_for_case(thermal)
     before = s.time_blocking()["cycles_per_pass"]
@@ -164,10 +165,16 @@ def test_four_cycles_take_single_isothermal_domains():
         s.set_time_blocking(4)
     assert e.value.status == lbm.ENOTSUP
     assert s.time_blocking()["cycles_per_pass"] == before
-    b = lbm.batch_for_cases([c for _, c in cases()[:2]])
+    tb = lbm.batch_for_cases([c for _, c in thermal_cases()])
     with pytest.raises(lbm.LBMError) as e:
-        b.set_time_blocking(4)
+        tb.set_time_blocking(4)
     assert e.value.status == lbm.ENOTSUP
+    iso = [c for _, c in cases()[:2]]
+    b = lbm.batch_for_cases(iso)
+    b.set_time_blocking(4)
+    shape = b.time_blocking()
+    assert (shape["cycles_per_pass"], shape["threads"], shape["rows"]) == (4, 768, 26)
+    assert shape["grid"] == sum(((c.nx + 63) // 64) * ((c.ny + 25) // 26) for c in iso)
     with pytest.raises(lbm.LBMError) as e:
         s.set_time_blocking(5)
     assert e.value.status == lbm.EINVAL
