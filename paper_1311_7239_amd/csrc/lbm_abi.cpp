@@ -1532,6 +1532,10 @@ extern "C" int lbm_create_batch(int32_t n, const lbm_desc *descs, const float *c
         e = upload_tiles4(c);
         c->four_ok = e == hipSuccess;
     }
+    // a tuning-cache entry cannot select a mode this batch does not have
+    if (c->batch_thermal && c->tblock > 2) c->tblock = 2;
+    if (c->tblock == 4 && !c->four_ok) c->tblock = 3;
+    if (c->tblock >= 2 && !two_cycle_possible(c)) c->tblock = 1;
     if (e != hipSuccess) {
         rc = device_fail(nullptr, e, "batch creation");
         delete c;

@@ -96,6 +96,29 @@ def test_batch_workgroups_walking_runs_of_tiles(kind, storage, tblock, tmp_path)
             assert torch.equal(got, df), k
 
 
+def test_cache_entry_cannot_select_a_missing_mode(tmp_path):
+    """A tuning-cache entry naming four cycles for a thermal batch (which has only one
+    and two) is clamped to two cycles; the batch still equals single domains bit for bit."""
+    from tests.test_gpu_timeblock import thermal_cases
+    cases = [c for _, c in thermal_cases()]
+    path = tmp_path / "tune.txt"
+    lbm.batch_for_cases(cases, tune_cache=path)
+    fields = path.read_text().split()
+    # mode 4, 16-row two-cycle tiles, grid3 and the four-cycle flag: a line the lookup accepts
+    fields[5], fields[7], fields[9], fields[10] = "4", "16", "5", "1"
+    path.write_text(" ".join(fields) + "\n")
+    b = lbm.batch_for_cases(cases, tune_cache=path)
+    assert b.time_blocking()["cycles_per_pass"] == 2
+    b.step(9)
+    for k, c in enumerate(cases):
+        s = lbm.solver_for_case(c)
+        s.step(9)
+        df, dg = s.populations(thermal=True)
+        got = b.populations(k, thermal=True)
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], df) and torch.equal(got[1], dg), k
+
+
 def test_batch_matches_oracle():
     cases = mixed_cases()[:3]
     b = lbm.batch_for_cases(cases)
