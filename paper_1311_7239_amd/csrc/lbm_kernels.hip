@@ -1048,8 +1048,9 @@ hipError_t launch_step3(const Dom &d, int storage, int swizzle, float *urec1, fl
 
 // ------------------------------------------------- four cycles per pass
 
-// Temporal blocking over four cycles, for single isothermal domains that do
-// not record: the three-cycle pass with one more LDS phase. A workgroup owns a
+// Temporal blocking over four cycles, for isothermal domains (single, batched,
+// and the recording pass of the adjoint's recomputation): the three-cycle pass
+// with one more LDS phase. A workgroup owns a
 // TW x TH tile. Phase A gathers f(t) from HBM on the tile plus a three-node
 // ring and collides into LDS; phase B gathers f(t+1) from LDS on the tile plus
 // a two-node ring and phase C f(t+2) on the tile plus a one-node ring, each
